@@ -1,0 +1,6 @@
+"""CPU FP64 oracle for the two-sided sketched rank estimator (test infrastructure only).
+
+Only tests/, __graft_entry__.smoke() and bench.py's CPU-baseline leg may import this
+package.  The product library never does.
+"""
+from .pyoracle import *  # noqa: F401,F403

@@ -1,0 +1,133 @@
+"""Seeded synthetic test matrices (no part of the estimator's arithmetic).
+
+Shared by the tests, the benchmark and the smoke check, for both the GPU library
+and the CPU oracle.  Every matrix is synthetic with a prescribed spectrum, as in
+the paper's experiments (Sec. 6: diagonal test matrices with gaps, polynomial and
+exponential decay).  Dense planted matrices A = U diag(s) V^T use thin Haar factors
+(QR of a seeded Gaussian, columns multiplied by sign(diag R), Mezzadri 2007), are
+formed in FP64 and rounded once to the storage type.
+
+All generation goes through ``torch`` so that large inputs can be produced directly
+in device memory; a given (seed, device type) always yields the same bytes.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+
+def _gen(seed: int, device) -> torch.Generator:
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return g
+
+
+def haar(rows: int, cols: int, seed: int, device="cpu") -> torch.Tensor:
+    """Thin Haar-distributed factor with orthonormal columns (rows >= cols), FP64."""
+    g = _gen(seed, device)
+    G = torch.randn(rows, cols, generator=g, dtype=torch.float64, device=device)
+    Q, R = torch.linalg.qr(G, mode="reduced")
+    d = torch.sign(torch.diagonal(R))
+    d[d == 0] = 1.0
+    return Q * d
+
+
+def planted(m: int, n: int, sigma, seed: int, dtype=torch.float64, noise: float = 0.0,
+            device="cpu", chunk_rows: int = 4096) -> torch.Tensor:
+    """A = U diag(sigma) V^T (+ noise * N(0,1)) rounded once to ``dtype``.
+
+    U is m x R and V is n x R thin Haar with R = len(sigma) <= min(m, n).
+    """
+    s = torch.as_tensor(np.asarray(sigma, dtype=np.float64), device=device)
+    R = s.numel()
+    if R > min(m, n):
+        raise ValueError("len(sigma) must not exceed min(m, n)")
+    U = haar(m, R, seed, device)
+    V = haar(n, R, seed + 7919, device)
+    W = (V * s).T.contiguous()  # R x n
+    A = torch.empty(m, n, dtype=dtype, device=device)
+    gn = _gen(seed + 104729, device) if noise else None
+    for r0 in range(0, m, chunk_rows):
+        r1 = min(m, r0 + chunk_rows)
+        blk = U[r0:r1] @ W
+        if noise:
+            blk += noise * torch.randn(r1 - r0, n, generator=gn, dtype=torch.float64, device=device)
+        A[r0:r1] = blk.to(dtype)
+        del blk
+    return A
+
+
+def exact_rank(m: int, n: int, r: int, seed: int, dtype=torch.float64, device="cpu") -> torch.Tensor:
+    """A = B C with Gaussian B (m x r) and C (r x n): rank exactly r (a.s.)."""
+    g = _gen(seed, device)
+    Bm = torch.randn(m, r, generator=g, dtype=torch.float64, device=device)
+    Cm = torch.randn(r, n, generator=g, dtype=torch.float64, device=device)
+    return (Bm @ Cm).to(dtype)
+
+
+def gaussian(m: int, n: int, seed: int, dtype=torch.float64, device="cpu") -> torch.Tensor:
+    g = _gen(seed, device)
+    return torch.randn(m, n, generator=g, dtype=torch.float64, device=device).to(dtype)
+
+
+def small_integers(m: int, n: int, seed: int, lo: int = -8, hi: int = 8, dtype=torch.float32,
+                   device="cpu") -> torch.Tensor:
+    """Integer-valued entries: every sum of products stays exact in FP32/FP64."""
+    g = _gen(seed, device)
+    return torch.randint(lo, hi + 1, (m, n), generator=g, device=device).to(dtype)
+
+
+# --- spectra ------------------------------------------------------------------
+
+def spectrum_gap(n: int, block: int = 100, levels=(1.0, 1e-4, 1e-8, 1e-12, 1e-16)) -> np.ndarray:
+    """Sec. 6, matrix A_G: constant blocks of `block` values at each level."""
+    s = np.full(n, levels[-1], dtype=np.float64)
+    for b, v in enumerate(levels):
+        s[b * block:(b + 1) * block] = v
+    return s[:n]
+
+
+def spectrum_poly(n: int, p: float) -> np.ndarray:
+    """Sec. 6, A_SP (p = 1) and A_FP (p = 3): s_i = i^-p."""
+    return np.arange(1, n + 1, dtype=np.float64) ** (-p)
+
+
+def spectrum_exp(n: int, q: float) -> np.ndarray:
+    """Sec. 6, A_SE (q = 0.01) and A_FE (q = 0.5): s_i = 10^(-q (i-1))."""
+    return 10.0 ** (-q * np.arange(n, dtype=np.float64))
+
+
+def spectrum_step(n: int, r: int, hi: float = 1.0, lo: float = 1e-8) -> np.ndarray:
+    s = np.full(n, lo, dtype=np.float64)
+    s[:r] = hi
+    return s
+
+
+# --- the workload shapes ----------------------------------------------------------
+
+def c1_matrix(seed: int = 1001, device="cpu") -> torch.Tensor:
+    """FP64 2000 x 1000, s = 1 (x20) then 1e-8 (x980): eps = 1e-6 gives rank 20."""
+    return planted(2000, 1000, spectrum_step(1000, 20, 1.0, 1e-8), seed, torch.float64, 0.0, device)
+
+
+def c2_spectrum(R: int = 1024) -> np.ndarray:
+    """s_i = 10^(-i/20), i = 1..R."""
+    return 10.0 ** (-np.arange(1, R + 1, dtype=np.float64) / 20.0)
+
+
+def c2_matrix(m: int = 65536, n: int = 16384, R: int = 1024, seed: int = 1002, device="cpu") -> torch.Tensor:
+    """FP32 m x n = U diag(10^(-i/20)) V^T + 1e-9 N, rounded once to FP32."""
+    return planted(m, n, c2_spectrum(R), seed, torch.float32, 1e-9, device)
+
+
+def c3_spectrum(R: int = 1024, r: int = 200) -> np.ndarray:
+    """1 for the first r values, then 1e-4 decaying by a factor 10 every 100 values."""
+    i = np.arange(1, R + 1, dtype=np.float64)
+    s = 1e-4 * 10.0 ** (-(i - (r + 1)) / 100.0)
+    s[:r] = 1.0
+    return s
+
+
+def c3_matrix(m: int = 32768, n: int = 8192, R: int = 1024, seed: int = 1003, device="cpu") -> torch.Tensor:
+    return planted(m, n, c3_spectrum(R), seed, torch.float32, 0.0, device)
+
