@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of the two-sided sketched rank estimator on one MI355X.
+
+One step = Algorithm 1 end to end on one matrix (draw X, A X pass, draw Y, Y B
+pass, FP64 small SVD, count, results to the host), through the library's C ABI.
+Default workload: FP32 A of 65536 x 16384 = U diag(10^(-i/20)) V^T + 1e-9 N
+(R = 1024, thin Haar factors), SRHT X of 16384 x 384 and SRHT Y of 576 x 65536,
+eps alternating 1e-3 / 1e-5, a fresh sketch seed every step.  A is resident in
+HBM before timing starts.
+
+Prints one JSON line.  `roofline` describes the A X pass (the dominant kernel):
+algorithmic bytes m*n*4 divided by that kernel's mean duration, measured with
+HIP events recorded on the library's stream around it in every timed step.
+`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "c2": dict(m=65536, n=16384, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="srht", y="srht",
+               desc="plain method at scale: FP32 65536x16384, s_i=10^(-i/20) (R=1024) + 1e-9 noise, "
+                    "SRHT X 16384x384, SRHT Y 576x65536, eps 1e-3/1e-5"),
+    "c1": dict(m=2000, n=1000, R=1000, k=40, l=60, eps=(1e-6,), x="gaussian", y="gaussian",
+               desc="plain method, CPU-sized: FP64 2000x1000, step spectrum (20 x 1, then 1e-8), "
+                    "Gaussian X 1000x40, Gaussian Y 60x2000, eps 1e-6"),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("srht.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2105_07388_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per launch of the A X kernel from committed rocprofv3 counter runs,
+    only if they were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = t.get(workload)
+    if not rec or rec.get("src_digest") != kernel_source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def make_matrix(name, w, device):
+    import torch
+
+    from paper_2105_07388_amd import inputs
+    if name == "c2":
+        return inputs.c2_matrix(w["m"], w["n"], w["R"], device=device)
+    if name == "c1":
+        return inputs.c1_matrix(device=device)
+    raise ValueError(name)
+
+
+def cpu_baseline(A_dev, w, rows: int):
+    """Oracle timed on a bounded sample: its A X step on the first `rows` rows
+    (scaled to m), its Y B step on an m x k matrix and its SVD on an l x k one."""
+    import numpy as np
+
+    import oracle
+    m, n, k, l = w["m"], w["n"], w["k"], w["l"]
+    rows = min(rows, m)
+    xk = oracle.SRHT if w["x"] == "srht" else oracle.GAUSSIAN
+    yk = oracle.SRHT if w["y"] == "srht" else oracle.GAUSSIAN
+    A_s = A_dev[:rows].cpu().numpy()
+    t0 = time.perf_counter()
+    B = oracle.apply_x(A_s, xk, k, seed=0)
+    t_x = (time.perf_counter() - t0) * (m / rows)
+    Bfull = np.random.default_rng(0).standard_normal((m, k))
+    Bfull[:rows] = B
+    t0 = time.perf_counter()
+    Cm = oracle.apply_y(Bfull, yk, l, seed=0)
+    t_y = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.jacobi_sv(Cm)
+    t_svd = time.perf_counter() - t0
+    total = t_x + t_y + t_svd
+    return {"value": 1.0 / total, "unit": "rank estimates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"A X on the first {rows} of {m} rows scaled by {m / rows:g}, Y B on a full {m}x{k} B, "
+                      f"Jacobi SVD of the {l}x{k} sketch; seconds: ax {t_x:.2f}, yb {t_y:.2f}, svd {t_svd:.2f}"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-rows", type=int, default=8192, help="rows of A in the oracle's timed sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the estimator here is a single-GPU "
+              "build and multi-GPU sharding is not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2105_07388_amd as re_
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    A = make_matrix(args.workload, w, dev)
+    torch.cuda.synchronize()
+    h = re_.Handle(dev)
+    h.set_profiling(True)
+    print(f"[bench] {args.workload}: A {tuple(A.shape)} {A.dtype} resident; warmup {args.warmup}", file=sys.stderr,
+          flush=True)
+
+    def step(i):
+        eps = w["eps"][i % len(w["eps"])]
+        return re_.rank_estimate(A, eps, k=w["k"], l=w["l"], x=w["x"], y=w["y"], seed=1000003 * (i + 1),
+                                 handle=h)
+
+    for i in range(args.warmup):
+        step(-1 - i)
+    torch.cuda.synchronize()
+    stages = []
+    ranks = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r, _, info = step(i)
+        ranks.append(r)
+        stages.append(h.last_stage_ms())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    st_mean = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
+    ax_ms = st_mean["ax"]
+    elem = A.element_size()
+    alg_bytes = w["m"] * w["n"] * elem
+    achieved = alg_bytes / (ax_ms * 1e-3) / 1e9
+    print(f"[bench] stages (ms): " + ", ".join(f"{k} {v:.4f}" for k, v in st_mean.items()) + f"; ranks {sorted(set(ranks))}",
+          file=sys.stderr, flush=True)
+    out = {
+        "metric": "rank estimates/s + sketch GB/s vs HBM peak; learned vs doubling, same rank",
+        "value": args.steps / elapsed,
+        "unit": "rank estimates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if elem == 4 else "f64",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "m": w["m"], "n": w["n"], "k": w["k"], "l": w["l"], "eps": list(w["eps"]),
+                   "x": w["x"], "y": w["y"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(args.workload),
+                     "kernel": "A X pass", "algorithmic_bytes_per_launch": alg_bytes, "mean_ms": ax_ms},
+        "stage_ms": st_mean,
+    }
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(A, w, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

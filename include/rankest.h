@@ -1,0 +1,198 @@
+/*
+ * rankest.h — C ABI of librankest, an MI355X (gfx950) implementation of the
+ * two-sided sketched numerical-rank estimator of M. Meier and Y. Nakatsukasa,
+ * "Fast Randomized Numerical Rank Estimation for Numerically Low-Rank
+ * Matrices" (arXiv 2105.07388), Algorithm 1 (Sec. 5).
+ *
+ * Given an m x n matrix A in device memory, a relative tolerance eps and a
+ * sketch width k = round(1.1 r1) (r1 = the rank upper bound of Algorithm 1),
+ * the library forms the sketch Y A X (X: n x k, Y: l x m random embeddings),
+ * computes its singular values in FP64, scales them by 1/sqrt(k l) (the
+ * embedding normalisations of Sec. 1, X = G/sqrt(k), and Eq. (Theta)), and
+ * counts those above eps * sigma_1 among the first r1 (Def. 1, Algorithm 1
+ * steps 7-8).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are row-major with a leading dimension in elements.
+ *   - "device" pointers are memory allocated on the handle's GPU; "host"
+ *     pointers are ordinary host memory.  The caller owns all pointers it
+ *     passes; the library owns only the workspace inside the handle.
+ *   - Calls enqueue work on the handle's stream.  Entry points that write to
+ *     host memory synchronise that stream before returning; entry points that
+ *     write only device memory return without synchronising.
+ *   - Every call returns a re_status.  On error nothing has been written to
+ *     the host outputs; device outputs may hold partial results.  No entry
+ *     point prints, aborts or throws.
+ *   - A handle is not thread-safe: use one handle per host thread.
+ */
+#ifndef RANKEST_H
+#define RANKEST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RE_OK = 0,
+  RE_ERR_INVALID_ARG = -1,   /* an argument is out of range or a pointer is NULL */
+  RE_ERR_UNSUPPORTED = -2,   /* a valid combination this build does not implement */
+  RE_ERR_NO_MEMORY = -3,     /* a workspace allocation failed */
+  RE_ERR_HIP = -4,           /* a HIP runtime call failed */
+  RE_ERR_NONFINITE = -5,     /* A (or the sketch) holds NaN or Inf */
+  RE_ERR_NO_CONVERGENCE = -6 /* the small SVD did not converge */
+} re_status;
+
+/* Storage type of A. */
+typedef enum { RE_F64 = 0, RE_F32 = 1 } re_dtype;
+
+/* Random embedding families (Sec. 3.3): a Gaussian embedding, or a
+ * subsampled randomized Hadamard transform sqrt(N/k) S H D (Eq. (Theta), with
+ * the Hadamard matrix as the trigonometric transform and N = the dimension
+ * zero-padded to a power of two). */
+typedef enum { RE_GAUSSIAN = 0, RE_SRHT = 1 } re_kind;
+
+/* Arithmetic of the A X contraction.  NATIVE: the storage type of A.
+ * BF16 / FP16: A and a Gaussian X rounded to that format, FP32 accumulation.
+ * AUTO: the cheapest format whose rounding floor stays below eps/4. */
+typedef enum { RE_PREC_NATIVE = 0, RE_PREC_BF16 = 1, RE_PREC_FP16 = 2, RE_PREC_AUTO = 3 } re_prec;
+
+/* The sketch of Algorithm 1: X is n x k (k = round(1.1 r1), step 1) and Y is
+ * l x m (l = r2, step 4; 0 selects the paper's r2 = 2k). */
+typedef struct {
+  int32_t x_kind; /* re_kind of X */
+  int32_t y_kind; /* re_kind of Y */
+  int32_t k;      /* columns of X, 1 <= k <= n (n rounded up to a power of two for SRHT) */
+  int32_t l;      /* rows of Y, k <= l <= m (m rounded up for SRHT); 0 means 2k */
+  int32_t prec;   /* re_prec */
+} re_sketch;
+
+/* Result flags. */
+enum {
+  RE_FLAG_NOT_CONVERGED = 1u, /* all of the first r1 estimates exceed eps*sigma_1: rank >= r1 (Algorithm 1 step 8) */
+  RE_FLAG_ZERO = 2u,          /* sigma_1 of the sketch is zero */
+  RE_FLAG_PREC_FALLBACK = 4u  /* AUTO could not use a low-precision format */
+};
+
+typedef struct re_handle_s* re_handle;
+
+/* Create a handle bound to the current HIP device and to `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *h receives the handle. */
+re_status re_create(re_handle* h, void* hip_stream);
+
+/* Release the handle and all of its workspace.  NULL is accepted. */
+re_status re_destroy(re_handle h);
+
+/* Rebind the handle to another stream of the same device. */
+re_status re_set_stream(re_handle h, void* hip_stream);
+
+/* Bytes of device workspace the handle currently holds. */
+re_status re_workspace_bytes(re_handle h, size_t* bytes);
+
+/* Stages of re_rank_estimate timed by re_set_profiling: drawing X, the A X
+ * pass, drawing Y, the Y B pass, the small SVD, and the count with the copy
+ * of the results to the host (Algorithm 1 steps 2, 3, 5, 6, 7, 8). */
+enum {
+  RE_STAGE_X_DRAW = 0,
+  RE_STAGE_AX = 1,
+  RE_STAGE_Y_DRAW = 2,
+  RE_STAGE_YB = 3,
+  RE_STAGE_SVD = 4,
+  RE_STAGE_RANK = 5,  /* the count plus the copy of the results to the host */
+  RE_NUM_STAGES = 6
+};
+
+/* enable != 0: record HIP events on the handle's stream around each stage of
+ * every later re_rank_estimate call (adds seven event records per call). */
+re_status re_set_profiling(re_handle h, int32_t enable);
+
+/* Durations in milliseconds of the stages of the last re_rank_estimate call
+ * (ms: host array of RE_NUM_STAGES doubles, indexed by RE_STAGE_*).
+ * Requires profiling enabled. */
+re_status re_last_stage_ms(re_handle h, double* ms);
+
+/*
+ * Algorithm 1 of the paper on one matrix.
+ *   A_dev      device, m x n row-major with leading dimension lda >= n, type dt;
+ *              read only; 16-byte aligned.
+ *   eps        relative tolerance, 0 < eps < 1 (Def. 1).
+ *   sk         sketch description (host).
+ *   seed       key of the counter-based generator defining X and Y.
+ *   r_out      host: the rank estimate r^ (number of the first r1 estimates
+ *              strictly above eps * sigma_1).
+ *   sigma_out  host, k doubles: sigma_i(Y A X) / sqrt(k l), descending.
+ *   r1_out     host or NULL: r1, the largest r with round(1.1 r) <= k.
+ *   flags_out  host or NULL: RE_FLAG_* bits.
+ * Errors: RE_ERR_INVALID_ARG for bad sizes or pointers, RE_ERR_UNSUPPORTED for
+ * low precision with an FP64 A or an SRHT X, RE_ERR_NONFINITE when A holds
+ * NaN/Inf, RE_ERR_NO_CONVERGENCE when the small SVD fails.
+ * Synchronises the handle's stream.
+ */
+re_status re_rank_estimate(re_handle h, const void* A_dev, int32_t dt, int64_t m, int64_t n, int64_t lda, double eps,
+                           const re_sketch* sk, uint64_t seed, int32_t* r_out, double* sigma_out, int32_t* r1_out,
+                           uint32_t* flags_out);
+
+/*
+ * Stage entry points.  Each runs one step of Algorithm 1 on device buffers,
+ * enqueued on the handle's stream without synchronising, so that a caller can
+ * run, time or check the steps one at a time.
+ */
+
+/* Philox4x64-10 of the sketch specification: out[4i..4i+3] = Philox(ctr[4i..4i+3],
+ * key = (seed, 0)).  ctr_dev and out_dev are device arrays of 4*count uint64. */
+re_status re_philox(re_handle h, const uint64_t* ctr_dev, uint64_t seed, int64_t count, uint64_t* out_dev);
+
+/* Gaussian sketch entries (Sec. 1: iid N(0,1), scale applied at the end):
+ * out[i*cols + j] = round_fmt(z(a, b)) with (a, b) = (i, j), or (j, i) when
+ * swap_ab != 0, drawn from counter stream `stream_id` (1 for X, 2 for Y).
+ * fmt: 0 FP64, 1 FP32, 2 BF16, 3 FP16 (elements of 8, 4, 2, 2 bytes). */
+re_status re_gauss_fill(re_handle h, int32_t fmt, int64_t rows, int64_t cols, uint64_t seed, int32_t stream_id,
+                        int32_t swap_ab, void* out_dev);
+
+/* Rademacher diagonal D of an SRHT (Eq. (Theta)): bit i of word i/32 of
+ * bits_dev (device, npad/32 words rounded up) is set when d_i = -1.
+ * stream_id 3 for X, 4 for Y. */
+re_status re_srht_signs(re_handle h, int64_t npad, uint64_t seed, int32_t stream_id, uint32_t* bits_dev);
+
+/* Row sampler S of an SRHT (uniform sampling without replacement, Appendix):
+ * the k indices of [0, npad) with the smallest 64-bit keys (ties by index),
+ * written in ascending order to idx_dev (device, k int32).  stream_id 5 (X) or 6 (Y). */
+re_status re_srht_select(re_handle h, int64_t npad, int64_t k, uint64_t seed, int32_t stream_id, int32_t* idx_dev);
+
+/* Algorithm 1 step 3, B = A X without the 1/sqrt(k) scale.  A_dev as in
+ * re_rank_estimate; B_dev device, m x k row-major, FP64 when dt = RE_F64 and
+ * FP32 otherwise.  For SRHT this is B[i][t] = (H (d .* [a_i, 0]))[S_t]. */
+re_status re_sketch_x(re_handle h, const void* A_dev, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                      const re_sketch* sk, uint64_t seed, void* B_dev);
+
+/* Algorithm 1 step 6, C = Y B without the 1/sqrt(l) scale.  B_dev device,
+ * m x k row-major of type bdt (RE_F64 or RE_F32); it is used as scratch and
+ * overwritten, and must provide re_sketch_y_rows(m) rows.  C_dev device,
+ * l x k row-major FP64. */
+re_status re_sketch_y(re_handle h, void* B_dev, int32_t bdt, int64_t m, int64_t k, const re_sketch* sk,
+                      uint64_t seed, double* C_dev);
+int64_t re_sketch_y_rows(int64_t m);
+
+/* Algorithm 1 step 7: the k singular values of the l x k FP64 row-major
+ * device matrix C_dev (k <= l), multiplied by `scale`, descending, into
+ * sigma_dev (device, k doubles).  C_dev is not modified. */
+re_status re_singular_values(re_handle h, const double* C_dev, int64_t l, int64_t k, double scale,
+                             double* sigma_dev);
+
+/* Algorithm 1 step 8 on device: out_dev[0] = r^, out_dev[1] = flags for the
+ * descending sigma_dev[0..k) with r1 and eps (strict inequality of Def. 1). */
+re_status re_rank_count(re_handle h, const double* sigma_dev, int64_t k, int32_t r1, double eps, int32_t* out_dev);
+
+/* r1 derived from the sketch width k (Algorithm 1 step 1 inverted). */
+int32_t re_r1_from_k(int32_t k);
+
+/* Human-readable text for a status code. */
+const char* re_status_string(re_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RANKEST_H */

@@ -9,7 +9,8 @@ import os
 
 import numpy as np
 
-from .build import LIB, build
+from .build import LIB
+from .build import build as _build_lib
 
 GAUSSIAN, SRHT = 0, 1
 FMT_F64, FMT_F32, FMT_BF16, FMT_F16 = 0, 1, 2, 3
@@ -23,7 +24,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
-            build()
+            _build_lib()
         L = C.CDLL(LIB)
         u64, i64, i32, dbl, vp = C.c_uint64, C.c_int64, C.c_int, C.c_double, C.c_void_p
         L.or_philox4x64_10.argtypes = [vp, vp, vp]

@@ -1,0 +1,27 @@
+"""MI355X (gfx950) implementation of the two-sided sketched numerical-rank
+estimator of Meier & Nakatsukasa (arXiv 2105.07388, Algorithm 1).
+
+The estimator runs entirely in the HIP library ``librankest.so`` (C ABI in
+include/rankest.h); this package only marshals arguments.  Importing it does not
+load the library; the first call does, and raises ``RankEstError`` if the
+library has not been built.
+"""
+from ._binding import (  # noqa: F401
+    FLAG_NOT_CONVERGED,
+    FLAG_PREC_FALLBACK,
+    FLAG_ZERO,
+    Handle,
+    RankEstError,
+    default_handle,
+    gauss_fill,
+    lib,
+    philox,
+    r1_from_k,
+    rank_count,
+    rank_estimate,
+    singular_values,
+    sketch_x,
+    sketch_y,
+    srht_select,
+    srht_signs,
+)

@@ -1,0 +1,287 @@
+"""ctypes binding of librankest (include/rankest.h): argument marshalling only.
+
+Tensors must live on the GPU; every computation runs in the HIP library.  When
+the library has not been built, every call raises ``RankEstError`` — there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librankest.so")
+
+RE_OK, RE_ERR_INVALID_ARG, RE_ERR_UNSUPPORTED, RE_ERR_NO_MEMORY = 0, -1, -2, -3
+RE_ERR_HIP, RE_ERR_NONFINITE, RE_ERR_NO_CONVERGENCE = -4, -5, -6
+RE_F64, RE_F32 = 0, 1
+RE_GAUSSIAN, RE_SRHT = 0, 1
+PREC = {"native": 0, "bf16": 1, "fp16": 2, "auto": 3}
+KIND = {"gaussian": RE_GAUSSIAN, "srht": RE_SRHT}
+FLAG_NOT_CONVERGED, FLAG_ZERO, FLAG_PREC_FALLBACK = 1, 2, 4
+FMT = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+FMT_DTYPE = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float16}
+STAGES = ("x_draw", "ax", "y_draw", "yb", "svd", "rank")
+NUM_STAGES = len(STAGES)
+
+
+class RankEstError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        msg = _status_text(status)
+        super().__init__(f"{where}: {msg} (status {status})" if where else f"{msg} (status {status})")
+        self.status = status
+
+
+class ReSketch(C.Structure):
+    _fields_ = [("x_kind", C.c_int32), ("y_kind", C.c_int32), ("k", C.c_int32), ("l", C.c_int32),
+                ("prec", C.c_int32)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Load librankest.so; raises RankEstError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RankEstError(RE_ERR_HIP, f"HIP library missing at {LIB_PATH}; build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+        sig = {
+            "re_create": ([C.POINTER(vp), vp], i32),
+            "re_destroy": ([vp], i32),
+            "re_set_stream": ([vp, vp], i32),
+            "re_workspace_bytes": ([vp, C.POINTER(C.c_size_t)], i32),
+            "re_set_profiling": ([vp, i32], i32),
+            "re_last_stage_ms": ([vp, vp], i32),
+            "re_rank_estimate": ([vp, vp, i32, i64, i64, i64, dbl, C.POINTER(ReSketch), u64, C.POINTER(i32), vp,
+                                  C.POINTER(i32), C.POINTER(C.c_uint32)], i32),
+            "re_philox": ([vp, vp, u64, i64, vp], i32),
+            "re_gauss_fill": ([vp, i32, i64, i64, u64, i32, i32, vp], i32),
+            "re_srht_signs": ([vp, i64, u64, i32, vp], i32),
+            "re_srht_select": ([vp, i64, i64, u64, i32, vp], i32),
+            "re_sketch_x": ([vp, vp, i32, i64, i64, i64, C.POINTER(ReSketch), u64, vp], i32),
+            "re_sketch_y": ([vp, vp, i32, i64, i64, C.POINTER(ReSketch), u64, vp], i32),
+            "re_sketch_y_rows": ([i64], i64),
+            "re_singular_values": ([vp, vp, i64, i64, dbl, vp], i32),
+            "re_rank_count": ([vp, vp, i64, i32, dbl, vp], i32),
+            "re_r1_from_k": ([i32], i32),
+            "re_status_string": ([i32], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+        return _lib
+
+
+def _status_text(status: int) -> str:
+    try:
+        return lib().re_status_string(status).decode()
+    except Exception:
+        return "librankest status"
+
+
+def _check(st: int, where: str):
+    if st != RE_OK:
+        raise RankEstError(st, where)
+
+
+class Handle:
+    """One library handle bound to a device; follows torch's current stream."""
+
+    def __init__(self, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index)
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().re_create(C.byref(self._h), C.c_void_p(torch.cuda.current_stream().cuda_stream)), "re_create")
+        self._stream = torch.cuda.current_stream(self.device).cuda_stream
+
+    def bind(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        if s != self._stream:
+            _check(lib().re_set_stream(self._h, C.c_void_p(s)), "re_set_stream")
+            self._stream = s
+        return self._h
+
+    def workspace_bytes(self) -> int:
+        n = C.c_size_t(0)
+        _check(lib().re_workspace_bytes(self._h, C.byref(n)), "re_workspace_bytes")
+        return n.value
+
+    def set_profiling(self, enable: bool = True):
+        _check(lib().re_set_profiling(self._h, int(bool(enable))), "re_set_profiling")
+
+    def last_stage_ms(self) -> dict:
+        """Per-stage durations (ms) of the last rank_estimate on this handle (HIP events)."""
+        ms = np.zeros(NUM_STAGES, dtype=np.float64)
+        _check(lib().re_last_stage_ms(self._h, ms.ctypes.data_as(C.c_void_p)), "re_last_stage_ms")
+        return dict(zip(STAGES, ms.tolist()))
+
+    def close(self):
+        if self._h:
+            lib().re_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_handles: dict = {}
+
+
+def default_handle(device=None) -> Handle:
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index
+    h = _handles.get(dev)
+    if h is None:
+        h = _handles[dev] = Handle(dev)
+    return h
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+def _need_cuda(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return RE_F64
+    if t.dtype == torch.float32:
+        return RE_F32
+    raise ValueError("A must be float32 or float64")
+
+
+def make_sketch(k: int, l: int = 0, x: str = "gaussian", y: str = "gaussian", precision: str = "native") -> ReSketch:
+    return ReSketch(KIND[x], KIND[y], int(k), int(l), PREC[precision])
+
+
+def _check_matrix(A: torch.Tensor):
+    _need_cuda(A, "A")
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D tensor with unit column stride")
+
+
+def rank_estimate(A: torch.Tensor, eps: float, *, k: int, l: int = 0, x: str = "gaussian", y: str = "gaussian",
+                  precision: str = "native", seed: int = 0, handle: Handle | None = None):
+    """Algorithm 1 on one matrix.  Returns (r, sigma[k] (numpy float64), info dict)."""
+    _check_matrix(A)
+    h = handle or default_handle(A.device)
+    m, n = A.shape
+    sk = make_sketch(k, l, x, y, precision)
+    r = C.c_int32(0)
+    r1 = C.c_int32(0)
+    fl = C.c_uint32(0)
+    sigma = np.zeros(int(k), dtype=np.float64)
+    st = lib().re_rank_estimate(h.bind(), _ptr(A), _dtype_code(A), m, n, A.stride(0), float(eps), C.byref(sk),
+                                int(seed) % 2**64, C.byref(r), sigma.ctypes.data_as(C.c_void_p), C.byref(r1),
+                                C.byref(fl))
+    _check(st, "re_rank_estimate")
+    return r.value, sigma, {"r1": r1.value, "flags": fl.value, "k": int(k), "l": int(l) if l else 2 * int(k)}
+
+
+# --- stage entry points ------------------------------------------------------------------------
+
+def philox(ctr: torch.Tensor, seed: int, handle: Handle | None = None) -> torch.Tensor:
+    """ctr: int64 CUDA tensor (count, 4) holding the uint64 counter bits."""
+    _need_cuda(ctr, "ctr")
+    ctr = ctr.contiguous()
+    out = torch.empty_like(ctr)
+    h = handle or default_handle(ctr.device)
+    _check(lib().re_philox(h.bind(), _ptr(ctr), int(seed) % 2**64, ctr.shape[0], _ptr(out)), "re_philox")
+    return out
+
+
+def gauss_fill(fmt: str, rows: int, cols: int, seed: int, stream_id: int, swap_ab: bool = False,
+               device="cuda", handle: Handle | None = None) -> torch.Tensor:
+    code = FMT[fmt]
+    out = torch.empty(rows, cols, dtype=FMT_DTYPE[code], device=device)
+    h = handle or default_handle(out.device)
+    _check(lib().re_gauss_fill(h.bind(), code, rows, cols, int(seed) % 2**64, stream_id, int(swap_ab), _ptr(out)),
+           "re_gauss_fill")
+    return out
+
+
+def srht_signs(npad: int, seed: int, stream_id: int, device="cuda", handle: Handle | None = None) -> torch.Tensor:
+    """Packed sign bits (int32 view of the uint32 words); bit set = -1."""
+    out = torch.zeros((npad + 31) // 32, dtype=torch.int32, device=device)
+    h = handle or default_handle(out.device)
+    _check(lib().re_srht_signs(h.bind(), npad, int(seed) % 2**64, stream_id, _ptr(out)), "re_srht_signs")
+    return out
+
+
+def srht_select(npad: int, k: int, seed: int, stream_id: int, device="cuda", handle: Handle | None = None):
+    out = torch.empty(max(k, 1), dtype=torch.int32, device=device)
+    h = handle or default_handle(out.device)
+    _check(lib().re_srht_select(h.bind(), npad, k, int(seed) % 2**64, stream_id, _ptr(out)), "re_srht_select")
+    return out[:k]
+
+
+def sketch_x(A: torch.Tensor, *, k: int, l: int = 0, x: str = "gaussian", y: str = "gaussian",
+             precision: str = "native", seed: int = 0, handle: Handle | None = None) -> torch.Tensor:
+    """B = A X (unscaled), m x k, FP64 for an FP64 A else FP32."""
+    _check_matrix(A)
+    m, n = A.shape
+    B = torch.empty(m, k, dtype=A.dtype, device=A.device)
+    sk = make_sketch(k, l, x, y, precision)
+    h = handle or default_handle(A.device)
+    _check(lib().re_sketch_x(h.bind(), _ptr(A), _dtype_code(A), m, n, A.stride(0), C.byref(sk), int(seed) % 2**64,
+                             _ptr(B)), "re_sketch_x")
+    return B
+
+
+def sketch_y(B: torch.Tensor, *, l: int, x: str = "gaussian", y: str = "gaussian", seed: int = 0,
+             handle: Handle | None = None) -> torch.Tensor:
+    """C = Y B (unscaled), l x k FP64.  B is copied into a scratch buffer first."""
+    _need_cuda(B, "B")
+    m, k = B.shape
+    rows = lib().re_sketch_y_rows(m)
+    scratch = torch.zeros(max(rows, m), k, dtype=B.dtype, device=B.device)
+    scratch[:m].copy_(B)
+    Cm = torch.empty(l, k, dtype=torch.float64, device=B.device)
+    sk = make_sketch(k, l, x, y, "native")
+    h = handle or default_handle(B.device)
+    _check(lib().re_sketch_y(h.bind(), _ptr(scratch), _dtype_code(B), m, k, C.byref(sk), int(seed) % 2**64, _ptr(Cm)),
+           "re_sketch_y")
+    return Cm
+
+
+def singular_values(Cm: torch.Tensor, scale: float = 1.0, handle: Handle | None = None) -> torch.Tensor:
+    _need_cuda(Cm, "C")
+    Cm = Cm.to(torch.float64).contiguous()
+    l, k = Cm.shape
+    sigma = torch.empty(k, dtype=torch.float64, device=Cm.device)
+    h = handle or default_handle(Cm.device)
+    _check(lib().re_singular_values(h.bind(), _ptr(Cm), l, k, float(scale), _ptr(sigma)), "re_singular_values")
+    return sigma
+
+
+def rank_count(sigma: torch.Tensor, r1: int, eps: float, handle: Handle | None = None):
+    _need_cuda(sigma, "sigma")
+    sigma = sigma.to(torch.float64).contiguous()
+    out = torch.zeros(4, dtype=torch.int32, device=sigma.device)
+    h = handle or default_handle(sigma.device)
+    _check(lib().re_rank_count(h.bind(), _ptr(sigma), sigma.numel(), int(r1), float(eps), _ptr(out)), "re_rank_count")
+    o = out.cpu().tolist()
+    return o[0], o[1], o[2]
+
+
+def r1_from_k(k: int) -> int:
+    return lib().re_r1_from_k(int(k))

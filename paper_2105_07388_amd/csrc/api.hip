@@ -1,0 +1,362 @@
+// C ABI of librankest: handle, workspace and the entry points of rankest.h.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "common.h"
+
+#define RE_API extern "C" __attribute__((visibility("default")))
+
+struct re_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* host = nullptr;  // pinned staging for device-to-host results
+  size_t host_bytes = 0;
+  bool prof = false;     // record stage events inside re_rank_estimate
+  hipEvent_t ev[RE_NUM_STAGES + 1] = {};
+  double stage_ms[RE_NUM_STAGES] = {};
+};
+
+namespace re {
+namespace {
+
+size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+re_status ensure_ws(re_handle h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return RE_OK;
+  RE_TRY_HIP(hipStreamSynchronize(h->stream));
+  if (h->ws) (void)hipFree(h->ws);
+  h->ws = nullptr;
+  h->ws_bytes = 0;
+  const size_t want = al256(bytes + bytes / 8);
+  if (hipMalloc(&h->ws, want) != hipSuccess) {
+    (void)hipGetLastError();
+    h->ws = nullptr;
+    return RE_ERR_NO_MEMORY;
+  }
+  h->ws_bytes = want;
+  return RE_OK;
+}
+
+re_status ensure_host(re_handle h, size_t bytes) {
+  if (bytes <= h->host_bytes) return RE_OK;
+  RE_TRY_HIP(hipStreamSynchronize(h->stream));
+  if (h->host) (void)hipHostFree(h->host);
+  h->host = nullptr;
+  h->host_bytes = 0;
+  if (hipHostMalloc(&h->host, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    h->host = nullptr;
+    return RE_ERR_NO_MEMORY;
+  }
+  h->host_bytes = bytes;
+  return RE_OK;
+}
+
+// Bump allocator over one workspace region.
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += al256(bytes);
+    return o;
+  }
+};
+
+int32_t r1_from_k(int32_t k) {
+  int32_t r1 = 0;
+  for (int32_t r = 1; r <= k; ++r)
+    if ((11 * r + 5) / 10 <= k) r1 = r;
+  return r1;
+}
+
+int elem_size(int fmt) { return fmt == kF64 ? 8 : fmt == kF32 ? 4 : 2; }
+
+// Sketch entry formats: the contraction runs in the storage type of A.
+int x_fmt(int32_t dt) { return dt == RE_F64 ? kF64 : kF32; }
+
+struct Resolved {
+  int32_t xk, yk;
+  int64_t k, l, npad_n, npad_m;
+};
+
+// Checks the arguments of one estimate; `sides` selects which embedding's
+// sizes are checked (1: X, 2: Y, 3: both).
+re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda, const re_sketch* sk, Resolved* rs,
+                   int sides = 3) {
+  if (!A || !sk) return RE_ERR_INVALID_ARG;
+  if (dt != RE_F64 && dt != RE_F32) return RE_ERR_INVALID_ARG;
+  if (m < 1 || n < 1 || lda < n) return RE_ERR_INVALID_ARG;
+  if (((uintptr_t)A) % 16 != 0) return RE_ERR_INVALID_ARG;
+  if ((sk->x_kind != RE_GAUSSIAN && sk->x_kind != RE_SRHT) || (sk->y_kind != RE_GAUSSIAN && sk->y_kind != RE_SRHT))
+    return RE_ERR_INVALID_ARG;
+  if (sk->prec < RE_PREC_NATIVE || sk->prec > RE_PREC_AUTO) return RE_ERR_INVALID_ARG;
+  rs->xk = sk->x_kind;
+  rs->yk = sk->y_kind;
+  rs->k = sk->k;
+  rs->l = sk->l == 0 ? 2 * (int64_t)sk->k : sk->l;
+  rs->npad_n = next_pow2(n);
+  rs->npad_m = next_pow2(m);
+  const int64_t kmax = rs->xk == RE_SRHT ? rs->npad_n : n;
+  const int64_t lmax = rs->yk == RE_SRHT ? rs->npad_m : m;
+  if (rs->k < 1 || rs->l < rs->k) return RE_ERR_INVALID_ARG;
+  if ((sides & 1) && rs->k > kmax) return RE_ERR_INVALID_ARG;
+  if ((sides & 2) && rs->l > lmax) return RE_ERR_INVALID_ARG;
+  if (rs->k > (int64_t)INT32_MAX / 2) return RE_ERR_INVALID_ARG;
+  if (sk->prec != RE_PREC_NATIVE) {
+    if (dt == RE_F64 || rs->xk == RE_SRHT) return RE_ERR_UNSUPPORTED;
+    return RE_ERR_UNSUPPORTED;  // low-precision contraction not built into this library
+  }
+  return RE_OK;
+}
+
+// Workspace plan of one estimate.
+struct Plan {
+  size_t xbits, ybits, xsel, ysel, selscr, X, Y, B, C, svd, sigma, info, out3, total;
+};
+
+Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
+  Carve c;
+  Plan p{};
+  const int fx = x_fmt(dt);
+  const size_t be = dt == RE_F64 ? 8 : 4;
+  const int64_t brows = rs.yk == RE_SRHT ? (int64_t)srht_cols_rows_alloc(m) : m;
+  p.xbits = c.take((size_t)cdiv(rs.npad_n, 32) * 4);
+  p.ybits = c.take((size_t)cdiv(rs.npad_m, 32) * 4);
+  p.xsel = c.take((size_t)rs.k * 4);
+  p.ysel = c.take((size_t)rs.l * 4);
+  p.selscr = c.take(select_scratch_bytes(rs.npad_n > rs.npad_m ? rs.npad_n : rs.npad_m));
+  p.X = c.take(rs.xk == RE_GAUSSIAN ? (size_t)n * rs.k * elem_size(fx) : 0);
+  p.Y = c.take(rs.yk == RE_GAUSSIAN ? (size_t)rs.l * m * elem_size(fx) : 0);
+  p.B = c.take((size_t)brows * rs.k * be);
+  p.C = c.take((size_t)rs.l * rs.k * 8);
+  p.svd = c.take(svd_scratch_bytes(rs.l, rs.k));
+  p.sigma = c.take((size_t)rs.k * 8);
+  p.info = c.take(16);
+  p.out3 = c.take(16);
+  p.total = c.off;
+  return p;
+}
+
+char* at(re_handle h, size_t off) { return (char*)h->ws + off; }
+
+void mark(re_handle h, int i) {
+  if (h->prof) (void)hipEventRecord(h->ev[i], h->stream);
+}
+
+// Algorithm 1 steps 2-3: draw X (stage RE_STAGE_X_DRAW), form B = A X (RE_STAGE_AX).
+re_status run_x(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                const Resolved& rs, uint64_t seed, void* B) {
+  hipStream_t s = h->stream;
+  if (rs.xk == RE_SRHT) {
+    uint32_t* bits = (uint32_t*)at(h, p.xbits);
+    int32_t* sel = (int32_t*)at(h, p.xsel);
+    RE_TRY(launch_sign_bits(s, rs.npad_n, seed, kXSign, bits));
+    RE_TRY(launch_select(s, rs.npad_n, rs.k, seed, kXSel, at(h, p.selscr), sel));
+    mark(h, RE_STAGE_AX);
+    return launch_srht_rows(s, A, dt, m, n, lda, bits, sel, rs.k, B);
+  }
+  const int fx = x_fmt(dt);
+  void* X = at(h, p.X);
+  RE_TRY(launch_gauss_fill(s, fx, n, rs.k, seed, kXGauss, 0, X));
+  mark(h, RE_STAGE_AX);
+  const int t = dt == RE_F64 ? 0 : 1;
+  return launch_gemm_f64acc(s, m, rs.k, n, A, t, lda, X, t, rs.k, B, t, rs.k);
+}
+
+// Algorithm 1 steps 5-6: draw Y (RE_STAGE_Y_DRAW), form C = Y B (RE_STAGE_YB).
+re_status run_y(re_handle h, const Plan& p, void* B, int32_t bdt, int64_t m, const Resolved& rs, uint64_t seed,
+                double* C) {
+  hipStream_t s = h->stream;
+  if (rs.yk == RE_SRHT) {
+    uint32_t* bits = (uint32_t*)at(h, p.ybits);
+    int32_t* sel = (int32_t*)at(h, p.ysel);
+    RE_TRY(launch_sign_bits(s, rs.npad_m, seed, kYSign, bits));
+    RE_TRY(launch_select(s, rs.npad_m, rs.l, seed, kYSel, at(h, p.selscr), sel));
+    mark(h, RE_STAGE_YB);
+    return launch_srht_cols(s, B, bdt, m, rs.k, bits, sel, rs.l, C);
+  }
+  const int fy = bdt == RE_F64 ? kF64 : kF32;
+  void* Y = at(h, p.Y);
+  RE_TRY(launch_gauss_fill(s, fy, rs.l, m, seed, kYGauss, 1, Y));
+  mark(h, RE_STAGE_YB);
+  const int t = bdt == RE_F64 ? 0 : 1;
+  return launch_gemm_f64acc(s, rs.l, rs.k, m, Y, t, m, B, t, rs.k, C, 0, rs.k);
+}
+
+}  // namespace
+}  // namespace re
+
+using namespace re;
+
+RE_API re_status re_create(re_handle* h, void* hip_stream) {
+  if (!h) return RE_ERR_INVALID_ARG;
+  re_handle_s* p = new (std::nothrow) re_handle_s();
+  if (!p) return RE_ERR_NO_MEMORY;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return RE_ERR_HIP;
+  }
+  p->stream = (hipStream_t)hip_stream;
+  *h = p;
+  return RE_OK;
+}
+
+RE_API re_status re_set_profiling(re_handle h, int32_t enable) {
+  if (!h) return RE_ERR_INVALID_ARG;
+  if (enable && !h->ev[0])
+    for (int i = 0; i <= RE_NUM_STAGES; ++i) RE_TRY_HIP(hipEventCreate(&h->ev[i]));
+  h->prof = enable != 0;
+  return RE_OK;
+}
+
+RE_API re_status re_last_stage_ms(re_handle h, double* ms) {
+  if (!h || !ms || !h->prof) return RE_ERR_INVALID_ARG;
+  for (int i = 0; i < RE_NUM_STAGES; ++i) ms[i] = h->stage_ms[i];
+  return RE_OK;
+}
+
+RE_API re_status re_destroy(re_handle h) {
+  if (!h) return RE_OK;
+  if (h->stream || h->ws) (void)hipStreamSynchronize(h->stream);
+  for (int i = 0; i <= RE_NUM_STAGES; ++i)
+    if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->host) (void)hipHostFree(h->host);
+  delete h;
+  return RE_OK;
+}
+
+RE_API re_status re_set_stream(re_handle h, void* hip_stream) {
+  if (!h) return RE_ERR_INVALID_ARG;
+  RE_TRY_HIP(hipStreamSynchronize(h->stream));
+  h->stream = (hipStream_t)hip_stream;
+  return RE_OK;
+}
+
+RE_API re_status re_workspace_bytes(re_handle h, size_t* bytes) {
+  if (!h || !bytes) return RE_ERR_INVALID_ARG;
+  *bytes = h->ws_bytes;
+  return RE_OK;
+}
+
+RE_API int32_t re_r1_from_k(int32_t k) { return re::r1_from_k(k); }
+
+RE_API re_status re_rank_estimate(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                                  double eps, const re_sketch* sk, uint64_t seed, int32_t* r_out, double* sigma_out,
+                                  int32_t* r1_out, uint32_t* flags_out) {
+  if (!h || !r_out || !sigma_out) return RE_ERR_INVALID_ARG;
+  if (!(eps > 0.0 && eps < 1.0)) return RE_ERR_INVALID_ARG;
+  Resolved rs;
+  RE_TRY(validate(A, dt, m, n, lda, sk, &rs));
+  const Plan p = plan(dt, m, n, rs);
+  RE_TRY(ensure_ws(h, p.total));
+  RE_TRY(ensure_host(h, (size_t)rs.k * 8 + 64));
+  void* B = at(h, p.B);
+  double* C = (double*)at(h, p.C);
+  double* sigma = (double*)at(h, p.sigma);
+  int32_t* info = (int32_t*)at(h, p.info);
+  int32_t* out3 = (int32_t*)at(h, p.out3);
+  const int32_t r1 = re::r1_from_k((int32_t)rs.k);
+  mark(h, RE_STAGE_X_DRAW);
+  RE_TRY(run_x(h, p, A, dt, m, n, lda, rs, seed, B));
+  mark(h, RE_STAGE_Y_DRAW);
+  RE_TRY(run_y(h, p, B, dt, m, rs, seed, C));
+  const double scale = 1.0 / sqrt((double)rs.k * (double)rs.l);
+  mark(h, RE_STAGE_SVD);
+  RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info));
+  mark(h, RE_STAGE_RANK);
+  RE_TRY(launch_rank_count(h->stream, sigma, rs.k, r1, eps, info, out3));
+  char* host = (char*)h->host;
+  RE_TRY_HIP(hipMemcpyAsync(host, out3, 16, hipMemcpyDeviceToHost, h->stream));
+  RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)rs.k * 8, hipMemcpyDeviceToHost, h->stream));
+  mark(h, RE_NUM_STAGES);
+  RE_TRY_HIP(hipStreamSynchronize(h->stream));
+  if (h->prof) {
+    for (int i = 0; i < RE_NUM_STAGES; ++i) {
+      float ms = 0.f;
+      h->stage_ms[i] = hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess ? (double)ms : -1.0;
+    }
+  }
+  const int32_t* o3 = (const int32_t*)host;
+  if (o3[2] != 0) return (re_status)o3[2];
+  *r_out = o3[0];
+  memcpy(sigma_out, host + 64, (size_t)rs.k * 8);
+  if (r1_out) *r1_out = r1;
+  if (flags_out) *flags_out = (uint32_t)o3[1];
+  return RE_OK;
+}
+
+RE_API re_status re_philox(re_handle h, const uint64_t* ctr, uint64_t seed, int64_t count, uint64_t* out) {
+  if (!h || count < 0 || (count > 0 && (!ctr || !out))) return RE_ERR_INVALID_ARG;
+  return launch_philox(h->stream, ctr, seed, count, out);
+}
+
+RE_API re_status re_gauss_fill(re_handle h, int32_t fmt, int64_t rows, int64_t cols, uint64_t seed, int32_t stream_id,
+                               int32_t swap_ab, void* out) {
+  if (!h || rows < 0 || cols < 0 || fmt < 0 || fmt > 3 || (rows * cols > 0 && !out)) return RE_ERR_INVALID_ARG;
+  return launch_gauss_fill(h->stream, fmt, rows, cols, seed, stream_id, swap_ab, out);
+}
+
+RE_API re_status re_srht_signs(re_handle h, int64_t npad, uint64_t seed, int32_t stream_id, uint32_t* bits) {
+  if (!h || npad < 0 || (npad > 0 && !bits)) return RE_ERR_INVALID_ARG;
+  return launch_sign_bits(h->stream, npad, seed, stream_id, bits);
+}
+
+RE_API re_status re_srht_select(re_handle h, int64_t npad, int64_t k, uint64_t seed, int32_t stream_id, int32_t* idx) {
+  if (!h || npad < 1 || k < 0 || k > npad || npad > (int64_t)INT32_MAX || (k > 0 && !idx)) return RE_ERR_INVALID_ARG;
+  RE_TRY(ensure_ws(h, select_scratch_bytes(npad)));
+  return launch_select(h->stream, npad, k, seed, stream_id, h->ws, idx);
+}
+
+RE_API re_status re_sketch_x(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                             const re_sketch* sk, uint64_t seed, void* B) {
+  if (!h || !B) return RE_ERR_INVALID_ARG;
+  Resolved rs;
+  RE_TRY(validate(A, dt, m, n, lda, sk, &rs, 1));
+  const Plan p = plan(dt, m, n, rs);
+  RE_TRY(ensure_ws(h, p.total));
+  return run_x(h, p, A, dt, m, n, lda, rs, seed, B);
+}
+
+RE_API int64_t re_sketch_y_rows(int64_t m) { return (int64_t)srht_cols_rows_alloc(m); }
+
+RE_API re_status re_sketch_y(re_handle h, void* B, int32_t bdt, int64_t m, int64_t k, const re_sketch* sk,
+                             uint64_t seed, double* C) {
+  if (!h || !B || !C || !sk || m < 1 || k < 1 || sk->k != k) return RE_ERR_INVALID_ARG;
+  Resolved rs;
+  // validate the Y side only: a stand-in A of m x k with lda = k
+  RE_TRY(validate(B, bdt, m, k, k, sk, &rs, 2));
+  const Plan p = plan(bdt, m, k, rs);
+  RE_TRY(ensure_ws(h, p.total));
+  return run_y(h, p, B, bdt, m, rs, seed, C);
+}
+
+RE_API re_status re_singular_values(re_handle h, const double* C, int64_t l, int64_t k, double scale, double* sigma) {
+  if (!h || !C || !sigma || k < 1 || l < k) return RE_ERR_INVALID_ARG;
+  const size_t need = al256(svd_scratch_bytes(l, k)) + 256;
+  RE_TRY(ensure_ws(h, need));
+  int32_t* info = (int32_t*)((char*)h->ws + al256(svd_scratch_bytes(l, k)));
+  return launch_svd(h->stream, C, l, k, scale, h->ws, sigma, info);
+}
+
+RE_API re_status re_rank_count(re_handle h, const double* sigma, int64_t k, int32_t r1, double eps, int32_t* out) {
+  if (!h || !sigma || !out || k < 1 || r1 < 1 || !(eps > 0.0 && eps < 1.0)) return RE_ERR_INVALID_ARG;
+  return launch_rank_count(h->stream, sigma, k, r1, eps, nullptr, out);
+}
+
+RE_API const char* re_status_string(re_status s) {
+  switch (s) {
+    case RE_OK: return "ok";
+    case RE_ERR_INVALID_ARG: return "invalid argument";
+    case RE_ERR_UNSUPPORTED: return "unsupported combination";
+    case RE_ERR_NO_MEMORY: return "out of device or pinned memory";
+    case RE_ERR_HIP: return "HIP runtime error";
+    case RE_ERR_NONFINITE: return "non-finite values in the input or the sketch";
+    case RE_ERR_NO_CONVERGENCE: return "small SVD did not complete";
+    default: return "unknown status";
+  }
+}

@@ -1,0 +1,356 @@
+// Algorithm 1 steps 7-8: singular values of the small l x k sketch C = Y A X
+// in FP64, then the count of estimates above eps * sigma_1.
+//
+// Singular values are computed by
+//   (1) Householder bidiagonalisation C = Q B P^T (Golub-Kahan), run by P
+//       co-resident workgroups that each own the rows r = w (mod P) of a
+//       working copy; every column step needs one reduction over all rows,
+//       so the workgroups meet at one grid barrier per column;
+//   (2) the singular values of the upper bidiagonal B, which are the positive
+//       eigenvalues of the 2k x 2k Golub-Kahan tridiagonal with zero diagonal
+//       and off-diagonal (d1, e1, d2, e2, ..., dk); each value is found by
+//       multisection on Sturm counts, one wavefront per singular value.
+// Both steps are backward stable, so each sigma_i is within a small multiple
+// of u ||C|| of its exact value.
+#include "common.h"
+
+namespace re {
+
+namespace {
+
+constexpr int kBidiagThreads = 256;
+constexpr int kWaves = kBidiagThreads / 64;
+
+struct BidiagArgs {
+  const double* C;   // l x k input, row-major
+  double* W;         // l x k working copy
+  double* part;      // [2][P][k + 1] partial reductions
+  double* rowbuf;    // [2][k + 1] the pivot row
+  double* d;         // k diagonal of B
+  double* e;         // k - 1 superdiagonal of B
+  unsigned* bar;     // grid barrier counter
+  int32_t* info;     // status (0 ok, RE_ERR_*)
+  int64_t l, k;
+  int P;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Grid barrier over the P workgroups of the bidiagonalisation.  The counter
+// grows monotonically; a bounded wait turns a missing workgroup into an error
+// instead of a hang.
+__device__ bool grid_barrier(unsigned* bar, unsigned target, int32_t* info) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    ok = 1;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1l << 26)) {
+        ok = 0;
+        __hip_atomic_store(info, (int32_t)RE_ERR_NO_CONVERGENCE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok != 0;
+}
+
+// Column step partials of column c over this workgroup's rows r >= c:
+//   part[0] = sum W[r][c]^2,  part[1 + (j - c - 1)] = sum W[r][c] W[r][j]  (j > c)
+// and, from the owner of row c, rowbuf = W[c][c..k).
+__device__ void column_partials(const BidiagArgs& a, int64_t c, int w, double* gacc /* [kWaves][k+1] LDS */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t k = a.k, len = k - c;  // len = 1 + (k - c - 1)
+  double* g = gacc + (int64_t)wave * (k + 1);
+  for (int64_t j = lane; j < len; j += 64) g[j] = 0.0;
+  const int64_t par = c & 1;
+  for (int64_t r = w + (int64_t)wave * a.P; r < a.l; r += (int64_t)kWaves * a.P) {
+    if (r < c) continue;
+    const double* row = a.W + r * k;
+    const double x = row[c];
+    for (int64_t j = lane; j < len; j += 64) g[j] += x * row[c + j];
+    if (r == c)
+      for (int64_t j = lane; j < len; j += 64) a.rowbuf[par * (k + 1) + j] = row[c + j];
+  }
+  __syncthreads();
+  double* out = a.part + (par * a.P + w) * (k + 1);
+  for (int64_t j = threadIdx.x; j < len; j += blockDim.x) {
+    double s = 0.0;
+    for (int v = 0; v < kWaves; ++v) s += gacc[(int64_t)v * (k + 1) + j];
+    out[j] = s;
+  }
+}
+
+__global__ void __launch_bounds__(kBidiagThreads) k_bidiag(BidiagArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t k = a.k, l = a.l;
+  double* wv = reinterpret_cast<double*>(smem_raw);  // [k+1] column-step coefficients w_j
+  double* vv = wv + (k + 1);                           // [k+1] row reflector v
+  double* gacc = vv + (k + 1);                         // [kWaves][k+1]
+  __shared__ double s_scalars[4];
+  const int w = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned epoch = 0;
+
+  // private copy of this workgroup's rows; non-finite input is reported
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  for (int64_t r = w + (int64_t)wave * a.P; r < l; r += (int64_t)kWaves * a.P)
+    for (int64_t j = lane; j < k; j += 64) {
+      const double x = a.C[r * k + j];
+      if (!isfinite(x)) s_bad = 1;
+      a.W[r * k + j] = x;
+    }
+  __syncthreads();
+  if (s_bad) __hip_atomic_store(a.info, (int32_t)RE_ERR_NONFINITE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  column_partials(a, 0, w, gacc);
+  if (!grid_barrier(a.bar, (unsigned)a.P * ++epoch, a.info)) return;
+
+  for (int64_t c = 0; c < k; ++c) {
+    const int64_t par = c & 1, len = k - c;
+    // ---- reduce the partials of column c (every workgroup, same order) ----
+    for (int64_t j = threadIdx.x; j < len; j += blockDim.x) {
+      double s = 0.0;
+      for (int p = 0; p < a.P; ++p) s += a.part[(par * a.P + p) * (k + 1) + j];
+      wv[j] = s;  // wv[0] = ||x||^2, wv[j] = x . W[:, c + j]
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double s0 = wv[0], x0 = a.rowbuf[par * (k + 1)];
+      const double nx = sqrt(s0);
+      double alpha = 0.0, tau = 0.0;
+      if (nx > 0.0) {
+        alpha = -copysign(nx, x0);
+        tau = 1.0 / (s0 - alpha * x0);
+      }
+      s_scalars[0] = alpha;
+      s_scalars[1] = tau;
+      s_scalars[2] = x0 - alpha;  // first entry of the column reflector u
+      if (w == 0) a.d[c] = alpha;
+    }
+    __syncthreads();
+    const double alpha = s_scalars[0], tau = s_scalars[1], u0 = s_scalars[2];
+    // w_j = tau (x . W[:, j] - alpha W[c][j]); updated pivot row y_j = W[c][j] - u0 w_j
+    for (int64_t j = 1 + threadIdx.x; j < len; j += blockDim.x) {
+      const double row = a.rowbuf[par * (k + 1) + j];
+      const double wj = tau * (wv[j] - alpha * row);
+      wv[j] = wj;
+      vv[j] = row - u0 * wj;
+    }
+    __syncthreads();
+    // ---- row reflector of the updated pivot row (entries c+1 .. k-1) ----
+    if (len > 1) {
+      double p = 0.0;
+      for (int64_t j = 1 + threadIdx.x; j < len; j += blockDim.x) p += vv[j] * vv[j];
+      p = wave_sum(p);
+      if (lane == 0) gacc[wave] = p;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double ny2 = 0.0;
+        for (int v = 0; v < kWaves; ++v) ny2 += gacc[v];
+        const double y0 = vv[1], ny = sqrt(ny2);
+        double beta = 0.0, tau2 = 0.0;
+        if (ny > 0.0) {
+          beta = -copysign(ny, y0);
+          tau2 = 1.0 / (ny2 - beta * y0);
+        }
+        s_scalars[3] = tau2;
+        vv[1] = y0 - beta;
+        if (w == 0) a.e[c] = beta;
+      }
+      __syncthreads();
+    }
+    const double tau2 = (len > 1) ? s_scalars[3] : 0.0;
+    // ---- apply both reflectors to this workgroup's rows r > c ----
+    for (int64_t r = w + (int64_t)wave * a.P; r < l; r += (int64_t)kWaves * a.P) {
+      if (r <= c) continue;
+      double* row = a.W + r * k;
+      const double ur = row[c];
+      double z = 0.0;
+      for (int64_t j = 1 + lane; j < len; j += 64) {
+        const double v = row[c + j] - ur * wv[j];
+        row[c + j] = v;
+        z += v * vv[j];
+      }
+      z = wave_sum(z) * tau2;
+      for (int64_t j = 1 + lane; j < len; j += 64) row[c + j] -= z * vv[j];
+    }
+    __syncthreads();
+    if (c + 1 < k) {
+      column_partials(a, c + 1, w, gacc);
+      if (!grid_barrier(a.bar, (unsigned)a.P * ++epoch, a.info)) return;
+    }
+  }
+}
+
+// ---- singular values of the bidiagonal by multisection on Sturm counts ----
+
+// Number of eigenvalues below x > 0 of the Golub-Kahan tridiagonal with zero
+// diagonal and off-diagonal b[0..nb), minus the k negative ones: the number
+// of singular values below x.
+__device__ int count_below(const double* b, int nb, double x, double pivmin) {
+  double q = -x;
+  int neg = 1;  // q0 = -x < 0
+  for (int j = 0; j < nb; ++j) {
+    const double bb = b[j] * b[j];
+    q = -x - bb / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    neg += (q < 0.0);
+  }
+  return neg - (nb + 1) / 2;
+}
+
+__global__ void __launch_bounds__(256) k_bidiag_sv(const double* __restrict__ d, const double* __restrict__ e,
+                                                   int64_t k, double scale, const int32_t* __restrict__ info,
+                                                   double* __restrict__ sigma) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* b = reinterpret_cast<double*>(smem_raw);  // 2k - 1 off-diagonal entries
+  const int nb = (int)(2 * k - 1);
+  double bound = 0.0, maxb2 = 0.0;
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) b[j] = (j & 1) ? e[j >> 1] : d[j >> 1];
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {  // every thread, same order
+    const double left = j > 0 ? fabs(b[j - 1]) : 0.0;
+    bound = fmax(bound, fabs(b[j]) + left);
+    maxb2 = fmax(maxb2, b[j] * b[j]);
+  }
+  bound = fmax(bound, nb > 0 ? fabs(b[nb - 1]) : 0.0);
+  const bool all_zero = !(bound > 0.0);  // B = 0 (NaN is reported through info)
+  bound = bound * (1.0 + 1e-14) + 1e-300;
+  const double pivmin = 0x1.0p-1022 * fmax(1.0, maxb2);
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = blockDim.x / 64;
+  for (int64_t jj = blockIdx.x * waves + (threadIdx.x >> 6); jj < k; jj += (int64_t)gridDim.x * waves) {
+    // jj-th largest singular value: #{sigma < lo} <= k-1-jj < #{sigma < hi}
+    const int want = (int)(k - 1 - jj);
+    double lo = 0.0, hi = bound;
+    for (int it = 0; it < 10; ++it) {
+      const double x = lo + (hi - lo) * (double)(lane + 1) * (1.0 / 65.0);
+      const int cnt = count_below(b, nb, x, pivmin);
+      const uint64_t le = __ballot(cnt <= want);  // monotone in lane
+      const int nle = __popcll(le);               // lanes 0..nle-1 satisfy cnt <= want
+      const double nlo = nle > 0 ? lo + (hi - lo) * (double)nle * (1.0 / 65.0) : lo;
+      const double nhi = nle < 64 ? lo + (hi - lo) * (double)(nle + 1) * (1.0 / 65.0) : hi;
+      lo = nlo;
+      hi = nhi;
+    }
+    if (lane == 0) sigma[jj] = all_zero ? 0.0 : 0.5 * (lo + hi) * scale;
+  }
+  (void)info;
+}
+
+__global__ void k_count(const double* __restrict__ sigma, int64_t k, int32_t r1, double eps,
+                        const int32_t* __restrict__ info, int32_t* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t st = info ? info[0] : 0;
+  uint32_t flags = 0;
+  int32_t r = 0;
+  for (int64_t i = 0; i < k && st == 0; ++i)
+    if (!isfinite(sigma[i])) st = RE_ERR_NONFINITE;
+  if (st == 0) {
+    if (k == 0 || sigma[0] == 0.0) {
+      flags |= RE_FLAG_ZERO;
+    } else {
+      const double tau = eps * sigma[0];
+      const int64_t lim = r1 < k ? r1 : k;
+      while (r < lim && sigma[r] > tau) ++r;
+      if (r == r1) flags |= RE_FLAG_NOT_CONVERGED;
+    }
+  }
+  out[0] = r;
+  out[1] = (int32_t)flags;
+  out[2] = st;
+}
+
+__global__ void k_svd_init(unsigned* bar, int32_t* info) {
+  if (threadIdx.x == 0) {
+    bar[0] = 0;
+    info[0] = 0;
+  }
+}
+
+int choose_P(int64_t l) {
+  int64_t P = l / 32;
+  if (P < 1) P = 1;
+  if (P > 64) P = 64;
+  return (int)P;
+}
+
+struct SvdLayout {
+  size_t W, part, rowbuf, d, e, bar, total;
+};
+
+SvdLayout svd_layout(int64_t l, int64_t k) {
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const int P = choose_P(l);
+  SvdLayout s{};
+  size_t o = 0;
+  s.W = o; o += al((size_t)l * k * 8);
+  s.part = o; o += al((size_t)2 * P * (k + 1) * 8);
+  s.rowbuf = o; o += al((size_t)2 * (k + 1) * 8);
+  s.d = o; o += al((size_t)k * 8);
+  s.e = o; o += al((size_t)k * 8);
+  s.bar = o; o += 256;
+  s.total = o;
+  return s;
+}
+
+}  // namespace
+
+size_t svd_scratch_bytes(int64_t l, int64_t k) { return svd_layout(l, k).total; }
+
+re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, double scale, void* scratch,
+                     double* sigma, int32_t* info) {
+  if (k <= 0) return RE_OK;
+  if (k > l) return RE_ERR_INVALID_ARG;
+  const SvdLayout L = svd_layout(l, k);
+  char* base = (char*)scratch;
+  BidiagArgs a;
+  a.C = C;
+  a.W = (double*)(base + L.W);
+  a.part = (double*)(base + L.part);
+  a.rowbuf = (double*)(base + L.rowbuf);
+  a.d = (double*)(base + L.d);
+  a.e = (double*)(base + L.e);
+  a.bar = (unsigned*)(base + L.bar);
+  a.info = info;
+  a.l = l;
+  a.k = k;
+  a.P = choose_P(l);
+  const size_t lds = (size_t)(2 + kWaves) * (k + 1) * 8;
+  if (lds > 160 * 1024) return RE_ERR_UNSUPPORTED;
+  if (lds > 64 * 1024)
+    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_svd_init, dim3(1), dim3(64), 0, s, a.bar, info);
+  void* params[] = {&a};
+  RE_TRY_HIP(hipLaunchCooperativeKernel((const void*)k_bidiag, dim3(a.P), dim3(kBidiagThreads), params, (unsigned)lds, s));
+  const size_t lds2 = (size_t)(2 * k) * 8;
+  if (lds2 > 160 * 1024) return RE_ERR_UNSUPPORTED;
+  if (lds2 > 64 * 1024)
+    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag_sv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+  const int waves_per_block = 4;
+  const int blocks = (int)cdiv(k, waves_per_block);
+  hipLaunchKernelGGL(k_bidiag_sv, dim3(blocks), dim3(64 * waves_per_block), lds2, s, a.d, a.e, k, scale, info, sigma);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
+
+re_status launch_rank_count(hipStream_t s, const double* sigma, int64_t k, int32_t r1, double eps, const int32_t* info,
+                            int32_t* out3) {
+  hipLaunchKernelGGL(k_count, dim3(1), dim3(64), 0, s, sigma, k, r1, eps, info, out3);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
+
+}  // namespace re
