@@ -49,6 +49,103 @@ __global__ void __launch_bounds__(256) k_srht_rows_lds(const TA* __restrict__ A,
 }
 
 // ---------------------------------------------------------------------------
+// X side, N = 2^14 FP32 rows (the streaming pass that dominates the method):
+// 256 threads, 64 values per thread, no padding (n = N).
+//   load     thread t reads float4 chunks t + 256 j (j < 16): it holds the
+//            positions q = 1024 j + 4 t + c, so its register bits are q's bits
+//            {0, 1, 10..13}; signs are XOR masks prepared once per thread;
+//   phase 1  the six butterfly stages over those bits, in registers;
+//   LDS      the row is written to LDS at f(q) = q ^ (((q >> 8) & 15) << 2),
+//            a bijection that keeps both access patterns below free of bank
+//            conflicts for 32- and 64-bank LDS;
+//   phase 2  thread t re-reads the 64 positions whose bits {2..7} vary
+//            (the others fixed by t) and applies those six stages in place;
+//   output   only the k sampled outputs are completed: each needs the four
+//            values that differ in bits {8, 9} (the last two stages).
+// ---------------------------------------------------------------------------
+constexpr int kN14 = 1 << 14;
+
+__device__ __forceinline__ int lds_swz14(int q) { return q ^ (((q >> 8) & 15) << 2); }
+
+__device__ __forceinline__ void fwht64(float* x) {
+#pragma unroll
+  for (int h = 1; h < 64; h <<= 1) {
+#pragma unroll
+    for (int e = 0; e < 64; ++e) {
+      if (!(e & h)) {
+        const float a = x[e], b = x[e | h];
+        x[e] = a + b;
+        x[e | h] = a - b;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256, 2) k_srht_rows_n14(const float* __restrict__ A, int64_t m, int64_t lda,
+                                                          const uint32_t* __restrict__ bits,
+                                                          const int32_t* __restrict__ sel, int k,
+                                                          float* __restrict__ B) {
+  __shared__ __align__(16) float lds[kN14];
+  const int t = threadIdx.x, w = t >> 6;
+  uint32_t msk[64];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const uint32_t wb = bits[32 * j + (t >> 3)] >> (4 * (t & 7));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) msk[4 * j + c] = ((wb >> c) & 1u) << 31;
+  }
+  int wa[4];  // phase-1 store address of chunk j is wa[j & 3] + 1024 j
+#pragma unroll
+  for (int r = 0; r < 4; ++r) wa[r] = (4 * t) ^ ((4 * r + w) << 2);
+  const int base = (t & 3) + 256 * ((t >> 2) & 3) + 1024 * (t >> 4);
+  const int sw = ((t >> 2) & 3) | (((t >> 4) & 3) << 2);
+  int ra[16];  // phase-2 address of value u = 16 h + i is ra[i] + 64 h
+#pragma unroll
+  for (int i = 0; i < 16; ++i) ra[i] = base + 4 * (i ^ sw);
+
+  for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
+    const float4* src = reinterpret_cast<const float4*>(A + row * lda) + t;
+    float x[64];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const float4 v = src[256 * j];
+      x[4 * j + 0] = v.x;
+      x[4 * j + 1] = v.y;
+      x[4 * j + 2] = v.z;
+      x[4 * j + 3] = v.w;
+    }
+#pragma unroll
+    for (int e = 0; e < 64; ++e) x[e] = __uint_as_float(__float_as_uint(x[e]) ^ msk[e]);
+    fwht64(x);
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      *reinterpret_cast<float4*>(&lds[wa[j & 3] + 1024 * j]) = make_float4(x[4 * j], x[4 * j + 1], x[4 * j + 2], x[4 * j + 3]);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[16 * h + i] = lds[ra[i] + 64 * h];
+    fwht64(x);
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) lds[ra[i] + 64 * h] = x[16 * h + i];
+    __syncthreads();
+    for (int s = t; s < k; s += 256) {
+      const int p = sel[s];
+      const int ph = (p >> 8) & 3, pl = p & ~0x300;
+      const float v0 = lds[lds_swz14(pl)], v1 = lds[lds_swz14(pl | 0x100)];
+      const float v2 = lds[lds_swz14(pl | 0x200)], v3 = lds[lds_swz14(pl | 0x300)];
+      // (H_4 [v0 v1 v2 v3])[ph] with the Sylvester signs (-1)^popcount(ph & b)
+      const float a01 = (ph & 1) ? v0 - v1 : v0 + v1;
+      const float a23 = (ph & 1) ? v2 - v3 : v2 + v3;
+      B[row * k + s] = (ph & 2) ? a01 - a23 : a01 + a23;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Y side.  H_M = H_{M/L} (x) H_L with the row index split (hi, lo):
 //   lo pass: every block of L consecutive rows is signed and transformed over
 //            its L rows, in place (rows past m read as zero);
@@ -118,12 +215,30 @@ re_status allow_lds(K kernel, size_t bytes) {
 
 }  // namespace
 
+static int num_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
 re_status launch_srht_rows(hipStream_t s, const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                            const uint32_t* bits, const int32_t* sel, int64_t k, void* B) {
   const int64_t N = next_pow2(n);
   const int logN = ilog2_exact(N);
   const int grid = (int)(m < 8192 ? m : 8192);
   if (m <= 0) return RE_OK;
+  if (dtype == RE_F32 && n == kN14 && lda % 4 == 0 && ((uintptr_t)A % 16) == 0 && k <= INT32_MAX) {
+    const int64_t g = 2 * (int64_t)num_cus();
+    hipLaunchKernelGGL(k_srht_rows_n14, dim3((unsigned)(m < g ? m : g)), dim3(256), 0, s, (const float*)A, m, lda,
+                       bits, sel, (int)k, (float*)B);
+    RE_TRY_HIP(hipGetLastError());
+    return RE_OK;
+  }
   if (dtype == RE_F32) {
     const size_t lds = (size_t)N * sizeof(float);
     RE_TRY(allow_lds(k_srht_rows_lds<float, float>, lds));

@@ -40,6 +40,39 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Cross-lane moves of a double by a DPP pattern (two 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over each row of 16 lanes, result in every lane of the row:
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x140>(v);
+  return v;
+}
+
+// Sum over the wavefront, result in every lane.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v = row16_sum(v);
+  const uint64_t u = __double_as_longlong(v);
+  double t = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, 16 * r);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 16 * r);
+    t += __longlong_as_double(((uint64_t)hi << 32) | lo);
+  }
+  return t;
+}
+
 // Grid barrier over the P workgroups of the bidiagonalisation.  The counter
 // grows monotonically; a bounded wait turns a missing workgroup into an error
 // instead of a hang.
@@ -194,17 +227,205 @@ __global__ void __launch_bounds__(kBidiagThreads) k_bidiag(BidiagArgs a) {
   }
 }
 
+// ---- bidiagonalisation with the rows resident in LDS ----------------------
+// Same reduction as k_bidiag, organised for latency: 1024 threads, each
+// workgroup keeps its rows (r = w mod P) in LDS, the scalars of each step
+// are recomputed by every thread instead of broadcast, and the values
+// exchanged between workgroups (partials, pivot row) travel through
+// agent-coherent stores and loads, so a grid barrier needs only the
+// completion of those stores and one counter.
+constexpr int kB2Threads = 1024;
+constexpr int kB2Waves = kB2Threads / 64;
+
+struct Bidiag2Args {
+  const double* C;
+  double* part;    // [2][P][k + 1]
+  double* rowbuf;  // [2][k + 1]
+  double* d;
+  double* e;
+  unsigned* bar;
+  int32_t* info;
+  int64_t l, k, kp;  // kp: LDS row stride in doubles (kp = 16 mod 32)
+  int P, nr_max;
+};
+
+__device__ __forceinline__ void st_coh(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coh(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ bool grid_sync_coh(unsigned* bar, unsigned target, int32_t* info) {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's coherent stores are complete
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    ok = 1;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1l << 26)) {
+        ok = 0;
+        __hip_atomic_store(info, (int32_t)RE_ERR_NO_CONVERGENCE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// Partials of column c from this workgroup's rows r >= c (thread per column):
+// part[j] = sum_r W[r][c] W[r][c + j]; the owner of row c also sends W[c][c..k).
+__device__ void partials_lds(const Bidiag2Args& a, const double* Wl, int nr, int64_t c, int w) {
+  const int64_t k = a.k, len = k - c;
+  const int P = a.P;
+  const int64_t par = c & 1;
+  const int i0 = c > w ? (int)((c - w + P - 1) / P) : 0;
+  const bool owner = (c % P) == w;
+  const int iown = (int)(c / P);
+  const int64_t kp = a.kp;
+  for (int64_t j = threadIdx.x; j < len; j += blockDim.x) {
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+    int i = i0;
+    for (; i + 3 < nr; i += 4) {
+      const double* r0 = Wl + (int64_t)i * kp + c;
+      g0 += r0[0] * r0[j];
+      g1 += r0[kp] * r0[kp + j];
+      g2 += r0[2 * kp] * r0[2 * kp + j];
+      g3 += r0[3 * kp] * r0[3 * kp + j];
+    }
+    for (; i < nr; ++i) {
+      const double* r0 = Wl + (int64_t)i * kp + c;
+      g0 += r0[0] * r0[j];
+    }
+    st_coh(&a.part[(par * P + w) * (k + 1) + j], (g0 + g1) + (g2 + g3));
+    if (owner) st_coh(&a.rowbuf[par * (k + 1) + j], Wl[(int64_t)iown * kp + c + j]);
+  }
+}
+
+template <int KPL>
+__global__ void __launch_bounds__(kB2Threads) k_bidiag_lds(Bidiag2Args a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t k = a.k, l = a.l, kp = a.kp;
+  const int P = a.P, w = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nr = (int)((l - w + P - 1) / P);
+  double* Wl = reinterpret_cast<double*>(smem_raw);  // [nr_max][kp]
+  double* wv = Wl + (int64_t)a.nr_max * kp;           // [k + 1]
+  double* vv = wv + (k + 1);                           // [k + 1]
+  double* red = vv + (k + 1);                          // [kB2Waves]
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int64_t e = tid; e < (int64_t)nr * k; e += kB2Threads) {
+    const int64_t i = e / k, j = e - i * k;
+    const double x = a.C[(w + P * i) * k + j];
+    if (!isfinite(x)) s_bad = 1;
+    Wl[i * kp + j] = x;
+  }
+  __syncthreads();
+  if (s_bad) __hip_atomic_store(a.info, (int32_t)RE_ERR_NONFINITE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned epoch = 0;
+  partials_lds(a, Wl, nr, 0, w);
+  if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+
+  for (int64_t c = 0; c < k; ++c) {
+    const int64_t par = c & 1, len = k - c;
+    // reduce the partials of column c; vv holds the pivot row W[c][c..k)
+    for (int64_t j = tid; j < len; j += kB2Threads) {
+      // issue the coherent loads in batches of 16, then add them in order
+      const double* src = a.part + par * P * (k + 1) + j;
+      const double rb = ld_coh(&a.rowbuf[par * (k + 1) + j]);
+      double s = 0.0;
+      for (int p0 = 0; p0 < P; p0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = (p0 + q < P) ? ld_coh(src + (int64_t)(p0 + q) * (k + 1)) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) s += v[q];
+      }
+      wv[j] = s;
+      vv[j] = rb;
+    }
+    __syncthreads();
+    // column reflector (every thread): H x = alpha e1, u = x - alpha e1, tau = 2 / u.u
+    const double s0 = wv[0], x0 = vv[0];
+    const double nx = sqrt(s0);
+    const double alpha = nx > 0.0 ? -copysign(nx, x0) : 0.0;
+    const double tau = nx > 0.0 ? 1.0 / (s0 - alpha * x0) : 0.0;
+    const double u0 = x0 - alpha;
+    if (w == 0 && tid == 0) a.d[c] = alpha;
+    // w_j = tau (x . W[:, c+j] - alpha W[c][c+j]); updated pivot row y_j = W[c][c+j] - u0 w_j
+    double pp = 0.0;
+    for (int64_t j = 1 + tid; j < len; j += kB2Threads) {
+      const double row = vv[j];
+      const double wj = tau * (wv[j] - alpha * row);
+      const double y = row - u0 * wj;
+      wv[j] = wj;
+      vv[j] = y;
+      pp += y * y;
+    }
+    pp = wave_sum_dpp(pp);
+    if (lane == 0) red[wave] = pp;
+    __syncthreads();
+    double ny2 = 0.0;
+#pragma unroll
+    for (int v = 0; v < kB2Waves; ++v) ny2 += red[v];
+    const double y0 = len > 1 ? vv[1] : 0.0;
+    const double ny = sqrt(ny2);
+    const double beta = ny > 0.0 ? -copysign(ny, y0) : 0.0;
+    const double tau2 = ny > 0.0 ? 1.0 / (ny2 - beta * y0) : 0.0;
+    const double v1 = y0 - beta;  // first entry of the row reflector; vv[j] for j >= 2
+    if (w == 0 && tid == 0 && len > 1) a.e[c] = beta;
+    // apply both reflectors to the rows r > c: 16 lanes per row, 4 rows per
+    // wavefront; the second pass recomputes the column-step values from LDS
+    const int l16 = lane & 15;
+    for (int i = 4 * wave + (lane >> 4); i - (lane >> 4) < nr; i += 4 * kB2Waves) {
+      const int64_t r = w + (int64_t)P * i;
+      const bool live = i < nr && r > c;  // every lane takes part in the row sums
+      double* row = Wl + (int64_t)(live ? i : 0) * kp + c;
+      const double ur = live ? row[0] : 0.0;
+      const int64_t jend = live ? len : 0;
+      double z0 = 0.0, z1 = 0.0;
+      int64_t j = 1 + l16;
+      for (; j + 16 < jend; j += 32) {
+        z0 += (row[j] - ur * wv[j]) * (j == 1 ? v1 : vv[j]);
+        z1 += (row[j + 16] - ur * wv[j + 16]) * vv[j + 16];
+      }
+      if (j < jend) z0 += (row[j] - ur * wv[j]) * (j == 1 ? v1 : vv[j]);
+      const double z = row16_sum(z0 + z1) * tau2;
+      for (int64_t jj = 1 + l16; jj < jend; jj += 16) {
+        const double vj = jj == 1 ? v1 : vv[jj];
+        row[jj] = (row[jj] - ur * wv[jj]) - z * vj;
+      }
+    }
+    __syncthreads();
+    if (c + 1 < k) {
+      partials_lds(a, Wl, nr, c + 1, w);
+      if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+    }
+  }
+}
+
 // ---- singular values of the bidiagonal by multisection on Sturm counts ----
 
 // Number of eigenvalues below x > 0 of the Golub-Kahan tridiagonal with zero
 // diagonal and off-diagonal b[0..nb), minus the k negative ones: the number
 // of singular values below x.
-__device__ int count_below(const double* b, int nb, double x, double pivmin) {
+// bb[j] = b[j]^2; the pivots q_j of the LDL^T factorisation of T - x I follow
+// q_j = -x - bb[j-1] / q_{j-1}, the division done as a hardware reciprocal
+// refined by two Newton steps.
+__device__ int count_below(const double* bb, int nb, double x, double pivmin) {
   double q = -x;
   int neg = 1;  // q0 = -x < 0
   for (int j = 0; j < nb; ++j) {
-    const double bb = b[j] * b[j];
-    q = -x - bb / q;
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(r, fma(-q, r, 1.0), r);
+    r = fma(r, fma(-q, r, 1.0), r);
+    q = fma(-bb[j], r, -x);
     if (fabs(q) < pivmin) q = -pivmin;
     neg += (q < 0.0);
   }
@@ -217,8 +438,12 @@ __global__ void __launch_bounds__(256) k_bidiag_sv(const double* __restrict__ d,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* b = reinterpret_cast<double*>(smem_raw);  // 2k - 1 off-diagonal entries
   const int nb = (int)(2 * k - 1);
+  double* bb = b + nb;                                // their squares
   double bound = 0.0, maxb2 = 0.0;
-  for (int j = threadIdx.x; j < nb; j += blockDim.x) b[j] = (j & 1) ? e[j >> 1] : d[j >> 1];
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+    b[j] = (j & 1) ? e[j >> 1] : d[j >> 1];
+    bb[j] = b[j] * b[j];
+  }
   __syncthreads();
   for (int j = 0; j < nb; ++j) {  // every thread, same order
     const double left = j > 0 ? fabs(b[j - 1]) : 0.0;
@@ -237,7 +462,7 @@ __global__ void __launch_bounds__(256) k_bidiag_sv(const double* __restrict__ d,
     double lo = 0.0, hi = bound;
     for (int it = 0; it < 10; ++it) {
       const double x = lo + (hi - lo) * (double)(lane + 1) * (1.0 / 65.0);
-      const int cnt = count_below(b, nb, x, pivmin);
+      const int cnt = count_below(bb, nb, x, pivmin);
       const uint64_t le = __ballot(cnt <= want);  // monotone in lane
       const int nle = __popcll(le);               // lanes 0..nle-1 satisfy cnt <= want
       const double nlo = nle > 0 ? lo + (hi - lo) * (double)nle * (1.0 / 65.0) : lo;
@@ -250,21 +475,37 @@ __global__ void __launch_bounds__(256) k_bidiag_sv(const double* __restrict__ d,
   (void)info;
 }
 
-__global__ void k_count(const double* __restrict__ sigma, int64_t k, int32_t r1, double eps,
-                        const int32_t* __restrict__ info, int32_t* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// r^ = #{ i < r1 : sigma_i > eps sigma_1 } over the descending estimates.
+__global__ void __launch_bounds__(256) k_count(const double* __restrict__ sigma, int64_t k, int32_t r1, double eps,
+                                              const int32_t* __restrict__ info, int32_t* __restrict__ out) {
+  __shared__ int s_bad, s_cnt;
+  if (threadIdx.x == 0) {
+    s_bad = 0;
+    s_cnt = 0;
+  }
+  __syncthreads();
+  const double s1 = k > 0 ? sigma[0] : 0.0;
+  const double tau = eps * s1;
+  const int64_t lim = r1 < k ? r1 : k;
+  int bad = 0, cnt = 0;
+  for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
+    const double v = sigma[i];
+    bad |= !isfinite(v);
+    cnt += (i < lim && v > tau);
+  }
+  if (bad) atomicOr(&s_bad, 1);
+  atomicAdd(&s_cnt, cnt);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   int32_t st = info ? info[0] : 0;
+  if (st == 0 && s_bad) st = RE_ERR_NONFINITE;
   uint32_t flags = 0;
   int32_t r = 0;
-  for (int64_t i = 0; i < k && st == 0; ++i)
-    if (!isfinite(sigma[i])) st = RE_ERR_NONFINITE;
   if (st == 0) {
-    if (k == 0 || sigma[0] == 0.0) {
+    if (k == 0 || s1 == 0.0) {
       flags |= RE_FLAG_ZERO;
     } else {
-      const double tau = eps * sigma[0];
-      const int64_t lim = r1 < k ? r1 : k;
-      while (r < lim && sigma[r] > tau) ++r;
+      r = s_cnt;
       if (r == r1) flags |= RE_FLAG_NOT_CONVERGED;
     }
   }
@@ -287,17 +528,43 @@ int choose_P(int64_t l) {
   return (int)P;
 }
 
+// LDS-resident bidiagonalisation: the fewest workgroups whose rows fit in
+// LDS next to two k+1 vectors; P = 0 when no such launch exists (k > 1025
+// or more than 64 workgroups needed), and the global-memory kernel runs.
+constexpr size_t kLdsBudget = 156 * 1024;
+struct LdsPlan {
+  int P, nr_max;
+  size_t bytes;
+};
+int64_t lds_stride(int64_t k) { return k + ((16 - k % 32) + 32) % 32; }
+
+LdsPlan lds_plan(int64_t l, int64_t k) {
+  LdsPlan p{0, 0, 0};
+  if (k > 1025) return p;
+  const size_t fixed = (size_t)(2 * (k + 1) + kB2Waves) * 8;
+  for (int P = 1; P <= 64 && P <= l; ++P) {
+    const int64_t nr = (l + P - 1) / P;
+    const size_t bytes = (size_t)nr * lds_stride(k) * 8 + fixed;
+    if (bytes <= kLdsBudget) {
+      p.P = P;
+      p.nr_max = (int)nr;
+      p.bytes = bytes;
+      return p;
+    }
+  }
+  return p;
+}
+
 struct SvdLayout {
   size_t W, part, rowbuf, d, e, bar, total;
 };
 
 SvdLayout svd_layout(int64_t l, int64_t k) {
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-  const int P = choose_P(l);
   SvdLayout s{};
   size_t o = 0;
   s.W = o; o += al((size_t)l * k * 8);
-  s.part = o; o += al((size_t)2 * P * (k + 1) * 8);
+  s.part = o; o += al((size_t)2 * 64 * (k + 1) * 8);
   s.rowbuf = o; o += al((size_t)2 * (k + 1) * 8);
   s.d = o; o += al((size_t)k * 8);
   s.e = o; o += al((size_t)k * 8);
@@ -328,14 +595,39 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
   a.l = l;
   a.k = k;
   a.P = choose_P(l);
-  const size_t lds = (size_t)(2 + kWaves) * (k + 1) * 8;
-  if (lds > 160 * 1024) return RE_ERR_UNSUPPORTED;
-  if (lds > 64 * 1024)
-    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_svd_init, dim3(1), dim3(64), 0, s, a.bar, info);
-  void* params[] = {&a};
-  RE_TRY_HIP(hipLaunchCooperativeKernel((const void*)k_bidiag, dim3(a.P), dim3(kBidiagThreads), params, (unsigned)lds, s));
-  const size_t lds2 = (size_t)(2 * k) * 8;
+  const LdsPlan lp = lds_plan(l, k);
+  if (lp.P > 0) {
+    Bidiag2Args b2;
+    b2.C = C;
+    b2.part = a.part;
+    b2.rowbuf = a.rowbuf;
+    b2.d = a.d;
+    b2.e = a.e;
+    b2.bar = a.bar;
+    b2.info = info;
+    b2.l = l;
+    b2.k = k;
+    b2.kp = lds_stride(k);
+    b2.P = lp.P;
+    b2.nr_max = lp.nr_max;
+    const void* fn = k <= 65 ? (const void*)k_bidiag_lds<1>
+                   : k <= 129 ? (const void*)k_bidiag_lds<2>
+                   : k <= 257 ? (const void*)k_bidiag_lds<4>
+                   : k <= 513 ? (const void*)k_bidiag_lds<8> : (const void*)k_bidiag_lds<16>;
+    if (lp.bytes > 64 * 1024)
+      RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.bytes));
+    void* params2[] = {&b2};
+    RE_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(lp.P), dim3(kB2Threads), params2, (unsigned)lp.bytes, s));
+  } else {
+    const size_t lds = (size_t)(2 + kWaves) * (k + 1) * 8;
+    if (lds > 160 * 1024) return RE_ERR_UNSUPPORTED;
+    if (lds > 64 * 1024)
+      RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    void* params[] = {&a};
+    RE_TRY_HIP(hipLaunchCooperativeKernel((const void*)k_bidiag, dim3(a.P), dim3(kBidiagThreads), params, (unsigned)lds, s));
+  }
+  const size_t lds2 = (size_t)(4 * k) * 8;
   if (lds2 > 160 * 1024) return RE_ERR_UNSUPPORTED;
   if (lds2 > 64 * 1024)
     RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag_sv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
@@ -348,7 +640,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
 
 re_status launch_rank_count(hipStream_t s, const double* sigma, int64_t k, int32_t r1, double eps, const int32_t* info,
                             int32_t* out3) {
-  hipLaunchKernelGGL(k_count, dim3(1), dim3(64), 0, s, sigma, k, r1, eps, info, out3);
+  hipLaunchKernelGGL(k_count, dim3(1), dim3(256), 0, s, sigma, k, r1, eps, info, out3);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
 }

@@ -138,7 +138,7 @@ def test_gaussian_y(orc, dtype):
 def _svd_cases():
     rng = np.random.default_rng(5)
     out = []
-    for l, k in [(1, 1), (2, 2), (60, 40), (144, 96), (576, 384), (33, 33), (768, 512), (100, 3)]:
+    for l, k in [(1, 1), (2, 2), (60, 40), (144, 96), (576, 384), (33, 33), (768, 512), (100, 3), (700, 600)]:
         out.append((f"rand{l}x{k}", rng.standard_normal((l, k))))
     l, k = 200, 120
     U, _ = np.linalg.qr(rng.standard_normal((l, k)))
@@ -161,6 +161,16 @@ def test_singular_values(orc, name, Cm):
     assert np.all(np.abs(got - want) <= 1e-12 * s1), np.abs(got - want).max() / s1
     big = want >= 1e-4 * s1
     assert np.all(np.abs(got - want)[big] <= 1e-10 * want[big])
+
+
+def test_singular_values_global_memory_path():
+    """k > 1025 runs the global-memory bidiagonalisation; checked against LAPACK
+    (the oracle's Jacobi is pinned to it and would take minutes at this size)."""
+    rng = np.random.default_rng(11)
+    Cm = rng.standard_normal((1100, 1030)) * (10.0 ** -np.linspace(0, 6, 1030))[None, :]
+    got = _np(re_.singular_values(torch.from_numpy(Cm).to(DEV), 1.0))
+    want = np.linalg.svd(Cm, compute_uv=False)
+    assert np.all(np.abs(got - want) <= 1e-12 * want[0]), np.abs(got - want).max() / want[0]
 
 
 def test_rank_count_cases():
