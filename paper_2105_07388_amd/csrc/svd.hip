@@ -12,6 +12,8 @@
 //       multisection on Sturm counts, one wavefront per singular value.
 // Both steps are backward stable, so each sigma_i is within a small multiple
 // of u ||C|| of its exact value.
+#include <stdlib.h>
+
 #include "common.h"
 
 namespace re {
@@ -288,20 +290,18 @@ __device__ void partials_lds(const Bidiag2Args& a, const double* Wl, int nr, int
   const int iown = (int)(c / P);
   const int64_t kp = a.kp;
   for (int64_t j = threadIdx.x; j < len; j += blockDim.x) {
-    double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+    double g[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int i = i0;
-    for (; i + 3 < nr; i += 4) {
+    for (; i + 7 < nr; i += 8) {
       const double* r0 = Wl + (int64_t)i * kp + c;
-      g0 += r0[0] * r0[j];
-      g1 += r0[kp] * r0[kp + j];
-      g2 += r0[2 * kp] * r0[2 * kp + j];
-      g3 += r0[3 * kp] * r0[3 * kp + j];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) g[q] += r0[q * kp] * r0[q * kp + j];
     }
     for (; i < nr; ++i) {
       const double* r0 = Wl + (int64_t)i * kp + c;
-      g0 += r0[0] * r0[j];
+      g[0] += r0[0] * r0[j];
     }
-    st_coh(&a.part[(par * P + w) * (k + 1) + j], (g0 + g1) + (g2 + g3));
+    st_coh(&a.part[(par * P + w) * (k + 1) + j], ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])));
     if (owner) st_coh(&a.rowbuf[par * (k + 1) + j], Wl[(int64_t)iown * kp + c + j]);
   }
 }
@@ -389,17 +389,25 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_lds(Bidiag2Args a) {
       double* row = Wl + (int64_t)(live ? i : 0) * kp + c;
       const double ur = live ? row[0] : 0.0;
       const int64_t jend = live ? len : 0;
-      double z0 = 0.0, z1 = 0.0;
-      int64_t j = 1 + l16;
-      for (; j + 16 < jend; j += 32) {
+      double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+      for (int64_t j = 1 + l16; j < jend; j += 64) {
+        const int64_t j1 = j + 16, j2 = j + 32, j3 = j + 48;
         z0 += (row[j] - ur * wv[j]) * (j == 1 ? v1 : vv[j]);
-        z1 += (row[j + 16] - ur * wv[j + 16]) * vv[j + 16];
+        if (j1 < jend) z1 += (row[j1] - ur * wv[j1]) * vv[j1];
+        if (j2 < jend) z2 += (row[j2] - ur * wv[j2]) * vv[j2];
+        if (j3 < jend) z3 += (row[j3] - ur * wv[j3]) * vv[j3];
       }
-      if (j < jend) z0 += (row[j] - ur * wv[j]) * (j == 1 ? v1 : vv[j]);
-      const double z = row16_sum(z0 + z1) * tau2;
-      for (int64_t jj = 1 + l16; jj < jend; jj += 16) {
-        const double vj = jj == 1 ? v1 : vv[jj];
-        row[jj] = (row[jj] - ur * wv[jj]) - z * vj;
+      const double z = row16_sum((z0 + z1) + (z2 + z3)) * tau2;
+      for (int64_t j = 1 + l16; j < jend; j += 64) {
+        const int64_t j1 = j + 16, j2 = j + 32, j3 = j + 48;
+        const double a0 = row[j], b0 = wv[j], c0 = j == 1 ? v1 : vv[j];
+        const double a1 = j1 < jend ? row[j1] : 0.0, b1 = j1 < jend ? wv[j1] : 0.0, c1 = j1 < jend ? vv[j1] : 0.0;
+        const double a2 = j2 < jend ? row[j2] : 0.0, b2 = j2 < jend ? wv[j2] : 0.0, c2 = j2 < jend ? vv[j2] : 0.0;
+        const double a3 = j3 < jend ? row[j3] : 0.0, b3 = j3 < jend ? wv[j3] : 0.0, c3 = j3 < jend ? vv[j3] : 0.0;
+        row[j] = (a0 - ur * b0) - z * c0;
+        if (j1 < jend) row[j1] = (a1 - ur * b1) - z * c1;
+        if (j2 < jend) row[j2] = (a2 - ur * b2) - z * c2;
+        if (j3 < jend) row[j3] = (a3 - ur * b3) - z * c3;
       }
     }
     __syncthreads();
@@ -410,6 +418,110 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_lds(Bidiag2Args a) {
   }
 }
 
+// ---- bidiagonalisation of a sketch held by one workgroup ----------------
+// When the whole l x k sketch fits in LDS one workgroup reduces it alone:
+// the column partials go straight to LDS and workgroup barriers replace the
+// grid barrier.  Launched with one workgroup per problem, so it also runs
+// many independent sketches at once (problem b = blockIdx.x).
+struct SmallBatch {
+  const double* const* C;  // per problem: l x k row-major input (NULL: single problem below)
+  double* const* d;        // per problem: k diagonal entries
+  double* const* e;        // per problem: k - 1 superdiagonal entries
+  const int32_t* l;        // per problem rows
+  const int32_t* k;        // per problem columns
+  int32_t* info;           // per problem status
+  int kp;                  // LDS row stride in doubles (kp = 16 mod 32, kp >= max k)
+  const double* C1;        // the single problem when C is NULL
+  double* d1;
+  double* e1;
+  int32_t l1, k1;
+};
+
+__global__ void __launch_bounds__(kB2Threads) k_bidiag_1wg(SmallBatch sb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  const bool one = sb.C == nullptr;
+  const int64_t l = one ? sb.l1 : sb.l[b], k = one ? sb.k1 : sb.k[b], kp = sb.kp;
+  const double* C = one ? sb.C1 : sb.C[b];
+  double* dd = one ? sb.d1 : sb.d[b];
+  double* ee = one ? sb.e1 : sb.e[b];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* Wl = reinterpret_cast<double*>(smem_raw);  // [l][kp]
+  double* wv = Wl + l * kp;                           // [k + 1]
+  double* vv = wv + (k + 1);                          // [k + 1]
+  double* red = vv + (k + 1);                         // [kB2Waves]
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int64_t e = tid; e < l * k; e += kB2Threads) {
+    const int64_t i = e / k, j = e - i * k;
+    const double x = C[e];
+    if (!isfinite(x)) s_bad = 1;
+    Wl[i * kp + j] = x;
+  }
+  __syncthreads();
+  if (tid == 0) sb.info[b] = s_bad ? (int32_t)RE_ERR_NONFINITE : 0;
+  for (int64_t c = 0; c < k; ++c) {
+    const int64_t len = k - c;
+    // column partials of column c straight into LDS: wv = x . W[:, c + j], vv = W[c][c + j]
+    for (int64_t j = tid; j < len; j += kB2Threads) {
+      double g[4] = {0.0, 0.0, 0.0, 0.0};
+      int64_t i = c;
+      for (; i + 3 < l; i += 4) {
+        const double* r0 = Wl + i * kp + c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] += r0[q * kp] * r0[q * kp + j];
+      }
+      for (; i < l; ++i) g[0] += Wl[i * kp + c] * Wl[i * kp + c + j];
+      wv[j] = (g[0] + g[1]) + (g[2] + g[3]);
+      vv[j] = Wl[c * kp + c + j];
+    }
+    __syncthreads();
+    const double s0 = wv[0], x0 = vv[0];
+    const double nx = sqrt(s0);
+    const double alpha = nx > 0.0 ? -copysign(nx, x0) : 0.0;
+    const double tau = nx > 0.0 ? 1.0 / (s0 - alpha * x0) : 0.0;
+    const double u0 = x0 - alpha;
+    if (tid == 0) dd[c] = alpha;
+    double pp = 0.0;
+    for (int64_t j = 1 + tid; j < len; j += kB2Threads) {
+      const double row = vv[j];
+      const double wj = tau * (wv[j] - alpha * row);
+      const double y = row - u0 * wj;
+      wv[j] = wj;
+      vv[j] = y;
+      pp += y * y;
+    }
+    pp = wave_sum_dpp(pp);
+    if (lane == 0) red[wave] = pp;
+    __syncthreads();
+    double ny2 = 0.0;
+#pragma unroll
+    for (int v = 0; v < kB2Waves; ++v) ny2 += red[v];
+    const double y0 = len > 1 ? vv[1] : 0.0;
+    const double ny = sqrt(ny2);
+    const double beta = ny > 0.0 ? -copysign(ny, y0) : 0.0;
+    const double tau2 = ny > 0.0 ? 1.0 / (ny2 - beta * y0) : 0.0;
+    const double v1 = y0 - beta;
+    if (tid == 0 && len > 1) ee[c] = beta;
+    const int l16 = lane & 15;
+    for (int64_t i = c + 1 + 4 * wave + (lane >> 4); i - (lane >> 4) < l; i += 4 * kB2Waves) {
+      const bool live = i < l;
+      double* row = Wl + (live ? i : 0) * kp + c;
+      const double ur = live ? row[0] : 0.0;
+      const int64_t jend = live ? len : 0;
+      double z0 = 0.0, z1 = 0.0;
+      for (int64_t j = 1 + l16; j < jend; j += 32) {
+        z0 += (row[j] - ur * wv[j]) * (j == 1 ? v1 : vv[j]);
+        if (j + 16 < jend) z1 += (row[j + 16] - ur * wv[j + 16]) * vv[j + 16];
+      }
+      const double z = row16_sum(z0 + z1) * tau2;
+      for (int64_t j = 1 + l16; j < jend; j += 16) row[j] = (row[j] - ur * wv[j]) - z * (j == 1 ? v1 : vv[j]);
+    }
+    __syncthreads();
+  }
+}
+
 // ---- singular values of the bidiagonal by multisection on Sturm counts ----
 
 // Number of eigenvalues below x > 0 of the Golub-Kahan tridiagonal with zero
@@ -417,13 +529,12 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_lds(Bidiag2Args a) {
 // of singular values below x.
 // bb[j] = b[j]^2; the pivots q_j of the LDL^T factorisation of T - x I follow
 // q_j = -x - bb[j-1] / q_{j-1}, the division done as a hardware reciprocal
-// refined by two Newton steps.
+// refined by one Newton step.
 __device__ int count_below(const double* bb, int nb, double x, double pivmin) {
   double q = -x;
   int neg = 1;  // q0 = -x < 0
   for (int j = 0; j < nb; ++j) {
     double r = __builtin_amdgcn_rcp(q);
-    r = fma(r, fma(-q, r, 1.0), r);
     r = fma(r, fma(-q, r, 1.0), r);
     q = fma(-bb[j], r, -x);
     if (fabs(q) < pivmin) q = -pivmin;
@@ -460,7 +571,7 @@ __global__ void __launch_bounds__(256) k_bidiag_sv(const double* __restrict__ d,
     // jj-th largest singular value: #{sigma < lo} <= k-1-jj < #{sigma < hi}
     const int want = (int)(k - 1 - jj);
     double lo = 0.0, hi = bound;
-    for (int it = 0; it < 10; ++it) {
+    for (int it = 0; it < 9; ++it) {  // 65^9 > 2^54: below one ulp of the bound
       const double x = lo + (hi - lo) * (double)(lane + 1) * (1.0 / 65.0);
       const int cnt = count_below(bb, nb, x, pivmin);
       const uint64_t le = __ballot(cnt <= want);  // monotone in lane
@@ -538,11 +649,30 @@ struct LdsPlan {
 };
 int64_t lds_stride(int64_t k) { return k + ((16 - k % 32) + 32) % 32; }
 
+// LDS bytes of the single-workgroup bidiagonalisation of an l x k sketch.
+size_t small_lds_bytes(int64_t l, int64_t k) {
+  return (size_t)l * lds_stride(k) * 8 + (size_t)(2 * (k + 1) + kB2Waves) * 8;
+}
+
+// Rows per workgroup at most `svd_rows_target()` (fewer rows shorten the
+// per-column update; more workgroups lengthen the reduction), overridable
+// with RANKEST_SVD_ROWS for tuning.
+int svd_rows_target() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("RANKEST_SVD_ROWS");
+    v = e ? atoi(e) : 48;
+    if (v < 1) v = 1;
+  }
+  return v;
+}
+
 LdsPlan lds_plan(int64_t l, int64_t k) {
   LdsPlan p{0, 0, 0};
   if (k > 1025) return p;
   const size_t fixed = (size_t)(2 * (k + 1) + kB2Waves) * 8;
-  for (int P = 1; P <= 64 && P <= l; ++P) {
+  const int P0 = (int)((l + svd_rows_target() - 1) / svd_rows_target());
+  for (int P = P0 < 1 ? 1 : (P0 > 64 ? 64 : P0); P <= 64 && P <= l; ++P) {
     const int64_t nr = (l + P - 1) / P;
     const size_t bytes = (size_t)nr * lds_stride(k) * 8 + fixed;
     if (bytes <= kLdsBudget) {
@@ -597,7 +727,20 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
   a.P = choose_P(l);
   hipLaunchKernelGGL(k_svd_init, dim3(1), dim3(64), 0, s, a.bar, info);
   const LdsPlan lp = lds_plan(l, k);
-  if (lp.P > 0) {
+  const size_t one_bytes = small_lds_bytes(l, k);
+  if (one_bytes <= kLdsBudget) {
+    SmallBatch sb{};
+    sb.kp = (int)lds_stride(k);
+    sb.C1 = C;
+    sb.d1 = a.d;
+    sb.e1 = a.e;
+    sb.l1 = (int32_t)l;
+    sb.k1 = (int32_t)k;
+    sb.info = info;
+    if (one_bytes > 64 * 1024)
+      RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag_1wg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)one_bytes));
+    hipLaunchKernelGGL(k_bidiag_1wg, dim3(1), dim3(kB2Threads), one_bytes, s, sb);
+  } else if (lp.P > 0) {
     Bidiag2Args b2;
     b2.C = C;
     b2.part = a.part;
