@@ -4,6 +4,8 @@
 //   Y side (Algorithm 1 step 6):  C[s][t] = (H_M (d' .* [B[:,t], 0]))[S'_s]
 // H is the unnormalised Sylvester-ordered Walsh-Hadamard matrix,
 // H[p][q] = (-1)^popcount(p & q); N, M are n, m rounded up to powers of two.
+#include <stdlib.h>
+
 #include "common.h"
 
 namespace re {
@@ -67,6 +69,13 @@ constexpr int kN14 = 1 << 14;
 
 __device__ __forceinline__ int lds_swz14(int q) { return q ^ (((q >> 8) & 15) << 2); }
 
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+// 16-byte load of data read exactly once (non-temporal hint).
+__device__ __forceinline__ fx4 ld_stream(const float* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const fx4*>(p));
+}
+
 __device__ __forceinline__ void fwht64(float* x) {
 #pragma unroll
   for (int h = 1; h < 64; h <<= 1) {
@@ -103,33 +112,52 @@ __global__ void __launch_bounds__(256, 2) k_srht_rows_n14(const float* __restric
 #pragma unroll
   for (int i = 0; i < 16; ++i) ra[i] = base + 4 * (i ^ sw);
 
-  for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
-    const float4* src = reinterpret_cast<const float4*>(A + row * lda) + t;
-    float x[64];
+  // software pipeline: the loads of the next row are issued as soon as the
+  // current row has left the registers for LDS, so they overlap phase 2,
+  // the output step and the barriers
+  float x[64];
+  int64_t row = blockIdx.x;
+  if (row < m) {
+    const float* src = A + row * lda + 4 * t;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const float4 v = src[256 * j];
+      const fx4 v = ld_stream(src + 1024 * j);
       x[4 * j + 0] = v.x;
       x[4 * j + 1] = v.y;
       x[4 * j + 2] = v.z;
       x[4 * j + 3] = v.w;
     }
+  }
+  for (; row < m; row += gridDim.x) {
 #pragma unroll
     for (int e = 0; e < 64; ++e) x[e] = __uint_as_float(__float_as_uint(x[e]) ^ msk[e]);
     fwht64(x);
 #pragma unroll
     for (int j = 0; j < 16; ++j)
       *reinterpret_cast<float4*>(&lds[wa[j & 3] + 1024 * j]) = make_float4(x[4 * j], x[4 * j + 1], x[4 * j + 2], x[4 * j + 3]);
+    const int64_t next = row + gridDim.x;
+    if (next < m) {
+      const float* src = A + next * lda + 4 * t;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const fx4 v = ld_stream(src + 1024 * j);
+        x[4 * j + 0] = v.x;
+        x[4 * j + 1] = v.y;
+        x[4 * j + 2] = v.z;
+        x[4 * j + 3] = v.w;
+      }
+    }
     __syncthreads();
+    float y[64];
 #pragma unroll
     for (int h = 0; h < 4; ++h)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) x[16 * h + i] = lds[ra[i] + 64 * h];
-    fwht64(x);
+      for (int i = 0; i < 16; ++i) y[16 * h + i] = lds[ra[i] + 64 * h];
+    fwht64(y);
 #pragma unroll
     for (int h = 0; h < 4; ++h)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) lds[ra[i] + 64 * h] = x[16 * h + i];
+      for (int i = 0; i < 16; ++i) lds[ra[i] + 64 * h] = y[16 * h + i];
     __syncthreads();
     for (int s = t; s < k; s += 256) {
       const int p = sel[s];
@@ -140,6 +168,112 @@ __global__ void __launch_bounds__(256, 2) k_srht_rows_n14(const float* __restric
       const float a01 = (ph & 1) ? v0 - v1 : v0 + v1;
       const float a23 = (ph & 1) ? v2 - v3 : v2 + v3;
       B[row * k + s] = (ph & 2) ? a01 - a23 : a01 + a23;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// X side, N = 2^14 FP32 rows, 512 threads with 32 values each (twice the
+// wavefronts per CU of the kernel above, at most 128 VGPRs):
+//   load     thread t holds q = 2048 j + 4 t + c (j < 8): register bits {0, 1, 11, 12, 13};
+//   phase 1  those five butterfly stages in registers;
+//   LDS      f(q) = q ^ (((q >> 7) & 15) << 2), conflict-free for both patterns;
+//   phase 2  thread t holds the 32 positions whose bits {2..6} vary: five stages;
+//   output   bits {7..10} are finished only for the k sampled outputs: each sums
+//            its 16 partial values with the Sylvester signs of its bits 7..10.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void fwht32(float* x) {
+#pragma unroll
+  for (int h = 1; h < 32; h <<= 1) {
+#pragma unroll
+    for (int e = 0; e < 32; ++e) {
+      if (!(e & h)) {
+        const float a = x[e], b = x[e | h];
+        x[e] = a + b;
+        x[e | h] = a - b;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(512, 2) __attribute__((amdgpu_waves_per_eu(4))) k_srht_rows_n14w(const float* __restrict__ A, int64_t m, int64_t lda,
+                                                           const uint32_t* __restrict__ bits,
+                                                           const int32_t* __restrict__ sel, int k,
+                                                           float* __restrict__ B) {
+  __shared__ __align__(16) float lds[kN14];
+  const int t = threadIdx.x;
+  uint32_t msk = 0;  // bit 4 j + c: sign of position 2048 j + 4 t + c
+#pragma unroll
+  for (int j = 0; j < 8; ++j) msk |= ((bits[64 * j + (t >> 3)] >> (4 * (t & 7))) & 15u) << (4 * j);
+  const int wa = (4 * t) ^ (((t >> 5) & 15) << 2);  // phase-1 store of chunk j at wa + 2048 j
+  const int base = (t & 3) + 128 * ((t >> 2) & 15) + 2048 * (t >> 6);
+  const int sw = (t >> 2) & 15;
+  int ra[16];  // phase-2 value u = 16 h + i lives at ra[i] + 64 h
+#pragma unroll
+  for (int i = 0; i < 16; ++i) ra[i] = base + 4 * (i ^ sw);
+  // this thread's sampled output (k <= 512): its 16 partial values and their signs
+  const bool has = t < k;
+  int pa[16];
+  uint32_t sgn = 0;
+  {
+    const int p = has ? sel[t] : 0;
+    const int pl = p & ~(15 << 7), ph = (p >> 7) & 15;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      pa[b] = (pl ^ (b << 2)) + 128 * b;
+      sgn |= (uint32_t)(__popc(ph & b) & 1) << b;
+    }
+  }
+  for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
+    const float* src = A + row * lda + 4 * t;
+    float x[32];
+    // keep the 32 shifted sign masks from being hoisted into 32 live registers
+    asm volatile("" : "+v"(msk));
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const fx4 v = ld_stream(src + 2048 * j);
+      x[4 * j + 0] = v.x;
+      x[4 * j + 1] = v.y;
+      x[4 * j + 2] = v.z;
+      x[4 * j + 3] = v.w;
+    }
+#pragma unroll
+    for (int e = 0; e < 32; ++e) x[e] = __uint_as_float(__float_as_uint(x[e]) ^ ((msk << (31 - e)) & 0x80000000u));
+    fwht32(x);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      *reinterpret_cast<float4*>(&lds[wa + 2048 * j]) = make_float4(x[4 * j], x[4 * j + 1], x[4 * j + 2], x[4 * j + 3]);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[16 * h + i] = lds[ra[i] + 64 * h];
+    fwht32(x);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) lds[ra[i] + 64 * h] = x[16 * h + i];
+    __syncthreads();
+    if (has) {
+      float v[16];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) v[b] = __uint_as_float(__float_as_uint(lds[pa[b]]) ^ (((sgn >> b) & 1u) << 31));
+#pragma unroll
+      for (int w = 8; w > 0; w >>= 1)
+#pragma unroll
+        for (int b = 0; b < w; ++b) v[b] += v[b + w];
+      B[row * k + t] = v[0];
+    }
+    for (int s = t + 512; s < k; s += 512) {  // samples beyond the first 512
+      const int p = sel[s];
+      const int pl = p & ~(15 << 7), ph = (p >> 7) & 15;
+      float acc = 0.0f;
+      for (int b = 0; b < 16; ++b) {
+        const float val = lds[(pl ^ (b << 2)) + 128 * b];
+        acc += (__popc(ph & b) & 1) ? -val : val;
+      }
+      B[row * k + s] = acc;
     }
     __syncthreads();
   }
@@ -234,8 +368,13 @@ re_status launch_srht_rows(hipStream_t s, const void* A, int dtype, int64_t m, i
   if (m <= 0) return RE_OK;
   if (dtype == RE_F32 && n == kN14 && lda % 4 == 0 && ((uintptr_t)A % 16) == 0 && k <= INT32_MAX) {
     const int64_t g = 2 * (int64_t)num_cus();
-    hipLaunchKernelGGL(k_srht_rows_n14, dim3((unsigned)(m < g ? m : g)), dim3(256), 0, s, (const float*)A, m, lda,
-                       bits, sel, (int)k, (float*)B);
+    static const int variant = getenv("RANKEST_FWHT14") ? atoi(getenv("RANKEST_FWHT14")) : 1;
+    if (variant == 1)
+      hipLaunchKernelGGL(k_srht_rows_n14w, dim3((unsigned)(m < g ? m : g)), dim3(512), 0, s, (const float*)A, m, lda,
+                         bits, sel, (int)k, (float*)B);
+    else
+      hipLaunchKernelGGL(k_srht_rows_n14, dim3((unsigned)(m < g ? m : g)), dim3(256), 0, s, (const float*)A, m, lda,
+                         bits, sel, (int)k, (float*)B);
     RE_TRY_HIP(hipGetLastError());
     return RE_OK;
   }
