@@ -28,6 +28,11 @@ WORKLOADS = {
     "c2": dict(m=65536, n=16384, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="srht", y="srht",
                desc="plain method at scale: FP32 65536x16384, s_i=10^(-i/20) (R=1024) + 1e-9 noise, "
                     "SRHT X 16384x384, SRHT Y 576x65536, eps 1e-3/1e-5"),
+    "c3": dict(m=32768, n=8192, R=1024, k=512, l=768, eps=(1e-2, 1e-3), prec=("bf16", "fp16"), x="gaussian",
+               y="srht",
+               desc="precision form: FP32 32768x8192, 200 values at 1 then 1e-4 decaying geometrically, Gaussian X "
+                    "8192x512 in BF16 (eps 1e-2) / FP16 (eps 1e-3) on MFMA with FP32 accumulation, SRHT Y 768x32768, "
+                    "FP64 SVD"),
     "c1": dict(m=2000, n=1000, R=1000, k=40, l=60, eps=(1e-6,), x="gaussian", y="gaussian",
                desc="plain method, CPU-sized: FP64 2000x1000, step spectrum (20 x 1, then 1e-8), "
                     "Gaussian X 1000x40, Gaussian Y 60x2000, eps 1e-6"),
@@ -65,6 +70,8 @@ def make_matrix(name, w, device):
         return inputs.c2_matrix(w["m"], w["n"], w["R"], device=device)
     if name == "c1":
         return inputs.c1_matrix(device=device)
+    if name == "c3":
+        return inputs.c3_matrix(w["m"], w["n"], w["R"], device=device)
     raise ValueError(name)
 
 
@@ -127,8 +134,9 @@ def main():
 
     def step(i):
         eps = w["eps"][i % len(w["eps"])]
-        return re_.rank_estimate(A, eps, k=w["k"], l=w["l"], x=w["x"], y=w["y"], seed=1000003 * (i + 1),
-                                 handle=h)
+        prec = w.get("prec", ("native",))[i % len(w.get("prec", ("native",)))]
+        return re_.rank_estimate(A, eps, k=w["k"], l=w["l"], x=w["x"], y=w["y"], precision=prec,
+                                 seed=1000003 * (i + 1), handle=h)
 
     for i in range(args.warmup):
         step(-1 - i)
@@ -151,6 +159,13 @@ def main():
     achieved = alg_bytes / (ax_ms * 1e-3) / 1e9
     print(f"[bench] stages (ms): " + ", ".join(f"{k} {v:.4f}" for k, v in st_mean.items()) + f"; ranks {sorted(set(ranks))}",
           file=sys.stderr, flush=True)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(args.workload),
+            "kernel": "A X pass", "algorithmic_bytes_per_launch": alg_bytes, "mean_ms": ax_ms}
+    if w["x"] == "gaussian" and "prec" in w:
+        flops = 2.0 * w["m"] * w["n"] * w["k"]
+        roof["mfma"] = {"achieved_tflops": flops / (ax_ms * 1e-3) / 1e12, "peak_tflops": 2500.0,
+                        "frac": flops / (ax_ms * 1e-3) / 2.5e15, "flops_per_launch": flops}
     out = {
         "metric": "rank estimates/s + sketch GB/s vs HBM peak; learned vs doubling, same rank",
         "value": args.steps / elapsed,
@@ -162,13 +177,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if elem == 4 else "f64",
+        "dtype": "/".join(w["prec"]) if "prec" in w else ("f32" if elem == 4 else "f64"),
         "data": "synthetic",
         "config": {"workload": w["desc"], "m": w["m"], "n": w["n"], "k": w["k"], "l": w["l"], "eps": list(w["eps"]),
                    "x": w["x"], "y": w["y"], "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(args.workload),
-                     "kernel": "A X pass", "algorithmic_bytes_per_launch": alg_bytes, "mean_ms": ax_ms},
+        "roofline": roof,
         "stage_ms": st_mean,
     }
     if not args.no_cpu:

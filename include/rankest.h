@@ -55,8 +55,13 @@ typedef enum { RE_F64 = 0, RE_F32 = 1 } re_dtype;
 typedef enum { RE_GAUSSIAN = 0, RE_SRHT = 1 } re_kind;
 
 /* Arithmetic of the A X contraction.  NATIVE: the storage type of A.
- * BF16 / FP16: A and a Gaussian X rounded to that format, FP32 accumulation.
- * AUTO: the cheapest format whose rounding floor stays below eps/4. */
+ * BF16 / FP16: A (FP32 only) and a Gaussian X rounded to that format on the
+ * matrix cores, FP32 accumulation; FP16 first scales A by an exact power of
+ * two so that its sampled largest entry sits near 2^12.
+ * AUTO: BF16, then FP16, then FP32, keeping the first whose rounding floor
+ * phi = (u / sqrt(3)) ||A||_F (1/sqrt(k) + 1/sqrt(m)) (||A||_F from a sample
+ * of A's entries) is at most eps * sigma_1 / 4, with sigma_1 the estimate the
+ * sketch itself returns; a rejected format costs one more pass over A. */
 typedef enum { RE_PREC_NATIVE = 0, RE_PREC_BF16 = 1, RE_PREC_FP16 = 2, RE_PREC_AUTO = 3 } re_prec;
 
 /* The sketch of Algorithm 1: X is n x k (k = round(1.1 r1), step 1) and Y is
@@ -73,7 +78,9 @@ typedef struct {
 enum {
   RE_FLAG_NOT_CONVERGED = 1u, /* all of the first r1 estimates exceed eps*sigma_1: rank >= r1 (Algorithm 1 step 8) */
   RE_FLAG_ZERO = 2u,          /* sigma_1 of the sketch is zero */
-  RE_FLAG_PREC_FALLBACK = 4u  /* AUTO could not use a low-precision format */
+  RE_FLAG_PREC_FALLBACK = 4u, /* AUTO could not use a low-precision format */
+  RE_FLAG_USED_BF16 = 8u,     /* the A X contraction ran in BF16 */
+  RE_FLAG_USED_FP16 = 16u     /* the A X contraction ran in FP16 */
 };
 
 typedef struct re_handle_s* re_handle;

@@ -9,6 +9,8 @@ library has not been built.
 from ._binding import (  # noqa: F401
     FLAG_NOT_CONVERGED,
     FLAG_PREC_FALLBACK,
+    FLAG_USED_BF16,
+    FLAG_USED_FP16,
     FLAG_ZERO,
     Handle,
     RankEstError,

@@ -22,7 +22,7 @@ RE_F64, RE_F32 = 0, 1
 RE_GAUSSIAN, RE_SRHT = 0, 1
 PREC = {"native": 0, "bf16": 1, "fp16": 2, "auto": 3}
 KIND = {"gaussian": RE_GAUSSIAN, "srht": RE_SRHT}
-FLAG_NOT_CONVERGED, FLAG_ZERO, FLAG_PREC_FALLBACK = 1, 2, 4
+FLAG_NOT_CONVERGED, FLAG_ZERO, FLAG_PREC_FALLBACK, FLAG_USED_BF16, FLAG_USED_FP16 = 1, 2, 4, 8, 16
 FMT = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 FMT_DTYPE = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float16}
 STAGES = ("x_draw", "ax", "y_draw", "yb", "svd", "rank")

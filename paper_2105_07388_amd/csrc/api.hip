@@ -81,6 +81,8 @@ int x_fmt(int32_t dt) { return dt == RE_F64 ? kF64 : kF32; }
 struct Resolved {
   int32_t xk, yk;
   int64_t k, l, npad_n, npad_m;
+  int fmt_x = -1;     // contraction format of a Gaussian X (kF64, kF32, kBF16, kF16)
+  int scale_exp = 0;  // FP16: A is scaled by 2^scale_exp before rounding
 };
 
 // Checks the arguments of one estimate; `sides` selects which embedding's
@@ -106,16 +108,13 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
   if ((sides & 1) && rs->k > kmax) return RE_ERR_INVALID_ARG;
   if ((sides & 2) && rs->l > lmax) return RE_ERR_INVALID_ARG;
   if (rs->k > (int64_t)INT32_MAX / 2) return RE_ERR_INVALID_ARG;
-  if (sk->prec != RE_PREC_NATIVE) {
-    if (dt == RE_F64 || rs->xk == RE_SRHT) return RE_ERR_UNSUPPORTED;
-    return RE_ERR_UNSUPPORTED;  // low-precision contraction not built into this library
-  }
+  if (sk->prec != RE_PREC_NATIVE && (dt == RE_F64 || rs->xk == RE_SRHT)) return RE_ERR_UNSUPPORTED;
   return RE_OK;
 }
 
 // Workspace plan of one estimate.
 struct Plan {
-  size_t xbits, ybits, xsel, ysel, selscr, X, Y, B, C, svd, sigma, info, out3, total;
+  size_t xbits, ybits, xsel, ysel, selscr, X, Y, B, C, svd, sigma, info, out3, stats, total;
 };
 
 Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
@@ -129,7 +128,7 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   p.xsel = c.take((size_t)rs.k * 4);
   p.ysel = c.take((size_t)rs.l * 4);
   p.selscr = c.take(select_scratch_bytes(rs.npad_n > rs.npad_m ? rs.npad_n : rs.npad_m));
-  p.X = c.take(rs.xk == RE_GAUSSIAN ? (size_t)n * rs.k * elem_size(fx) : 0);
+  p.X = c.take(rs.xk == RE_GAUSSIAN ? (size_t)n * rs.k * (size_t)elem_size(fx) : 0);  // FP32/FP64; 2-byte formats fit too
   p.Y = c.take(rs.yk == RE_GAUSSIAN ? (size_t)rs.l * m * elem_size(fx) : 0);
   p.B = c.take((size_t)brows * rs.k * be);
   p.C = c.take((size_t)rs.l * rs.k * 8);
@@ -137,6 +136,7 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   p.sigma = c.take((size_t)rs.k * 8);
   p.info = c.take(16);
   p.out3 = c.take(16);
+  p.stats = c.take(32);
   p.total = c.off;
   return p;
 }
@@ -159,8 +159,14 @@ re_status run_x(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m
     mark(h, RE_STAGE_AX);
     return launch_srht_rows(s, A, dt, m, n, lda, bits, sel, rs.k, B);
   }
-  const int fx = x_fmt(dt);
   void* X = at(h, p.X);
+  if (rs.fmt_x == kBF16 || rs.fmt_x == kF16) {
+    // X^T (k x n) so that each column of X is contiguous along K
+    RE_TRY(launch_gauss_fill(s, rs.fmt_x, rs.k, n, seed, kXGauss, 1, X));
+    mark(h, RE_STAGE_AX);
+    return launch_gemm_lp(s, rs.fmt_x, (const float*)A, m, n, lda, X, rs.k, rs.scale_exp, (float*)B);
+  }
+  const int fx = x_fmt(dt);
   RE_TRY(launch_gauss_fill(s, fx, n, rs.k, seed, kXGauss, 0, X));
   mark(h, RE_STAGE_AX);
   const int t = dt == RE_F64 ? 0 : 1;
@@ -245,22 +251,19 @@ RE_API re_status re_workspace_bytes(re_handle h, size_t* bytes) {
 
 RE_API int32_t re_r1_from_k(int32_t k) { return re::r1_from_k(k); }
 
-RE_API re_status re_rank_estimate(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
-                                  double eps, const re_sketch* sk, uint64_t seed, int32_t* r_out, double* sigma_out,
-                                  int32_t* r1_out, uint32_t* flags_out) {
-  if (!h || !r_out || !sigma_out) return RE_ERR_INVALID_ARG;
-  if (!(eps > 0.0 && eps < 1.0)) return RE_ERR_INVALID_ARG;
-  Resolved rs;
-  RE_TRY(validate(A, dt, m, n, lda, sk, &rs));
-  const Plan p = plan(dt, m, n, rs);
-  RE_TRY(ensure_ws(h, p.total));
-  RE_TRY(ensure_host(h, (size_t)rs.k * 8 + 64));
+namespace re {
+namespace {
+
+// One pass of Algorithm 1 with the formats in rs; results left in the
+// handle's pinned staging buffer (16 bytes of r, flags, status; then sigma).
+re_status run_once(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                   double eps, const Resolved& rs, uint64_t seed) {
   void* B = at(h, p.B);
   double* C = (double*)at(h, p.C);
   double* sigma = (double*)at(h, p.sigma);
   int32_t* info = (int32_t*)at(h, p.info);
   int32_t* out3 = (int32_t*)at(h, p.out3);
-  const int32_t r1 = re::r1_from_k((int32_t)rs.k);
+  const int32_t r1 = r1_from_k((int32_t)rs.k);
   mark(h, RE_STAGE_X_DRAW);
   RE_TRY(run_x(h, p, A, dt, m, n, lda, rs, seed, B));
   mark(h, RE_STAGE_Y_DRAW);
@@ -281,12 +284,71 @@ RE_API re_status re_rank_estimate(re_handle h, const void* A, int32_t dt, int64_
       h->stage_ms[i] = hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess ? (double)ms : -1.0;
     }
   }
+  return RE_OK;
+}
+
+double unit_roundoff(int fmt) { return fmt == kBF16 ? 0x1.0p-8 : fmt == kF16 ? 0x1.0p-11 : 0x1.0p-24; }
+
+}  // namespace
+}  // namespace re
+
+RE_API re_status re_rank_estimate(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                                  double eps, const re_sketch* sk, uint64_t seed, int32_t* r_out, double* sigma_out,
+                                  int32_t* r1_out, uint32_t* flags_out) {
+  if (!h || !r_out || !sigma_out) return RE_ERR_INVALID_ARG;
+  if (!(eps > 0.0 && eps < 1.0)) return RE_ERR_INVALID_ARG;
+  Resolved rs;
+  RE_TRY(validate(A, dt, m, n, lda, sk, &rs));
+  rs.fmt_x = x_fmt(dt);
+  const Plan p = plan(dt, m, n, rs);
+  RE_TRY(ensure_ws(h, p.total));
+  RE_TRY(ensure_host(h, (size_t)rs.k * 8 + 64));
+  const char* host = (const char*)h->host;
+  uint32_t extra = 0;
+  if (sk->prec == RE_PREC_NATIVE) {
+    RE_TRY(run_once(h, p, A, dt, m, n, lda, eps, rs, seed));
+  } else {
+    // sampled ||A||_F^2 and max |a|: FP16 scale and the AUTO acceptance test
+    double* st = (double*)at(h, p.stats);
+    RE_TRY(launch_sample_stats(h->stream, (const float*)A, m, n, lda, st));
+    double stats[3];
+    RE_TRY_HIP(hipMemcpyAsync(stats, st, sizeof(stats), hipMemcpyDeviceToHost, h->stream));
+    RE_TRY_HIP(hipStreamSynchronize(h->stream));
+    const double frob = sqrt(stats[0] * ((double)m * (double)n / (stats[2] > 0 ? stats[2] : 1.0)));
+    const double amax = stats[1];
+    const double shape = 1.0 / sqrt((double)rs.k) + 1.0 / sqrt((double)m);
+    int tries[3] = {kBF16, kF16, kF32};
+    int ntries = 3;
+    if (sk->prec == RE_PREC_BF16) { tries[0] = kBF16; ntries = 1; }
+    if (sk->prec == RE_PREC_FP16) { tries[0] = kF16; ntries = 1; }
+    re_status last = RE_OK;
+    for (int t = 0; t < ntries; ++t) {
+      rs.fmt_x = tries[t];
+      rs.scale_exp = 0;
+      if (rs.fmt_x == kF16 && amax > 0.0) {
+        int e2 = 0;
+        frexp(amax, &e2);   // amax < 2^e2
+        rs.scale_exp = 12 - e2;
+      }
+      last = run_once(h, p, A, dt, m, n, lda, eps, rs, seed);
+      const int32_t* o3 = (const int32_t*)host;
+      if (sk->prec != RE_PREC_AUTO || rs.fmt_x == kF32) break;
+      if (last != RE_OK) return last;
+      const double s1 = ((const double*)(host + 64))[0];
+      const double phi = unit_roundoff(rs.fmt_x) / sqrt(3.0) * frob * shape;
+      if (o3[2] == 0 && phi <= eps * s1 / 4.0) break;  // accepted
+      if (t + 1 == ntries - 1) extra |= RE_FLAG_PREC_FALLBACK;
+    }
+    RE_TRY(last);
+    if (rs.fmt_x == kBF16) extra |= RE_FLAG_USED_BF16;
+    if (rs.fmt_x == kF16) extra |= RE_FLAG_USED_FP16;
+  }
   const int32_t* o3 = (const int32_t*)host;
   if (o3[2] != 0) return (re_status)o3[2];
   *r_out = o3[0];
   memcpy(sigma_out, host + 64, (size_t)rs.k * 8);
-  if (r1_out) *r1_out = r1;
-  if (flags_out) *flags_out = (uint32_t)o3[1];
+  if (r1_out) *r1_out = r1_from_k((int32_t)rs.k);
+  if (flags_out) *flags_out = (uint32_t)o3[1] | extra;
   return RE_OK;
 }
 
@@ -317,8 +379,22 @@ RE_API re_status re_sketch_x(re_handle h, const void* A, int32_t dt, int64_t m, 
   if (!h || !B) return RE_ERR_INVALID_ARG;
   Resolved rs;
   RE_TRY(validate(A, dt, m, n, lda, sk, &rs, 1));
+  if (sk->prec == RE_PREC_AUTO) return RE_ERR_INVALID_ARG;  // the stage call needs an explicit format
+  rs.fmt_x = sk->prec == RE_PREC_BF16 ? kBF16 : sk->prec == RE_PREC_FP16 ? kF16 : x_fmt(dt);
   const Plan p = plan(dt, m, n, rs);
   RE_TRY(ensure_ws(h, p.total));
+  if (rs.fmt_x == kF16) {
+    double* st = (double*)at(h, p.stats);
+    RE_TRY(launch_sample_stats(h->stream, (const float*)A, m, n, lda, st));
+    double stats[3];
+    RE_TRY_HIP(hipMemcpyAsync(stats, st, sizeof(stats), hipMemcpyDeviceToHost, h->stream));
+    RE_TRY_HIP(hipStreamSynchronize(h->stream));
+    if (stats[1] > 0.0) {
+      int e2 = 0;
+      frexp(stats[1], &e2);
+      rs.scale_exp = 12 - e2;
+    }
+  }
   return run_x(h, p, A, dt, m, n, lda, rs, seed, B);
 }
 
