@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rows", type=int, default=8192, help="rows of A in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="before timing, copy a buffer of this many GiB once (a plain copy kernel of known size that "
+                         "calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the estimator here is a single-GPU "
@@ -127,6 +130,14 @@ def main():
     torch.cuda.set_device(dev)
     A = make_matrix(args.workload, w, dev)
     torch.cuda.synchronize()
+    if args.calib_copy_gib > 0:
+        nb = int(args.calib_copy_gib * 2**30) // 4
+        src = torch.ones(nb, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     h = re_.Handle(dev)
     h.set_profiling(True)
     print(f"[bench] {args.workload}: A {tuple(A.shape)} {A.dtype} resident; warmup {args.warmup}", file=sys.stderr,

@@ -48,7 +48,7 @@ typedef enum {
 /* Storage type of A. */
 typedef enum { RE_F64 = 0, RE_F32 = 1 } re_dtype;
 
-/* Random embedding families (Sec. 3.3): a Gaussian embedding, or a
+/* Random embedding families (Sec. 3.3, Sec. 4): a Gaussian embedding, or a
  * subsampled randomized Hadamard transform sqrt(N/k) S H D (Eq. (Theta), with
  * the Hadamard matrix as the trigonometric transform and N = the dimension
  * zero-padded to a power of two). */
@@ -163,7 +163,7 @@ re_status re_gauss_fill(re_handle h, int32_t fmt, int64_t rows, int64_t cols, ui
  * stream_id 3 for X, 4 for Y. */
 re_status re_srht_signs(re_handle h, int64_t npad, uint64_t seed, int32_t stream_id, uint32_t* bits_dev);
 
-/* Row sampler S of an SRHT (uniform sampling without replacement, Appendix):
+/* Row sampler S of an SRHT (uniform sampling without replacement, Appendix A.1):
  * the k indices of [0, npad) with the smallest 64-bit keys (ties by index),
  * written in ascending order to idx_dev (device, k int32).  stream_id 5 (X) or 6 (Y). */
 re_status re_srht_select(re_handle h, int64_t npad, int64_t k, uint64_t seed, int32_t stream_id, int32_t* idx_dev);

@@ -136,7 +136,7 @@ static int cmp_i64(const void* pa, const void* pb) {
 }
 
 /* Uniform sampling of k of npad indices without replacement (the row sampler
- * S of the SRTT, Appendix: uniform sampling without replacement): the k
+ * S of the SRTT, Appendix A.1: uniform sampling without replacement): the k
  * indices whose iid 64-bit keys are smallest, ties broken by index, returned
  * in ascending index order. */
 OR_EXPORT int or_select(uint64_t seed, int64_t npad, int64_t k, uint64_t stream, uint64_t blk, int64_t* idx) {

@@ -56,7 +56,7 @@ def test_gauss_moments_and_ks(orc):
 
 
 def test_gauss_singular_values_marchenko_pastur(orc):
-    """Davidson-Szarek (Sec. 3.2): sqrt(m)-sqrt(n)-t <= s_min <= s_max <= sqrt(m)+sqrt(n)+t
+    """Davidson-Szarek (Theorem 3, Sec. 3): sqrt(m)-sqrt(n)-t <= s_min <= s_max <= sqrt(m)+sqrt(n)+t
     with probability >= 1 - exp(-t^2/2) each; t = 4 makes a failure ~1e-3."""
     m, n = 600, 60
     G = np.array([[orc.gauss(3, i, j, 1) for j in range(n)] for i in range(m)])
@@ -128,7 +128,7 @@ def test_select_nested_in_k(orc):
 
 
 def test_select_uniform_inclusion(orc):
-    """Uniform sampling without replacement (Appendix): each index is included with
+    """Uniform sampling without replacement (Appendix A.1): each index is included with
     probability k/n; chi-square over seeds."""
     npad, k, trials = 64, 8, 800
     counts = np.zeros(npad)
@@ -334,7 +334,7 @@ def test_c1_planted_gap_every_seed(orc):
 
 
 def test_theorem2_expectation_bounds(orc):
-    """Thm. 2: 1 - sqrt(i/r) <= E s_i(AX)/s_i(A) <= 1 + sqrt((r-i+1)/r) + (s_{r+1}/s_i)(1 + sqrt((n-r)/r))
+    """Theorem 4 (Sec. 3): 1 - sqrt(i/r) <= E s_i(AX)/s_i(A) <= 1 + sqrt((r-i+1)/r) + (s_{r+1}/s_i)(1 + sqrt((n-r)/r))
     for a Gaussian embedding X = G/sqrt(r); the mean over seeds sits inside the bounds."""
     n, r = 120, 20
     sig = np.concatenate([10.0 ** -np.linspace(0, 2, 10), np.full(n - 10, 1e-3)])
