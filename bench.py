@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 WORKLOADS = {
     "c2": dict(m=65536, n=16384, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="srht", y="srht",
                desc="plain method at scale: FP32 65536x16384, s_i=10^(-i/20) (R=1024) + 1e-9 noise, "
@@ -33,6 +34,10 @@ WORKLOADS = {
                desc="precision form: FP32 32768x8192, 200 values at 1 then 1e-4 decaying geometrically, Gaussian X "
                     "8192x512 in BF16 (eps 1e-2) / FP16 (eps 1e-3) on MFMA with FP32 accumulation, SRHT Y 768x32768, "
                     "FP64 SVD"),
+    "c4": dict(nblocks=4096, k=96, l=144, eps=(1e-6,), x="gaussian", y="gaussian",
+               desc="batched form: 4096 FP32 blocks of 1/|x-y| between two separated uniform 2-D clusters, m, n "
+                    "uniform in [256, 4096], Gaussian X 96 columns and Y 144 rows per block, eps 1e-6, one "
+                    "graph launch per batch"),
     "c1": dict(m=2000, n=1000, R=1000, k=40, l=60, eps=(1e-6,), x="gaussian", y="gaussian",
                desc="plain method, CPU-sized: FP64 2000x1000, step spectrum (20 x 1, then 1e-8), "
                     "Gaussian X 1000x40, Gaussian Y 60x2000, eps 1e-6"),
@@ -40,24 +45,28 @@ WORKLOADS = {
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def kernel_source_digest() -> str:
+TRAFFIC_SOURCES = {"c2": ("srht.hip", "common.h"), "c3": ("gemm_lp.hip", "common.h"),
+                   "c4": ("batch.hip", "batch.h", "common.h")}
+
+
+def kernel_source_digest(workload: str) -> str:
     h = hashlib.sha256()
-    for f in ("srht.hip", "common.h"):
+    for f in TRAFFIC_SOURCES.get(workload, ("srht.hip", "common.h")):
         with open(os.path.join(ROOT, "paper_2105_07388_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(workload: str):
-    """HBM bytes per launch of the A X kernel from committed rocprofv3 counter runs,
-    only if they were taken on the current kernel source."""
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3
+    counter runs, only if they were taken on the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     rec = t.get(workload)
-    if not rec or rec.get("src_digest") != kernel_source_digest():
+    if not rec or rec.get("src_digest") != kernel_source_digest(workload):
         return None
     return rec.get("bytes_per_launch")
 
@@ -103,6 +112,108 @@ def cpu_baseline(A_dev, w, rows: int):
                       f"Jacobi SVD of the {l}x{k} sketch; seconds: ax {t_x:.2f}, yb {t_y:.2f}, svd {t_svd:.2f}"}
 
 
+def cpu_baseline_batched(views, params, w, nsample: int):
+    """Oracle timed on a stratified sample of blocks (sorted by size, evenly
+    spaced), scaled to the whole batch by the ratio of m*n."""
+    import numpy as np
+
+    import oracle
+    sizes = np.array([p["m"] * p["n"] for p in params], dtype=np.float64)
+    order = np.argsort(sizes)
+    pick = order[np.linspace(0, len(order) - 1, nsample).astype(int)]
+    t = 0.0
+    for b in pick:
+        A = views[b].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.rank_estimate(A, w["eps"][0], oracle.GAUSSIAN, oracle.GAUSSIAN, k=w["k"], l=w["l"], seed=5)
+        t += time.perf_counter() - t0
+    total = t * sizes.sum() / sizes[pick].sum()
+    return {"value": len(params) / total, "unit": "rank estimates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{nsample} blocks spread over the size range, {t:.1f} s, scaled to the batch by total m*n"}
+
+
+def bench_batched(args, w, dev):
+    import numpy as np
+    import torch
+
+    import paper_2105_07388_amd as re_
+    from paper_2105_07388_amd import inputs
+
+    t0 = time.perf_counter()
+    buf, views, params = inputs.kernel_blocks(w["nblocks"], device=dev)
+    torch.cuda.synchronize()
+    table = re_.make_blocks(views)
+    nb = len(views)
+    mn = float(sum(p["m"] * p["n"] for p in params))
+    print(f"[bench] c4: {nb} blocks, {mn * 4 / 1e9:.1f} GB resident (built in {time.perf_counter() - t0:.1f} s); "
+          f"warmup {args.warmup}", file=sys.stderr, flush=True)
+    h = re_.Handle(dev)
+    k, l, eps = w["k"], w["l"], w["eps"][0]
+    for i in range(args.warmup):
+        re_.rank_estimate_batched(table, eps, k=k, l=l, seed=7 + i, handle=h)
+    torch.cuda.synchronize()
+    ranks = None
+    t0 = time.perf_counter()
+    for i in range(args.steps):  # graph replays
+        ranks, _, _ = re_.rank_estimate_batched(table, eps, k=k, l=l, seed=1000003 * (i + 1), handle=h)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # stage times: the same launches issued directly with HIP events between them
+    h.set_profiling(True)
+    stages = []
+    for i in range(max(3, min(args.steps, 10))):
+        re_.rank_estimate_batched(table, eps, k=k, l=l, seed=1000003 * (i + 1), handle=h)
+        stages.append(h.last_stage_ms())
+    h.set_profiling(False)
+    st_mean = {kk: float(np.mean([s[kk] for s in stages])) for kk in stages[0]}
+    print("[bench] stages (ms): " + ", ".join(f"{kk} {v:.3f}" for kk, v in st_mean.items()) +
+          f"; ranks {int(ranks.min())}..{int(ranks.max())}", file=sys.stderr, flush=True)
+    ax_ms = st_mean["ax"]
+    flops = 2.0 * mn * k
+    achieved = flops / (ax_ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": load_traffic("c4"),
+            "kernel": "persistent FP32 MFMA A X over all blocks", "algorithmic_flops_per_launch": flops,
+            "algorithmic_bytes_per_launch": mn * 4, "hbm_GBs": mn * 4 / (ax_ms * 1e-3) / 1e9, "mean_ms": ax_ms}
+    # the same estimates block by block through the single-matrix call
+    nloop = min(nb, args.loop_blocks)
+    sizes = np.array([p["m"] * p["n"] for p in params], dtype=np.float64)
+    pick = np.argsort(sizes)[np.linspace(0, nb - 1, nloop).astype(int)]
+    h2 = re_.Handle(dev)
+    for b in pick[:4]:
+        re_.rank_estimate(views[b], eps, k=k, l=l, seed=3, handle=h2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in pick:
+        re_.rank_estimate(views[b], eps, k=k, l=l, seed=3, handle=h2)
+    torch.cuda.synchronize()
+    t_loop = (time.perf_counter() - t0) * sizes.sum() / sizes[pick].sum()
+    out = {
+        "metric": "rank estimates/s + sketch GB/s vs HBM peak; learned vs doubling, same rank",
+        "value": nb * args.steps / elapsed,
+        "unit": "rank estimates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "nblocks": nb, "k": k, "l": l, "eps": [eps], "x": "gaussian",
+                   "y": "gaussian", "entries": mn, "parallelism": "single GPU"},
+        "roofline": roof,
+        "stage_ms": st_mean,
+        "per_block_loop": {"value": nb / t_loop, "unit": "rank estimates/s",
+                           "sample": f"{nloop} blocks through the single-matrix call, scaled by total m*n"},
+    }
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle on a sample of blocks", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_batched(views, params, w, args.cpu_blocks)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +222,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-rows", type=int, default=8192, help="rows of A in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--loop-blocks", type=int, default=256, help="c4: blocks timed through the single-matrix call")
+    ap.add_argument("--cpu-blocks", type=int, default=12, help="c4: blocks in the oracle's timed sample")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="before timing, copy a buffer of this many GiB once (a plain copy kernel of known size that "
                          "calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -128,6 +241,8 @@ def main():
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload == "c4":
+        return bench_batched(args, w, dev)
     A = make_matrix(args.workload, w, dev)
     torch.cuda.synchronize()
     if args.calib_copy_gib > 0:

@@ -123,7 +123,7 @@ re_status re_last_stage_ms(re_handle h, double* ms);
 /*
  * Algorithm 1 of the paper on one matrix.
  *   A_dev      device, m x n row-major with leading dimension lda >= n, type dt;
- *              read only; 16-byte aligned.
+ *              read only; aligned to its element size (16-byte alignment with lda % 4 == 0 enables the vector-load kernels).
  *   eps        relative tolerance, 0 < eps < 1 (Def. 1).
  *   sk         sketch description (host).
  *   seed       key of the counter-based generator defining X and Y.
@@ -140,6 +140,39 @@ re_status re_last_stage_ms(re_handle h, double* ms);
 re_status re_rank_estimate(re_handle h, const void* A_dev, int32_t dt, int64_t m, int64_t n, int64_t lda, double eps,
                            const re_sketch* sk, uint64_t seed, int32_t* r_out, double* sigma_out, int32_t* r1_out,
                            uint32_t* flags_out);
+
+/* One block of a batched call: caller-owned device matrix, m x n row-major
+ * with leading dimension lda >= n (FP32, 4-byte aligned). */
+typedef struct {
+  const void* A;
+  int64_t m, n, lda;
+} re_block;
+
+/*
+ * Algorithm 1 on many independent blocks (for example the off-diagonal blocks
+ * of a hierarchical matrix) in one graph launch.  Gaussian X and Y only, FP32
+ * blocks, native precision.  X and Y are master sketches of n_max x k and
+ * l x m_max drawn once per call; block b uses X's first n_b rows and Y's
+ * first m_b columns, so every block gets exactly the estimate that
+ * re_rank_estimate with the same seed returns for it.  The A X contraction of
+ * all blocks is one persistent matrix-core kernel fed by an atomic queue of
+ * (block, row tile, column chunk) items; the Y B products, small SVDs and
+ * counts run one workgroup per block.  The work is captured once into a HIP
+ * graph (re-captured when the shapes or the workspace change) and the tile
+ * shape of the persistent kernel is chosen by timing the candidates on the
+ * first call for a shape (cached in the handle, and in the text file named by
+ * RANKEST_AUTOTUNE_CACHE when that variable is set).
+ *   blocks     host array of nblocks descriptors (k <= n_b, l <= m_b each)
+ *   r_out      host, nblocks: rank estimates
+ *   sigma_out  host, nblocks * k: estimates of block b at b * k
+ *   flags_out  host or NULL, nblocks: RE_FLAG_* bits
+ * Errors as re_rank_estimate; RE_ERR_UNSUPPORTED for SRHT sketches, FP64
+ * blocks, low precision, or an l x k sketch too large for one workgroup.
+ * Synchronises the handle's stream.
+ */
+re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, int32_t nblocks, int32_t dt, double eps,
+                                   const re_sketch* sk, uint64_t seed, int32_t* r_out, double* sigma_out,
+                                   uint32_t* flags_out);
 
 /*
  * Stage entry points.  Each runs one step of Algorithm 1 on device buffers,

@@ -17,10 +17,12 @@ from ._binding import (  # noqa: F401
     default_handle,
     gauss_fill,
     lib,
+    make_blocks,
     philox,
     r1_from_k,
     rank_count,
     rank_estimate,
+    rank_estimate_batched,
     singular_values,
     sketch_x,
     sketch_y,

@@ -41,6 +41,10 @@ class ReSketch(C.Structure):
                 ("prec", C.c_int32)]
 
 
+class ReBlock(C.Structure):
+    _fields_ = [("A", C.c_void_p), ("m", C.c_int64), ("n", C.c_int64), ("lda", C.c_int64)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -66,6 +70,7 @@ def lib():
             "re_last_stage_ms": ([vp, vp], i32),
             "re_rank_estimate": ([vp, vp, i32, i64, i64, i64, dbl, C.POINTER(ReSketch), u64, C.POINTER(i32), vp,
                                   C.POINTER(i32), C.POINTER(C.c_uint32)], i32),
+            "re_rank_estimate_batched": ([vp, vp, i32, i32, dbl, C.POINTER(ReSketch), u64, vp, vp, vp], i32),
             "re_philox": ([vp, vp, u64, i64, vp], i32),
             "re_gauss_fill": ([vp, i32, i64, i64, u64, i32, i32, vp], i32),
             "re_srht_signs": ([vp, i64, u64, i32, vp], i32),
@@ -195,6 +200,43 @@ def rank_estimate(A: torch.Tensor, eps: float, *, k: int, l: int = 0, x: str = "
                                 C.byref(fl))
     _check(st, "re_rank_estimate")
     return r.value, sigma, {"r1": r1.value, "flags": fl.value, "k": int(k), "l": int(l) if l else 2 * int(k)}
+
+
+def make_blocks(blocks) -> "C.Array[ReBlock]":
+    """Descriptor table of a batched call from FP32 GPU matrices (row-major views
+    with unit column stride).  The table holds raw pointers: keep the tensors
+    alive while it is in use."""
+    arr = (ReBlock * len(blocks))()
+    for i, A in enumerate(blocks):
+        _check_matrix(A)
+        if A.dtype != torch.float32:
+            raise ValueError("batched blocks must be float32")
+        arr[i].A = A.data_ptr()
+        arr[i].m, arr[i].n = A.shape
+        arr[i].lda = A.stride(0)
+    return arr
+
+
+def rank_estimate_batched(blocks, eps: float, *, k: int, l: int = 0, seed: int = 0, handle: Handle | None = None):
+    """Algorithm 1 on many FP32 blocks in one graph launch (Gaussian X and Y).
+
+    ``blocks`` is a list of GPU tensors or a table from ``make_blocks``.
+    Returns (r int32[nb], sigma float64[nb, k], flags uint32[nb])."""
+    table = blocks if isinstance(blocks, C.Array) else make_blocks(blocks)
+    nb = len(table)
+    if nb == 0:
+        return np.zeros(0, np.int32), np.zeros((0, int(k))), np.zeros(0, np.uint32)
+    dev = torch.device("cuda", torch.cuda.current_device()) if handle is None else handle.device
+    h = handle or default_handle(dev)
+    sk = make_sketch(k, l, "gaussian", "gaussian", "native")
+    r = np.zeros(nb, dtype=np.int32)
+    sigma = np.zeros((nb, int(k)), dtype=np.float64)
+    fl = np.zeros(nb, dtype=np.uint32)
+    st = lib().re_rank_estimate_batched(h.bind(), C.cast(table, C.c_void_p), nb, RE_F32, float(eps), C.byref(sk),
+                                        int(seed) % 2**64, r.ctypes.data_as(C.c_void_p),
+                                        sigma.ctypes.data_as(C.c_void_p), fl.ctypes.data_as(C.c_void_p))
+    _check(st, "re_rank_estimate_batched")
+    return r, sigma, fl
 
 
 # --- stage entry points ------------------------------------------------------------------------

@@ -2,8 +2,15 @@
 #include <math.h>
 #include <string.h>
 
-#include <new>
+#include <stdio.h>
+#include <stdlib.h>
 
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "batch.h"
 #include "common.h"
 
 #define RE_API extern "C" __attribute__((visibility("default")))
@@ -18,6 +25,11 @@ struct re_handle_s {
   bool prof = false;     // record stage events inside re_rank_estimate
   hipEvent_t ev[RE_NUM_STAGES + 1] = {};
   double stage_ms[RE_NUM_STAGES] = {};
+  // batched form: captured graph and autotuned tile shapes
+  hipStream_t cap = nullptr;
+  hipGraphExec_t bexec = nullptr;
+  std::string bkey;
+  std::map<std::string, std::pair<int, int>> tuned;  // shape key -> (waves, grid)
 };
 
 namespace re {
@@ -92,7 +104,7 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
   if (!A || !sk) return RE_ERR_INVALID_ARG;
   if (dt != RE_F64 && dt != RE_F32) return RE_ERR_INVALID_ARG;
   if (m < 1 || n < 1 || lda < n) return RE_ERR_INVALID_ARG;
-  if (((uintptr_t)A) % 16 != 0) return RE_ERR_INVALID_ARG;
+  if (((uintptr_t)A) % (dt == RE_F64 ? 8 : 4) != 0) return RE_ERR_INVALID_ARG;
   if ((sk->x_kind != RE_GAUSSIAN && sk->x_kind != RE_SRHT) || (sk->y_kind != RE_GAUSSIAN && sk->y_kind != RE_SRHT))
     return RE_ERR_INVALID_ARG;
   if (sk->prec < RE_PREC_NATIVE || sk->prec > RE_PREC_AUTO) return RE_ERR_INVALID_ARG;
@@ -114,7 +126,7 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
 
 // Workspace plan of one estimate.
 struct Plan {
-  size_t xbits, ybits, xsel, ysel, selscr, X, Y, B, C, svd, sigma, info, out3, stats, total;
+  size_t xbits, ybits, xsel, ysel, selscr, X, Y, B, C, svd, sigma, info, out3, stats, gdesc, ydesc, queue, total;
 };
 
 Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
@@ -137,11 +149,20 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   p.info = c.take(16);
   p.out3 = c.take(16);
   p.stats = c.take(32);
+  p.gdesc = c.take(sizeof(GemmDesc));
+  p.ydesc = c.take(sizeof(YDesc));
+  p.queue = c.take(16);
   p.total = c.off;
   return p;
 }
 
 char* at(re_handle h, size_t off) { return (char*)h->ws + off; }
+
+void drop_graph(re_handle h) {
+  if (h->bexec) (void)hipGraphExecDestroy(h->bexec);
+  h->bexec = nullptr;
+  h->bkey.clear();
+}
 
 void mark(re_handle h, int i) {
   if (h->prof) (void)hipEventRecord(h->ev[i], h->stream);
@@ -169,8 +190,10 @@ re_status run_x(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m
   const int fx = x_fmt(dt);
   RE_TRY(launch_gauss_fill(s, fx, n, rs.k, seed, kXGauss, 0, X));
   mark(h, RE_STAGE_AX);
-  const int t = dt == RE_F64 ? 0 : 1;
-  return launch_gemm_f64acc(s, m, rs.k, n, A, t, lda, X, t, rs.k, B, t, rs.k);
+  if (dt == RE_F32)  // FP32: the matrix-core contraction shared with the batched form
+    return launch_gemm_f32_single(s, (const float*)A, m, n, lda, (const float*)X, rs.k, (float*)B,
+                                  (GemmDesc*)at(h, p.gdesc), (unsigned*)at(h, p.queue));
+  return launch_gemm_f64acc(s, m, rs.k, n, A, 0, lda, X, 0, rs.k, B, 0, rs.k);
 }
 
 // Algorithm 1 steps 5-6: draw Y (RE_STAGE_Y_DRAW), form C = Y B (RE_STAGE_YB).
@@ -189,8 +212,9 @@ re_status run_y(re_handle h, const Plan& p, void* B, int32_t bdt, int64_t m, con
   void* Y = at(h, p.Y);
   RE_TRY(launch_gauss_fill(s, fy, rs.l, m, seed, kYGauss, 1, Y));
   mark(h, RE_STAGE_YB);
-  const int t = bdt == RE_F64 ? 0 : 1;
-  return launch_gemm_f64acc(s, rs.l, rs.k, m, Y, t, m, B, t, rs.k, C, 0, rs.k);
+  if (bdt == RE_F32)  // the batched form's kernel, so one block of a batch matches a single call
+    return launch_ygemm_single(s, (const float*)B, m, rs.k, (const float*)Y, m, rs.l, C, (YDesc*)at(h, p.ydesc));
+  return launch_gemm_f64acc(s, rs.l, rs.k, m, Y, 0, m, B, 0, rs.k, C, 0, rs.k);
 }
 
 }  // namespace
@@ -230,6 +254,8 @@ RE_API re_status re_destroy(re_handle h) {
   if (h->stream || h->ws) (void)hipStreamSynchronize(h->stream);
   for (int i = 0; i <= RE_NUM_STAGES; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  drop_graph(h);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   if (h->ws) (void)hipFree(h->ws);
   if (h->host) (void)hipHostFree(h->host);
   delete h;
@@ -350,6 +376,322 @@ RE_API re_status re_rank_estimate(re_handle h, const void* A, int32_t dt, int64_
   if (r1_out) *r1_out = r1_from_k((int32_t)rs.k);
   if (flags_out) *flags_out = (uint32_t)o3[1] | extra;
   return RE_OK;
+}
+
+namespace re {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Batched form.  Device workspace: [descriptor region | results region |
+// sketches and intermediates]; the descriptor region is a byte image of the
+// host staging area and is refreshed by one copy before every graph launch,
+// the results region comes back by one copy captured in the graph.
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+  // descriptor region (offsets from its start; same in host staging)
+  size_t hdr, gdesc, ydesc, sdesc, cptr, dptr, eptr, lv, kv, desc_bytes;
+  // results region (offsets from its start)
+  size_t out3, sigma, res_bytes;
+  // the rest (offsets from the workspace start)
+  size_t desc0, res0, X, Y, B, C, d, e, info, queue, total;
+};
+
+BatchPlan batch_plan(int nb, int64_t k, int64_t l, int64_t nmax, int64_t mmax, int64_t brows_total) {
+  BatchPlan p{};
+  Carve a;
+  p.hdr = a.take(sizeof(BatchHeader));
+  p.gdesc = a.take((size_t)nb * sizeof(GemmDesc));
+  p.ydesc = a.take((size_t)nb * sizeof(YDesc));
+  p.sdesc = a.take((size_t)nb * sizeof(SvDesc));
+  p.cptr = a.take((size_t)nb * 8);
+  p.dptr = a.take((size_t)nb * 8);
+  p.eptr = a.take((size_t)nb * 8);
+  p.lv = a.take((size_t)nb * 4);
+  p.kv = a.take((size_t)nb * 4);
+  p.desc_bytes = a.off;
+  Carve r;
+  p.out3 = r.take((size_t)nb * 16);
+  p.sigma = r.take((size_t)nb * k * 8);
+  p.res_bytes = r.off;
+  Carve c;
+  p.desc0 = c.take(p.desc_bytes);
+  p.res0 = c.take(p.res_bytes);
+  p.X = c.take((size_t)nmax * k * 4);
+  p.Y = c.take((size_t)l * mmax * 4);
+  p.B = c.take((size_t)brows_total * k * 4);  // block b at a 256-byte aligned row offset
+  p.C = c.take((size_t)nb * l * k * 8);
+  p.d = c.take((size_t)nb * k * 8);
+  p.e = c.take((size_t)nb * k * 8);
+  p.info = c.take((size_t)nb * 4);
+  p.queue = c.take(16);
+  p.total = c.off;
+  return p;
+}
+
+int device_cus(int dev) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  return cus;
+}
+
+// Autotuner cache file: one JSON object, one "key": [waves, grid] pair per line.
+void load_tune_cache(re_handle h) {
+  const char* path = getenv("RANKEST_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (fgets(line, sizeof(line), f)) {
+    char key[256];
+    int w = 0, g = 0;
+    if (sscanf(line, " \"%255[^\"]\" : [ %d , %d ]", key, &w, &g) == 3 && (w == 4 || w == 8) && g > 0)
+      h->tuned[key] = {w, g};
+  }
+  fclose(f);
+}
+
+void save_tune_cache(re_handle h) {
+  const char* path = getenv("RANKEST_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : h->tuned)
+    fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.first, kv.second.second,
+            ++i < h->tuned.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+}
+
+// Fills the host image of the descriptor region for tile height 32 * waves;
+// returns the total number of work items.
+int64_t fill_batch_desc(char* img, const BatchPlan& p, char* ws, const re_block* blocks, int nb, int64_t k, int64_t l,
+                        double eps, uint64_t seed, int waves) {
+  BatchHeader* hd = (BatchHeader*)(img + p.hdr);
+  hd->seed = seed;
+  GemmDesc* gd = (GemmDesc*)(img + p.gdesc);
+  YDesc* yd = (YDesc*)(img + p.ydesc);
+  SvDesc* sd = (SvDesc*)(img + p.sdesc);
+  const double** cp = (const double**)(img + p.cptr);
+  double** dp = (double**)(img + p.dptr);
+  double** ep = (double**)(img + p.eptr);
+  int32_t* lv = (int32_t*)(img + p.lv);
+  int32_t* kv = (int32_t*)(img + p.kv);
+  char* res = ws + p.res0;
+  const int32_t r1 = r1_from_k((int32_t)k);
+  const double scale = 1.0 / sqrt((double)k * (double)l);
+  int64_t item = 0, brow = 0;
+  for (int b = 0; b < nb; ++b) {
+    const re_block& bl = blocks[b];
+    float* Bb = (float*)(ws + p.B) + brow * k;
+    double* Cb = (double*)(ws + p.C) + (size_t)b * l * k;
+    double* db = (double*)(ws + p.d) + (size_t)b * k;
+    double* eb = (double*)(ws + p.e) + (size_t)b * k;
+    gd[b].A = (const float*)bl.A;
+    gd[b].B = Bb;
+    gd[b].m = bl.m;
+    gd[b].n = bl.n;
+    gd[b].lda = bl.lda;
+    gd[b].ldb = k;
+    gd[b].item0 = item;
+    gd[b].ncc = gemm_col_chunks(k);
+    item += gemm_items(bl.m, k, waves);
+    yd[b].B = Bb;
+    yd[b].C = Cb;
+    yd[b].m = bl.m;
+    yd[b].ldb = k;
+    cp[b] = Cb;
+    dp[b] = db;
+    ep[b] = eb;
+    lv[b] = (int32_t)l;
+    kv[b] = (int32_t)k;
+    sd[b].d = db;
+    sd[b].e = eb;
+    sd[b].sigma = (double*)(res + p.sigma) + (size_t)b * k;
+    sd[b].info = (const int32_t*)(ws + p.info) + b;
+    sd[b].out3 = (int32_t*)(res + p.out3) + 4 * b;
+    sd[b].k = (int32_t)k;
+    sd[b].r1 = r1;
+    sd[b].scale = scale;
+    sd[b].eps = eps;
+    brow += (bl.m + 63) / 64 * 64;
+  }
+  return item;
+}
+
+// The captured sequence: master sketches, persistent A X, batched Y B, small
+// SVDs, counts, results to the host.  With profiling on, the same sequence is
+// issued directly on the stream with stage events between the launches.
+re_status enqueue_batch(re_handle h, hipStream_t s, const BatchPlan& p, int nb, int64_t k, int64_t l, int64_t nmax,
+                        int64_t mmax, int64_t total, int waves, int grid, void* host_res) {
+  char* ws = (char*)h->ws;
+  char* dsc = ws + p.desc0;
+  float* X = (float*)(ws + p.X);
+  float* Y = (float*)(ws + p.Y);
+  auto ev = [&](int i) -> re_status {
+    if (h->prof) RE_TRY_HIP(hipEventRecord(h->ev[i], s));
+    return RE_OK;
+  };
+  RE_TRY(ev(RE_STAGE_X_DRAW));
+  RE_TRY(launch_gauss_master(s, (const BatchHeader*)(dsc + p.hdr), nmax, k, l, mmax, X, Y));
+  RE_TRY(ev(RE_STAGE_AX));
+  RE_TRY(launch_gemm_f32_persistent(s, (const GemmDesc*)(dsc + p.gdesc), nb, X, k, total, (unsigned*)(ws + p.queue),
+                                    waves, grid));
+  RE_TRY(ev(RE_STAGE_Y_DRAW));
+  RE_TRY(ev(RE_STAGE_YB));
+  RE_TRY(launch_ygemm_batched(s, (const YDesc*)(dsc + p.ydesc), nb, Y, mmax, l, k));
+  RE_TRY(ev(RE_STAGE_SVD));
+  RE_TRY(launch_bidiag_batched(s, (const double* const*)(dsc + p.cptr), (double* const*)(dsc + p.dptr),
+                               (double* const*)(dsc + p.eptr), (const int32_t*)(dsc + p.lv),
+                               (const int32_t*)(dsc + p.kv), (int32_t*)(ws + p.info), nb, l, k));
+  RE_TRY(launch_sv_count_batched(s, (const SvDesc*)(dsc + p.sdesc), nb, k));
+  RE_TRY(ev(RE_STAGE_RANK));
+  RE_TRY_HIP(hipMemcpyAsync(host_res, ws + p.res0, p.res_bytes, hipMemcpyDeviceToHost, s));
+  RE_TRY(ev(RE_NUM_STAGES));
+  return RE_OK;
+}
+
+}  // namespace
+}  // namespace re
+
+RE_API re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, int32_t nblocks, int32_t dt, double eps,
+                                          const re_sketch* sk, uint64_t seed, int32_t* r_out, double* sigma_out,
+                                          uint32_t* flags_out) {
+  if (!h || !sk || nblocks < 0 || (nblocks > 0 && (!blocks || !r_out || !sigma_out))) return RE_ERR_INVALID_ARG;
+  if (!(eps > 0.0 && eps < 1.0)) return RE_ERR_INVALID_ARG;
+  if (dt != RE_F64 && dt != RE_F32) return RE_ERR_INVALID_ARG;
+  if ((sk->x_kind != RE_GAUSSIAN && sk->x_kind != RE_SRHT) || (sk->y_kind != RE_GAUSSIAN && sk->y_kind != RE_SRHT) ||
+      sk->prec < RE_PREC_NATIVE || sk->prec > RE_PREC_AUTO)
+    return RE_ERR_INVALID_ARG;
+  if (dt != RE_F32 || sk->x_kind != RE_GAUSSIAN || sk->y_kind != RE_GAUSSIAN || sk->prec != RE_PREC_NATIVE)
+    return RE_ERR_UNSUPPORTED;
+  const int64_t k = sk->k, l = sk->l == 0 ? 2 * (int64_t)sk->k : sk->l;
+  if (k < 1 || l < k || k > 4096) return RE_ERR_INVALID_ARG;
+  if (nblocks == 0) return RE_OK;
+  if (batched_svd_lds_bytes(l, k) > 156 * 1024) return RE_ERR_UNSUPPORTED;
+  int64_t nmax = 0, mmax = 0, brows = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    const re_block& bl = blocks[b];
+    if (!bl.A || bl.m < l || bl.n < k || bl.lda < bl.n || ((uintptr_t)bl.A) % 4 != 0) return RE_ERR_INVALID_ARG;
+    if (bl.m > (int64_t)INT32_MAX || bl.n > (int64_t)INT32_MAX) return RE_ERR_INVALID_ARG;
+    nmax = bl.n > nmax ? bl.n : nmax;
+    mmax = bl.m > mmax ? bl.m : mmax;
+    brows += (bl.m + 63) / 64 * 64;
+  }
+  if (gemm_items(brows, k, 4) >= (int64_t)INT32_MAX) return RE_ERR_INVALID_ARG;
+  const BatchPlan p = batch_plan(nblocks, k, l, nmax, mmax, brows);
+  const void* old_ws = h->ws;
+  RE_TRY(ensure_ws(h, p.total));
+  RE_TRY(ensure_host(h, p.desc_bytes + p.res_bytes));
+  if (h->ws != old_ws) drop_graph(h);
+  char* img = (char*)h->host;
+  char* host_res = img + p.desc_bytes;
+  char* ws = (char*)h->ws;
+  hipStream_t s = h->stream;
+  if (!h->cap) {
+    RE_TRY_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    load_tune_cache(h);
+  }
+
+  // autotune the persistent contraction for this size bucket
+  const int cus = device_cus(h->device);
+  const int64_t items4 = gemm_items(brows, k, 4);
+  int lg = 0;
+  while ((int64_t(1) << lg) < items4) ++lg;
+  char key[128];
+  snprintf(key, sizeof(key), "gfx950:f32:k%lld:items2^%d", (long long)k, lg);
+  // RANKEST_BATCH_TILE="waves:grid per CU" pins the tile shape (tuning sweeps, tests)
+  if (const char* pin = getenv("RANKEST_BATCH_TILE")) {
+    int w = 0, gm = 0;
+    if (sscanf(pin, "%d:%d", &w, &gm) != 2 || (w != 4 && w != 8) || gm < 1 || gm > 64) return RE_ERR_INVALID_ARG;
+    h->tuned[key] = {w, gm * cus};
+  }
+  auto it = h->tuned.find(key);
+  if (it == h->tuned.end()) {
+    const int cand[4][2] = {{4, 2}, {4, 4}, {8, 1}, {8, 2}};
+    hipEvent_t e0, e1;
+    RE_TRY_HIP(hipEventCreate(&e0));
+    RE_TRY_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    std::pair<int, int> pick{4, 2 * cus};
+    for (const auto& c : cand) {
+      const int w = c[0];
+      const int64_t tot = fill_batch_desc(img, p, ws, blocks, nblocks, k, l, eps, seed, w);
+      const int g = (int)(tot < (int64_t)c[1] * cus ? tot : (int64_t)c[1] * cus);
+      RE_TRY_HIP(hipMemcpyAsync(ws + p.desc0, img, p.desc_bytes, hipMemcpyHostToDevice, s));
+      RE_TRY(launch_gauss_master(s, (const BatchHeader*)(ws + p.desc0 + p.hdr), nmax, k, l, mmax, (float*)(ws + p.X),
+                                 (float*)(ws + p.Y)));
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        RE_TRY_HIP(hipEventRecord(e0, s));
+        RE_TRY(launch_gemm_f32_persistent(s, (const GemmDesc*)(ws + p.desc0 + p.gdesc), nblocks, (const float*)(ws + p.X),
+                                          k, tot, (unsigned*)(ws + p.queue), w, g));
+        RE_TRY_HIP(hipEventRecord(e1, s));
+        RE_TRY_HIP(hipEventSynchronize(e1));
+        RE_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+      }
+      if (ms < best) {
+        best = ms;
+        pick = {w, c[1] * cus};
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->tuned[key] = pick;
+    save_tune_cache(h);
+    it = h->tuned.find(key);
+  }
+  const int waves = it->second.first;
+  const int64_t total = fill_batch_desc(img, p, ws, blocks, nblocks, k, l, eps, seed, waves);
+  const int grid = (int)(total < it->second.second ? total : it->second.second);
+
+  // (re)capture when anything baked into the graph changed
+  char gkey[256];
+  snprintf(gkey, sizeof(gkey), "%p %p %d %lld %lld %lld %lld %lld %lld %d %d", (void*)ws, (void*)host_res, nblocks,
+           (long long)k, (long long)l, (long long)nmax, (long long)mmax, (long long)brows, (long long)total, waves, grid);
+  if (h->prof) {  // eager issue of the same launches, stage events in between
+    RE_TRY_HIP(hipMemcpyAsync(ws + p.desc0, img, p.desc_bytes, hipMemcpyHostToDevice, s));
+    RE_TRY(enqueue_batch(h, s, p, nblocks, k, l, nmax, mmax, total, waves, grid, host_res));
+  } else if (!h->bexec || h->bkey != gkey) {
+    drop_graph(h);
+    RE_TRY_HIP(hipStreamSynchronize(s));
+    RE_TRY_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
+    const re_status st = enqueue_batch(h, h->cap, p, nblocks, k, l, nmax, mmax, total, waves, grid, host_res);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(h->cap, &g);
+    if (st != RE_OK || ce != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return st != RE_OK ? st : RE_ERR_HIP;
+    }
+    const hipError_t ie = hipGraphInstantiate(&h->bexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      h->bexec = nullptr;
+      return RE_ERR_HIP;
+    }
+    h->bkey = gkey;
+  }
+  if (!h->prof) {
+    RE_TRY_HIP(hipMemcpyAsync(ws + p.desc0, img, p.desc_bytes, hipMemcpyHostToDevice, s));
+    RE_TRY_HIP(hipGraphLaunch(h->bexec, s));
+  }
+  RE_TRY_HIP(hipStreamSynchronize(s));
+  if (h->prof) {
+    for (int i = 0; i < RE_NUM_STAGES; ++i) {
+      float ms = 0.f;
+      h->stage_ms[i] = hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess ? (double)ms : -1.0;
+    }
+  }
+  re_status worst = RE_OK;
+  for (int b = 0; b < nblocks; ++b) {
+    const int32_t* o3 = (const int32_t*)(host_res + p.out3) + 4 * b;
+    r_out[b] = o3[2] == 0 ? o3[0] : -1;
+    if (flags_out) flags_out[b] = (uint32_t)o3[1];
+    if (o3[2] != 0 && worst == RE_OK) worst = (re_status)o3[2];
+  }
+  memcpy(sigma_out, host_res + p.sigma, (size_t)nblocks * k * 8);
+  return worst;
 }
 
 RE_API re_status re_philox(re_handle h, const uint64_t* ctr, uint64_t seed, int64_t count, uint64_t* out) {

@@ -1,0 +1,280 @@
+// Many independent sketches at once (the batched form of Algorithm 1): the
+// FP32 Gaussian contraction B_b = A_b X[:n_b] for every block on the matrix
+// cores in one persistent launch, then C_b = Y[:, :m_b] B_b, the small SVDs
+// and the counts, one workgroup per block.  X (n_max x k) and Y (l x m_max)
+// are master sketches: counter-indexed, so block b's leading rows / columns
+// are exactly the sketch a single-matrix call with the same seed draws.
+#include "common.h"
+#include "batch.h"
+
+namespace re {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kBK = 16;      // K per step
+constexpr int kApad = 17;    // LDS row pitch of the A tile (floats)
+
+// Block of a work item: the last b with desc[b].item0 <= item.
+__device__ __forceinline__ int find_block(const GemmDesc* __restrict__ desc, int nblk, int64_t item) {
+  int lo = 0, hi = nblk - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].item0 <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Persistent FP32 MFMA contraction.  A workgroup of WAVES wavefronts takes
+// items from an atomic queue; an item is 32*WAVES rows of one block by up to
+// 32*NT columns.  Wavefront w owns 32 rows and NT 32x32 accumulator tiles
+// (v_mfma_f32_32x32x2_f32: lane l holds row / column l % 32 and K index l / 32
+// of the operands; accumulator q of lane l is row 8 (q/4) + 4 (l/32) + q%4,
+// column l % 32).
+template <int WAVES, int NT>
+__global__ void __launch_bounds__(64 * WAVES) k_gemm_f32_persistent(const GemmDesc* __restrict__ desc, int nblk,
+                                                                    const float* __restrict__ X, int64_t k,
+                                                                    int64_t total, unsigned* __restrict__ queue) {
+  constexpr int BM = 32 * WAVES, BN = 32 * NT, NTH = 64 * WAVES;
+  __shared__ float sA[2][BM * kApad];
+  __shared__ float sX[2][kBK * BN];
+  __shared__ int64_t s_item;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (;;) {
+    if (tid == 0) s_item = (int64_t)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int64_t item = s_item;
+    __syncthreads();
+    if (item >= total) break;
+    const int b = find_block(desc, nblk, item);
+    const GemmDesc d = desc[b];
+    const int64_t local = item - d.item0;
+    const int64_t rt = local / d.ncc, cc = local - rt * d.ncc;
+    const int64_t row0 = rt * BM, col0 = cc * BN;
+    const float* __restrict__ A = d.A;
+    const int64_t m = d.m, n = d.n, lda = d.lda;
+
+    float ra[BM * kBK / NTH];
+    float rx[kBK * BN / NTH];
+    auto load = [&](int64_t k0) {
+      // A: BM x 16, each thread a run of consecutive K values of one row
+      constexpr int PER = BM * kBK / NTH;  // 8
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid * PER + q;
+        const int r = e / kBK, kk = e % kBK;
+        const int64_t gr = row0 + r, gk = k0 + kk;
+        ra[q] = (gr < m && gk < n) ? A[gr * lda + gk] : 0.0f;
+      }
+      constexpr int PX = kBK * BN / NTH;
+#pragma unroll
+      for (int q = 0; q < PX; ++q) {
+        const int e = tid * PX + q;
+        const int kr = e / BN, c = e % BN;
+        const int64_t gk = k0 + kr, gc = col0 + c;
+        rx[q] = (gk < n && gc < k) ? X[gk * k + gc] : 0.0f;
+      }
+    };
+    auto store = [&](int buf) {
+      constexpr int PER = BM * kBK / NTH;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid * PER + q;
+        sA[buf][(e / kBK) * kApad + (e % kBK)] = ra[q];
+      }
+      constexpr int PX = kBK * BN / NTH;
+#pragma unroll
+      for (int q = 0; q < PX; ++q) sX[buf][tid * PX + q] = rx[q];
+    };
+    f32x16 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[t][q] = 0.0f;
+    const int64_t nsteps = (n + kBK - 1) / kBK;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int64_t st = 0; st < nsteps; ++st) {
+      const int buf = st & 1;
+      if (st + 1 < nsteps) load((st + 1) * kBK);
+#pragma unroll
+      for (int kk = 0; kk < kBK; kk += 2) {
+        const float a = sA[buf][(32 * wave + (lane & 31)) * kApad + kk + (lane >> 5)];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const float xb = sX[buf][(kk + (lane >> 5)) * BN + 32 * t + (lane & 31)];
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, xb, acc[t], 0, 0, 0);
+        }
+      }
+      if (st + 1 < nsteps) store(buf ^ 1);
+      __syncthreads();
+    }
+    float* __restrict__ Bo = d.B;
+    const int64_t ldb = d.ldb;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int64_t r = row0 + 32 * wave + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        const int64_t c = col0 + 32 * t + (lane & 31);
+        if (r < m && c < k) Bo[r * ldb + c] = acc[t][q];
+      }
+  }
+}
+
+__global__ void k_zero_u32(unsigned* p) {
+  if (threadIdx.x == 0) p[0] = 0u;
+}
+
+// Writes one descriptor passed by value (stream-ordered, so a host buffer is
+// never read after the call returns).
+template <typename D>
+__global__ void k_put_desc(D v, D* out) {
+  if (threadIdx.x == 0) *out = v;
+}
+
+// Master sketches of a batched call, seed read from the device header so the
+// captured graph serves every seed: X[i][j] (n_max x k) from counter (i, j)
+// of the X stream and Y[i][j] (l x m_max) from counter (j, i) of the Y
+// stream, FP32, the same values the single-matrix draw produces.
+__global__ void k_gauss_master(const BatchHeader* __restrict__ hdr, int64_t nmax, int64_t k, int64_t l, int64_t mmax,
+                               float* __restrict__ X, float* __restrict__ Y) {
+  const uint64_t seed = hdr->seed;
+  const int64_t nx = nmax * k, total = nx + l * mmax;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nx) {
+      const int64_t i = e / k, j = e - i * k;
+      X[e] = (float)gauss01(i, j, kXGauss, seed);
+    } else {
+      const int64_t f = e - nx, i = f / mmax, j = f - i * mmax;
+      Y[f] = (float)gauss01(j, i, kYGauss, seed);
+    }
+  }
+}
+
+// C_b (l x k, FP64) = Y[:, :m_b] (FP32, leading dimension ldy) B_b (m_b x k,
+// FP32), FP64 accumulation; one workgroup per (block, 64-row slice of C_b).
+constexpr int kYM = 64, kYN = 96, kYK = 16;
+__global__ void __launch_bounds__(256) k_ygemm_batched(const YDesc* __restrict__ desc, const float* __restrict__ Y,
+                                                       int64_t ldy, int64_t l, int64_t k) {
+  __shared__ double sy[kYK][kYM + 1];
+  __shared__ double sb[kYK][kYN + 1];
+  const YDesc d = desc[blockIdx.y];
+  const int64_t s0 = (int64_t)blockIdx.x * kYM;
+  if (s0 >= l) return;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;  // 16 x 16 threads, 4 x 6 outputs each
+  for (int64_t c0 = 0; c0 < k; c0 += kYN) {
+    double acc[4][6] = {};
+    for (int64_t i0 = 0; i0 < d.m; i0 += kYK) {
+      for (int e = threadIdx.x; e < kYM * kYK; e += 256) {
+        const int r = e / kYK, c = e % kYK;
+        const int64_t gs = s0 + r, gi = i0 + c;
+        sy[c][r] = (gs < l && gi < d.m) ? (double)Y[gs * ldy + gi] : 0.0;
+      }
+      for (int e = threadIdx.x; e < kYK * kYN; e += 256) {
+        const int r = e / kYN, c = e % kYN;
+        const int64_t gi = i0 + r, gc = c0 + c;
+        sb[r][c] = (gi < d.m && gc < k) ? (double)d.B[gi * d.ldb + gc] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kYK; ++kk) {
+        double a[4], bb[6];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = sy[kk][ty + 16 * i];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) bb[j] = sb[kk][tx + 16 * j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 6; ++j) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        const int64_t gs = s0 + ty + 16 * i, gc = c0 + tx + 16 * j;
+        if (gs < l && gc < k) d.C[gs * k + gc] = acc[i][j];
+      }
+  }
+}
+
+}  // namespace
+
+re_status launch_gemm_f32_persistent(hipStream_t s, const GemmDesc* desc, int nblk, const float* X, int64_t k,
+                                     int64_t total, unsigned* queue, int waves, int grid) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, queue);
+  const int nt = (int)(k >= 128 ? 4 : cdiv(k, 32));
+#define RE_GEMM_CASE(W, N)                                                                                   \
+  if (waves == W && nt == N) {                                                                               \
+    hipLaunchKernelGGL((k_gemm_f32_persistent<W, N>), dim3(grid), dim3(64 * W), 0, s, desc, nblk, X, k, total, \
+                       queue);                                                                               \
+    RE_TRY_HIP(hipGetLastError());                                                                           \
+    return RE_OK;                                                                                            \
+  }
+  RE_GEMM_CASE(4, 1) RE_GEMM_CASE(4, 2) RE_GEMM_CASE(4, 3) RE_GEMM_CASE(4, 4)
+  RE_GEMM_CASE(8, 1) RE_GEMM_CASE(8, 2) RE_GEMM_CASE(8, 3) RE_GEMM_CASE(8, 4)
+#undef RE_GEMM_CASE
+  return RE_ERR_INVALID_ARG;
+}
+
+re_status launch_gemm_f32_single(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t lda, const float* X,
+                                 int64_t k, float* B, GemmDesc* dscratch, unsigned* queue) {
+  GemmDesc d;
+  d.A = A;
+  d.B = B;
+  d.m = m;
+  d.n = n;
+  d.lda = lda;
+  d.ldb = k;
+  d.item0 = 0;
+  d.ncc = gemm_col_chunks(k);
+  hipLaunchKernelGGL(k_put_desc<GemmDesc>, dim3(1), dim3(64), 0, s, d, dscratch);
+  const int64_t total = gemm_items(m, k, 4);
+  const int64_t g = total < 2048 ? total : 2048;
+  return launch_gemm_f32_persistent(s, dscratch, 1, X, k, total, queue, 4, (int)g);
+}
+
+re_status launch_ygemm_single(hipStream_t s, const float* B, int64_t m, int64_t k, const float* Y, int64_t ldy,
+                              int64_t l, double* C, YDesc* dscratch) {
+  YDesc d;
+  d.B = B;
+  d.C = C;
+  d.m = m;
+  d.ldb = k;
+  hipLaunchKernelGGL(k_put_desc<YDesc>, dim3(1), dim3(64), 0, s, d, dscratch);
+  return launch_ygemm_batched(s, dscratch, 1, Y, ldy, l, k);
+}
+
+re_status launch_gauss_master(hipStream_t s, const BatchHeader* hdr, int64_t nmax, int64_t k, int64_t l, int64_t mmax,
+                              float* X, float* Y) {
+  const int64_t total = nmax * k + l * mmax;
+  if (total <= 0) return RE_OK;
+  const int64_t g = cdiv(total, 256) < 4096 ? cdiv(total, 256) : 4096;
+  hipLaunchKernelGGL(k_gauss_master, dim3((unsigned)g), dim3(256), 0, s, hdr, nmax, k, l, mmax, X, Y);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
+
+int64_t gemm_items(int64_t m, int64_t k, int waves) {
+  const int64_t bm = 32 * waves, bn = k >= 128 ? 128 : 32 * cdiv(k, 32);
+  return cdiv(m, bm) * cdiv(k, bn);
+}
+
+int gemm_col_chunks(int64_t k) { return (int)cdiv(k, k >= 128 ? 128 : 32 * cdiv(k, 32)); }
+
+re_status launch_ygemm_batched(hipStream_t s, const YDesc* desc, int nblk, const float* Y, int64_t ldy, int64_t l,
+                               int64_t k) {
+  if (nblk <= 0) return RE_OK;
+  hipLaunchKernelGGL(k_ygemm_batched, dim3((unsigned)cdiv(l, kYM), (unsigned)nblk), dim3(256), 0, s, desc, Y, ldy, l,
+                     k);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
+
+}  // namespace re

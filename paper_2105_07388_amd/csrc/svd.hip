@@ -15,6 +15,7 @@
 #include <stdlib.h>
 
 #include "common.h"
+#include "batch.h"
 
 namespace re {
 
@@ -703,6 +704,89 @@ SvdLayout svd_layout(int64_t l, int64_t k) {
   return s;
 }
 
+// Batched singular values of bidiagonals (problem = blockIdx.y) and counts
+// (problem = blockIdx.x); same arithmetic as k_bidiag_sv and k_count.
+__global__ void __launch_bounds__(256) k_bidiag_sv_batched(const SvDesc* __restrict__ desc) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const SvDesc dsc = desc[blockIdx.y];
+  const int64_t k = dsc.k;
+  const int64_t waves = blockDim.x / 64;
+  if ((int64_t)blockIdx.x * waves >= k) return;
+  double* b = reinterpret_cast<double*>(smem_raw);
+  const int nb = (int)(2 * k - 1);
+  double* bb = b + nb;
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+    b[j] = (j & 1) ? dsc.e[j >> 1] : dsc.d[j >> 1];
+    bb[j] = b[j] * b[j];
+  }
+  __syncthreads();
+  double bound = 0.0, maxb2 = 0.0;
+  for (int j = 0; j < nb; ++j) {
+    const double left = j > 0 ? fabs(b[j - 1]) : 0.0;
+    bound = fmax(bound, fabs(b[j]) + left);
+    maxb2 = fmax(maxb2, bb[j]);
+  }
+  bound = fmax(bound, nb > 0 ? fabs(b[nb - 1]) : 0.0);
+  const bool all_zero = !(bound > 0.0);
+  bound = bound * (1.0 + 1e-14) + 1e-300;
+  const double pivmin = 0x1.0p-1022 * fmax(1.0, maxb2);
+  const int lane = threadIdx.x & 63;
+  for (int64_t jj = blockIdx.x * waves + (threadIdx.x >> 6); jj < k; jj += (int64_t)gridDim.x * waves) {
+    const int want = (int)(k - 1 - jj);
+    double lo = 0.0, hi = bound;
+    for (int it = 0; it < 9; ++it) {
+      const double x = lo + (hi - lo) * (double)(lane + 1) * (1.0 / 65.0);
+      const int cnt = count_below(bb, nb, x, pivmin);
+      const uint64_t le = __ballot(cnt <= want);
+      const int nle = __popcll(le);
+      const double nlo = nle > 0 ? lo + (hi - lo) * (double)nle * (1.0 / 65.0) : lo;
+      const double nhi = nle < 64 ? lo + (hi - lo) * (double)(nle + 1) * (1.0 / 65.0) : hi;
+      lo = nlo;
+      hi = nhi;
+    }
+    if (lane == 0) dsc.sigma[jj] = all_zero ? 0.0 : 0.5 * (lo + hi) * dsc.scale;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_count_batched(const SvDesc* __restrict__ desc) {
+  const SvDesc d = desc[blockIdx.x];
+  __shared__ int s_bad, s_cnt;
+  if (threadIdx.x == 0) {
+    s_bad = 0;
+    s_cnt = 0;
+  }
+  __syncthreads();
+  const int64_t k = d.k;
+  const double s1 = k > 0 ? d.sigma[0] : 0.0;
+  const double tau = d.eps * s1;
+  const int64_t lim = d.r1 < k ? d.r1 : k;
+  int bad = 0, cnt = 0;
+  for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
+    const double v = d.sigma[i];
+    bad |= !isfinite(v);
+    cnt += (i < lim && v > tau);
+  }
+  if (bad) atomicOr(&s_bad, 1);
+  atomicAdd(&s_cnt, cnt);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int32_t st = d.info ? d.info[0] : 0;
+  if (st == 0 && s_bad) st = RE_ERR_NONFINITE;
+  uint32_t flags = 0;
+  int32_t r = 0;
+  if (st == 0) {
+    if (k == 0 || s1 == 0.0) {
+      flags |= RE_FLAG_ZERO;
+    } else {
+      r = s_cnt;
+      if (r == d.r1) flags |= RE_FLAG_NOT_CONVERGED;
+    }
+  }
+  d.out3[0] = r;
+  d.out3[1] = (int32_t)flags;
+  d.out3[2] = st;
+}
+
 }  // namespace
 
 size_t svd_scratch_bytes(int64_t l, int64_t k) { return svd_layout(l, k).total; }
@@ -777,6 +861,41 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
   const int waves_per_block = 4;
   const int blocks = (int)cdiv(k, waves_per_block);
   hipLaunchKernelGGL(k_bidiag_sv, dim3(blocks), dim3(64 * waves_per_block), lds2, s, a.d, a.e, k, scale, info, sigma);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
+
+size_t batched_svd_lds_bytes(int64_t lmax, int64_t kmax) { return small_lds_bytes(lmax, kmax); }
+
+re_status launch_bidiag_batched(hipStream_t s, const double* const* C, double* const* d, double* const* e,
+                                const int32_t* l, const int32_t* k, int32_t* info, int nblk, int64_t lmax,
+                                int64_t kmax) {
+  if (nblk <= 0) return RE_OK;
+  const size_t bytes = small_lds_bytes(lmax, kmax);
+  if (bytes > kLdsBudget) return RE_ERR_UNSUPPORTED;
+  SmallBatch sb{};
+  sb.C = C;
+  sb.d = d;
+  sb.e = e;
+  sb.l = l;
+  sb.k = k;
+  sb.info = info;
+  sb.kp = (int)lds_stride(kmax);
+  if (bytes > 64 * 1024)
+    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag_1wg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  hipLaunchKernelGGL(k_bidiag_1wg, dim3((unsigned)nblk), dim3(kB2Threads), bytes, s, sb);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
+
+re_status launch_sv_count_batched(hipStream_t s, const SvDesc* desc, int nblk, int64_t kmax) {
+  if (nblk <= 0) return RE_OK;
+  const size_t lds2 = (size_t)(4 * kmax) * 8;
+  if (lds2 > 160 * 1024) return RE_ERR_UNSUPPORTED;
+  if (lds2 > 64 * 1024)
+    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag_sv_batched, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+  hipLaunchKernelGGL(k_bidiag_sv_batched, dim3((unsigned)cdiv(kmax, 4), (unsigned)nblk), dim3(256), lds2, s, desc);
+  hipLaunchKernelGGL(k_count_batched, dim3((unsigned)nblk), dim3(256), 0, s, desc);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
 }

@@ -131,3 +131,66 @@ def c3_spectrum(R: int = 1024, r: int = 200) -> np.ndarray:
 def c3_matrix(m: int = 32768, n: int = 8192, R: int = 1024, seed: int = 1003, device="cpu") -> torch.Tensor:
     return planted(m, n, c3_spectrum(R), seed, torch.float32, 0.0, device)
 
+
+
+# --- kernel blocks of a hierarchical matrix ----------------------------------------
+
+def kernel_block_params(nblocks: int, seed: int = 1004, size_lo: int = 256, size_hi: int = 4096,
+                        gap_lo: float = 0.08, gap_hi: float = 3.0) -> list[dict]:
+    """Shapes and cluster gaps of `nblocks` off-diagonal blocks: m, n uniform
+    integers in [size_lo, size_hi], the gap g log-uniform in [gap_lo, gap_hi],
+    one point seed per block.  Calibrated with full SVDs: at eps = 1e-6 the
+    rank is about 63 for 4096 x 4096 at g = 0.08, 37 for 256 x 256 at g = 0.1
+    and 6 at g = 3 for any size, so the ranks span about 6 to 63."""
+    rng = np.random.default_rng(seed)
+    m = rng.integers(size_lo, size_hi + 1, nblocks)
+    n = rng.integers(size_lo, size_hi + 1, nblocks)
+    g = np.exp(rng.uniform(np.log(gap_lo), np.log(gap_hi), nblocks))
+    ps = rng.integers(0, 2**62, nblocks)
+    return [dict(m=int(m[b]), n=int(n[b]), gap=float(g[b]), seed=int(ps[b])) for b in range(nblocks)]
+
+
+def kernel_block_points(p: dict) -> tuple[torch.Tensor, torch.Tensor]:
+    """FP32 target points (m x 2) uniform in [1+g, 2+g] x [0, 1] and source
+    points (n x 2) uniform in [0, 1]^2, drawn on the CPU."""
+    gen = torch.Generator(device="cpu")
+    gen.manual_seed(p["seed"])
+    t = torch.rand(p["m"], 2, generator=gen, dtype=torch.float32)
+    t[:, 0] += 1.0 + p["gap"]
+    s = torch.rand(p["n"], 2, generator=gen, dtype=torch.float32)
+    return t, s
+
+
+def kernel_block(p: dict, device="cpu", out: torch.Tensor | None = None) -> torch.Tensor:
+    """A[i, j] = 1 / |t_i - s_j|, evaluated in FP64 from the FP32 points (one
+    operation per kernel, so no fused multiply-add) and rounded once to FP32."""
+    t, s = kernel_block_points(p)
+    t = t.to(device=device, dtype=torch.float64)
+    s = s.to(device=device, dtype=torch.float64)
+    dx = t[:, 0:1] - s[:, 0].unsqueeze(0)
+    dy = t[:, 1:2] - s[:, 1].unsqueeze(0)
+    r2 = dx * dx
+    r2 += dy * dy
+    del dx, dy
+    A = (1.0 / torch.sqrt(r2)).to(torch.float32)
+    if out is None:
+        return A
+    out.copy_(A)
+    return out
+
+
+def kernel_blocks(nblocks: int, seed: int = 1004, device="cpu", **kw) -> tuple[torch.Tensor, list, list[dict]]:
+    """All blocks in one flat FP32 buffer, each block contiguous (lda = n) and
+    256-byte aligned.  Returns (buffer, list of m x n views, parameters)."""
+    params = kernel_block_params(nblocks, seed, **kw)
+    offs, off = [], 0
+    for p in params:
+        offs.append(off)
+        off += (p["m"] * p["n"] + 63) // 64 * 64
+    buf = torch.empty(max(off, 1), dtype=torch.float32, device=device)
+    views = []
+    for p, o in zip(params, offs):
+        v = buf[o:o + p["m"] * p["n"]].view(p["m"], p["n"])
+        kernel_block(p, device, out=v)
+        views.append(v)
+    return buf, views, params
