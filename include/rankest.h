@@ -142,7 +142,7 @@ re_status re_rank_estimate(re_handle h, const void* A_dev, int32_t dt, int64_t m
                            uint32_t* flags_out);
 
 /* One block of a batched call: caller-owned device matrix, m x n row-major
- * with leading dimension lda >= n (FP32, 4-byte aligned). */
+ * with leading dimension n <= lda < 2^23 (FP32, 4-byte aligned). */
 typedef struct {
   const void* A;
   int64_t m, n, lda;
@@ -159,9 +159,13 @@ typedef struct {
  * (block, row tile, column chunk) items; the Y B products, small SVDs and
  * counts run one workgroup per block.  The work is captured once into a HIP
  * graph (re-captured when the shapes or the workspace change) and the tile
- * shape of the persistent kernel is chosen by timing the candidates on the
- * first call for a shape (cached in the handle, and in the text file named by
- * RANKEST_AUTOTUNE_CACHE when that variable is set).
+ * shape of the persistent kernel (wavefronts per workgroup, K step, resident
+ * workgroups) is chosen by timing the candidates on the first call for a size
+ * bucket (cached in the handle, and in the JSON file named by
+ * RANKEST_AUTOTUNE_CACHE when that variable is set; RANKEST_BATCH_TILE =
+ * "waves:kstep:workgroups per CU" pins it).  With profiling on, the same
+ * launches are issued directly on the stream so that stage events separate
+ * them.
  *   blocks     host array of nblocks descriptors (k <= n_b, l <= m_b each)
  *   r_out      host, nblocks: rank estimates
  *   sigma_out  host, nblocks * k: estimates of block b at b * k

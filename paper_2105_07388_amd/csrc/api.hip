@@ -29,7 +29,10 @@ struct re_handle_s {
   hipStream_t cap = nullptr;
   hipGraphExec_t bexec = nullptr;
   std::string bkey;
-  std::map<std::string, std::pair<int, int>> tuned;  // shape key -> (waves, grid)
+  struct Tile {
+    int waves, bk, grid;
+  };
+  std::map<std::string, Tile> tuned;  // shape key -> persistent contraction tile
 };
 
 namespace re {
@@ -190,7 +193,7 @@ re_status run_x(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m
   const int fx = x_fmt(dt);
   RE_TRY(launch_gauss_fill(s, fx, n, rs.k, seed, kXGauss, 0, X));
   mark(h, RE_STAGE_AX);
-  if (dt == RE_F32)  // FP32: the matrix-core contraction shared with the batched form
+  if (dt == RE_F32 && lda < kMaxBatchLda)  // FP32: the matrix-core contraction shared with the batched form
     return launch_gemm_f32_single(s, (const float*)A, m, n, lda, (const float*)X, rs.k, (float*)B,
                                   (GemmDesc*)at(h, p.gdesc), (unsigned*)at(h, p.queue));
   return launch_gemm_f64acc(s, m, rs.k, n, A, 0, lda, X, 0, rs.k, B, 0, rs.k);
@@ -434,7 +437,7 @@ int device_cus(int dev) {
   return cus;
 }
 
-// Autotuner cache file: one JSON object, one "key": [waves, grid] pair per line.
+// Autotuner cache file: one JSON object, one "key": [waves, bk, grid] entry per line.
 void load_tune_cache(re_handle h) {
   const char* path = getenv("RANKEST_AUTOTUNE_CACHE");
   if (!path) return;
@@ -443,9 +446,10 @@ void load_tune_cache(re_handle h) {
   char line[512];
   while (fgets(line, sizeof(line), f)) {
     char key[256];
-    int w = 0, g = 0;
-    if (sscanf(line, " \"%255[^\"]\" : [ %d , %d ]", key, &w, &g) == 3 && (w == 4 || w == 8) && g > 0)
-      h->tuned[key] = {w, g};
+    int w = 0, bk = 0, g = 0;
+    if (sscanf(line, " \"%255[^\"]\" : [ %d , %d , %d ]", key, &w, &bk, &g) == 4 && (w == 4 || w == 8) &&
+        (bk == 16 || bk == 32) && g > 0)
+      h->tuned[key] = {w, bk, g};
   }
   fclose(f);
 }
@@ -458,7 +462,7 @@ void save_tune_cache(re_handle h) {
   fprintf(f, "{\n");
   size_t i = 0;
   for (const auto& kv : h->tuned)
-    fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.first, kv.second.second,
+    fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.waves, kv.second.bk, kv.second.grid,
             ++i < h->tuned.size() ? "," : "");
   fprintf(f, "}\n");
   fclose(f);
@@ -524,7 +528,7 @@ int64_t fill_batch_desc(char* img, const BatchPlan& p, char* ws, const re_block*
 // SVDs, counts, results to the host.  With profiling on, the same sequence is
 // issued directly on the stream with stage events between the launches.
 re_status enqueue_batch(re_handle h, hipStream_t s, const BatchPlan& p, int nb, int64_t k, int64_t l, int64_t nmax,
-                        int64_t mmax, int64_t total, int waves, int grid, void* host_res) {
+                        int64_t mmax, int64_t total, int waves, int grid, int bk, void* host_res) {
   char* ws = (char*)h->ws;
   char* dsc = ws + p.desc0;
   float* X = (float*)(ws + p.X);
@@ -537,7 +541,7 @@ re_status enqueue_batch(re_handle h, hipStream_t s, const BatchPlan& p, int nb, 
   RE_TRY(launch_gauss_master(s, (const BatchHeader*)(dsc + p.hdr), nmax, k, l, mmax, X, Y));
   RE_TRY(ev(RE_STAGE_AX));
   RE_TRY(launch_gemm_f32_persistent(s, (const GemmDesc*)(dsc + p.gdesc), nb, X, k, total, (unsigned*)(ws + p.queue),
-                                    waves, grid));
+                                    waves, grid, bk));
   RE_TRY(ev(RE_STAGE_Y_DRAW));
   RE_TRY(ev(RE_STAGE_YB));
   RE_TRY(launch_ygemm_batched(s, (const YDesc*)(dsc + p.ydesc), nb, Y, mmax, l, k));
@@ -573,7 +577,8 @@ RE_API re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, i
   int64_t nmax = 0, mmax = 0, brows = 0;
   for (int b = 0; b < nblocks; ++b) {
     const re_block& bl = blocks[b];
-    if (!bl.A || bl.m < l || bl.n < k || bl.lda < bl.n || ((uintptr_t)bl.A) % 4 != 0) return RE_ERR_INVALID_ARG;
+    if (!bl.A || bl.m < l || bl.n < k || bl.lda < bl.n || bl.lda >= kMaxBatchLda || ((uintptr_t)bl.A) % 4 != 0)
+      return RE_ERR_INVALID_ARG;
     if (bl.m > (int64_t)INT32_MAX || bl.n > (int64_t)INT32_MAX) return RE_ERR_INVALID_ARG;
     nmax = bl.n > nmax ? bl.n : nmax;
     mmax = bl.m > mmax ? bl.m : mmax;
@@ -601,24 +606,26 @@ RE_API re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, i
   while ((int64_t(1) << lg) < items4) ++lg;
   char key[128];
   snprintf(key, sizeof(key), "gfx950:f32:k%lld:items2^%d", (long long)k, lg);
-  // RANKEST_BATCH_TILE="waves:grid per CU" pins the tile shape (tuning sweeps, tests)
+  // RANKEST_BATCH_TILE="waves:bk:grid per CU" pins the tile shape (tuning sweeps, tests)
   if (const char* pin = getenv("RANKEST_BATCH_TILE")) {
-    int w = 0, gm = 0;
-    if (sscanf(pin, "%d:%d", &w, &gm) != 2 || (w != 4 && w != 8) || gm < 1 || gm > 64) return RE_ERR_INVALID_ARG;
-    h->tuned[key] = {w, gm * cus};
+    int w = 0, bk = 0, gm = 0;
+    if (sscanf(pin, "%d:%d:%d", &w, &bk, &gm) != 3 || (w != 4 && w != 8) || (bk != 16 && bk != 32) || gm < 1 ||
+        gm > 64)
+      return RE_ERR_INVALID_ARG;
+    h->tuned[key] = {w, bk, gm * cus};
   }
   auto it = h->tuned.find(key);
   if (it == h->tuned.end()) {
-    const int cand[4][2] = {{4, 2}, {4, 4}, {8, 1}, {8, 2}};
+    const int cand[5][3] = {{4, 16, 2}, {4, 16, 3}, {4, 32, 2}, {8, 16, 2}, {8, 32, 1}};
     hipEvent_t e0, e1;
     RE_TRY_HIP(hipEventCreate(&e0));
     RE_TRY_HIP(hipEventCreate(&e1));
     float best = 1e30f;
-    std::pair<int, int> pick{4, 2 * cus};
+    re_handle_s::Tile pick{4, 32, 2 * cus};
     for (const auto& c : cand) {
       const int w = c[0];
       const int64_t tot = fill_batch_desc(img, p, ws, blocks, nblocks, k, l, eps, seed, w);
-      const int g = (int)(tot < (int64_t)c[1] * cus ? tot : (int64_t)c[1] * cus);
+      const int g = (int)(tot < (int64_t)c[2] * cus ? tot : (int64_t)c[2] * cus);
       RE_TRY_HIP(hipMemcpyAsync(ws + p.desc0, img, p.desc_bytes, hipMemcpyHostToDevice, s));
       RE_TRY(launch_gauss_master(s, (const BatchHeader*)(ws + p.desc0 + p.hdr), nmax, k, l, mmax, (float*)(ws + p.X),
                                  (float*)(ws + p.Y)));
@@ -626,14 +633,14 @@ RE_API re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, i
       for (int rep = 0; rep < 2; ++rep) {
         RE_TRY_HIP(hipEventRecord(e0, s));
         RE_TRY(launch_gemm_f32_persistent(s, (const GemmDesc*)(ws + p.desc0 + p.gdesc), nblocks, (const float*)(ws + p.X),
-                                          k, tot, (unsigned*)(ws + p.queue), w, g));
+                                          k, tot, (unsigned*)(ws + p.queue), w, g, c[1]));
         RE_TRY_HIP(hipEventRecord(e1, s));
         RE_TRY_HIP(hipEventSynchronize(e1));
         RE_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
       }
       if (ms < best) {
         best = ms;
-        pick = {w, c[1] * cus};
+        pick = {w, c[1], c[2] * cus};
       }
     }
     (void)hipEventDestroy(e0);
@@ -642,22 +649,23 @@ RE_API re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, i
     save_tune_cache(h);
     it = h->tuned.find(key);
   }
-  const int waves = it->second.first;
+  const int waves = it->second.waves, bk = it->second.bk;
   const int64_t total = fill_batch_desc(img, p, ws, blocks, nblocks, k, l, eps, seed, waves);
-  const int grid = (int)(total < it->second.second ? total : it->second.second);
+  const int grid = (int)(total < it->second.grid ? total : it->second.grid);
 
   // (re)capture when anything baked into the graph changed
   char gkey[256];
-  snprintf(gkey, sizeof(gkey), "%p %p %d %lld %lld %lld %lld %lld %lld %d %d", (void*)ws, (void*)host_res, nblocks,
-           (long long)k, (long long)l, (long long)nmax, (long long)mmax, (long long)brows, (long long)total, waves, grid);
+  snprintf(gkey, sizeof(gkey), "%p %p %d %lld %lld %lld %lld %lld %lld %d %d %d", (void*)ws, (void*)host_res, nblocks,
+           (long long)k, (long long)l, (long long)nmax, (long long)mmax, (long long)brows, (long long)total, waves, grid,
+           bk);
   if (h->prof) {  // eager issue of the same launches, stage events in between
     RE_TRY_HIP(hipMemcpyAsync(ws + p.desc0, img, p.desc_bytes, hipMemcpyHostToDevice, s));
-    RE_TRY(enqueue_batch(h, s, p, nblocks, k, l, nmax, mmax, total, waves, grid, host_res));
+    RE_TRY(enqueue_batch(h, s, p, nblocks, k, l, nmax, mmax, total, waves, grid, bk, host_res));
   } else if (!h->bexec || h->bkey != gkey) {
     drop_graph(h);
     RE_TRY_HIP(hipStreamSynchronize(s));
     RE_TRY_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
-    const re_status st = enqueue_batch(h, h->cap, p, nblocks, k, l, nmax, mmax, total, waves, grid, host_res);
+    const re_status st = enqueue_batch(h, h->cap, p, nblocks, k, l, nmax, mmax, total, waves, grid, bk, host_res);
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(h->cap, &g);
     if (st != RE_OK || ce != hipSuccess) {

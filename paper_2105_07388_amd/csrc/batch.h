@@ -8,6 +8,10 @@
 
 namespace re {
 
+// Largest leading dimension of the persistent contraction (it indexes a
+// 256-row tile with 32-bit offsets).
+constexpr int64_t kMaxBatchLda = int64_t(1) << 23;
+
 // One block of the FP32 contraction B = A X[:n]: its work items are
 // item0 .. item0 + (row tiles x column chunks) - 1.
 struct GemmDesc {
@@ -54,7 +58,7 @@ __attribute__((visibility("hidden"))) re_status launch_gauss_master(hipStream_t 
                                                                    float* Y);
 __attribute__((visibility("hidden"))) re_status launch_gemm_f32_persistent(hipStream_t s, const GemmDesc* desc, int nblk,
                                                                           const float* X, int64_t k, int64_t total,
-                                                                          unsigned* queue, int waves, int grid);
+                                                                          unsigned* queue, int waves, int grid, int bk);
 __attribute__((visibility("hidden"))) int64_t gemm_items(int64_t m, int64_t k, int waves);
 __attribute__((visibility("hidden"))) int gemm_col_chunks(int64_t k);
 __attribute__((visibility("hidden"))) re_status launch_ygemm_batched(hipStream_t s, const YDesc* desc, int nblk,

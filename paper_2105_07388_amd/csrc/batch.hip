@@ -13,8 +13,6 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kBK = 16;      // K per step
-constexpr int kApad = 17;    // LDS row pitch of the A tile (floats)
 
 // Block of a work item: the last b with desc[b].item0 <= item.
 __device__ __forceinline__ int find_block(const GemmDesc* __restrict__ desc, int nblk, int64_t item) {
@@ -29,15 +27,18 @@ __device__ __forceinline__ int find_block(const GemmDesc* __restrict__ desc, int
 
 // Persistent FP32 MFMA contraction.  A workgroup of WAVES wavefronts takes
 // items from an atomic queue; an item is 32*WAVES rows of one block by up to
-// 32*NT columns.  Wavefront w owns 32 rows and NT 32x32 accumulator tiles
+// 32*NT columns, swept along K in steps of kBK through double-buffered LDS
+// tiles.  Every output is the same sequence of MFMA accumulations whatever
+// WAVES and kBK are, so the tile shape never changes the result.  Wavefront w owns 32 rows and NT 32x32 accumulator tiles
 // (v_mfma_f32_32x32x2_f32: lane l holds row / column l % 32 and K index l / 32
 // of the operands; accumulator q of lane l is row 8 (q/4) + 4 (l/32) + q%4,
 // column l % 32).
-template <int WAVES, int NT>
+template <int WAVES, int NT, int kBK>
 __global__ void __launch_bounds__(64 * WAVES) k_gemm_f32_persistent(const GemmDesc* __restrict__ desc, int nblk,
                                                                     const float* __restrict__ X, int64_t k,
                                                                     int64_t total, unsigned* __restrict__ queue) {
   constexpr int BM = 32 * WAVES, BN = 32 * NT, NTH = 64 * WAVES;
+  constexpr int kApad = kBK + 1;  // LDS row pitch of the A tile (floats)
   __shared__ float sA[2][BM * kApad];
   __shared__ float sX[2][kBK * BN];
   __shared__ int64_t s_item;
@@ -53,40 +54,44 @@ __global__ void __launch_bounds__(64 * WAVES) k_gemm_f32_persistent(const GemmDe
     const int64_t local = item - d.item0;
     const int64_t rt = local / d.ncc, cc = local - rt * d.ncc;
     const int64_t row0 = rt * BM, col0 = cc * BN;
-    const float* __restrict__ A = d.A;
-    const int64_t m = d.m, n = d.n, lda = d.lda;
+    const int64_t m = d.m, n = d.n;
+    const int rows_here = (int)(m - row0 < BM ? m - row0 : BM);
+    // 32-bit offsets inside the item (the host keeps BM * lda below 2^31)
+    const unsigned lda = (unsigned)d.lda;
+    const float* __restrict__ Ab = d.A + row0 * d.lda;
 
-    float ra[BM * kBK / NTH];
-    float rx[kBK * BN / NTH];
+    // A: thread t loads PER consecutive K values of tile row ar
+    constexpr int PER = BM * kBK / NTH;
+    const int ar = (tid * PER) / kBK, ak = (tid * PER) % kBK;
+    // X: thread t loads PX consecutive columns of tile row xr
+    constexpr int PX = kBK * BN / NTH;
+    const int xr = (tid * PX) / BN, xc = (tid * PX) % BN;
+    const bool xcols_full = col0 + xc + PX <= k;
+    float ra[PER];
+    float rx[PX];
     auto load = [&](int64_t k0) {
-      // A: BM x 16, each thread a run of consecutive K values of one row
-      constexpr int PER = BM * kBK / NTH;  // 8
+      const float* __restrict__ sa = Ab + ar * lda + (k0 + ak);
+      if (ar < rows_here && k0 + ak + PER <= n) {
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int e = tid * PER + q;
-        const int r = e / kBK, kk = e % kBK;
-        const int64_t gr = row0 + r, gk = k0 + kk;
-        ra[q] = (gr < m && gk < n) ? A[gr * lda + gk] : 0.0f;
+        for (int q = 0; q < PER; ++q) ra[q] = sa[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) ra[q] = (ar < rows_here && k0 + ak + q < n) ? sa[q] : 0.0f;
       }
-      constexpr int PX = kBK * BN / NTH;
+      const float* __restrict__ sx = X + (k0 + xr) * k + (col0 + xc);
+      if (k0 + xr < n && xcols_full) {
 #pragma unroll
-      for (int q = 0; q < PX; ++q) {
-        const int e = tid * PX + q;
-        const int kr = e / BN, c = e % BN;
-        const int64_t gk = k0 + kr, gc = col0 + c;
-        rx[q] = (gk < n && gc < k) ? X[gk * k + gc] : 0.0f;
+        for (int q = 0; q < PX; ++q) rx[q] = sx[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < PX; ++q) rx[q] = (k0 + xr < n && col0 + xc + q < k) ? sx[q] : 0.0f;
       }
     };
     auto store = [&](int buf) {
-      constexpr int PER = BM * kBK / NTH;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int e = tid * PER + q;
-        sA[buf][(e / kBK) * kApad + (e % kBK)] = ra[q];
-      }
-      constexpr int PX = kBK * BN / NTH;
+      for (int q = 0; q < PER; ++q) sA[buf][ar * kApad + ak + q] = ra[q];
 #pragma unroll
-      for (int q = 0; q < PX; ++q) sX[buf][tid * PX + q] = rx[q];
+      for (int q = 0; q < PX; ++q) sX[buf][xr * BN + xc + q] = rx[q];
     };
     f32x16 acc[NT];
 #pragma unroll
@@ -207,18 +212,22 @@ __global__ void __launch_bounds__(256) k_ygemm_batched(const YDesc* __restrict__
 }  // namespace
 
 re_status launch_gemm_f32_persistent(hipStream_t s, const GemmDesc* desc, int nblk, const float* X, int64_t k,
-                                     int64_t total, unsigned* queue, int waves, int grid) {
+                                     int64_t total, unsigned* queue, int waves, int grid, int bk) {
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, queue);
   const int nt = (int)(k >= 128 ? 4 : cdiv(k, 32));
-#define RE_GEMM_CASE(W, N)                                                                                   \
-  if (waves == W && nt == N) {                                                                               \
-    hipLaunchKernelGGL((k_gemm_f32_persistent<W, N>), dim3(grid), dim3(64 * W), 0, s, desc, nblk, X, k, total, \
-                       queue);                                                                               \
-    RE_TRY_HIP(hipGetLastError());                                                                           \
-    return RE_OK;                                                                                            \
+#define RE_GEMM_CASE(W, N, BK)                                                                                     \
+  if (waves == W && nt == N && bk == BK) {                                                                         \
+    hipLaunchKernelGGL((k_gemm_f32_persistent<W, N, BK>), dim3(grid), dim3(64 * W), 0, s, desc, nblk, X, k, total, \
+                       queue);                                                                                     \
+    RE_TRY_HIP(hipGetLastError());                                                                                 \
+    return RE_OK;                                                                                                  \
   }
-  RE_GEMM_CASE(4, 1) RE_GEMM_CASE(4, 2) RE_GEMM_CASE(4, 3) RE_GEMM_CASE(4, 4)
-  RE_GEMM_CASE(8, 1) RE_GEMM_CASE(8, 2) RE_GEMM_CASE(8, 3) RE_GEMM_CASE(8, 4)
+#define RE_GEMM_CASES(BK)                                                                                     \
+  RE_GEMM_CASE(4, 1, BK) RE_GEMM_CASE(4, 2, BK) RE_GEMM_CASE(4, 3, BK) RE_GEMM_CASE(4, 4, BK)                  \
+  RE_GEMM_CASE(8, 1, BK) RE_GEMM_CASE(8, 2, BK) RE_GEMM_CASE(8, 3, BK) RE_GEMM_CASE(8, 4, BK)
+  RE_GEMM_CASES(16)
+  RE_GEMM_CASES(32)
+#undef RE_GEMM_CASES
 #undef RE_GEMM_CASE
   return RE_ERR_INVALID_ARG;
 }
@@ -237,7 +246,7 @@ re_status launch_gemm_f32_single(hipStream_t s, const float* A, int64_t m, int64
   hipLaunchKernelGGL(k_put_desc<GemmDesc>, dim3(1), dim3(64), 0, s, d, dscratch);
   const int64_t total = gemm_items(m, k, 4);
   const int64_t g = total < 2048 ? total : 2048;
-  return launch_gemm_f32_persistent(s, dscratch, 1, X, k, total, queue, 4, (int)g);
+  return launch_gemm_f32_persistent(s, dscratch, 1, X, k, total, queue, 4, (int)g, 32);
 }
 
 re_status launch_ygemm_single(hipStream_t s, const float* B, int64_t m, int64_t k, const float* Y, int64_t ldy,

@@ -451,6 +451,7 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_1wg(SmallBatch sb) {
   double* wv = Wl + l * kp;                           // [k + 1]
   double* vv = wv + (k + 1);                          // [k + 1]
   double* red = vv + (k + 1);                         // [kB2Waves]
+  double* part = red + kB2Waves;                      // [kB2Threads] row-group partials
   __shared__ int s_bad;
   if (tid == 0) s_bad = 0;
   __syncthreads();
@@ -462,20 +463,38 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_1wg(SmallBatch sb) {
   }
   __syncthreads();
   if (tid == 0) sb.info[b] = s_bad ? (int32_t)RE_ERR_NONFINITE : 0;
-  for (int64_t c = 0; c < k; ++c) {
-    const int64_t len = k - c;
-    // column partials of column c straight into LDS: wv = x . W[:, c + j], vv = W[c][c + j]
-    for (int64_t j = tid; j < len; j += kB2Threads) {
-      double g[4] = {0.0, 0.0, 0.0, 0.0};
-      int64_t i = c;
-      for (; i + 3 < l; i += 4) {
-        const double* r0 = Wl + i * kp + c;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) g[q] += r0[q * kp] * r0[q * kp + j];
+  for (int c = 0; c < (int)k; ++c) {
+    const int len = (int)k - c;
+    // column partials of column c: wv = x . W[:, c + j], vv = W[c][c + j].
+    // Thread t takes column j = t % len over rows c + g, c + g + G, ...
+    // (g = t / len, G groups); the G partials are then summed in order.
+    if (len <= kB2Threads) {
+      const int G = min(kB2Threads / len, 32);
+      const int j = tid % len, g = tid / len;
+      if (g < G) {
+        double a0 = 0.0, a1 = 0.0;
+        int i = c + g;
+        for (; i + G < (int)l; i += 2 * G) {
+          a0 += Wl[i * kp + c] * Wl[i * kp + c + j];
+          a1 += Wl[(i + G) * kp + c] * Wl[(i + G) * kp + c + j];
+        }
+        if (i < (int)l) a0 += Wl[i * kp + c] * Wl[i * kp + c + j];
+        part[g * len + j] = a0 + a1;
       }
-      for (; i < l; ++i) g[0] += Wl[i * kp + c] * Wl[i * kp + c + j];
-      wv[j] = (g[0] + g[1]) + (g[2] + g[3]);
-      vv[j] = Wl[c * kp + c + j];
+      __syncthreads();
+      if (tid < len) {
+        double t = 0.0;
+        for (int q = 0; q < G; ++q) t += part[q * len + tid];
+        wv[tid] = t;
+        vv[tid] = Wl[c * kp + c + tid];
+      }
+    } else {
+      for (int j = tid; j < len; j += kB2Threads) {
+        double a0 = 0.0;
+        for (int i = c; i < (int)l; ++i) a0 += Wl[i * kp + c] * Wl[i * kp + c + j];
+        wv[j] = a0;
+        vv[j] = Wl[c * kp + c + j];
+      }
     }
     __syncthreads();
     const double s0 = wv[0], x0 = vv[0];
@@ -534,6 +553,7 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_1wg(SmallBatch sb) {
 __device__ int count_below(const double* bb, int nb, double x, double pivmin) {
   double q = -x;
   int neg = 1;  // q0 = -x < 0
+#pragma unroll 4
   for (int j = 0; j < nb; ++j) {
     double r = __builtin_amdgcn_rcp(q);
     r = fma(r, fma(-q, r, 1.0), r);
@@ -652,7 +672,7 @@ int64_t lds_stride(int64_t k) { return k + ((16 - k % 32) + 32) % 32; }
 
 // LDS bytes of the single-workgroup bidiagonalisation of an l x k sketch.
 size_t small_lds_bytes(int64_t l, int64_t k) {
-  return (size_t)l * lds_stride(k) * 8 + (size_t)(2 * (k + 1) + kB2Waves) * 8;
+  return (size_t)l * lds_stride(k) * 8 + (size_t)(2 * (k + 1) + kB2Waves + kB2Threads) * 8;
 }
 
 // Rows per workgroup at most `svd_rows_target()` (fewer rows shorten the
@@ -704,16 +724,20 @@ SvdLayout svd_layout(int64_t l, int64_t k) {
   return s;
 }
 
-// Batched singular values of bidiagonals (problem = blockIdx.y) and counts
-// (problem = blockIdx.x); same arithmetic as k_bidiag_sv and k_count.
-__global__ void __launch_bounds__(256) k_bidiag_sv_batched(const SvDesc* __restrict__ desc) {
+// Batched counts (problem = blockIdx.x); same arithmetic as k_count.
+// Singular values of small bidiagonals, one lane per value: 56 bisection
+// steps on the Sturm count (the interval shrinks below 2^-56 of the bound,
+// as the 65-way multisection does in 9 rounds), one workgroup per problem
+// (problem = blockIdx.x of desc, or `one` when desc is NULL).  Used for every
+// sketch whose bidiagonalisation fits one workgroup, single or batched, so a
+// block of a batch and the same matrix alone give the same bits.
+constexpr int kBisectSteps = 56;
+__global__ void __launch_bounds__(256) k_sv_bisect(const SvDesc* __restrict__ desc, SvDesc one) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const SvDesc dsc = desc[blockIdx.y];
-  const int64_t k = dsc.k;
-  const int64_t waves = blockDim.x / 64;
-  if ((int64_t)blockIdx.x * waves >= k) return;
+  const SvDesc dsc = desc ? desc[blockIdx.x] : one;
+  const int k = dsc.k;
   double* b = reinterpret_cast<double*>(smem_raw);
-  const int nb = (int)(2 * k - 1);
+  const int nb = 2 * k - 1;
   double* bb = b + nb;
   for (int j = threadIdx.x; j < nb; j += blockDim.x) {
     b[j] = (j & 1) ? dsc.e[j >> 1] : dsc.d[j >> 1];
@@ -721,7 +745,7 @@ __global__ void __launch_bounds__(256) k_bidiag_sv_batched(const SvDesc* __restr
   }
   __syncthreads();
   double bound = 0.0, maxb2 = 0.0;
-  for (int j = 0; j < nb; ++j) {
+  for (int j = 0; j < nb; ++j) {  // every thread, same order
     const double left = j > 0 ? fabs(b[j - 1]) : 0.0;
     bound = fmax(bound, fabs(b[j]) + left);
     maxb2 = fmax(maxb2, bb[j]);
@@ -730,21 +754,15 @@ __global__ void __launch_bounds__(256) k_bidiag_sv_batched(const SvDesc* __restr
   const bool all_zero = !(bound > 0.0);
   bound = bound * (1.0 + 1e-14) + 1e-300;
   const double pivmin = 0x1.0p-1022 * fmax(1.0, maxb2);
-  const int lane = threadIdx.x & 63;
-  for (int64_t jj = blockIdx.x * waves + (threadIdx.x >> 6); jj < k; jj += (int64_t)gridDim.x * waves) {
-    const int want = (int)(k - 1 - jj);
+  for (int jj = threadIdx.x; jj < k; jj += blockDim.x) {
+    const int want = k - 1 - jj;  // #{sigma < lo} <= want < #{sigma < hi}
     double lo = 0.0, hi = bound;
-    for (int it = 0; it < 9; ++it) {
-      const double x = lo + (hi - lo) * (double)(lane + 1) * (1.0 / 65.0);
-      const int cnt = count_below(bb, nb, x, pivmin);
-      const uint64_t le = __ballot(cnt <= want);
-      const int nle = __popcll(le);
-      const double nlo = nle > 0 ? lo + (hi - lo) * (double)nle * (1.0 / 65.0) : lo;
-      const double nhi = nle < 64 ? lo + (hi - lo) * (double)(nle + 1) * (1.0 / 65.0) : hi;
-      lo = nlo;
-      hi = nhi;
+    for (int it = 0; it < kBisectSteps; ++it) {
+      const double x = 0.5 * (lo + hi);
+      if (count_below(bb, nb, x, pivmin) <= want) lo = x;
+      else hi = x;
     }
-    if (lane == 0) dsc.sigma[jj] = all_zero ? 0.0 : 0.5 * (lo + hi) * dsc.scale;
+    dsc.sigma[jj] = all_zero ? 0.0 : 0.5 * (lo + hi) * dsc.scale;
   }
 }
 
@@ -856,6 +874,18 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
   }
   const size_t lds2 = (size_t)(4 * k) * 8;
   if (lds2 > 160 * 1024) return RE_ERR_UNSUPPORTED;
+  if (one_bytes <= kLdsBudget) {  // the batched form's per-lane bisection
+    SvDesc one{};
+    one.d = a.d;
+    one.e = a.e;
+    one.sigma = sigma;
+    one.k = (int32_t)k;
+    one.scale = scale;
+    const int thr = k >= 256 ? 256 : (int)cdiv(k, 64) * 64;
+    hipLaunchKernelGGL(k_sv_bisect, dim3(1), dim3(thr), lds2, s, (const SvDesc*)nullptr, one);
+    RE_TRY_HIP(hipGetLastError());
+    return RE_OK;
+  }
   if (lds2 > 64 * 1024)
     RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag_sv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
   const int waves_per_block = 4;
@@ -893,8 +923,9 @@ re_status launch_sv_count_batched(hipStream_t s, const SvDesc* desc, int nblk, i
   const size_t lds2 = (size_t)(4 * kmax) * 8;
   if (lds2 > 160 * 1024) return RE_ERR_UNSUPPORTED;
   if (lds2 > 64 * 1024)
-    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag_sv_batched, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
-  hipLaunchKernelGGL(k_bidiag_sv_batched, dim3((unsigned)cdiv(kmax, 4), (unsigned)nblk), dim3(256), lds2, s, desc);
+    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_sv_bisect, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+  const int thr = kmax >= 256 ? 256 : (int)cdiv(kmax, 64) * 64;
+  hipLaunchKernelGGL(k_sv_bisect, dim3((unsigned)nblk), dim3(thr), lds2, s, desc, SvDesc{});
   hipLaunchKernelGGL(k_count_batched, dim3((unsigned)nblk), dim3(256), 0, s, desc);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
