@@ -4,3 +4,4 @@ Only tests/, __graft_entry__.smoke() and bench.py's CPU-baseline leg may import 
 package.  The product library never does.
 """
 from .pyoracle import *  # noqa: F401,F403
+from . import learned  # noqa: F401,E402
