@@ -229,6 +229,56 @@ re_status re_singular_values(re_handle h, const double* C_dev, int64_t l, int64_
  * descending sigma_dev[0..k) with r1 and eps (strict inequality of Def. 1). */
 re_status re_rank_count(re_handle h, const double* sigma_dev, int64_t k, int32_t r1, double eps, int32_t* out_dev);
 
+/* ------------------------------------------------------------------------
+ * Adaptive sketch width.  When r1 is too small (r^ = r1) the paper reruns
+ * Algorithm 1 with a larger r1, appending columns to X and rows to Y and
+ * keeping what was computed (Sec. 5, with the update r1 := 2 r1, whose
+ * overhead for Gaussian sketches is at most a factor 2).  Sec. 7 leaves open
+ * how to pick the new r1 from the first run; the learned policy below (an
+ * addition of this library, not a claim of the paper) lets a small network
+ * read the pilot sketch and propose the width, with doubling as fallback.
+ * ------------------------------------------------------------------------ */
+#define RE_MLP_INPUTS 35   /* log10(s_i/s_1), i < 32 (clamped at -8), log10 m, log10 n, log10 eps */
+#define RE_MLP_PARAMS 6529 /* W1 (64x35), b1 (64), W2 (64x64), b2 (64), w3 (64), b3 (1), row-major */
+
+typedef struct {
+  int32_t k0;          /* pilot width (e.g. 32); the pilot uses l = l_for(k0) rows */
+  int32_t k_max;       /* largest width; 0 means min(m, n) */
+  double l_ratio;      /* rows of Y per column of X: l = clamp(round(l_ratio k), k, m) */
+  const float* mlp;    /* device, RE_MLP_PARAMS floats, or NULL for plain doubling */
+  double delta;        /* margin added to the network output (natural log of the width) */
+} re_adaptive;
+
+/*
+ * Rank estimate with an adaptive width, FP32 A and Gaussian X and Y.  Round 1
+ * runs Algorithm 1 at k0.  While r^ = r1(k) and k < k_max: the next width is
+ * the network's proposal after round 1 when `mlp` is given (ceil(exp(y +
+ * delta)) rounded up to a multiple of 8, clamped to [2 k0, k_max]), and 2k
+ * otherwise.  Each round draws only the new columns of X and rows of Y, forms
+ * only the new columns of A X (one more pass over A), recomputes Y B, its SVD
+ * and the count; the final estimate equals re_rank_estimate at the final
+ * (k, l) with the same seed.
+ *   sigma_out   host, k_max doubles: the final round's estimates (k_out of them)
+ *   k_out, l_out, rounds_out, k_proposed_out (0 when no proposal), flags_out:
+ *               host, may be NULL
+ * Errors as re_rank_estimate; RE_ERR_UNSUPPORTED unless dt = RE_F32.
+ */
+re_status re_rank_adaptive(re_handle h, const void* A_dev, int32_t dt, int64_t m, int64_t n, int64_t lda, double eps,
+                           const re_adaptive* ad, uint64_t seed, int32_t* r_out, double* sigma_out, int32_t* k_out,
+                           int32_t* l_out, int32_t* rounds_out, int32_t* k_proposed_out, uint32_t* flags_out);
+
+/* The network, FP32, on device buffers (training and inference).
+ * x_dev: batch x RE_MLP_INPUTS row-major; y_dev, t_dev: batch. */
+re_status re_mlp_forward(re_handle h, const float* params_dev, const float* x_dev, int64_t batch, float* y_dev);
+/* grad_dev (RE_MLP_PARAMS) = gradient of (1/batch) sum (y - t)^2; loss_dev
+ * (1 float, may be NULL) = that loss.  Deterministic. */
+re_status re_mlp_loss_grad(re_handle h, const float* params_dev, const float* x_dev, const float* t_dev,
+                           int64_t batch, float* grad_dev, float* loss_dev);
+/* One Adam step (Kingma & Ba) on n parameters; step counts from 1; m_dev and
+ * v_dev start at zero. */
+re_status re_mlp_adam(re_handle h, float* params_dev, const float* grad_dev, float* m_dev, float* v_dev, int64_t n,
+                      int32_t step, double lr, double beta1, double beta2, double eps);
+
 /* r1 derived from the sketch width k (Algorithm 1 step 1 inverted). */
 int32_t re_r1_from_k(int32_t k);
 

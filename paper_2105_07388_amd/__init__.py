@@ -18,8 +18,12 @@ from ._binding import (  # noqa: F401
     gauss_fill,
     lib,
     make_blocks,
+    mlp_adam,
+    mlp_forward,
+    mlp_loss_grad,
     philox,
     r1_from_k,
+    rank_adaptive,
     rank_count,
     rank_estimate,
     rank_estimate_batched,

@@ -41,6 +41,14 @@ class ReSketch(C.Structure):
                 ("prec", C.c_int32)]
 
 
+class ReAdaptive(C.Structure):
+    _fields_ = [("k0", C.c_int32), ("k_max", C.c_int32), ("l_ratio", C.c_double), ("mlp", C.c_void_p),
+                ("delta", C.c_double)]
+
+
+MLP_INPUTS, MLP_PARAMS = 35, 6529
+
+
 class ReBlock(C.Structure):
     _fields_ = [("A", C.c_void_p), ("m", C.c_int64), ("n", C.c_int64), ("lda", C.c_int64)]
 
@@ -71,6 +79,12 @@ def lib():
             "re_rank_estimate": ([vp, vp, i32, i64, i64, i64, dbl, C.POINTER(ReSketch), u64, C.POINTER(i32), vp,
                                   C.POINTER(i32), C.POINTER(C.c_uint32)], i32),
             "re_rank_estimate_batched": ([vp, vp, i32, i32, dbl, C.POINTER(ReSketch), u64, vp, vp, vp], i32),
+            "re_rank_adaptive": ([vp, vp, i32, i64, i64, i64, dbl, C.POINTER(ReAdaptive), u64, C.POINTER(i32), vp,
+                                  C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                  C.POINTER(C.c_uint32)], i32),
+            "re_mlp_forward": ([vp, vp, vp, i64, vp], i32),
+            "re_mlp_loss_grad": ([vp, vp, vp, vp, i64, vp, vp], i32),
+            "re_mlp_adam": ([vp, vp, vp, vp, vp, i64, i32, dbl, dbl, dbl, dbl], i32),
             "re_philox": ([vp, vp, u64, i64, vp], i32),
             "re_gauss_fill": ([vp, i32, i64, i64, u64, i32, i32, vp], i32),
             "re_srht_signs": ([vp, i64, u64, i32, vp], i32),
@@ -200,6 +214,63 @@ def rank_estimate(A: torch.Tensor, eps: float, *, k: int, l: int = 0, x: str = "
                                 C.byref(fl))
     _check(st, "re_rank_estimate")
     return r.value, sigma, {"r1": r1.value, "flags": fl.value, "k": int(k), "l": int(l) if l else 2 * int(k)}
+
+
+def rank_adaptive(A: torch.Tensor, eps: float, *, k0: int = 32, k_max: int = 0, l_ratio: float = 1.5,
+                  mlp: torch.Tensor | None = None, delta: float = 0.0, seed: int = 0, handle: Handle | None = None):
+    """Rank estimate with an adaptive sketch width (FP32 A, Gaussian sketches):
+    doubling from k0, or the network's proposal after the pilot when `mlp`
+    (device float32 parameter vector) is given.  Returns (r, sigma, info) with
+    info = {k, l, rounds, k_proposed, flags}."""
+    _check_matrix(A)
+    if mlp is not None:
+        _need_cuda(mlp, "mlp")
+        if mlp.dtype != torch.float32 or mlp.numel() != MLP_PARAMS or not mlp.is_contiguous():
+            raise ValueError(f"mlp must be a contiguous float32 tensor of {MLP_PARAMS} values")
+    h = handle or default_handle(A.device)
+    m, n = A.shape
+    ad = ReAdaptive(int(k0), int(k_max), float(l_ratio), mlp.data_ptr() if mlp is not None else None, float(delta))
+    kcap = min(m, n) if k_max <= 0 else min(m, n, k_max)
+    sigma = np.zeros(kcap, dtype=np.float64)
+    r, kk, ll, rounds, kp = (C.c_int32(0) for _ in range(5))
+    fl = C.c_uint32(0)
+    st = lib().re_rank_adaptive(h.bind(), _ptr(A), _dtype_code(A), m, n, A.stride(0), float(eps), C.byref(ad),
+                                int(seed) % 2**64, C.byref(r), sigma.ctypes.data_as(C.c_void_p), C.byref(kk),
+                                C.byref(ll), C.byref(rounds), C.byref(kp), C.byref(fl))
+    _check(st, "re_rank_adaptive")
+    return r.value, sigma[:kk.value], {"k": kk.value, "l": ll.value, "rounds": rounds.value,
+                                       "k_proposed": kp.value, "flags": fl.value}
+
+
+def mlp_forward(params: torch.Tensor, x: torch.Tensor, handle: Handle | None = None) -> torch.Tensor:
+    """Network outputs for a batch of feature rows (device float32)."""
+    _need_cuda(params, "params")
+    _need_cuda(x, "x")
+    x = x.contiguous()
+    y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    h = handle or default_handle(x.device)
+    _check(lib().re_mlp_forward(h.bind(), _ptr(params), _ptr(x), x.shape[0], _ptr(y)), "re_mlp_forward")
+    return y
+
+
+def mlp_loss_grad(params: torch.Tensor, x: torch.Tensor, t: torch.Tensor, handle: Handle | None = None):
+    """(gradient of the mean squared error, loss) on device, float32."""
+    x = x.contiguous()
+    t = t.contiguous()
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    h = handle or default_handle(x.device)
+    _check(lib().re_mlp_loss_grad(h.bind(), _ptr(params), _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss)),
+           "re_mlp_loss_grad")
+    return g, loss
+
+
+def mlp_adam(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
+             beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, handle: Handle | None = None):
+    """One Adam step in place on device float32 tensors."""
+    h = handle or default_handle(params.device)
+    _check(lib().re_mlp_adam(h.bind(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), int(step),
+                             float(lr), float(beta1), float(beta2), float(eps)), "re_mlp_adam")
 
 
 def make_blocks(blocks) -> "C.Array[ReBlock]":

@@ -12,6 +12,7 @@
 
 #include "batch.h"
 #include "common.h"
+#include "learned.h"
 
 #define RE_API extern "C" __attribute__((visibility("default")))
 
@@ -194,7 +195,7 @@ re_status run_x(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m
   RE_TRY(launch_gauss_fill(s, fx, n, rs.k, seed, kXGauss, 0, X));
   mark(h, RE_STAGE_AX);
   if (dt == RE_F32 && lda < kMaxBatchLda)  // FP32: the matrix-core contraction shared with the batched form
-    return launch_gemm_f32_single(s, (const float*)A, m, n, lda, (const float*)X, rs.k, (float*)B,
+    return launch_gemm_f32_single(s, (const float*)A, m, n, lda, (const float*)X, rs.k, (float*)B, rs.k,
                                   (GemmDesc*)at(h, p.gdesc), (unsigned*)at(h, p.queue));
   return launch_gemm_f64acc(s, m, rs.k, n, A, 0, lda, X, 0, rs.k, B, 0, rs.k);
 }
@@ -216,7 +217,7 @@ re_status run_y(re_handle h, const Plan& p, void* B, int32_t bdt, int64_t m, con
   RE_TRY(launch_gauss_fill(s, fy, rs.l, m, seed, kYGauss, 1, Y));
   mark(h, RE_STAGE_YB);
   if (bdt == RE_F32)  // the batched form's kernel, so one block of a batch matches a single call
-    return launch_ygemm_single(s, (const float*)B, m, rs.k, (const float*)Y, m, rs.l, C, (YDesc*)at(h, p.ydesc));
+    return launch_ygemm_single(s, (const float*)B, m, rs.k, rs.k, (const float*)Y, m, rs.l, C, (YDesc*)at(h, p.ydesc));
   return launch_gemm_f64acc(s, rs.l, rs.k, m, Y, 0, m, B, 0, rs.k, C, 0, rs.k);
 }
 
@@ -700,6 +701,159 @@ RE_API re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, i
   }
   memcpy(sigma_out, host_res + p.sigma, (size_t)nblocks * k * 8);
   return worst;
+}
+
+// ---------------------------------------------------------------------------
+// Learned sketch-size policy: the network on device buffers, and the adaptive
+// driver that appends sketch columns and rows round by round.
+// ---------------------------------------------------------------------------
+RE_API re_status re_mlp_forward(re_handle h, const float* params_dev, const float* x_dev, int64_t batch, float* y_dev) {
+  if (!h || batch < 0 || (batch > 0 && (!params_dev || !x_dev || !y_dev))) return RE_ERR_INVALID_ARG;
+  return launch_mlp_forward(h->stream, params_dev, x_dev, batch, y_dev, nullptr, nullptr);
+}
+
+RE_API re_status re_mlp_loss_grad(re_handle h, const float* params_dev, const float* x_dev, const float* t_dev,
+                                  int64_t batch, float* grad_dev, float* loss_dev) {
+  if (!h || batch < 1 || !params_dev || !x_dev || !t_dev || !grad_dev) return RE_ERR_INVALID_ARG;
+  RE_TRY(ensure_ws(h, (mlp_scratch_floats(batch) + (size_t)batch) * sizeof(float)));
+  return launch_mlp_loss_grad(h->stream, params_dev, x_dev, t_dev, batch, (float*)h->ws, grad_dev, loss_dev);
+}
+
+RE_API re_status re_mlp_adam(re_handle h, float* params_dev, const float* grad_dev, float* m_dev, float* v_dev,
+                             int64_t n, int32_t step, double lr, double beta1, double beta2, double eps) {
+  if (!h || n < 0 || step < 1 || (n > 0 && (!params_dev || !grad_dev || !m_dev || !v_dev))) return RE_ERR_INVALID_ARG;
+  if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+    return RE_ERR_INVALID_ARG;
+  const double c1 = 1.0 / (1.0 - pow(beta1, (double)step)), c2 = 1.0 / (1.0 - pow(beta2, (double)step));
+  return launch_mlp_adam(h->stream, params_dev, grad_dev, m_dev, v_dev, n, (float)lr, (float)beta1, (float)beta2,
+                         (float)eps, (float)c1, (float)c2);
+}
+
+namespace re {
+namespace {
+
+int64_t l_for(int64_t k, double ratio, int64_t m) {
+  int64_t l = (int64_t)floor(ratio * (double)k + 0.5);
+  if (l < k) l = k;
+  if (l > m) l = m;
+  return l;
+}
+
+// Network input from the pilot estimates (same definition as RE_MLP_INPUTS).
+void pilot_features(const double* s, int64_t k, int64_t m, int64_t n, double eps, float* f) {
+  for (int i = 0; i < 32; ++i) {
+    double v = -8.0;
+    if (i < k && s[0] > 0.0) {
+      const double q = s[i] / s[0];
+      v = q > 0.0 ? log10(q) : -8.0;
+      if (v < -8.0) v = -8.0;
+    }
+    f[i] = (float)v;
+  }
+  f[32] = (float)log10((double)m);
+  f[33] = (float)log10((double)n);
+  f[34] = (float)log10(eps);
+}
+
+struct AdPlan {
+  size_t B, Xn, Y, C, svd, sigma, info, out3, gdesc, ydesc, queue, feat, yout, total;
+};
+
+}  // namespace
+}  // namespace re
+
+RE_API re_status re_rank_adaptive(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                                  double eps, const re_adaptive* ad, uint64_t seed, int32_t* r_out, double* sigma_out,
+                                  int32_t* k_out, int32_t* l_out, int32_t* rounds_out, int32_t* k_proposed_out,
+                                  uint32_t* flags_out) {
+  if (!h || !A || !ad || !r_out || !sigma_out) return RE_ERR_INVALID_ARG;
+  if (dt != RE_F64 && dt != RE_F32) return RE_ERR_INVALID_ARG;
+  if (dt != RE_F32) return RE_ERR_UNSUPPORTED;
+  if (!(eps > 0.0 && eps < 1.0) || m < 1 || n < 1 || lda < n || lda >= kMaxBatchLda || ((uintptr_t)A) % 4 != 0)
+    return RE_ERR_INVALID_ARG;
+  if (ad->k0 < 1 || !(ad->l_ratio >= 1.0) || ad->k_max < 0 || !isfinite(ad->delta)) return RE_ERR_INVALID_ARG;
+  int64_t kmax = m < n ? m : n;
+  if (ad->k_max > 0 && ad->k_max < kmax) kmax = ad->k_max;
+  if (kmax > (int64_t)INT32_MAX / 2) return RE_ERR_INVALID_ARG;
+  const int64_t lmax = l_for(kmax, ad->l_ratio, m);
+  AdPlan p{};
+  Carve c;
+  p.B = c.take((size_t)m * kmax * 4);
+  p.Xn = c.take((size_t)n * kmax * 4);
+  p.Y = c.take((size_t)lmax * m * 4);
+  p.C = c.take((size_t)lmax * kmax * 8);
+  p.svd = c.take(svd_scratch_bytes(lmax, kmax));
+  p.sigma = c.take((size_t)kmax * 8);
+  p.info = c.take(16);
+  p.out3 = c.take(16);
+  p.gdesc = c.take(sizeof(GemmDesc));
+  p.ydesc = c.take(sizeof(YDesc));
+  p.queue = c.take(16);
+  p.feat = c.take(RE_MLP_INPUTS * 4);
+  p.yout = c.take(16);
+  p.total = c.off;
+  RE_TRY(ensure_ws(h, p.total));
+  RE_TRY(ensure_host(h, 256 + (size_t)kmax * 8));  // out3 | sigma | features
+  hipStream_t s = h->stream;
+  char* host = (char*)h->host;
+  float* B = (float*)at(h, p.B);
+  float* Y = (float*)at(h, p.Y);
+  double* C = (double*)at(h, p.C);
+  double* sigma = (double*)at(h, p.sigma);
+  int32_t* info = (int32_t*)at(h, p.info);
+  int32_t* out3 = (int32_t*)at(h, p.out3);
+  int64_t k_old = 0, l_old = 0, k = ad->k0 < kmax ? ad->k0 : kmax;
+  int32_t rounds = 0, kprop = 0;
+  for (;;) {
+    const int64_t l = l_for(k, ad->l_ratio, m);
+    // Algorithm 1 steps 2-6 on the appended part only
+    RE_TRY(launch_gauss_sub(s, n, k - k_old, 0, k_old, seed, kXGauss, 0, k - k_old, (float*)at(h, p.Xn)));
+    RE_TRY(launch_gemm_f32_single(s, (const float*)A, m, n, lda, (const float*)at(h, p.Xn), k - k_old, B + k_old, kmax,
+                                  (GemmDesc*)at(h, p.gdesc), (unsigned*)at(h, p.queue)));
+    RE_TRY(launch_gauss_sub(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, Y + l_old * m));
+    RE_TRY(launch_ygemm_single(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, p.ydesc)));
+    // steps 7-8
+    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, p.svd), sigma, info));
+    RE_TRY(launch_rank_count(s, sigma, k, r1_from_k((int32_t)k), eps, info, out3));
+    RE_TRY_HIP(hipMemcpyAsync(host, out3, 16, hipMemcpyDeviceToHost, s));
+    RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)k * 8, hipMemcpyDeviceToHost, s));
+    RE_TRY_HIP(hipStreamSynchronize(s));
+    ++rounds;
+    const int32_t* o3 = (const int32_t*)host;
+    if (o3[2] != 0) return (re_status)o3[2];
+    const bool more = (o3[1] & RE_FLAG_NOT_CONVERGED) && k < kmax;
+    if (!more) {
+      *r_out = o3[0];
+      memcpy(sigma_out, host + 64, (size_t)k * 8);
+      if (k_out) *k_out = (int32_t)k;
+      if (l_out) *l_out = (int32_t)l;
+      if (rounds_out) *rounds_out = rounds;
+      if (k_proposed_out) *k_proposed_out = kprop;
+      if (flags_out) *flags_out = (uint32_t)o3[1];
+      return RE_OK;
+    }
+    k_old = k;
+    l_old = l;
+    if (rounds == 1 && ad->mlp) {
+      float* f = (float*)(host + 64 + (size_t)kmax * 8);
+      pilot_features((const double*)(host + 64), k, m, n, eps, f);
+      RE_TRY_HIP(hipMemcpyAsync(at(h, p.feat), f, RE_MLP_INPUTS * 4, hipMemcpyHostToDevice, s));
+      RE_TRY(launch_mlp_forward(s, ad->mlp, (const float*)at(h, p.feat), 1, (float*)at(h, p.yout), nullptr, nullptr));
+      float yv = 0.f;
+      RE_TRY_HIP(hipMemcpyAsync(&yv, at(h, p.yout), 4, hipMemcpyDeviceToHost, s));
+      RE_TRY_HIP(hipStreamSynchronize(s));
+      double e = (double)yv + ad->delta;
+      if (!(e < 30.0)) e = 30.0;  // also catches NaN
+      int64_t kp = (int64_t)ceil(exp(e));
+      kp = (kp + 7) / 8 * 8;
+      if (kp < 2 * k_old) kp = 2 * k_old;
+      if (kp > kmax) kp = kmax;
+      kprop = (int32_t)kp;
+      k = kp;
+    } else {
+      k = 2 * k < kmax ? 2 * k : kmax;
+    }
+  }
 }
 
 RE_API re_status re_philox(re_handle h, const uint64_t* ctr, uint64_t seed, int64_t count, uint64_t* out) {

@@ -45,14 +45,20 @@ struct BatchHeader {
   uint64_t seed;
 };
 
-// B = A X for one FP32 matrix with the persistent kernel; dscratch receives its descriptor.
+// B = A X for one FP32 matrix with the persistent kernel (B leading
+// dimension ldb); dscratch receives its descriptor.
 __attribute__((visibility("hidden"))) re_status launch_gemm_f32_single(hipStream_t s, const float* A, int64_t m,
                                                                       int64_t n, int64_t lda, const float* X, int64_t k,
-                                                                      float* B, GemmDesc* dscratch, unsigned* queue);
+                                                                      float* B, int64_t ldb, GemmDesc* dscratch,
+                                                                      unsigned* queue);
+// Rows r0.. and columns c0.. of a Gaussian sketch, FP32, leading dimension ld.
+__attribute__((visibility("hidden"))) re_status launch_gauss_sub(hipStream_t s, int64_t rows, int64_t cols, int64_t r0,
+                                                                int64_t c0, uint64_t seed, int stream_id, int swap_ab,
+                                                                int64_t ld, float* out);
 // C = Y[:, :m] B (l x k FP64) for one block with the batched kernel.
 __attribute__((visibility("hidden"))) re_status launch_ygemm_single(hipStream_t s, const float* B, int64_t m, int64_t k,
-                                                                   const float* Y, int64_t ldy, int64_t l, double* C,
-                                                                   YDesc* dscratch);
+                                                                   int64_t ldb, const float* Y, int64_t ldy, int64_t l,
+                                                                   double* C, YDesc* dscratch);
 __attribute__((visibility("hidden"))) re_status launch_gauss_master(hipStream_t s, const BatchHeader* hdr, int64_t nmax,
                                                                    int64_t k, int64_t l, int64_t mmax, float* X,
                                                                    float* Y);

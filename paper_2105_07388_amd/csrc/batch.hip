@@ -141,6 +141,20 @@ __global__ void k_put_desc(D v, D* out) {
   if (threadIdx.x == 0) *out = v;
 }
 
+// out[i * ld + j] = entry (r0 + i, c0 + j) of a Gaussian sketch in FP32:
+// counter (r0 + i, c0 + j), or (c0 + j, r0 + i) when swap_ab (the Y layout).
+// Appending rows or columns to a sketch draws exactly the entries a wider
+// sketch would hold there.
+__global__ void k_gauss_sub(int64_t rows, int64_t cols, int64_t r0, int64_t c0, uint64_t seed, uint64_t stream,
+                            int swap_ab, int64_t ld, float* __restrict__ out) {
+  const int64_t total = rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / cols, j = e - i * cols;
+    const double z = swap_ab ? gauss01(c0 + j, r0 + i, stream, seed) : gauss01(r0 + i, c0 + j, stream, seed);
+    out[i * ld + j] = (float)z;
+  }
+}
+
 // Master sketches of a batched call, seed read from the device header so the
 // captured graph serves every seed: X[i][j] (n_max x k) from counter (i, j)
 // of the X stream and Y[i][j] (l x m_max) from counter (j, i) of the Y
@@ -233,14 +247,14 @@ re_status launch_gemm_f32_persistent(hipStream_t s, const GemmDesc* desc, int nb
 }
 
 re_status launch_gemm_f32_single(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t lda, const float* X,
-                                 int64_t k, float* B, GemmDesc* dscratch, unsigned* queue) {
+                                 int64_t k, float* B, int64_t ldb, GemmDesc* dscratch, unsigned* queue) {
   GemmDesc d;
   d.A = A;
   d.B = B;
   d.m = m;
   d.n = n;
   d.lda = lda;
-  d.ldb = k;
+  d.ldb = ldb;
   d.item0 = 0;
   d.ncc = gemm_col_chunks(k);
   hipLaunchKernelGGL(k_put_desc<GemmDesc>, dim3(1), dim3(64), 0, s, d, dscratch);
@@ -249,15 +263,26 @@ re_status launch_gemm_f32_single(hipStream_t s, const float* A, int64_t m, int64
   return launch_gemm_f32_persistent(s, dscratch, 1, X, k, total, queue, 4, (int)g, 32);
 }
 
-re_status launch_ygemm_single(hipStream_t s, const float* B, int64_t m, int64_t k, const float* Y, int64_t ldy,
-                              int64_t l, double* C, YDesc* dscratch) {
+re_status launch_ygemm_single(hipStream_t s, const float* B, int64_t m, int64_t k, int64_t ldb, const float* Y,
+                              int64_t ldy, int64_t l, double* C, YDesc* dscratch) {
   YDesc d;
   d.B = B;
   d.C = C;
   d.m = m;
-  d.ldb = k;
+  d.ldb = ldb;
   hipLaunchKernelGGL(k_put_desc<YDesc>, dim3(1), dim3(64), 0, s, d, dscratch);
   return launch_ygemm_batched(s, dscratch, 1, Y, ldy, l, k);
+}
+
+re_status launch_gauss_sub(hipStream_t s, int64_t rows, int64_t cols, int64_t r0, int64_t c0, uint64_t seed,
+                           int stream_id, int swap_ab, int64_t ld, float* out) {
+  const int64_t total = rows * cols;
+  if (total <= 0) return RE_OK;
+  const int64_t g = cdiv(total, 256) < 8192 ? cdiv(total, 256) : 8192;
+  hipLaunchKernelGGL(k_gauss_sub, dim3((unsigned)g), dim3(256), 0, s, rows, cols, r0, c0, seed, (uint64_t)stream_id,
+                     swap_ab, ld, out);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
 }
 
 re_status launch_gauss_master(hipStream_t s, const BatchHeader* hdr, int64_t nmax, int64_t k, int64_t l, int64_t mmax,

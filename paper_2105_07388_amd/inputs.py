@@ -194,3 +194,45 @@ def kernel_blocks(nblocks: int, seed: int = 1004, device="cpu", **kw) -> tuple[t
         kernel_block(p, device, out=v)
         views.append(v)
     return buf, views, params
+
+
+# --- the learned sketch-size set --------------------------------------------------
+
+def learned_params(count: int, seed: int = 1005, m_lo: int = 4096, m_hi: int = 65536,
+                   r_cap: int = 2000) -> list[dict]:
+    """Matrix recipes for the learned policy: m log-uniform in [m_lo, m_hi]
+    (a multiple of 256), n = m / 4, decay uniform over {poly, exp, step}, a
+    target eps log-uniform in [1e-6, 1e-2] and a target rank r log-uniform in
+    [10, min(r_cap, n / 4)] that the spectrum realises at that eps."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        m = int(np.exp(rng.uniform(np.log(m_lo), np.log(m_hi))) // 256 * 256)
+        m = max(m, 256)
+        n = m // 4
+        rmax = max(10, min(r_cap, n // 4))
+        r = int(round(np.exp(rng.uniform(np.log(10), np.log(rmax)))))
+        eps = float(np.exp(rng.uniform(np.log(1e-6), np.log(1e-2))))
+        decay = ("poly", "exp", "step")[int(rng.integers(0, 3))]
+        out.append(dict(m=m, n=n, r=r, eps=eps, decay=decay, R=min(n, 2 * r + 64), seed=int(seed * 100003 + i)))
+    return out
+
+
+def learned_spectrum(p: dict) -> np.ndarray:
+    """sigma_1 = 1 and rank_eps = r exactly: poly s_i = i^-a with
+    a = -ln(eps) / ln(r + 1/2); exp s_i = 10^(-q (i - 1)) with
+    q = -log10(eps) / (r - 1/2); step: 1 for i <= r, then 1e-3 eps."""
+    R, r, eps = p["R"], p["r"], p["eps"]
+    i = np.arange(1, R + 1, dtype=np.float64)
+    if p["decay"] == "poly":
+        return i ** (np.log(eps) / np.log(r + 0.5))
+    if p["decay"] == "exp":
+        return 10.0 ** (np.log10(eps) / (r - 0.5) * (i - 1))
+    s = np.full(R, 1e-3 * eps)
+    s[:r] = 1.0
+    return s
+
+
+def learned_matrix(p: dict, device="cpu") -> torch.Tensor:
+    """FP32 m x n = U diag(learned_spectrum(p)) V^T."""
+    return planted(p["m"], p["n"], learned_spectrum(p), p["seed"], torch.float32, 0.0, device)

@@ -96,9 +96,9 @@ def test_doubling_converges_at_first_sufficient_width(L, orc, rank, rounds, kfin
 def test_learned_round_uses_the_proposal(L):
     A = inputs.planted(600, 400, inputs.spectrum_step(400, 120, 1.0, 1e-10), 180).numpy()
     p = np.zeros(L.N_PARAMS)
-    L.unpack(p)["b3"][0] = math.log(200.0)  # constant network: proposes 200
+    L.unpack(p)["b3"][0] = math.log(197.5)  # constant network: proposes 200
     out = L.doubling(A, 1e-6, seed=5, params=p)
     assert (out["rounds"], out["k"], out["r"], out["k_proposed"]) == (2, 200, 120, 200)
-    L.unpack(p)["b3"][0] = math.log(100.0)  # too small: doubling continues from 104
+    L.unpack(p)["b3"][0] = math.log(97.5)  # too small: doubling continues from 104
     out = L.doubling(A, 1e-6, seed=5, params=p)
     assert (out["rounds"], out["k"], out["r"], out["k_proposed"]) == (3, 208, 120, 104)
