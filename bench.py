@@ -38,6 +38,10 @@ WORKLOADS = {
                desc="batched form: 4096 FP32 blocks of 1/|x-y| between two separated uniform 2-D clusters, m, n "
                     "uniform in [256, 4096], Gaussian X 96 columns and Y 144 rows per block, eps 1e-6, one "
                     "graph launch per batch"),
+    "c5": dict(count=24, m_lo=4096, m_hi=65536, r_cap=2000, k0=32, eps=(None,), x="gaussian", y="gaussian",
+               desc="learned sketch width: planted FP32 matrices (m log-uniform in [4096, 65536], n = m/4, poly / exp "
+                    "/ step decay, planted rank in [10, 2000] at eps in [1e-6, 1e-2]), Gaussian sketches, pilot "
+                    "k = 32, l = 1.5 k; the trained network with doubling fallback against doubling from 32"),
     "c1": dict(m=2000, n=1000, R=1000, k=40, l=60, eps=(1e-6,), x="gaussian", y="gaussian",
                desc="plain method, CPU-sized: FP64 2000x1000, step spectrum (20 x 1, then 1e-8), "
                     "Gaussian X 1000x40, Gaussian Y 60x2000, eps 1e-6"),
@@ -214,6 +218,74 @@ def bench_batched(args, w, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_learned(args, w, dev):
+    """One step = the adaptive estimate of every matrix of a fixed set of
+    recipes (unseen in training), with the trained network; doubling timed on
+    the same matrices and seeds for comparison."""
+    import numpy as np
+    import torch
+
+    import paper_2105_07388_amd as re_
+    from paper_2105_07388_amd import inputs, learned
+
+    policy, delta = learned.load_policy(device=dev)
+    recipes = inputs.learned_params(w["count"], seed=2005, m_lo=w["m_lo"], m_hi=w["m_hi"], r_cap=w["r_cap"])
+    mats = [inputs.learned_matrix(p, device=dev) for p in recipes]
+    truth = [int(np.count_nonzero(inputs.learned_spectrum(p) > p["eps"])) for p in recipes]
+    torch.cuda.synchronize()
+    print(f"[bench] c5: {len(mats)} matrices, {sum(A.numel() for A in mats) * 4 / 1e9:.1f} GB resident; "
+          f"warmup {args.warmup}", file=sys.stderr, flush=True)
+    h = re_.Handle(dev)
+
+    def one_pass(mlp, seed0):
+        out = []
+        for i, (A, p) in enumerate(zip(mats, recipes)):
+            r, _, info = re_.rank_adaptive(A, p["eps"], k_max=min(A.shape[1], 4096), mlp=mlp, delta=delta,
+                                           seed=seed0 + i, handle=h)
+            out.append((r, info["rounds"], info["k"]))
+        return out
+
+    res = {}
+    for name, mlp in (("learned", policy), ("doubling", None)):
+        for i in range(args.warmup):
+            one_pass(mlp, 500 + i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            runs = one_pass(mlp, 1000 * (i + 1))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = {"estimates_per_s": len(mats) * args.steps / el, "ms_per_pass": 1e3 * el / args.steps,
+                     "mean_rounds": float(np.mean([r[1] for r in runs])),
+                     "mean_k_final": float(np.mean([r[2] for r in runs])),
+                     "rank_agreement": float(np.mean([r[0] == t for r, t in zip(runs, truth)])),
+                     "ranks": [r[0] for r in runs]}
+    same = float(np.mean([a == b for a, b in zip(res["learned"]["ranks"], res["doubling"]["ranks"])]))
+    for v in res.values():
+        v.pop("ranks")
+    print(f"[bench] learned {res['learned']}; doubling {res['doubling']}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "rank estimates/s + sketch GB/s vs HBM peak; learned vs doubling, same rank",
+        "value": res["learned"]["estimates_per_s"],
+        "unit": "rank estimates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["learned"]["ms_per_pass"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "matrices": len(mats), "delta": delta, "parallelism": "single GPU"},
+        "learned": res["learned"],
+        "doubling": res["doubling"],
+        "speedup_vs_doubling": res["learned"]["estimates_per_s"] / res["doubling"]["estimates_per_s"],
+        "same_rank_learned_vs_doubling": same,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +315,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "c4":
         return bench_batched(args, w, dev)
+    if args.workload == "c5":
+        return bench_learned(args, w, dev)
     A = make_matrix(args.workload, w, dev)
     torch.cuda.synchronize()
     if args.calib_copy_gib > 0:

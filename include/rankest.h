@@ -159,20 +159,23 @@ typedef struct {
  * (block, row tile, column chunk) items; the Y B products, small SVDs and
  * counts run one workgroup per block.  The work is captured once into a HIP
  * graph (re-captured when the shapes or the workspace change) and the tile
- * shape of the persistent kernel (wavefronts per workgroup, K step, resident
- * workgroups) is chosen by timing the candidates on the first call for a size
- * bucket (cached in the handle, and in the JSON file named by
- * RANKEST_AUTOTUNE_CACHE when that variable is set; RANKEST_BATCH_TILE =
- * "waves:kstep:workgroups per CU" pins it).  With profiling on, the same
+ * shape of the persistent kernel (wavefronts per workgroup, 32-row tiles per
+ * wavefront, K step, resident workgroups) is chosen by timing the candidates
+ * on the first call for a size bucket (cached in the handle, and in the JSON
+ * file named by RANKEST_AUTOTUNE_CACHE when that variable is set;
+ * RANKEST_BATCH_TILE = "waves:tiles:kstep:workgroups per CU" pins it).  With profiling on, the same
  * launches are issued directly on the stream so that stage events separate
  * them.
  *   blocks     host array of nblocks descriptors (k <= n_b, l <= m_b each)
  *   r_out      host, nblocks: rank estimates
  *   sigma_out  host, nblocks * k: estimates of block b at b * k
  *   flags_out  host or NULL, nblocks: RE_FLAG_* bits
- * Errors as re_rank_estimate; RE_ERR_UNSUPPORTED for SRHT sketches, FP64
- * blocks, low precision, or an l x k sketch too large for one workgroup.
- * Synchronises the handle's stream.
+ * Argument errors as re_rank_estimate (every block checked before any work;
+ * outputs untouched); RE_ERR_UNSUPPORTED for SRHT sketches, FP64 blocks, low
+ * precision, or an l x k sketch too large for one workgroup.  When a block's
+ * sketch is not finite, the outputs of all blocks are written, that block's
+ * r is -1, and the call returns RE_ERR_NONFINITE.  Synchronises the handle's
+ * stream.
  */
 re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, int32_t nblocks, int32_t dt, double eps,
                                    const re_sketch* sk, uint64_t seed, int32_t* r_out, double* sigma_out,

@@ -31,7 +31,7 @@ struct re_handle_s {
   hipGraphExec_t bexec = nullptr;
   std::string bkey;
   struct Tile {
-    int waves, bk, grid;
+    int waves, mt, bk, grid;  // wavefronts, 32-row tiles per wavefront, K step, resident workgroups
   };
   std::map<std::string, Tile> tuned;  // shape key -> persistent contraction tile
 };
@@ -152,7 +152,7 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   p.sigma = c.take((size_t)rs.k * 8);
   p.info = c.take(16);
   p.out3 = c.take(16);
-  p.stats = c.take(32);
+  p.stats = c.take((4 + 2 * 256) * 8);  // sampled statistics and their per-workgroup partials
   p.gdesc = c.take(sizeof(GemmDesc));
   p.ydesc = c.take(sizeof(YDesc));
   p.queue = c.take(16);
@@ -438,7 +438,10 @@ int device_cus(int dev) {
   return cus;
 }
 
-// Autotuner cache file: one JSON object, one "key": [waves, bk, grid] entry per line.
+// Tile shapes the persistent contraction is instantiated for.
+bool tile_ok(int w, int mt, int bk) { return (w == 4 || w == 8) && ((mt == 1 && (bk == 16 || bk == 32)) || (mt == 2 && bk == 16)); }
+
+// Autotuner cache file: one JSON object, one "key": [waves, mt, bk, grid] entry per line.
 void load_tune_cache(re_handle h) {
   const char* path = getenv("RANKEST_AUTOTUNE_CACHE");
   if (!path) return;
@@ -447,10 +450,10 @@ void load_tune_cache(re_handle h) {
   char line[512];
   while (fgets(line, sizeof(line), f)) {
     char key[256];
-    int w = 0, bk = 0, g = 0;
-    if (sscanf(line, " \"%255[^\"]\" : [ %d , %d , %d ]", key, &w, &bk, &g) == 4 && (w == 4 || w == 8) &&
-        (bk == 16 || bk == 32) && g > 0)
-      h->tuned[key] = {w, bk, g};
+    int w = 0, mt = 0, bk = 0, g = 0;
+    if (sscanf(line, " \"%255[^\"]\" : [ %d , %d , %d , %d ]", key, &w, &mt, &bk, &g) == 5 && tile_ok(w, mt, bk) &&
+        g > 0)
+      h->tuned[key] = {w, mt, bk, g};
   }
   fclose(f);
 }
@@ -463,8 +466,8 @@ void save_tune_cache(re_handle h) {
   fprintf(f, "{\n");
   size_t i = 0;
   for (const auto& kv : h->tuned)
-    fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.waves, kv.second.bk, kv.second.grid,
-            ++i < h->tuned.size() ? "," : "");
+    fprintf(f, "  \"%s\": [%d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second.waves, kv.second.mt, kv.second.bk,
+            kv.second.grid, ++i < h->tuned.size() ? "," : "");
   fprintf(f, "}\n");
   fclose(f);
 }
@@ -472,7 +475,7 @@ void save_tune_cache(re_handle h) {
 // Fills the host image of the descriptor region for tile height 32 * waves;
 // returns the total number of work items.
 int64_t fill_batch_desc(char* img, const BatchPlan& p, char* ws, const re_block* blocks, int nb, int64_t k, int64_t l,
-                        double eps, uint64_t seed, int waves) {
+                        double eps, uint64_t seed, int rows_per_item) {
   BatchHeader* hd = (BatchHeader*)(img + p.hdr);
   hd->seed = seed;
   GemmDesc* gd = (GemmDesc*)(img + p.gdesc);
@@ -501,7 +504,7 @@ int64_t fill_batch_desc(char* img, const BatchPlan& p, char* ws, const re_block*
     gd[b].ldb = k;
     gd[b].item0 = item;
     gd[b].ncc = gemm_col_chunks(k);
-    item += gemm_items(bl.m, k, waves);
+    item += gemm_items(bl.m, k, rows_per_item);
     yd[b].B = Bb;
     yd[b].C = Cb;
     yd[b].m = bl.m;
@@ -529,7 +532,7 @@ int64_t fill_batch_desc(char* img, const BatchPlan& p, char* ws, const re_block*
 // SVDs, counts, results to the host.  With profiling on, the same sequence is
 // issued directly on the stream with stage events between the launches.
 re_status enqueue_batch(re_handle h, hipStream_t s, const BatchPlan& p, int nb, int64_t k, int64_t l, int64_t nmax,
-                        int64_t mmax, int64_t total, int waves, int grid, int bk, void* host_res) {
+                        int64_t mmax, int64_t total, const re_handle_s::Tile& tl, int grid, void* host_res) {
   char* ws = (char*)h->ws;
   char* dsc = ws + p.desc0;
   float* X = (float*)(ws + p.X);
@@ -542,7 +545,7 @@ re_status enqueue_batch(re_handle h, hipStream_t s, const BatchPlan& p, int nb, 
   RE_TRY(launch_gauss_master(s, (const BatchHeader*)(dsc + p.hdr), nmax, k, l, mmax, X, Y));
   RE_TRY(ev(RE_STAGE_AX));
   RE_TRY(launch_gemm_f32_persistent(s, (const GemmDesc*)(dsc + p.gdesc), nb, X, k, total, (unsigned*)(ws + p.queue),
-                                    waves, grid, bk));
+                                    tl.waves, grid, tl.bk, tl.mt));
   RE_TRY(ev(RE_STAGE_Y_DRAW));
   RE_TRY(ev(RE_STAGE_YB));
   RE_TRY(launch_ygemm_batched(s, (const YDesc*)(dsc + p.ydesc), nb, Y, mmax, l, k));
@@ -585,7 +588,7 @@ RE_API re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, i
     mmax = bl.m > mmax ? bl.m : mmax;
     brows += (bl.m + 63) / 64 * 64;
   }
-  if (gemm_items(brows, k, 4) >= (int64_t)INT32_MAX) return RE_ERR_INVALID_ARG;
+  if (gemm_items(brows, k, 32) >= (int64_t)INT32_MAX) return RE_ERR_INVALID_ARG;
   const BatchPlan p = batch_plan(nblocks, k, l, nmax, mmax, brows);
   const void* old_ws = h->ws;
   RE_TRY(ensure_ws(h, p.total));
@@ -602,31 +605,30 @@ RE_API re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, i
 
   // autotune the persistent contraction for this size bucket
   const int cus = device_cus(h->device);
-  const int64_t items4 = gemm_items(brows, k, 4);
+  const int64_t items4 = gemm_items(brows, k, 128);
   int lg = 0;
   while ((int64_t(1) << lg) < items4) ++lg;
   char key[128];
   snprintf(key, sizeof(key), "gfx950:f32:k%lld:items2^%d", (long long)k, lg);
-  // RANKEST_BATCH_TILE="waves:bk:grid per CU" pins the tile shape (tuning sweeps, tests)
+  // RANKEST_BATCH_TILE="waves:mt:bk:grid per CU" pins the tile shape (tuning sweeps, tests)
   if (const char* pin = getenv("RANKEST_BATCH_TILE")) {
-    int w = 0, bk = 0, gm = 0;
-    if (sscanf(pin, "%d:%d:%d", &w, &bk, &gm) != 3 || (w != 4 && w != 8) || (bk != 16 && bk != 32) || gm < 1 ||
-        gm > 64)
+    int w = 0, mt = 0, bk = 0, gm = 0;
+    if (sscanf(pin, "%d:%d:%d:%d", &w, &mt, &bk, &gm) != 4 || !tile_ok(w, mt, bk) || gm < 1 || gm > 64)
       return RE_ERR_INVALID_ARG;
-    h->tuned[key] = {w, bk, gm * cus};
+    h->tuned[key] = {w, mt, bk, gm * cus};
   }
   auto it = h->tuned.find(key);
   if (it == h->tuned.end()) {
-    const int cand[5][3] = {{4, 16, 2}, {4, 16, 3}, {4, 32, 2}, {8, 16, 2}, {8, 32, 1}};
+    const int cand[7][4] = {{4, 1, 16, 2}, {4, 1, 16, 3}, {4, 1, 32, 2}, {8, 1, 16, 2},
+                            {4, 2, 16, 2}, {4, 2, 16, 3}, {8, 2, 16, 1}};
     hipEvent_t e0, e1;
     RE_TRY_HIP(hipEventCreate(&e0));
     RE_TRY_HIP(hipEventCreate(&e1));
     float best = 1e30f;
-    re_handle_s::Tile pick{4, 32, 2 * cus};
+    re_handle_s::Tile pick{4, 1, 16, 2 * cus};
     for (const auto& c : cand) {
-      const int w = c[0];
-      const int64_t tot = fill_batch_desc(img, p, ws, blocks, nblocks, k, l, eps, seed, w);
-      const int g = (int)(tot < (int64_t)c[2] * cus ? tot : (int64_t)c[2] * cus);
+      const int64_t tot = fill_batch_desc(img, p, ws, blocks, nblocks, k, l, eps, seed, 32 * c[0] * c[1]);
+      const int g = (int)(tot < (int64_t)c[3] * cus ? tot : (int64_t)c[3] * cus);
       RE_TRY_HIP(hipMemcpyAsync(ws + p.desc0, img, p.desc_bytes, hipMemcpyHostToDevice, s));
       RE_TRY(launch_gauss_master(s, (const BatchHeader*)(ws + p.desc0 + p.hdr), nmax, k, l, mmax, (float*)(ws + p.X),
                                  (float*)(ws + p.Y)));
@@ -634,14 +636,14 @@ RE_API re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, i
       for (int rep = 0; rep < 2; ++rep) {
         RE_TRY_HIP(hipEventRecord(e0, s));
         RE_TRY(launch_gemm_f32_persistent(s, (const GemmDesc*)(ws + p.desc0 + p.gdesc), nblocks, (const float*)(ws + p.X),
-                                          k, tot, (unsigned*)(ws + p.queue), w, g, c[1]));
+                                          k, tot, (unsigned*)(ws + p.queue), c[0], g, c[2], c[1]));
         RE_TRY_HIP(hipEventRecord(e1, s));
         RE_TRY_HIP(hipEventSynchronize(e1));
         RE_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
       }
       if (ms < best) {
         best = ms;
-        pick = {w, c[1], c[2] * cus};
+        pick = {c[0], c[1], c[2], c[3] * cus};
       }
     }
     (void)hipEventDestroy(e0);
@@ -650,23 +652,23 @@ RE_API re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, i
     save_tune_cache(h);
     it = h->tuned.find(key);
   }
-  const int waves = it->second.waves, bk = it->second.bk;
-  const int64_t total = fill_batch_desc(img, p, ws, blocks, nblocks, k, l, eps, seed, waves);
-  const int grid = (int)(total < it->second.grid ? total : it->second.grid);
+  const re_handle_s::Tile tl = it->second;
+  const int64_t total = fill_batch_desc(img, p, ws, blocks, nblocks, k, l, eps, seed, 32 * tl.waves * tl.mt);
+  const int grid = (int)(total < tl.grid ? total : tl.grid);
 
   // (re)capture when anything baked into the graph changed
   char gkey[256];
-  snprintf(gkey, sizeof(gkey), "%p %p %d %lld %lld %lld %lld %lld %lld %d %d %d", (void*)ws, (void*)host_res, nblocks,
-           (long long)k, (long long)l, (long long)nmax, (long long)mmax, (long long)brows, (long long)total, waves, grid,
-           bk);
+  snprintf(gkey, sizeof(gkey), "%p %p %d %lld %lld %lld %lld %lld %lld %d %d %d %d", (void*)ws, (void*)host_res, nblocks,
+           (long long)k, (long long)l, (long long)nmax, (long long)mmax, (long long)brows, (long long)total, tl.waves,
+           tl.mt, tl.bk, grid);
   if (h->prof) {  // eager issue of the same launches, stage events in between
     RE_TRY_HIP(hipMemcpyAsync(ws + p.desc0, img, p.desc_bytes, hipMemcpyHostToDevice, s));
-    RE_TRY(enqueue_batch(h, s, p, nblocks, k, l, nmax, mmax, total, waves, grid, bk, host_res));
+    RE_TRY(enqueue_batch(h, s, p, nblocks, k, l, nmax, mmax, total, tl, grid, host_res));
   } else if (!h->bexec || h->bkey != gkey) {
     drop_graph(h);
     RE_TRY_HIP(hipStreamSynchronize(s));
     RE_TRY_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
-    const re_status st = enqueue_batch(h, h->cap, p, nblocks, k, l, nmax, mmax, total, waves, grid, bk, host_res);
+    const re_status st = enqueue_batch(h, h->cap, p, nblocks, k, l, nmax, mmax, total, tl, grid, host_res);
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(h->cap, &g);
     if (st != RE_OK || ce != hipSuccess) {

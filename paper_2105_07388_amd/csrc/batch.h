@@ -64,8 +64,9 @@ __attribute__((visibility("hidden"))) re_status launch_gauss_master(hipStream_t 
                                                                    float* Y);
 __attribute__((visibility("hidden"))) re_status launch_gemm_f32_persistent(hipStream_t s, const GemmDesc* desc, int nblk,
                                                                           const float* X, int64_t k, int64_t total,
-                                                                          unsigned* queue, int waves, int grid, int bk);
-__attribute__((visibility("hidden"))) int64_t gemm_items(int64_t m, int64_t k, int waves);
+                                                                          unsigned* queue, int waves, int grid, int bk,
+                                                                          int mt);
+__attribute__((visibility("hidden"))) int64_t gemm_items(int64_t m, int64_t k, int rows_per_item);
 __attribute__((visibility("hidden"))) int gemm_col_chunks(int64_t k);
 __attribute__((visibility("hidden"))) re_status launch_ygemm_batched(hipStream_t s, const YDesc* desc, int nblk,
                                                                     const float* Y, int64_t ldy, int64_t l, int64_t k);

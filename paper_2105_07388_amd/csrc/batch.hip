@@ -13,6 +13,13 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// Pointers read from descriptor tables are generic; the casts below let the
+// compiler emit global (not flat) memory instructions for them, so that the
+// LDS waits of the inner loops do not also wait for in-flight prefetches.
+typedef const float __attribute__((address_space(1)))* gcfloat;
+typedef float __attribute__((address_space(1)))* gfloat;
+typedef double __attribute__((address_space(1)))* gdouble;
+
 
 // Block of a work item: the last b with desc[b].item0 <= item.
 __device__ __forceinline__ int find_block(const GemmDesc* __restrict__ desc, int nblk, int64_t item) {
@@ -26,18 +33,19 @@ __device__ __forceinline__ int find_block(const GemmDesc* __restrict__ desc, int
 }
 
 // Persistent FP32 MFMA contraction.  A workgroup of WAVES wavefronts takes
-// items from an atomic queue; an item is 32*WAVES rows of one block by up to
-// 32*NT columns, swept along K in steps of kBK through double-buffered LDS
+// items from an atomic queue; an item is 32 MT WAVES rows of one block by up
+// to 32 NT columns, swept along K in steps of kBK through double-buffered LDS
 // tiles.  Every output is the same sequence of MFMA accumulations whatever
-// WAVES and kBK are, so the tile shape never changes the result.  Wavefront w owns 32 rows and NT 32x32 accumulator tiles
+// WAVES, MT and kBK are, so the tile shape never changes the result.
+// Wavefront w owns 32 MT rows and MT x NT 32x32 accumulator tiles
 // (v_mfma_f32_32x32x2_f32: lane l holds row / column l % 32 and K index l / 32
 // of the operands; accumulator q of lane l is row 8 (q/4) + 4 (l/32) + q%4,
 // column l % 32).
-template <int WAVES, int NT, int kBK>
+template <int WAVES, int NT, int kBK, int MT>
 __global__ void __launch_bounds__(64 * WAVES) k_gemm_f32_persistent(const GemmDesc* __restrict__ desc, int nblk,
                                                                     const float* __restrict__ X, int64_t k,
                                                                     int64_t total, unsigned* __restrict__ queue) {
-  constexpr int BM = 32 * WAVES, BN = 32 * NT, NTH = 64 * WAVES;
+  constexpr int BM = 32 * MT * WAVES, BN = 32 * NT, NTH = 64 * WAVES;
   constexpr int kApad = kBK + 1;  // LDS row pitch of the A tile (floats)
   __shared__ float sA[2][BM * kApad];
   __shared__ float sX[2][kBK * BN];
@@ -58,7 +66,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_gemm_f32_persistent(const GemmDe
     const int rows_here = (int)(m - row0 < BM ? m - row0 : BM);
     // 32-bit offsets inside the item (the host keeps BM * lda below 2^31)
     const unsigned lda = (unsigned)d.lda;
-    const float* __restrict__ Ab = d.A + row0 * d.lda;
+    const gcfloat Ab = (gcfloat)(d.A + row0 * d.lda);
 
     // A: thread t loads PER consecutive K values of tile row ar
     constexpr int PER = BM * kBK / NTH;
@@ -70,7 +78,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_gemm_f32_persistent(const GemmDe
     float ra[PER];
     float rx[PX];
     auto load = [&](int64_t k0) {
-      const float* __restrict__ sa = Ab + ar * lda + (k0 + ak);
+      const gcfloat sa = Ab + ar * lda + (k0 + ak);
       if (ar < rows_here && k0 + ak + PER <= n) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) ra[q] = sa[q];
@@ -93,11 +101,13 @@ __global__ void __launch_bounds__(64 * WAVES) k_gemm_f32_persistent(const GemmDe
 #pragma unroll
       for (int q = 0; q < PX; ++q) sX[buf][xr * BN + xc + q] = rx[q];
     };
-    f32x16 acc[NT];
+    f32x16 acc[MT][NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[t][q] = 0.0f;
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[mi][t][q] = 0.0f;
     const int64_t nsteps = (n + kBK - 1) / kBK;
     load(0);
     store(0);
@@ -107,26 +117,33 @@ __global__ void __launch_bounds__(64 * WAVES) k_gemm_f32_persistent(const GemmDe
       if (st + 1 < nsteps) load((st + 1) * kBK);
 #pragma unroll
       for (int kk = 0; kk < kBK; kk += 2) {
-        const float a = sA[buf][(32 * wave + (lane & 31)) * kApad + kk + (lane >> 5)];
+        float a[MT];
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi)
+          a[mi] = sA[buf][(32 * (MT * wave + mi) + (lane & 31)) * kApad + kk + (lane >> 5)];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const float xb = sX[buf][(kk + (lane >> 5)) * BN + 32 * t + (lane & 31)];
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, xb, acc[t], 0, 0, 0);
+#pragma unroll
+          for (int mi = 0; mi < MT; ++mi)
+            acc[mi][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mi], xb, acc[mi][t], 0, 0, 0);
         }
       }
       if (st + 1 < nsteps) store(buf ^ 1);
       __syncthreads();
     }
-    float* __restrict__ Bo = d.B;
+    const gfloat Bo = (gfloat)d.B;
     const int64_t ldb = d.ldb;
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int64_t r = row0 + 32 * wave + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-        const int64_t c = col0 + 32 * t + (lane & 31);
-        if (r < m && c < k) Bo[r * ldb + c] = acc[t][q];
-      }
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int64_t r = row0 + 32 * (MT * wave + mi) + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+          const int64_t c = col0 + 32 * t + (lane & 31);
+          if (r < m && c < k) Bo[r * ldb + c] = acc[mi][t][q];
+        }
   }
 }
 
@@ -175,72 +192,122 @@ __global__ void k_gauss_master(const BatchHeader* __restrict__ hdr, int64_t nmax
 }
 
 // C_b (l x k, FP64) = Y[:, :m_b] (FP32, leading dimension ldy) B_b (m_b x k,
-// FP32), FP64 accumulation; one workgroup per (block, 64-row slice of C_b).
-constexpr int kYM = 64, kYN = 96, kYK = 16;
-__global__ void __launch_bounds__(256) k_ygemm_batched(const YDesc* __restrict__ desc, const float* __restrict__ Y,
-                                                       int64_t ldy, int64_t l, int64_t k) {
-  __shared__ double sy[kYK][kYM + 1];
-  __shared__ double sb[kYK][kYN + 1];
+// FP32) on the FP64 matrix cores (v_mfma_f64_16x16x4f64: lane q holds
+// operand row / column q % 16 at K index q / 16; accumulator r of lane q is
+// row q / 16 + 4 r, column q % 16, as measured on gfx950).  One workgroup per (block, slab of
+// 16 * waves rows of C); wavefront w owns rows 16 w .. 16 w + 15 of the slab
+// and up to six 16-column tiles; K runs over m in chunks of 16 staged in LDS
+// as FP64 (the FP32 products are exact in FP64).  The sum over m is taken in
+// the same order for every block, so a batch and a single call agree.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kYKC = 16;                 // K per chunk
+constexpr int kYNT = 6, kYN = 16 * kYNT;  // column tiles per pass
+constexpr int kYApad = kYKC + 1, kYBpad = kYN + 4;
+constexpr int kYMinWaves = 4, kYMaxWaves = 9;
+
+__global__ void __launch_bounds__(64 * kYMaxWaves) k_ygemm_mfma(const YDesc* __restrict__ desc,
+                                                                const float* __restrict__ Y, int64_t ldy, int64_t l,
+                                                                int64_t k) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int waves = blockDim.x >> 6, nth = blockDim.x;
+  const int rows = 16 * waves;
+  double* sY = reinterpret_cast<double*>(smem_raw);  // [2][rows][kYApad]
+  double* sB = sY + 2 * rows * kYApad;                // [2][kYKC][kYBpad]
   const YDesc d = desc[blockIdx.y];
-  const int64_t s0 = (int64_t)blockIdx.x * kYM;
-  if (s0 >= l) return;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;  // 16 x 16 threads, 4 x 6 outputs each
+  const int64_t s0 = (int64_t)blockIdx.x * rows;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q16 = lane & 15, kq = lane >> 4;
+  const int64_t m = d.m;
+  const int64_t nchunks = (m + kYKC - 1) / kYKC;
+  // register staging: the next chunk's loads are in flight while the
+  // matrix cores work on the current one
+  constexpr int kPerY = 4;                          // rows * 16 / (64 * waves)
+  constexpr int kMaxPerB = kYKC * kYN / (64 * kYMinWaves);  // 6
+  const int perB = (kYKC * kYN + nth - 1) / nth;
+  const int yr = (tid * kPerY) / kYKC, yc = (tid * kPerY) % kYKC;
   for (int64_t c0 = 0; c0 < k; c0 += kYN) {
-    double acc[4][6] = {};
-    for (int64_t i0 = 0; i0 < d.m; i0 += kYK) {
-      for (int e = threadIdx.x; e < kYM * kYK; e += 256) {
-        const int r = e / kYK, c = e % kYK;
-        const int64_t gs = s0 + r, gi = i0 + c;
-        sy[c][r] = (gs < l && gi < d.m) ? (double)Y[gs * ldy + gi] : 0.0;
+    float ry[kPerY], rb[kMaxPerB];
+    const bool yrow_ok = s0 + yr < l;
+    const float* __restrict__ yrow = Y + (yrow_ok ? s0 + yr : 0) * ldy;
+    const unsigned ldb = (unsigned)d.ldb;  // 16 rows of B per chunk: 32-bit offsets
+    auto load = [&](int64_t i0) {
+#pragma unroll
+      for (int q = 0; q < kPerY; ++q) {
+        const int64_t gi = i0 + yc + q;
+        ry[q] = (yrow_ok && gi < m) ? yrow[gi] : 0.0f;
       }
-      for (int e = threadIdx.x; e < kYK * kYN; e += 256) {
-        const int r = e / kYN, c = e % kYN;
-        const int64_t gi = i0 + r, gc = c0 + c;
-        sb[r][c] = (gi < d.m && gc < k) ? (double)d.B[gi * d.ldb + gc] : 0.0;
+      const gcfloat bch = (gcfloat)(d.B + i0 * d.ldb + c0);
+#pragma unroll
+      for (int q = 0; q < kMaxPerB; ++q) {
+        const int e = tid + q * nth;
+        if (q < perB) {
+          const int r = e / kYN, c = e % kYN;
+          rb[q] = (e < kYKC * kYN && i0 + r < m && c0 + c < k) ? bch[r * ldb + c] : 0.0f;
+        }
       }
-      __syncthreads();
+    };
+    auto store = [&](int buf) {
+      double* y = sY + buf * rows * kYApad;
 #pragma unroll
-      for (int kk = 0; kk < kYK; ++kk) {
-        double a[4], bb[6];
+      for (int q = 0; q < kPerY; ++q) y[yr * kYApad + yc + q] = (double)ry[q];
+      double* bb = sB + buf * kYKC * kYBpad;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = sy[kk][ty + 16 * i];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) bb[j] = sb[kk][tx + 16 * j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 6; ++j) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
+      for (int q = 0; q < kMaxPerB; ++q) {
+        const int e = tid + q * nth;
+        if (q < perB && e < kYKC * kYN) bb[(e / kYN) * kYBpad + e % kYN] = (double)rb[q];
       }
+    };
+    f64x4 acc[kYNT];
+#pragma unroll
+    for (int t = 0; t < kYNT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+      const int buf = ch & 1;
+      if (ch + 1 < nchunks) load((ch + 1) * kYKC);
+      const double* y = sY + buf * rows * kYApad + (16 * wave + q16) * kYApad;
+      const double* bb = sB + buf * kYKC * kYBpad;
+#pragma unroll
+      for (int kk = 0; kk < kYKC; kk += 4) {
+        const double av = y[kk + kq];
+#pragma unroll
+        for (int t = 0; t < kYNT; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bb[(kk + kq) * kYBpad + 16 * t + q16], acc[t], 0, 0, 0);
+      }
+      if (ch + 1 < nchunks) store(buf ^ 1);
       __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int t = 0; t < kYNT; ++t)
 #pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        const int64_t gs = s0 + ty + 16 * i, gc = c0 + tx + 16 * j;
-        if (gs < l && gc < k) d.C[gs * k + gc] = acc[i][j];
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gs = s0 + 16 * wave + kq + 4 * r, gc = c0 + 16 * t + q16;
+        if (gs < l && gc < k) ((gdouble)d.C)[gs * k + gc] = acc[t][r];
       }
+    __syncthreads();
   }
 }
 
 }  // namespace
 
 re_status launch_gemm_f32_persistent(hipStream_t s, const GemmDesc* desc, int nblk, const float* X, int64_t k,
-                                     int64_t total, unsigned* queue, int waves, int grid, int bk) {
+                                     int64_t total, unsigned* queue, int waves, int grid, int bk, int mt) {
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, queue);
   const int nt = (int)(k >= 128 ? 4 : cdiv(k, 32));
-#define RE_GEMM_CASE(W, N, BK)                                                                                     \
-  if (waves == W && nt == N && bk == BK) {                                                                         \
-    hipLaunchKernelGGL((k_gemm_f32_persistent<W, N, BK>), dim3(grid), dim3(64 * W), 0, s, desc, nblk, X, k, total, \
-                       queue);                                                                                     \
-    RE_TRY_HIP(hipGetLastError());                                                                                 \
-    return RE_OK;                                                                                                  \
+#define RE_GEMM_CASE(W, N, BK, MT)                                                                              \
+  if (waves == W && nt == N && bk == BK && mt == MT) {                                                          \
+    hipLaunchKernelGGL((k_gemm_f32_persistent<W, N, BK, MT>), dim3(grid), dim3(64 * W), 0, s, desc, nblk, X, k, \
+                       total, queue);                                                                           \
+    RE_TRY_HIP(hipGetLastError());                                                                              \
+    return RE_OK;                                                                                               \
   }
-#define RE_GEMM_CASES(BK)                                                                                     \
-  RE_GEMM_CASE(4, 1, BK) RE_GEMM_CASE(4, 2, BK) RE_GEMM_CASE(4, 3, BK) RE_GEMM_CASE(4, 4, BK)                  \
-  RE_GEMM_CASE(8, 1, BK) RE_GEMM_CASE(8, 2, BK) RE_GEMM_CASE(8, 3, BK) RE_GEMM_CASE(8, 4, BK)
-  RE_GEMM_CASES(16)
-  RE_GEMM_CASES(32)
+#define RE_GEMM_CASES(BK, MT)                                                                           \
+  RE_GEMM_CASE(4, 1, BK, MT) RE_GEMM_CASE(4, 2, BK, MT) RE_GEMM_CASE(4, 3, BK, MT) RE_GEMM_CASE(4, 4, BK, MT) \
+  RE_GEMM_CASE(8, 1, BK, MT) RE_GEMM_CASE(8, 2, BK, MT) RE_GEMM_CASE(8, 3, BK, MT) RE_GEMM_CASE(8, 4, BK, MT)
+  RE_GEMM_CASES(16, 1)
+  RE_GEMM_CASES(32, 1)
+  RE_GEMM_CASES(16, 2)
 #undef RE_GEMM_CASES
 #undef RE_GEMM_CASE
   return RE_ERR_INVALID_ARG;
@@ -258,9 +325,9 @@ re_status launch_gemm_f32_single(hipStream_t s, const float* A, int64_t m, int64
   d.item0 = 0;
   d.ncc = gemm_col_chunks(k);
   hipLaunchKernelGGL(k_put_desc<GemmDesc>, dim3(1), dim3(64), 0, s, d, dscratch);
-  const int64_t total = gemm_items(m, k, 4);
+  const int64_t total = gemm_items(m, k, 32 * 4);
   const int64_t g = total < 2048 ? total : 2048;
-  return launch_gemm_f32_persistent(s, dscratch, 1, X, k, total, queue, 4, (int)g, 32);
+  return launch_gemm_f32_persistent(s, dscratch, 1, X, k, total, queue, 4, (int)g, 32, 1);
 }
 
 re_status launch_ygemm_single(hipStream_t s, const float* B, int64_t m, int64_t k, int64_t ldb, const float* Y,
@@ -295,8 +362,8 @@ re_status launch_gauss_master(hipStream_t s, const BatchHeader* hdr, int64_t nma
   return RE_OK;
 }
 
-int64_t gemm_items(int64_t m, int64_t k, int waves) {
-  const int64_t bm = 32 * waves, bn = k >= 128 ? 128 : 32 * cdiv(k, 32);
+int64_t gemm_items(int64_t m, int64_t k, int rows_per_item) {
+  const int64_t bm = rows_per_item, bn = k >= 128 ? 128 : 32 * cdiv(k, 32);
   return cdiv(m, bm) * cdiv(k, bn);
 }
 
@@ -304,9 +371,15 @@ int gemm_col_chunks(int64_t k) { return (int)cdiv(k, k >= 128 ? 128 : 32 * cdiv(
 
 re_status launch_ygemm_batched(hipStream_t s, const YDesc* desc, int nblk, const float* Y, int64_t ldy, int64_t l,
                                int64_t k) {
-  if (nblk <= 0) return RE_OK;
-  hipLaunchKernelGGL(k_ygemm_batched, dim3((unsigned)cdiv(l, kYM), (unsigned)nblk), dim3(256), 0, s, desc, Y, ldy, l,
-                     k);
+  if (nblk <= 0 || l <= 0 || k <= 0) return RE_OK;
+  int waves = (int)(cdiv(l, 16) < kYMaxWaves ? cdiv(l, 16) : kYMaxWaves);
+  if (waves < kYMinWaves) waves = kYMinWaves;
+  const int rows = 16 * waves;
+  const size_t lds = (size_t)(2 * rows * kYApad + 2 * kYKC * kYBpad) * sizeof(double);
+  if (lds > 64 * 1024)
+    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_ygemm_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_ygemm_mfma, dim3((unsigned)cdiv(l, rows), (unsigned)nblk), dim3(64 * waves), lds, s, desc, Y,
+                     ldy, l, k);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
 }

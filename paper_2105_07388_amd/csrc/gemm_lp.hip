@@ -4,8 +4,8 @@
 // inside the FP16 range), X holds Gaussian entries already rounded to the same
 // format, products accumulate in FP32 and B = 2^-s (A_f X) is written in FP32.
 //
-// Tiling: a workgroup owns 64 rows of A and BN = 4 * WN columns of B; each of
-// its four wavefronts owns a 64 x WN block made of 32x32 MFMA tiles
+// Tiling: a workgroup owns 64 WM rows of A and BN = 4 * WN columns of B; each
+// of its 4 WM wavefronts owns a 64 x WN block made of 32x32 MFMA tiles
 // (v_mfma_f32_32x32x16_{bf16,f16}).  K advances 32 at a time through
 // double-buffered LDS tiles whose rows are padded to 80 bytes, which keeps the
 // 16-byte operand reads free of bank conflicts.
@@ -70,29 +70,31 @@ __device__ __forceinline__ void tile_of(int nrb, int ncb, int& rb, int& cb) {
   }
 }
 
-template <typename T, int WN>
-__global__ void __launch_bounds__(256) k_gemm_lp(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
-                                                 const T* __restrict__ Xt, int64_t k, float scale, float unscale,
-                                                 float* __restrict__ B, int nrb, int ncb, int vec_a, int vec_x) {
+// WM wavefront rows: a workgroup of 256 WM threads owns BM = 64 WM rows, so
+// each X tile staged in LDS serves WM times as many rows of A.
+template <typename T, int WN, int WM>
+__global__ void __launch_bounds__(256 * WM) k_gemm_lp(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                                                      const T* __restrict__ Xt, int64_t k, float scale, float unscale,
+                                                      float* __restrict__ B, int nrb, int ncb, int vec_a, int vec_x) {
   typedef LpTraits<T> Tr;
   typedef typename Tr::vec8 vec8;
-  constexpr int BN = 4 * WN;
+  constexpr int BN = 4 * WN, BM = kBM * WM, NTH = 256 * WM;
   constexpr int NT = WN / 32;  // 32-wide MFMA tiles per wavefront along N
-  __shared__ __align__(16) uint16_t sA[2][kBM * kRowPad];
+  __shared__ __align__(16) uint16_t sA[2][BM * kRowPad];
   __shared__ __align__(16) uint16_t sX[2][BN * kRowPad];
   int rb, cb;
   tile_of(nrb, ncb, rb, cb);
   if (rb >= nrb) return;
-  const int64_t row0 = (int64_t)rb * kBM, col0 = (int64_t)cb * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = (int64_t)rb * BM, col0 = (int64_t)cb * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = (tid >> 6) & 3, wm = tid >> 8;
 
   // global -> register staging of one K step
   fx4 ra[2];
-  u32x4 rx[BN / 64];
+  u32x4 rx[BN * 4 / NTH];
   auto load_tile = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const int r = (tid >> 3) + 32 * i, kk = 4 * (tid & 7);
+      const int r = (tid >> 3) + (NTH / 8) * i, kk = 4 * (tid & 7);
       const int64_t gr = row0 + r, gk = k0 + kk;
       fx4 v = {0.f, 0.f, 0.f, 0.f};
       if (gr < m) {
@@ -106,8 +108,8 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const float* __restrict__ A, in
       ra[i] = v;
     }
 #pragma unroll
-    for (int i = 0; i < BN / 64; ++i) {
-      const int c = (tid >> 2) + 64 * i, kk = 8 * (tid & 3);
+    for (int i = 0; i < BN * 4 / NTH; ++i) {
+      const int c = (tid >> 2) + (NTH / 4) * i, kk = 8 * (tid & 3);
       const int64_t gc = col0 + c, gk = k0 + kk;
       u32x4 v = {0u, 0u, 0u, 0u};
       if (gc < k) {
@@ -127,7 +129,7 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const float* __restrict__ A, in
   auto store_tile = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const int r = (tid >> 3) + 32 * i, kk = 4 * (tid & 7);
+      const int r = (tid >> 3) + (NTH / 8) * i, kk = 4 * (tid & 7);
       u16x4 h;
       h.x = Tr::cvt(ra[i].x * scale);
       h.y = Tr::cvt(ra[i].y * scale);
@@ -136,8 +138,8 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const float* __restrict__ A, in
       *reinterpret_cast<u16x4*>(&sA[buf][r * kRowPad + kk]) = h;
     }
 #pragma unroll
-    for (int i = 0; i < BN / 64; ++i) {
-      const int c = (tid >> 2) + 64 * i, kk = 8 * (tid & 3);
+    for (int i = 0; i < BN * 4 / NTH; ++i) {
+      const int c = (tid >> 2) + (NTH / 4) * i, kk = 8 * (tid & 3);
       *reinterpret_cast<u32x4*>(&sX[buf][c * kRowPad + kk]) = rx[i];
     }
   };
@@ -164,7 +166,7 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const float* __restrict__ A, in
       vec8 af[2], bf[NT];
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
-        af[mi] = *reinterpret_cast<const vec8*>(&sA[buf][(32 * mi + (lane & 31)) * kRowPad + kk]);
+        af[mi] = *reinterpret_cast<const vec8*>(&sA[buf][(64 * wm + 32 * mi + (lane & 31)) * kRowPad + kk]);
 #pragma unroll
       for (int ni = 0; ni < NT; ++ni)
         bf[ni] = *reinterpret_cast<const vec8*>(&sX[buf][(WN * wave + 32 * ni + (lane & 31)) * kRowPad + kk]);
@@ -186,7 +188,7 @@ __global__ void __launch_bounds__(256) k_gemm_lp(const float* __restrict__ A, in
     for (int ni = 0; ni < NT; ++ni)
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const int64_t r = row0 + 32 * mi + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        const int64_t r = row0 + 64 * wm + 32 * mi + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
         const int64_t c = col0 + WN * wave + 32 * ni + (lane & 31);
         if (r < m && c < k) B[r * k + c] = acc[mi][ni][q] * unscale;
       }
@@ -196,17 +198,28 @@ template <typename T>
 re_status launch_t(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t lda, const void* Xt, int64_t k,
                    int scale_exp, float* B) {
   const float scale = ldexpf(1.0f, scale_exp), unscale = ldexpf(1.0f, -scale_exp);
-  const int nrb = (int)cdiv(m, kBM);
   const int vec_a = (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
   const int vec_x = (n % 8 == 0) && ((uintptr_t)Xt % 16 == 0);
+  // two wavefront rows (128 rows of A per X tile) while that still gives at
+  // least one workgroup per CU
+  const int wm = cdiv(m, 128) * cdiv(k, k > 256 ? 512 : 256) >= 256 ? 2 : 1;
+  const int nrb = (int)cdiv(m, kBM * wm);
   if (k > 256) {
     const int ncb = (int)cdiv(k, 512);
-    hipLaunchKernelGGL((k_gemm_lp<T, 128>), dim3((unsigned)(nrb * ncb)), dim3(256), 0, s, A, m, n, lda,
-                       (const T*)Xt, k, scale, unscale, B, nrb, ncb, vec_a, vec_x);
+    if (wm == 2)
+      hipLaunchKernelGGL((k_gemm_lp<T, 128, 2>), dim3((unsigned)(nrb * ncb)), dim3(512), 0, s, A, m, n, lda,
+                         (const T*)Xt, k, scale, unscale, B, nrb, ncb, vec_a, vec_x);
+    else
+      hipLaunchKernelGGL((k_gemm_lp<T, 128, 1>), dim3((unsigned)(nrb * ncb)), dim3(256), 0, s, A, m, n, lda,
+                         (const T*)Xt, k, scale, unscale, B, nrb, ncb, vec_a, vec_x);
   } else {
     const int ncb = (int)cdiv(k, 256);
-    hipLaunchKernelGGL((k_gemm_lp<T, 64>), dim3((unsigned)(nrb * ncb)), dim3(256), 0, s, A, m, n, lda,
-                       (const T*)Xt, k, scale, unscale, B, nrb, ncb, vec_a, vec_x);
+    if (wm == 2)
+      hipLaunchKernelGGL((k_gemm_lp<T, 64, 2>), dim3((unsigned)(nrb * ncb)), dim3(512), 0, s, A, m, n, lda,
+                         (const T*)Xt, k, scale, unscale, B, nrb, ncb, vec_a, vec_x);
+    else
+      hipLaunchKernelGGL((k_gemm_lp<T, 64, 1>), dim3((unsigned)(nrb * ncb)), dim3(256), 0, s, A, m, n, lda,
+                         (const T*)Xt, k, scale, unscale, B, nrb, ncb, vec_a, vec_x);
   }
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
@@ -214,16 +227,20 @@ re_status launch_t(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t 
 
 // Sampled statistics of A for the precision choice: sum of squares and the
 // largest magnitude over a strided sample of rows and columns.
+// Sampled sum of squares and largest magnitude of A on a grid of rows and
+// columns.  Workgroup g takes sampled rows g, g + G, ... and writes one
+// partial pair; k_sample_finish adds the G pairs in order.
+constexpr int kStatsGroups = 256;
 __global__ void __launch_bounds__(256) k_sample_stats(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
-                                                      int64_t rstep, int64_t cstep, double* __restrict__ out) {
+                                                      int64_t rstep, int64_t cstep, double* __restrict__ part) {
   __shared__ double s_sum[256];
   __shared__ float s_max[256];
   double sum = 0.0;
   float mx = 0.0f;
   const int64_t nr = (m + rstep - 1) / rstep, nc = (n + cstep - 1) / cstep;
-  for (int64_t r = threadIdx.x; r < nr; r += blockDim.x) {
+  for (int64_t r = blockIdx.x; r < nr; r += gridDim.x) {
     const float* row = A + r * rstep * lda;
-    for (int64_t c = 0; c < nc; ++c) {
+    for (int64_t c = threadIdx.x; c < nc; c += blockDim.x) {
       const float v = row[c * cstep];
       sum += (double)v * (double)v;
       mx = fmaxf(mx, fabsf(v));
@@ -240,10 +257,21 @@ __global__ void __launch_bounds__(256) k_sample_stats(const float* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = s_sum[0];
-    out[1] = (double)s_max[0];
-    out[2] = (double)(nr * nc);
+    part[2 * blockIdx.x] = s_sum[0];
+    part[2 * blockIdx.x + 1] = (double)s_max[0];
   }
+}
+
+__global__ void k_sample_finish(const double* __restrict__ part, int groups, int64_t count, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double sum = 0.0, mx = 0.0;
+  for (int g = 0; g < groups; ++g) {
+    sum += part[2 * g];
+    mx = fmax(mx, part[2 * g + 1]);
+  }
+  out[0] = sum;
+  out[1] = mx;
+  out[2] = (double)count;
 }
 
 }  // namespace
@@ -256,12 +284,18 @@ re_status launch_gemm_lp(hipStream_t s, int fmt, const float* A, int64_t m, int6
   return RE_ERR_INVALID_ARG;
 }
 
+// out3 must provide 4 + 2 * 256 doubles: the three results, then the
+// per-workgroup partials.
 re_status launch_sample_stats(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t lda, double* out3) {
   // about 2^17 entries on a coprime-ish grid of rows and columns
   int64_t rstep = m > 512 ? m / 512 : 1, cstep = n > 256 ? n / 256 : 1;
   if (rstep > 1 && rstep % 2 == 0) --rstep;
   if (cstep > 1 && cstep % 2 == 0) --cstep;
-  hipLaunchKernelGGL(k_sample_stats, dim3(1), dim3(256), 0, s, A, m, n, lda, rstep, cstep, out3);
+  const int64_t nr = (m + rstep - 1) / rstep, nc = (n + cstep - 1) / cstep;
+  const int groups = (int)(nr < kStatsGroups ? nr : kStatsGroups);
+  double* part = out3 + 4;
+  hipLaunchKernelGGL(k_sample_stats, dim3(groups), dim3(256), 0, s, A, m, n, lda, rstep, cstep, part);
+  hipLaunchKernelGGL(k_sample_finish, dim3(1), dim3(64), 0, s, part, groups, nr * nc, out3);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
 }

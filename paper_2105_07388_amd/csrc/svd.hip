@@ -103,27 +103,34 @@ __device__ bool grid_barrier(unsigned* bar, unsigned target, int32_t* info) {
 
 // Column step partials of column c over this workgroup's rows r >= c:
 //   part[0] = sum W[r][c]^2,  part[1 + (j - c - 1)] = sum W[r][c] W[r][j]  (j > c)
-// and, from the owner of row c, rowbuf = W[c][c..k).
-__device__ void column_partials(const BidiagArgs& a, int64_t c, int w, double* gacc /* [kWaves][k+1] LDS */) {
+// and, from the owner of row c, rowbuf = W[c][c..k).  Columns are taken in
+// chunks of kPartChunk so that the per-wavefront accumulators fit in LDS for
+// any k; every sum runs over the rows in the same order.
+constexpr int kPartChunk = 1024;
+__device__ void column_partials(const BidiagArgs& a, int64_t c, int w, double* gacc /* [kWaves][kPartChunk] LDS */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t k = a.k, len = k - c;  // len = 1 + (k - c - 1)
-  double* g = gacc + (int64_t)wave * (k + 1);
-  for (int64_t j = lane; j < len; j += 64) g[j] = 0.0;
+  double* g = gacc + (int64_t)wave * kPartChunk;
   const int64_t par = c & 1;
-  for (int64_t r = w + (int64_t)wave * a.P; r < a.l; r += (int64_t)kWaves * a.P) {
-    if (r < c) continue;
-    const double* row = a.W + r * k;
-    const double x = row[c];
-    for (int64_t j = lane; j < len; j += 64) g[j] += x * row[c + j];
-    if (r == c)
-      for (int64_t j = lane; j < len; j += 64) a.rowbuf[par * (k + 1) + j] = row[c + j];
-  }
-  __syncthreads();
   double* out = a.part + (par * a.P + w) * (k + 1);
-  for (int64_t j = threadIdx.x; j < len; j += blockDim.x) {
-    double s = 0.0;
-    for (int v = 0; v < kWaves; ++v) s += gacc[(int64_t)v * (k + 1) + j];
-    out[j] = s;
+  for (int64_t j0 = 0; j0 < len; j0 += kPartChunk) {
+    const int64_t jn = len - j0 < kPartChunk ? len - j0 : kPartChunk;
+    for (int64_t j = lane; j < jn; j += 64) g[j] = 0.0;
+    for (int64_t r = w + (int64_t)wave * a.P; r < a.l; r += (int64_t)kWaves * a.P) {
+      if (r < c) continue;
+      const double* row = a.W + r * k + c + j0;
+      const double x = a.W[r * k + c];
+      for (int64_t j = lane; j < jn; j += 64) g[j] += x * row[j];
+      if (r == c)
+        for (int64_t j = lane; j < jn; j += 64) a.rowbuf[par * (k + 1) + j0 + j] = row[j];
+    }
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < jn; j += blockDim.x) {
+      double s = 0.0;
+      for (int v = 0; v < kWaves; ++v) s += gacc[(int64_t)v * kPartChunk + j];
+      out[j0 + j] = s;
+    }
+    __syncthreads();
   }
 }
 
@@ -419,6 +426,163 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_lds(Bidiag2Args a) {
   }
 }
 
+// ---- bidiagonalisation with register-cached reflectors --------------------
+// The LDS-resident scheme above, reorganised to move less data through LDS:
+// one wavefront updates one row at a time with its 64 lanes (lane q owns the
+// columns c + 1 + q + 64 t, t < KPL), the reflector coefficients of those
+// columns stay in registers for all of the wavefront's rows, the updated
+// entries stay in registers between the row dot product and the write-back,
+// and the partial sums of the next column step are accumulated while the
+// rows are written (each wavefront adds its rows in order, the wavefronts
+// meet in at most 8 LDS slots), so no separate pass over the rows is needed.
+__device__ __forceinline__ double bcast_lane0(double v) {
+  const uint64_t u = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return __longlong_as_double(((uint64_t)hi << 32) | lo);
+}
+
+template <int KPL, int NT>
+__global__ void __launch_bounds__(NT) k_bidiag_reg(Bidiag2Args a) {
+  constexpr int NW = NT / 64;
+  constexpr int SLOTS = NW < 8 ? NW : 8;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t k = a.k, l = a.l, kp = a.kp;
+  const int P = a.P, w = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nr = (int)((l - w + P - 1) / P);
+  double* Wl = reinterpret_cast<double*>(smem_raw);  // [nr_max][kp]
+  double* wv = Wl + (int64_t)a.nr_max * kp;           // [k + 1]
+  double* vv = wv + (k + 1);                           // [k + 1]
+  double* red = vv + (k + 1);                          // [NW]
+  double* pw = red + NW;                               // [SLOTS][k + 1]
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int64_t e = tid; e < (int64_t)nr * k; e += NT) {
+    const int64_t i = e / k, j = e - i * k;
+    const double x = a.C[(w + P * i) * k + j];
+    if (!isfinite(x)) s_bad = 1;
+    Wl[i * kp + j] = x;
+  }
+  __syncthreads();
+  if (s_bad) __hip_atomic_store(a.info, (int32_t)RE_ERR_NONFINITE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned epoch = 0;
+  partials_lds(a, Wl, nr, 0, w);
+  if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+
+  for (int64_t c = 0; c < k; ++c) {
+    const int64_t par = c & 1, len = k - c;
+    for (int64_t j = tid; j < len; j += NT) {
+      const double* src = a.part + par * P * (k + 1) + j;
+      const double rb = ld_coh(&a.rowbuf[par * (k + 1) + j]);
+      double s = 0.0;
+      for (int p0 = 0; p0 < P; p0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = (p0 + q < P) ? ld_coh(src + (int64_t)(p0 + q) * (k + 1)) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) s += v[q];
+      }
+      wv[j] = s;
+      vv[j] = rb;
+    }
+    __syncthreads();
+    const double s0 = wv[0], x0 = vv[0];
+    const double nx = sqrt(s0);
+    const double alpha = nx > 0.0 ? -copysign(nx, x0) : 0.0;
+    const double tau = nx > 0.0 ? 1.0 / (s0 - alpha * x0) : 0.0;
+    const double u0 = x0 - alpha;
+    if (w == 0 && tid == 0) a.d[c] = alpha;
+    double pp = 0.0;
+    for (int64_t j = 1 + tid; j < len; j += NT) {
+      const double row = vv[j];
+      const double wj = tau * (wv[j] - alpha * row);
+      const double y = row - u0 * wj;
+      wv[j] = wj;
+      vv[j] = y;
+      pp += y * y;
+    }
+    pp = wave_sum_dpp(pp);
+    if (lane == 0) red[wave] = pp;
+    __syncthreads();
+    double ny2 = 0.0;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) ny2 += red[v];
+    const double y0 = len > 1 ? vv[1] : 0.0;
+    const double ny = sqrt(ny2);
+    const double beta = ny > 0.0 ? -copysign(ny, y0) : 0.0;
+    const double tau2 = ny > 0.0 ? 1.0 / (ny2 - beta * y0) : 0.0;
+    const double v1 = y0 - beta;
+    if (w == 0 && tid == 0 && len > 1) a.e[c] = beta;
+    // this lane's reflector coefficients, columns c + j with j = 1 + lane + 64 t
+    double cw[KPL], cv[KPL], pa[KPL];
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) {
+      const int64_t j = 1 + lane + 64 * t;
+      cw[t] = j < len ? wv[j] : 0.0;
+      cv[t] = j < len ? (j == 1 ? v1 : vv[j]) : 0.0;
+      pa[t] = 0.0;
+    }
+    for (int i = wave; i < nr; i += NW) {
+      if (w + (int64_t)P * i <= c) continue;  // rows above the pivot are final
+      double* row = Wl + (int64_t)i * kp + c;
+      const double ur = row[0];
+      double tv[KPL];
+      double zp = 0.0;
+#pragma unroll
+      for (int t = 0; t < KPL; ++t) {
+        const int64_t j = 1 + lane + 64 * t;
+        tv[t] = j < len ? row[j] - ur * cw[t] : 0.0;
+        zp += tv[t] * cv[t];
+      }
+      const double z = wave_sum_dpp(zp) * tau2;
+      const double x1 = bcast_lane0(tv[0] - z * cv[0]);  // the row's new entry in column c + 1
+#pragma unroll
+      for (int t = 0; t < KPL; ++t) {
+        const int64_t j = 1 + lane + 64 * t;
+        if (j < len) {
+          const double nv = tv[t] - z * cv[t];
+          row[j] = nv;
+          pa[t] += x1 * nv;
+        }
+      }
+    }
+    if (c + 1 < k) {
+      // partials of column c + 1: part[j - 1] = sum over rows of W[r][c+1] W[r][c+j]
+      if (wave >= SLOTS) {
+        double* dst = pw + (int64_t)(wave - SLOTS) * (k + 1);
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+          const int64_t j = 1 + lane + 64 * t;
+          if (j < len) dst[j - 1] = pa[t];
+        }
+      }
+      __syncthreads();
+      if (wave < SLOTS) {
+        double* dst = pw + (int64_t)wave * (k + 1);
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+          const int64_t j = 1 + lane + 64 * t;
+          if (j < len) dst[j - 1] = (wave + SLOTS < NW ? dst[j - 1] : 0.0) + pa[t];
+        }
+      }
+      __syncthreads();
+      const int64_t par1 = (c + 1) & 1, len1 = len - 1;
+      const bool owner = ((c + 1) % P) == w;
+      const int iown = (int)((c + 1) / P);
+      for (int64_t j = tid; j < len1; j += NT) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) s += pw[(int64_t)q * (k + 1) + j];
+        st_coh(&a.part[(par1 * P + w) * (k + 1) + j], s);
+        if (owner) st_coh(&a.rowbuf[par1 * (k + 1) + j], Wl[(int64_t)iown * kp + c + 1 + j]);
+      }
+      if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+    }
+  }
+}
+
 // ---- bidiagonalisation of a sketch held by one workgroup ----------------
 // When the whole l x k sketch fits in LDS one workgroup reduces it alone:
 // the column partials go straight to LDS and workgroup barriers replace the
@@ -688,6 +852,16 @@ int svd_rows_target() {
   return v;
 }
 
+// RANKEST_SVD_LEGACY=1 selects the plain LDS-resident kernel (comparisons).
+bool svd_legacy_lds() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("RANKEST_SVD_LEGACY");
+    v = (e && atoi(e) != 0) ? 1 : 0;
+  }
+  return v == 1;
+}
+
 LdsPlan lds_plan(int64_t l, int64_t k) {
   LdsPlan p{0, 0, 0};
   if (k > 1025) return p;
@@ -703,6 +877,40 @@ LdsPlan lds_plan(int64_t l, int64_t k) {
       return p;
     }
   }
+  return p;
+}
+
+// Plan of the register-cached kernel: KPL columns per lane (k <= 64 KPL + 1),
+// 1024 threads up to KPL = 8 and 512 beyond; rows per workgroup as lds_plan.
+struct RegPlan {
+  int P, nr_max, kpl, nt;
+  size_t bytes;
+};
+RegPlan reg_plan(int64_t l, int64_t k) {
+  RegPlan p{0, 0, 0, 0, 0};
+  const int64_t need = k <= 1 ? 1 : (k - 1 + 63) / 64;
+  static const int kpls[] = {1, 2, 4, 6, 8, 12, 16};
+  for (int v : kpls)
+    if (v >= need) {
+      p.kpl = v;
+      break;
+    }
+  if (p.kpl == 0) return p;
+  p.nt = p.kpl <= 8 ? 1024 : 512;
+  const int nw = p.nt / 64, slots = nw < 8 ? nw : 8;
+  const size_t fixed = (size_t)(2 * (k + 1) + nw + slots * (k + 1)) * 8;
+  const int P0 = (int)((l + svd_rows_target() - 1) / svd_rows_target());
+  for (int P = P0 < 1 ? 1 : (P0 > 64 ? 64 : P0); P <= 64 && P <= l; ++P) {
+    const int64_t nr = (l + P - 1) / P;
+    const size_t bytes = (size_t)nr * lds_stride(k) * 8 + fixed;
+    if (bytes <= kLdsBudget) {
+      p.P = P;
+      p.nr_max = (int)nr;
+      p.bytes = bytes;
+      return p;
+    }
+  }
+  p.kpl = 0;
   return p;
 }
 
@@ -842,6 +1050,31 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     if (one_bytes > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag_1wg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)one_bytes));
     hipLaunchKernelGGL(k_bidiag_1wg, dim3(1), dim3(kB2Threads), one_bytes, s, sb);
+  } else if (const RegPlan rp = reg_plan(l, k); rp.P > 0 && !svd_legacy_lds()) {
+    Bidiag2Args b2;
+    b2.C = C;
+    b2.part = a.part;
+    b2.rowbuf = a.rowbuf;
+    b2.d = a.d;
+    b2.e = a.e;
+    b2.bar = a.bar;
+    b2.info = info;
+    b2.l = l;
+    b2.k = k;
+    b2.kp = lds_stride(k);
+    b2.P = rp.P;
+    b2.nr_max = rp.nr_max;
+    const void* fn = rp.kpl == 1   ? (const void*)k_bidiag_reg<1, 1024>
+                     : rp.kpl == 2 ? (const void*)k_bidiag_reg<2, 1024>
+                     : rp.kpl == 4 ? (const void*)k_bidiag_reg<4, 1024>
+                     : rp.kpl == 6 ? (const void*)k_bidiag_reg<6, 1024>
+                     : rp.kpl == 8 ? (const void*)k_bidiag_reg<8, 1024>
+                     : rp.kpl == 12 ? (const void*)k_bidiag_reg<12, 512>
+                                    : (const void*)k_bidiag_reg<16, 512>;
+    if (rp.bytes > 64 * 1024)
+      RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rp.bytes));
+    void* params2[] = {&b2};
+    RE_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(rp.P), dim3(rp.nt), params2, (unsigned)rp.bytes, s));
   } else if (lp.P > 0) {
     Bidiag2Args b2;
     b2.C = C;
@@ -865,7 +1098,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     void* params2[] = {&b2};
     RE_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(lp.P), dim3(kB2Threads), params2, (unsigned)lp.bytes, s));
   } else {
-    const size_t lds = (size_t)(2 + kWaves) * (k + 1) * 8;
+    const size_t lds = (size_t)(2 * (k + 1) + kWaves * kPartChunk) * 8;
     if (lds > 160 * 1024) return RE_ERR_UNSUPPORTED;
     if (lds > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

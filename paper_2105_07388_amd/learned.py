@@ -166,13 +166,17 @@ def proposals(yhat: np.ndarray, delta: float, kmax: np.ndarray) -> np.ndarray:
     return np.minimum(np.maximum(k, 2 * K0), kmax)
 
 
-def choose_delta(yhat: np.ndarray, kstar: np.ndarray, kmax: np.ndarray) -> float:
-    """Margin on the validation set: the fewest mean rounds, ties broken by
-    the smaller mean final width relative to k*."""
+def choose_delta(yhat: np.ndarray, kstar: np.ndarray, kmax: np.ndarray, max_overshoot: float = 1.5) -> float:
+    """Margin on the validation set: the fewest mean rounds among the margins
+    whose mean final width stays within max_overshoot times k* (a larger
+    margin always saves rounds but pays for the extra columns)."""
     best = None
     for delta in np.arange(0.0, 1.01, 0.05):
         r, kf = simulate_rounds(proposals(yhat, delta, kmax), kstar, kmax)
-        score = (float(np.mean(r)), float(np.mean(kf / kstar)))
+        over = float(np.mean(kf / kstar))
+        if over > max_overshoot and delta > 0.0:
+            continue
+        score = (float(np.mean(r)), over)
         if best is None or score < best[0]:
             best = (score, float(delta))
     return best[1]
@@ -239,17 +243,21 @@ def fit(ds: dict, steps: int, out: str, extra: dict, log=print) -> dict:
     """Train on the training split, pick delta on validation, report the
     simulated rounds on the test split, save weights and summary."""
     tr, va, te = _split(ds["meta"])
-    p, hist = train(ds["X"][tr], ds["y"][tr], steps=steps, Xval=ds["X"][va], yval=ds["y"][va], log=log)
+    # the network is only consulted when the pilot did not converge
+    used = ~np.array([r["pilot_converged"] for r in ds["meta"]])
+    trn, van = tr & used, va & used
+    p, hist = train(ds["X"][trn], ds["y"][trn], steps=steps, Xval=ds["X"][van], yval=ds["y"][van], log=log)
     dev = p.device
     kst = np.array([r["k_star"] for r in ds["meta"]])
     kmx = np.array([min(r["n"], 4096) for r in ds["meta"]])
-    yv = B.mlp_forward(p, torch.from_numpy(ds["X"][va]).to(dev)).cpu().numpy()
-    delta = choose_delta(yv, kst[va], kmx[va])
+    yv = B.mlp_forward(p, torch.from_numpy(ds["X"][van]).to(dev)).cpu().numpy()
+    delta = choose_delta(yv, kst[van], kmx[van])
     yt = B.mlp_forward(p, torch.from_numpy(ds["X"][te]).to(dev)).cpu().numpy()
     r_l, k_l = simulate_rounds(proposals(yt, delta, kmx[te]), kst[te], kmx[te])
     r_d, k_d = simulate_rounds(np.minimum(2 * K0, kmx[te]), kst[te], kmx[te])
-    summary = dict(extra, samples=int(len(ds["y"])), train=int(tr.sum()), val=int(va.sum()), test=int(te.sum()),
-                   delta=delta, history=hist, test_mse=float(np.mean((yt - ds["y"][te]) ** 2)),
+    summary = dict(extra, samples=int(len(ds["y"])), train=int(trn.sum()), val=int(van.sum()), test=int(te.sum()),
+                   pilot_converged=float(1.0 - used.mean()), delta=delta, history=hist,
+                   test_mse_network_used=float(np.mean((yt - ds["y"][te])[used[te]] ** 2)),
                    test_mean_rounds_learned_simulated=float(np.mean(r_l)),
                    test_mean_rounds_doubling_simulated=float(np.mean(r_d)),
                    test_mean_kfinal_over_kstar_learned=float(np.mean(k_l / kst[te])),

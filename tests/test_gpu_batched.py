@@ -64,7 +64,7 @@ def test_batched_oracle_parity_and_ranks(orc):
         assert 3 <= r_o < re_.r1_from_k(K)
 
 
-@pytest.mark.parametrize("tile", ["4:16:2", "4:32:1", "8:16:1", "8:32:3"])
+@pytest.mark.parametrize("tile", ["4:1:16:2", "4:1:32:1", "8:1:16:1", "8:1:32:3", "4:2:16:2", "8:2:16:1"])
 def test_batched_tile_shapes_agree(tile, monkeypatch):
     buf, views, params = inputs.kernel_blocks(7, seed=31, device=DEV, size_lo=150, size_hi=700)
     ref = re_.rank_estimate_batched(views, 1e-6, k=K, l=L, seed=2, handle=re_.Handle())

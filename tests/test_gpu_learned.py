@@ -137,7 +137,7 @@ def test_trained_policy_beats_doubling():
     if not os.path.exists(learned.DEFAULT_WEIGHTS):
         pytest.skip("no trained weights committed")
     policy, delta = learned.load_policy()
-    params = inputs.learned_params(16, seed=3005, m_lo=1024, m_hi=4096)
+    params = inputs.learned_params(16, seed=3005, m_lo=4096, m_hi=8192)  # the training range's small end
     out = learned.compare(params, policy, delta, log=lambda s: None)
     assert out["learned"]["mean_rounds"] < out["doubling"]["mean_rounds"]
     assert out["learned"]["rank_agreement"] >= out["doubling"]["rank_agreement"] - 1.0 / 16

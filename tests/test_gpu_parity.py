@@ -166,11 +166,13 @@ def test_singular_values(orc, name, Cm):
     assert np.all(np.abs(got - want)[big] <= 1e-10 * want[big])
 
 
-def test_singular_values_global_memory_path():
-    """k > 1025 runs the global-memory bidiagonalisation; checked against LAPACK
-    (the oracle's Jacobi is pinned to it and would take minutes at this size)."""
+@pytest.mark.parametrize("l,k", [(1100, 1030), (2600, 2400)])
+def test_singular_values_global_memory_path(l, k):
+    """k > 1025 runs the global-memory bidiagonalisation (column partials in
+    chunks of 1024); checked against LAPACK (the oracle's Jacobi is pinned to
+    it and would take minutes at this size)."""
     rng = np.random.default_rng(11)
-    Cm = rng.standard_normal((1100, 1030)) * (10.0 ** -np.linspace(0, 6, 1030))[None, :]
+    Cm = rng.standard_normal((l, k)) * (10.0 ** -np.linspace(0, 6, k))[None, :]
     got = _np(re_.singular_values(torch.from_numpy(Cm).to(DEV), 1.0))
     want = np.linalg.svd(Cm, compute_uv=False)
     assert np.all(np.abs(got - want) <= 1e-12 * want[0]), np.abs(got - want).max() / want[0]
