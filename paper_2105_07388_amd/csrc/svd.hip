@@ -456,6 +456,7 @@ __global__ void __launch_bounds__(NT) k_bidiag_reg(Bidiag2Args a) {
   double* vv = wv + (k + 1);                           // [k + 1]
   double* red = vv + (k + 1);                          // [NW]
   double* pw = red + NW;                               // [SLOTS][k + 1]
+  double* sink = pw + SLOTS * (k + 1);                 // [NT]: target of masked-off stores
   __shared__ int s_bad;
   if (tid == 0) s_bad = 0;
   __syncthreads();
@@ -516,36 +517,45 @@ __global__ void __launch_bounds__(NT) k_bidiag_reg(Bidiag2Args a) {
     const double v1 = y0 - beta;
     if (w == 0 && tid == 0 && len > 1) a.e[c] = beta;
     // this lane's reflector coefficients, columns c + j with j = 1 + lane + 64 t
+    // (loads are issued unconditionally from a clamped in-range index and
+    // masked afterwards, so each batch of LDS reads costs one wait)
     double cw[KPL], cv[KPL], pa[KPL];
 #pragma unroll
     for (int t = 0; t < KPL; ++t) {
-      const int64_t j = 1 + lane + 64 * t;
-      cw[t] = j < len ? wv[j] : 0.0;
-      cv[t] = j < len ? (j == 1 ? v1 : vv[j]) : 0.0;
+      const int64_t j = 1 + lane + 64 * t, jc = j < len ? j : len - 1;
+      const double a = wv[jc], b = vv[jc];
+      cw[t] = j < len ? a : 0.0;
+      cv[t] = j < len ? (j == 1 ? v1 : b) : 0.0;
       pa[t] = 0.0;
     }
     for (int i = wave; i < nr; i += NW) {
       if (w + (int64_t)P * i <= c) continue;  // rows above the pivot are final
       double* row = Wl + (int64_t)i * kp + c;
+      double raw[KPL];
+#pragma unroll
+      for (int t = 0; t < KPL; ++t) {
+        const int64_t j = 1 + lane + 64 * t, jc = j < len ? j : len - 1;
+        raw[t] = row[jc];
+      }
       const double ur = row[0];
       double tv[KPL];
       double zp = 0.0;
 #pragma unroll
       for (int t = 0; t < KPL; ++t) {
         const int64_t j = 1 + lane + 64 * t;
-        tv[t] = j < len ? row[j] - ur * cw[t] : 0.0;
+        tv[t] = j < len ? raw[t] - ur * cw[t] : 0.0;
         zp += tv[t] * cv[t];
       }
       const double z = wave_sum_dpp(zp) * tau2;
       const double x1 = bcast_lane0(tv[0] - z * cv[0]);  // the row's new entry in column c + 1
+      // masked-off lanes (j >= len) have tv = cv = 0, so nv = 0 adds nothing
+      // to pa; their store goes to this thread's sink slot
 #pragma unroll
       for (int t = 0; t < KPL; ++t) {
         const int64_t j = 1 + lane + 64 * t;
-        if (j < len) {
-          const double nv = tv[t] - z * cv[t];
-          row[j] = nv;
-          pa[t] += x1 * nv;
-        }
+        const double nv = tv[t] - z * cv[t];
+        *(j < len ? row + j : sink + tid) = nv;
+        pa[t] += x1 * nv;
       }
     }
     if (c + 1 < k) {
@@ -852,6 +862,17 @@ int svd_rows_target() {
   return v;
 }
 
+// RANKEST_SVD_THREADS=1024 runs the register-cached kernel with 16
+// wavefronts for k <= 385 (tuning; 8 measured faster).
+bool svd_threads_1024() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("RANKEST_SVD_THREADS");
+    v = (e && atoi(e) == 1024) ? 1 : 0;
+  }
+  return v == 1;
+}
+
 // RANKEST_SVD_LEGACY=1 selects the plain LDS-resident kernel (comparisons).
 bool svd_legacy_lds() {
   static int v = -1;
@@ -881,7 +902,8 @@ LdsPlan lds_plan(int64_t l, int64_t k) {
 }
 
 // Plan of the register-cached kernel: KPL columns per lane (k <= 64 KPL + 1),
-// 1024 threads up to KPL = 8 and 512 beyond; rows per workgroup as lds_plan.
+// 512 threads (fewer wavefronts make the per-column barriers cheaper; 1024
+// fit the registers only up to KPL = 6); rows per workgroup as lds_plan.
 struct RegPlan {
   int P, nr_max, kpl, nt;
   size_t bytes;
@@ -896,9 +918,9 @@ RegPlan reg_plan(int64_t l, int64_t k) {
       break;
     }
   if (p.kpl == 0) return p;
-  p.nt = p.kpl <= 8 ? 1024 : 512;
+  p.nt = (p.kpl <= 6 && svd_threads_1024()) ? 1024 : 512;
   const int nw = p.nt / 64, slots = nw < 8 ? nw : 8;
-  const size_t fixed = (size_t)(2 * (k + 1) + nw + slots * (k + 1)) * 8;
+  const size_t fixed = (size_t)(2 * (k + 1) + nw + slots * (k + 1) + p.nt) * 8;
   const int P0 = (int)((l + svd_rows_target() - 1) / svd_rows_target());
   for (int P = P0 < 1 ? 1 : (P0 > 64 ? 64 : P0); P <= 64 && P <= l; ++P) {
     const int64_t nr = (l + P - 1) / P;
@@ -1064,11 +1086,12 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     b2.kp = lds_stride(k);
     b2.P = rp.P;
     b2.nr_max = rp.nr_max;
-    const void* fn = rp.kpl == 1   ? (const void*)k_bidiag_reg<1, 1024>
-                     : rp.kpl == 2 ? (const void*)k_bidiag_reg<2, 1024>
-                     : rp.kpl == 4 ? (const void*)k_bidiag_reg<4, 1024>
-                     : rp.kpl == 6 ? (const void*)k_bidiag_reg<6, 1024>
-                     : rp.kpl == 8 ? (const void*)k_bidiag_reg<8, 1024>
+    const bool t512 = rp.nt == 512;
+    const void* fn = rp.kpl == 1   ? (t512 ? (const void*)k_bidiag_reg<1, 512> : (const void*)k_bidiag_reg<1, 1024>)
+                     : rp.kpl == 2 ? (t512 ? (const void*)k_bidiag_reg<2, 512> : (const void*)k_bidiag_reg<2, 1024>)
+                     : rp.kpl == 4 ? (t512 ? (const void*)k_bidiag_reg<4, 512> : (const void*)k_bidiag_reg<4, 1024>)
+                     : rp.kpl == 6 ? (t512 ? (const void*)k_bidiag_reg<6, 512> : (const void*)k_bidiag_reg<6, 1024>)
+                     : rp.kpl == 8 ? (const void*)k_bidiag_reg<8, 512>
                      : rp.kpl == 12 ? (const void*)k_bidiag_reg<12, 512>
                                     : (const void*)k_bidiag_reg<16, 512>;
     if (rp.bytes > 64 * 1024)
