@@ -313,12 +313,6 @@ def main():
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    if args.workload == "c4":
-        return bench_batched(args, w, dev)
-    if args.workload == "c5":
-        return bench_learned(args, w, dev)
-    A = make_matrix(args.workload, w, dev)
-    torch.cuda.synchronize()
     if args.calib_copy_gib > 0:
         nb = int(args.calib_copy_gib * 2**30) // 4
         src = torch.ones(nb, dtype=torch.float32, device=dev)
@@ -327,6 +321,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "c4":
+        return bench_batched(args, w, dev)
+    if args.workload == "c5":
+        return bench_learned(args, w, dev)
+    A = make_matrix(args.workload, w, dev)
+    torch.cuda.synchronize()
     h = re_.Handle(dev)
     h.set_profiling(True)
     print(f"[bench] {args.workload}: A {tuple(A.shape)} {A.dtype} resident; warmup {args.warmup}", file=sys.stderr,
