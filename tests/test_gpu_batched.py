@@ -73,7 +73,7 @@ def test_batched_tile_shapes_agree(tile, monkeypatch):
     assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1]) and np.array_equal(ref[2], got[2])
 
 
-@pytest.mark.parametrize("k,l", [(8, 12), (33, 50), (64, 96), (100, 120)])
+@pytest.mark.parametrize("k,l", [(8, 12), (33, 50), (64, 96), (100, 120), (112, 128)])
 def test_batched_other_sketch_sizes(k, l):
     buf, views, params = inputs.kernel_blocks(5, seed=41 + k, device=DEV, size_lo=max(l, 200), size_hi=640)
     views.append(torch.randn(l, k, device=DEV))        # the smallest legal block
@@ -108,7 +108,7 @@ def test_batched_errors():
     with pytest.raises(ValueError):
         re_.rank_estimate_batched([A.double()], 1e-6, k=K, l=L)
     with pytest.raises(re_.RankEstError) as ei:  # an l x k sketch beyond one workgroup's LDS
-        re_.rank_estimate_batched([torch.randn(300, 200, device=DEV)], 1e-6, k=128, l=160)
+        re_.rank_estimate_batched([torch.randn(300, 200, device=DEV)], 1e-6, k=200, l=256)
     assert ei.value.status == -2
     # SRHT sketches and low precision are not offered by the batched form
     import ctypes as C

@@ -141,7 +141,8 @@ def test_gaussian_y(orc, dtype):
 def _svd_cases():
     rng = np.random.default_rng(5)
     out = []
-    for l, k in [(1, 1), (2, 2), (60, 40), (144, 96), (576, 384), (33, 33), (768, 512), (100, 3), (700, 600)]:
+    for l, k in [(1, 1), (2, 2), (60, 40), (144, 96), (576, 384), (33, 33), (768, 512), (100, 3), (700, 600),
+                 (160, 128), (150, 65), (17, 17), (129, 129), (161, 64)]:
         out.append((f"rand{l}x{k}", rng.standard_normal((l, k))))
     l, k = 200, 120
     U, _ = np.linalg.qr(rng.standard_normal((l, k)))
