@@ -282,6 +282,19 @@ re_status re_mlp_loss_grad(re_handle h, const float* params_dev, const float* x_
 re_status re_mlp_adam(re_handle h, float* params_dev, const float* grad_dev, float* m_dev, float* v_dev, int64_t n,
                       int32_t step, double lr, double beta1, double beta2, double eps);
 
+/* Rank without a tolerance: the largest gap among the first r1 estimates
+ * (Sec. 5 after Algorithm 1 suggests argmax_i s_i / s_{i+1}; Sec. 6.1 reads
+ * the gap of its test matrix off the sketched spectrum).  Host-only, on the
+ * descending estimates re_rank_estimate returns.
+ *   sigma     host, k descending values
+ *   r_out     host: the 1-based i in 1..min(r1, k)-1 with the largest
+ *             s_i / s_{i+1} (ties to the smallest i; a zero s_{i+1} after a
+ *             positive s_i counts as an infinite ratio); 0 when s_1 = 0 or
+ *             min(r1, k) < 2
+ *   ratio_out host or NULL: that ratio (0 when r_out is 0)
+ * RE_ERR_INVALID_ARG for NULL sigma / r_out or negative sizes. */
+re_status re_gap_rank(const double* sigma, int32_t k, int32_t r1, int32_t* r_out, double* ratio_out);
+
 /* r1 derived from the sketch width k (Algorithm 1 step 1 inverted). */
 int32_t re_r1_from_k(int32_t k);
 

@@ -15,6 +15,7 @@ from ._binding import (  # noqa: F401
     Handle,
     RankEstError,
     default_handle,
+    gap_rank,
     gauss_fill,
     lib,
     make_blocks,

@@ -95,6 +95,7 @@ def lib():
             "re_singular_values": ([vp, vp, i64, i64, dbl, vp], i32),
             "re_rank_count": ([vp, vp, i64, i32, dbl, vp], i32),
             "re_r1_from_k": ([i32], i32),
+            "re_gap_rank": ([vp, i32, i32, C.POINTER(i32), C.POINTER(dbl)], i32),
             "re_status_string": ([i32], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -394,6 +395,17 @@ def rank_count(sigma: torch.Tensor, r1: int, eps: float, handle: Handle | None =
     _check(lib().re_rank_count(h.bind(), _ptr(sigma), sigma.numel(), int(r1), float(eps), _ptr(out)), "re_rank_count")
     o = out.cpu().tolist()
     return o[0], o[1], o[2]
+
+
+def gap_rank(sigma, r1: int):
+    """Rank without a tolerance from the largest gap of the first r1 estimates
+    (host-only).  Returns (r, ratio)."""
+    s = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64))
+    r = C.c_int32(0)
+    q = C.c_double(0.0)
+    _check(lib().re_gap_rank(s.ctypes.data_as(C.c_void_p), int(s.size), int(r1), C.byref(r), C.byref(q)),
+           "re_gap_rank")
+    return r.value, q.value
 
 
 def r1_from_k(k: int) -> int:

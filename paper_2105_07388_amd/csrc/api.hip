@@ -281,6 +281,26 @@ RE_API re_status re_workspace_bytes(re_handle h, size_t* bytes) {
 
 RE_API int32_t re_r1_from_k(int32_t k) { return re::r1_from_k(k); }
 
+RE_API re_status re_gap_rank(const double* sigma, int32_t k, int32_t r1, int32_t* r_out, double* ratio_out) {
+  if (!sigma || !r_out || k < 0 || r1 < 0) return RE_ERR_INVALID_ARG;
+  const int32_t n = r1 < k ? r1 : k;
+  int32_t best_i = 0;
+  double best = 0.0;
+  if (n >= 2 && sigma[0] > 0.0) {
+    best = -1.0;
+    for (int32_t i = 1; i < n && sigma[i - 1] > 0.0; ++i) {
+      const double q = sigma[i] > 0.0 ? sigma[i - 1] / sigma[i] : HUGE_VAL;
+      if (q > best) {
+        best = q;
+        best_i = i;
+      }
+    }
+  }
+  *r_out = best_i;
+  if (ratio_out) *ratio_out = best_i > 0 ? best : 0.0;
+  return RE_OK;
+}
+
 namespace re {
 namespace {
 

@@ -210,10 +210,27 @@ def test_c1_plain_method(orc):
         r, s, info = re_.rank_estimate(Ad, 1e-6, k=40, l=60, seed=seed)
         out = orc.rank_estimate(A.numpy(), 1e-6, orc.GAUSSIAN, orc.GAUSSIAN, k=40, l=60, seed=seed)
         assert r == out[0] == 20
+        assert re_.gap_rank(s, info["r1"])[0] == 20  # no eps needed: the largest gap (Sec. 5, Sec. 6.1)
         s_o = out[1]
         assert np.all(np.abs(s - s_o) <= 1e-10 * s_o[0])
         big = s_o >= 1e-4 * s_o[0]
         assert np.all(np.abs(s - s_o)[big] <= 1e-10 * s_o[big])
+
+
+def test_gap_rank_on_planted_gap(orc):
+    """A graded spectrum 10^(-i/20) with one jump of 1e-4 after 37 values: the
+    largest ratio of the first r1 sketched estimates sits at the jump, and
+    matches the oracle's definition applied to the oracle's estimates."""
+    spec = 10.0 ** (-np.arange(300) / 20.0)
+    spec[37:] *= 1e-4
+    A = inputs.planted(3000, 1500, spec, 77, torch.float32)
+    for xk, yk in (("srht", "srht"), ("gaussian", "gaussian")):
+        r, s, info = re_.rank_estimate(A.to(DEV), 1e-3, k=96, l=144, x=xk, y=yk, seed=4)
+        g = re_.gap_rank(s, info["r1"])
+        out = orc.rank_estimate(A.numpy(), 1e-3, {"srht": 1, "gaussian": 0}[xk], {"srht": 1, "gaussian": 0}[yk],
+                                k=96, l=144, seed=4)
+        assert g[0] == 37 == orc.gap.gap_rank(out[1], out[2])[0]
+        assert g[1] > 1e3
 
 
 @pytest.mark.parametrize("m,n,xk,yk,dtype", [

@@ -63,3 +63,27 @@ def test_no_oracle_in_product():
                 assert "import oracle" not in txt and "from oracle" not in txt and "liboracle" not in txt, f
     with open(LIB, "rb") as fh:
         assert b"liboracle" not in fh.read()
+
+
+def test_gap_rank_matches_oracle(so, orc):
+    """re_gap_rank is host-only: checked against the oracle's definition here."""
+    import math
+
+    import numpy as np
+    f = so.re_gap_rank
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                  ctypes.POINTER(ctypes.c_double)]
+    f.restype = ctypes.c_int32
+    rng = np.random.default_rng(3)
+    cases = [np.array([1.0] * 20 + [1e-8] * 20), np.array([3.0, 1.0, 0.5, 0.0, 0.0]), np.zeros(4), np.array([2.0]),
+             np.sort(rng.random(50))[::-1].copy(), np.array([1.0, 1.0, 1.0])]
+    for s in cases:
+        for r1 in (0, 1, 2, 5, len(s), len(s) + 3):
+            r = ctypes.c_int32(-1)
+            q = ctypes.c_double(-1.0)
+            assert f(s.ctypes.data_as(ctypes.c_void_p), len(s), r1, ctypes.byref(r), ctypes.byref(q)) == 0
+            want_r, want_q = orc.gap.gap_rank(s, r1)
+            assert r.value == want_r
+            assert (math.isinf(q.value) and math.isinf(want_q)) or abs(q.value - want_q) <= 1e-15 * abs(want_q)
+    r = ctypes.c_int32(0)
+    assert f(None, 3, 2, ctypes.byref(r), None) == -1

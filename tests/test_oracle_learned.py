@@ -102,3 +102,20 @@ def test_learned_round_uses_the_proposal(L):
     L.unpack(p)["b3"][0] = math.log(97.5)  # too small: doubling continues from 104
     out = L.doubling(A, 1e-6, seed=5, params=p)
     assert (out["rounds"], out["k"], out["r"], out["k_proposed"]) == (3, 208, 120, 104)
+
+
+# --- gap-based rank (Sec. 5 after Algorithm 1, Sec. 6.1) ---------------------------
+
+def test_gap_rank_definition(orc):
+    G = orc.gap
+    s = [1.0] * 20 + [1e-8] * 20
+    assert G.gap_rank(s, 36) == (20, 1e8)
+    assert G.gap_rank(s, 15) == (1, 1.0)      # no gap inside the first r1: ties go to i = 1
+    assert G.gap_rank([3.0, 1.0, 0.5, 0.0, 0.0], 5) == (3, math.inf)
+    assert G.gap_rank([0.0, 0.0], 2) == (0, 0.0)
+    assert G.gap_rank([2.0], 1) == (0, 0.0)
+    # graded spectrum 10^(-i/20) with one planted jump of 1e-4 after 37 values
+    s = [10.0 ** (-i / 20) for i in range(60)]
+    s = s[:37] + [v * 1e-4 for v in s[37:]]
+    r, q = G.gap_rank(s, 54)
+    assert r == 37 and abs(q - 10.0 ** (1 / 20) * 1e4) < 1e-6 * q
