@@ -314,7 +314,6 @@ __device__ void partials_lds(const Bidiag2Args& a, const double* Wl, int nr, int
   }
 }
 
-template <int KPL>
 __global__ void __launch_bounds__(kB2Threads) k_bidiag_lds(Bidiag2Args a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t k = a.k, l = a.l, kp = a.kp;
@@ -1112,10 +1111,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     b2.kp = lds_stride(k);
     b2.P = lp.P;
     b2.nr_max = lp.nr_max;
-    const void* fn = k <= 65 ? (const void*)k_bidiag_lds<1>
-                   : k <= 129 ? (const void*)k_bidiag_lds<2>
-                   : k <= 257 ? (const void*)k_bidiag_lds<4>
-                   : k <= 513 ? (const void*)k_bidiag_lds<8> : (const void*)k_bidiag_lds<16>;
+    const void* fn = (const void*)k_bidiag_lds;
     if (lp.bytes > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.bytes));
     void* params2[] = {&b2};

@@ -167,11 +167,13 @@ def test_singular_values(orc, name, Cm):
     assert np.all(np.abs(got - want)[big] <= 1e-10 * want[big])
 
 
-@pytest.mark.parametrize("l,k", [(1100, 1030), (2600, 2400)])
+@pytest.mark.parametrize("l,k", [(1100, 1030), (2600, 2400), (1400, 700)])
 def test_singular_values_global_memory_path(l, k):
-    """k > 1025 runs the global-memory bidiagonalisation (column partials in
-    chunks of 1024); checked against LAPACK (the oracle's Jacobi is pinned to
-    it and would take minutes at this size)."""
+    """Large sketches: k > 1025 runs the global-memory bidiagonalisation
+    (column partials in chunks of 1024); 1400 x 700 is too tall for the
+    register-cached kernel's LDS plan and runs the plain LDS-resident one.
+    Checked against LAPACK (the oracle's Jacobi is pinned to it and would
+    take minutes at these sizes)."""
     rng = np.random.default_rng(11)
     Cm = rng.standard_normal((l, k)) * (10.0 ** -np.linspace(0, 6, k))[None, :]
     got = _np(re_.singular_values(torch.from_numpy(Cm).to(DEV), 1.0))
