@@ -559,15 +559,17 @@ __global__ void __launch_bounds__(NT) k_bidiag_reg(Bidiag2Args a) {
     }
     if (c + 1 < k) {
       // partials of column c + 1: part[j - 1] = sum over rows of W[r][c+1] W[r][c+j]
-      if (wave >= SLOTS) {
-        double* dst = pw + (int64_t)(wave - SLOTS) * (k + 1);
+      if constexpr (NW > SLOTS) {  // wavefronts past the slots hand their sums over first
+        if (wave >= SLOTS) {
+          double* dst = pw + (int64_t)(wave - SLOTS) * (k + 1);
 #pragma unroll
-        for (int t = 0; t < KPL; ++t) {
-          const int64_t j = 1 + lane + 64 * t;
-          if (j < len) dst[j - 1] = pa[t];
+          for (int t = 0; t < KPL; ++t) {
+            const int64_t j = 1 + lane + 64 * t;
+            if (j < len) dst[j - 1] = pa[t];
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
       if (wave < SLOTS) {
         double* dst = pw + (int64_t)wave * (k + 1);
 #pragma unroll
