@@ -6,3 +6,4 @@ package.  The product library never does.
 from .pyoracle import *  # noqa: F401,F403
 from . import learned  # noqa: F401,E402
 from . import gap  # noqa: F401,E402
+from . import rangefinder  # noqa: F401,E402
