@@ -80,7 +80,8 @@ enum {
   RE_FLAG_ZERO = 2u,          /* sigma_1 of the sketch is zero */
   RE_FLAG_PREC_FALLBACK = 4u, /* AUTO could not use a low-precision format */
   RE_FLAG_USED_BF16 = 8u,     /* the A X contraction ran in BF16 */
-  RE_FLAG_USED_FP16 = 16u     /* the A X contraction ran in FP16 */
+  RE_FLAG_USED_FP16 = 16u,    /* the A X contraction ran in FP16 */
+  RE_FLAG_COLUMNS_DROPPED = 32u /* re_rangefinder: columns of A X dependent at FP64 precision were left out of Q */
 };
 
 typedef struct re_handle_s* re_handle;
@@ -244,9 +245,13 @@ re_status re_rank_count(re_handle h, const double* sigma_dev, int64_t k, int32_t
 #define RE_MLP_INPUTS 35   /* log10(s_i/s_1), i < 32 (clamped at -8), log10 m, log10 n, log10 eps */
 #define RE_MLP_PARAMS 6529 /* W1 (64x35), b1 (64), W2 (64x64), b2 (64), w3 (64), b3 (1), row-major */
 
+/* Largest sketch width of the adaptive drivers (re_rank_adaptive,
+ * re_rangefinder): the widest small SVD the library forms in one call. */
+#define RE_MAX_ADAPTIVE_K 5120
+
 typedef struct {
   int32_t k0;          /* pilot width (e.g. 32); the pilot uses l = l_for(k0) rows */
-  int32_t k_max;       /* largest width; 0 means min(m, n) */
+  int32_t k_max;       /* largest width; 0 means min(m, n); capped at RE_MAX_ADAPTIVE_K */
   double l_ratio;      /* rows of Y per column of X: l = clamp(round(l_ratio k), k, m) */
   const float* mlp;    /* device, RE_MLP_PARAMS floats, or NULL for plain doubling */
   double delta;        /* margin added to the network output (natural log of the width) */
@@ -294,6 +299,80 @@ re_status re_mlp_adam(re_handle h, float* params_dev, const float* grad_dev, flo
  *   ratio_out host or NULL: that ratio (0 when r_out is 0)
  * RE_ERR_INVALID_ARG for NULL sigma / r_out or negative sizes. */
 re_status re_gap_rank(const double* sigma, int32_t k, int32_t r1, int32_t* r_out, double* ratio_out);
+
+/* --------------------------------------------------------------------------
+ * Rank estimation combined with the randomized rangefinder (Algorithm 3,
+ * Sec. 5.1): a fixed-precision QB factorisation A ~ Q B with
+ * ||A - Q B||_F <~ eps ||A||.
+ *
+ * 1. Rank estimation with appended sketches exactly as re_rank_adaptive with
+ *    mlp = NULL (Gaussian X and Y, k0, 2 k0, ... up to k_max, each round one
+ *    more pass over A for the new columns of X only), stopping at the first
+ *    width k for which step 2 finds an r.
+ * 2. With s_i the estimates of that round, i <= r1 = r1(k), extended by
+ *    s_i = s_{r1} for r1 < i <= n: r = the smallest r >= 1 with r + p <= k and
+ *    (1 + r/(p-1))^(1/2) (sum_{j>r} s_j^2)^(1/2) <= eps ||A||  (Eq. errRFfro;
+ *    the a priori bound of Halko, Martinsson and Tropp 2011, Thm. 10.5),
+ *    ||A|| = norm_a if norm_a > 0, else s_1.
+ * 3. Q = orthonormal basis of the first w = r + p columns of A X (thin QR by
+ *    shifted CholeskyQR3 in FP64; columns numerically dependent at FP64
+ *    precision are left out, setting RE_FLAG_COLUMNS_DROPPED and w < r + p).
+ * 4. B = Q^T A (one more pass over A: FP32 matrix-core products with Q
+ *    rounded to FP32, FP64 sums across every 256 rows of A).
+ *
+ *   A_dev      device, m x n FP32 row-major, lda >= n, lda < 2^23, 4-byte aligned
+ *   eps        0 < eps < 1
+ *   p          oversampling, 2 <= p < k_max
+ *   ad         host: k0, k_max, l_ratio as in re_rank_adaptive; mlp must be NULL
+ *   norm_a     ||A|| (spectral norm) if known and > 0; otherwise 0
+ *   Q_dev      device, FP64, m x k_max capacity row-major (ldq >= k_max, k_max
+ *              after clamping to min(m, n)); the first w columns are written
+ *   B_dev      device, FP64, k_max x n capacity (ldb >= n); the first w rows
+ *              are written
+ *   r_out      host: r; 0 when the sketch is zero (A = 0); -1 when no r with
+ *              r + p <= k_max qualifies (RE_FLAG_NOT_CONVERGED).  Q and B are
+ *              written only when r > 0.
+ *   w_out      host: columns of Q (0 unless r > 0)
+ *   sigma_out  host, k_max doubles: the final round's estimates (k_out of them)
+ *   k_out      host or NULL: the final width k;  flags_out: host or NULL
+ * Errors: RE_ERR_INVALID_ARG for bad sizes or pointers, RE_ERR_UNSUPPORTED
+ * unless dt = RE_F32 and mlp = NULL, RE_ERR_NONFINITE when the sketch or the
+ * QR meets NaN/Inf, RE_ERR_NO_CONVERGENCE when the small SVD fails.
+ * Synchronises the handle's stream before returning.
+ */
+re_status re_rangefinder(re_handle h, const void* A_dev, int32_t dt, int64_t m, int64_t n, int64_t lda, double eps,
+                         int32_t p, const re_adaptive* ad, double norm_a, uint64_t seed, double* Q_dev, int64_t ldq,
+                         double* B_dev, int64_t ldb, int32_t* r_out, int32_t* w_out, double* sigma_out, int32_t* k_out,
+                         uint32_t* flags_out);
+
+/* Step 3 of re_rangefinder alone (Algorithm 3, the thin QR of the kept
+ * sketch columns; Algorithm 2 step 2): an orthonormal basis of the columns of W.
+ *   W_dev      device, m x w row-major (ldw >= w), FP32 or FP64 (dt), m >= w >= 1
+ *   Q_dev      device, FP64, m x w capacity (ldq >= w); the first w_out columns are
+ *              written: Q R = W with diag(R) > 0 over the kept columns
+ *   w_out      host: kept columns (w unless some are numerically dependent at
+ *              FP64 precision; then RE_FLAG_COLUMNS_DROPPED).  After the
+ *              first, shifted pass a column whose pivot is below 16 u (u = 2^-53)
+ *              of the largest counts as dependent: directions of W with
+ *              singular values below about 4 u^(1/2) (11 (m w + w (w+1)) u)^(1/2)
+ *              ||W||_F are left out (about 1e-12 ||W||_F at m = 4000, w = 120).
+ *   flags_out  host or NULL
+ * Errors: RE_ERR_INVALID_ARG, RE_ERR_NONFINITE.  Synchronises the stream. */
+re_status re_thin_qr(re_handle h, const void* W_dev, int32_t dt, int64_t m, int64_t w, int64_t ldw, double* Q_dev,
+                     int64_t ldq, int32_t* w_out, uint32_t* flags_out);
+
+/* Step 4 of re_rangefinder alone (Algorithm 3, B = Q^T A; Algorithm 2 step 3):
+ * Q_dev FP64 m x w (ldq >= w), A_dev FP32 m x n (lda >= n), B_dev FP64 w x n
+ * (ldb >= n).  FP32 matrix-core products with Q rounded to FP32, FP64 sums
+ * across every 256 rows.  RE_ERR_UNSUPPORTED unless dt = RE_F32.  Does not
+ * synchronise. */
+re_status re_project(re_handle h, const double* Q_dev, int64_t ldq, int64_t w, const void* A_dev, int32_t dt,
+                     int64_t m, int64_t n, int64_t lda, double* B_dev, int64_t ldb);
+
+/* Durations in milliseconds of the three stages of the last re_rangefinder
+ * call with profiling enabled: ms[0] rank estimation (every round and the
+ * width rule), ms[1] the thin QR, ms[2] B = Q^T A. */
+re_status re_rangefinder_stage_ms(re_handle h, double* ms);
 
 /* r1 derived from the sketch width k (Algorithm 1 step 1 inverted). */
 int32_t re_r1_from_k(int32_t k);

@@ -11,6 +11,7 @@ from ._binding import (  # noqa: F401
     FLAG_PREC_FALLBACK,
     FLAG_USED_BF16,
     FLAG_USED_FP16,
+    FLAG_COLUMNS_DROPPED,
     FLAG_ZERO,
     Handle,
     RankEstError,
@@ -23,7 +24,10 @@ from ._binding import (  # noqa: F401
     mlp_forward,
     mlp_loss_grad,
     philox,
+    project,
     r1_from_k,
+    rangefinder,
+    rangefinder_stage_ms,
     rank_adaptive,
     rank_count,
     rank_estimate,
@@ -33,4 +37,5 @@ from ._binding import (  # noqa: F401
     sketch_y,
     srht_select,
     srht_signs,
+    thin_qr,
 )

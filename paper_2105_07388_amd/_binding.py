@@ -23,6 +23,8 @@ RE_GAUSSIAN, RE_SRHT = 0, 1
 PREC = {"native": 0, "bf16": 1, "fp16": 2, "auto": 3}
 KIND = {"gaussian": RE_GAUSSIAN, "srht": RE_SRHT}
 FLAG_NOT_CONVERGED, FLAG_ZERO, FLAG_PREC_FALLBACK, FLAG_USED_BF16, FLAG_USED_FP16 = 1, 2, 4, 8, 16
+FLAG_COLUMNS_DROPPED = 32
+MAX_ADAPTIVE_K = 5120  # RE_MAX_ADAPTIVE_K
 FMT = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 FMT_DTYPE = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float16}
 STAGES = ("x_draw", "ax", "y_draw", "yb", "svd", "rank")
@@ -82,6 +84,11 @@ def lib():
             "re_rank_adaptive": ([vp, vp, i32, i64, i64, i64, dbl, C.POINTER(ReAdaptive), u64, C.POINTER(i32), vp,
                                   C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
                                   C.POINTER(C.c_uint32)], i32),
+            "re_rangefinder": ([vp, vp, i32, i64, i64, i64, dbl, i32, C.POINTER(ReAdaptive), dbl, u64, vp, i64, vp,
+                                i64, C.POINTER(i32), C.POINTER(i32), vp, C.POINTER(i32), C.POINTER(C.c_uint32)], i32),
+            "re_rangefinder_stage_ms": ([vp, vp], i32),
+            "re_thin_qr": ([vp, vp, i32, i64, i64, i64, vp, i64, C.POINTER(i32), C.POINTER(C.c_uint32)], i32),
+            "re_project": ([vp, vp, i64, i64, vp, i32, i64, i64, i64, vp, i64], i32),
             "re_mlp_forward": ([vp, vp, vp, i64, vp], i32),
             "re_mlp_loss_grad": ([vp, vp, vp, vp, i64, vp, vp], i32),
             "re_mlp_adam": ([vp, vp, vp, vp, vp, i64, i32, dbl, dbl, dbl, dbl], i32),
@@ -231,7 +238,7 @@ def rank_adaptive(A: torch.Tensor, eps: float, *, k0: int = 32, k_max: int = 0, 
     h = handle or default_handle(A.device)
     m, n = A.shape
     ad = ReAdaptive(int(k0), int(k_max), float(l_ratio), mlp.data_ptr() if mlp is not None else None, float(delta))
-    kcap = min(m, n) if k_max <= 0 else min(m, n, k_max)
+    kcap = min(m, n, MAX_ADAPTIVE_K) if k_max <= 0 else min(m, n, k_max, MAX_ADAPTIVE_K)
     sigma = np.zeros(kcap, dtype=np.float64)
     r, kk, ll, rounds, kp = (C.c_int32(0) for _ in range(5))
     fl = C.c_uint32(0)
@@ -241,6 +248,77 @@ def rank_adaptive(A: torch.Tensor, eps: float, *, k0: int = 32, k_max: int = 0, 
     _check(st, "re_rank_adaptive")
     return r.value, sigma[:kk.value], {"k": kk.value, "l": ll.value, "rounds": rounds.value,
                                        "k_proposed": kp.value, "flags": fl.value}
+
+
+def rangefinder(A: torch.Tensor, eps: float, p: int = 10, *, k0: int = 32, k_max: int = 0, l_ratio: float = 2.0,
+                norm_a: float = 0.0, seed: int = 0, Q: torch.Tensor | None = None, B: torch.Tensor | None = None,
+                handle: Handle | None = None):
+    """Rank estimation followed by the randomized rangefinder (FP32 A): the
+    fixed-precision factorisation A ~ Q B of rank w.  Q (m x k_max capacity)
+    and B (k_max x n capacity) are FP64 device tensors, allocated here unless
+    given.  Returns (Q[:, :w], B[:w], info) with info = {r, w, k, sigma, flags}."""
+    _check_matrix(A)
+    h = handle or default_handle(A.device)
+    m, n = A.shape
+    kcap = min(m, n, MAX_ADAPTIVE_K) if k_max <= 0 else min(m, n, k_max, MAX_ADAPTIVE_K)
+    if Q is None:
+        Q = torch.empty(m, kcap, dtype=torch.float64, device=A.device)
+    if B is None:
+        B = torch.empty(kcap, n, dtype=torch.float64, device=A.device)
+    for t, name in ((Q, "Q"), (B, "B")):
+        _need_cuda(t, name)
+        if t.dtype != torch.float64 or t.stride(1) != 1:
+            raise ValueError(f"{name} must be a float64 tensor with unit column stride")
+    if Q.shape[0] < m or Q.shape[1] < kcap or B.shape[0] < kcap or B.shape[1] < n:
+        raise ValueError("Q must hold m x k_max and B k_max x n values")
+    ad = ReAdaptive(int(k0), int(k_max), float(l_ratio), None, 0.0)
+    sigma = np.zeros(kcap, dtype=np.float64)
+    r, w, kk = (C.c_int32(0) for _ in range(3))
+    fl = C.c_uint32(0)
+    st = lib().re_rangefinder(h.bind(), _ptr(A), _dtype_code(A), m, n, A.stride(0), float(eps), int(p), C.byref(ad),
+                              float(norm_a), int(seed) % 2**64, _ptr(Q), Q.stride(0), _ptr(B), B.stride(0),
+                              C.byref(r), C.byref(w), sigma.ctypes.data_as(C.c_void_p), C.byref(kk), C.byref(fl))
+    _check(st, "re_rangefinder")
+    wv = w.value
+    return Q[:m, :wv], B[:wv, :n], {"r": r.value, "w": wv, "k": kk.value, "sigma": sigma[:kk.value],
+                                    "flags": fl.value}
+
+
+def thin_qr(W: torch.Tensor, handle: Handle | None = None):
+    """Orthonormal basis of the columns of W (m x w, FP32 or FP64, on the GPU)
+    by the library's shifted CholeskyQR3.  Returns (Q[:, :w_kept], flags)."""
+    _check_matrix(W)
+    m, w = W.shape
+    Q = torch.empty(m, w, dtype=torch.float64, device=W.device)
+    h = handle or default_handle(W.device)
+    we = C.c_int32(0)
+    fl = C.c_uint32(0)
+    _check(lib().re_thin_qr(h.bind(), _ptr(W), _dtype_code(W), m, w, W.stride(0), _ptr(Q), Q.stride(0),
+                            C.byref(we), C.byref(fl)), "re_thin_qr")
+    return Q[:, :we.value], fl.value
+
+
+def project(Q: torch.Tensor, A: torch.Tensor, handle: Handle | None = None) -> torch.Tensor:
+    """B = Q^T A for FP64 Q (m x w) and FP32 A (m x n) on the GPU; B is FP64."""
+    _check_matrix(A)
+    _need_cuda(Q, "Q")
+    if Q.dtype != torch.float64 or Q.stride(1) != 1 or Q.shape[0] != A.shape[0]:
+        raise ValueError("Q must be a float64 m x w tensor with unit column stride")
+    m, n = A.shape
+    w = Q.shape[1]
+    B = torch.empty(w, n, dtype=torch.float64, device=A.device)
+    h = handle or default_handle(A.device)
+    _check(lib().re_project(h.bind(), _ptr(Q), Q.stride(0), w, _ptr(A), _dtype_code(A), m, n, A.stride(0), _ptr(B),
+                            B.stride(0)), "re_project")
+    return B
+
+
+def rangefinder_stage_ms(handle: Handle | None = None) -> list[float]:
+    """Stage times of the last profiled rangefinder call: estimation, thin QR, Q^T A."""
+    h = handle or default_handle()
+    ms = np.zeros(3, dtype=np.float64)
+    _check(lib().re_rangefinder_stage_ms(h.bind(), ms.ctypes.data_as(C.c_void_p)), "re_rangefinder_stage_ms")
+    return ms.tolist()
 
 
 def mlp_forward(params: torch.Tensor, x: torch.Tensor, handle: Handle | None = None) -> torch.Tensor:

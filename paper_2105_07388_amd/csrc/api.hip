@@ -13,6 +13,7 @@
 #include "batch.h"
 #include "common.h"
 #include "learned.h"
+#include "rangefinder.h"
 
 #define RE_API extern "C" __attribute__((visibility("default")))
 
@@ -34,6 +35,10 @@ struct re_handle_s {
     int waves, mt, bk, grid;  // wavefronts, 32-row tiles per wavefront, K step, resident workgroups
   };
   std::map<std::string, Tile> tuned;  // shape key -> persistent contraction tile
+  // rangefinder: QR and Q^T A workspace (sized once the width is known) and stage times
+  void* ws2 = nullptr;
+  size_t ws2_bytes = 0;
+  double rf_ms[3] = {};
 };
 
 namespace re {
@@ -54,6 +59,22 @@ re_status ensure_ws(re_handle h, size_t bytes) {
     return RE_ERR_NO_MEMORY;
   }
   h->ws_bytes = want;
+  return RE_OK;
+}
+
+re_status ensure_ws2(re_handle h, size_t bytes) {
+  if (bytes <= h->ws2_bytes) return RE_OK;
+  RE_TRY_HIP(hipStreamSynchronize(h->stream));
+  if (h->ws2) (void)hipFree(h->ws2);
+  h->ws2 = nullptr;
+  h->ws2_bytes = 0;
+  const size_t want = al256(bytes + bytes / 8);
+  if (hipMalloc(&h->ws2, want) != hipSuccess) {
+    (void)hipGetLastError();
+    h->ws2 = nullptr;
+    return RE_ERR_NO_MEMORY;
+  }
+  h->ws2_bytes = want;
   return RE_OK;
 }
 
@@ -261,6 +282,7 @@ RE_API re_status re_destroy(re_handle h) {
   drop_graph(h);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   if (h->ws) (void)hipFree(h->ws);
+  if (h->ws2) (void)hipFree(h->ws2);
   if (h->host) (void)hipHostFree(h->host);
   delete h;
   return RE_OK;
@@ -796,7 +818,7 @@ RE_API re_status re_rank_adaptive(re_handle h, const void* A, int32_t dt, int64_
   if (ad->k0 < 1 || !(ad->l_ratio >= 1.0) || ad->k_max < 0 || !isfinite(ad->delta)) return RE_ERR_INVALID_ARG;
   int64_t kmax = m < n ? m : n;
   if (ad->k_max > 0 && ad->k_max < kmax) kmax = ad->k_max;
-  if (kmax > (int64_t)INT32_MAX / 2) return RE_ERR_INVALID_ARG;
+  if (kmax > RE_MAX_ADAPTIVE_K) kmax = RE_MAX_ADAPTIVE_K;
   const int64_t lmax = l_for(kmax, ad->l_ratio, m);
   AdPlan p{};
   Carve c;
@@ -876,6 +898,192 @@ RE_API re_status re_rank_adaptive(re_handle h, const void* A, int32_t dt, int64_
       k = 2 * k < kmax ? 2 * k : kmax;
     }
   }
+}
+
+namespace re {
+namespace {
+
+// Thin QR of the m x w matrix V (FP32 if v32, else FP64; leading dimension
+// ldv) by shifted CholeskyQR3: the kept columns of Q go to Q (ldq), their
+// number to *w_eff.  Synchronises the stream once, before the last product.
+re_status rf_qr(re_handle h, const void* V, bool v32, int64_t m, int64_t w, int64_t ldv, double* Q, int64_t ldq,
+                int32_t* w_eff) {
+  hipStream_t s = h->stream;
+  int64_t gs = 0, grps = 0;
+  rf_row_split(m, cdiv(w, 64) * (cdiv(w, 64) + 1) / 2, &gs, &grps);
+  Carve c;
+  const size_t oQ1 = c.take((size_t)m * w * 8), oQ2 = c.take((size_t)m * w * 8);
+  const size_t oG = c.take((size_t)w * w * 8), oRi = c.take((size_t)w * w * 8);
+  const size_t oKeep = c.take((size_t)w * 4), oCnt = c.take(16);
+  const size_t oParts = c.take((size_t)gs * w * w * 8);
+  RE_TRY(ensure_ws2(h, c.off));
+  RE_TRY(ensure_host(h, 64));
+  char* base = (char*)h->ws2;
+  double* Q1 = (double*)(base + oQ1);
+  double* Q2 = (double*)(base + oQ2);
+  double* G = (double*)(base + oG);
+  double* Ri = (double*)(base + oRi);
+  int32_t* keep = (int32_t*)(base + oKeep);
+  int32_t* cnt = (int32_t*)(base + oCnt);
+  double* parts = (double*)(base + oParts);
+  const void* Vin[3] = {V, Q1, Q2};
+  const int64_t ldin[3] = {ldv, w, w};
+  double* Vout[2] = {Q1, Q2};
+  for (int pass = 0; pass < 3; ++pass) {
+    const bool f32 = pass == 0 && v32;
+    RE_TRY(launch_rf_gram(s, Vin[pass], f32, m, w, ldin[pass], gs, grps, parts));
+    RE_TRY(launch_rf_sum_parts(s, parts, gs, w, w, true, G, w));
+    RE_TRY(launch_rf_chol(s, G, w, pass == 0, m, Ri, keep, cnt));
+    if (pass < 2) {
+      RE_TRY(launch_rf_apply(s, Vin[pass], f32, m, w, ldin[pass], Ri, nullptr, Vout[pass], w));
+      continue;
+    }
+    char* host = (char*)h->host;
+    RE_TRY_HIP(hipMemcpyAsync(host + 16, cnt, 8, hipMemcpyDeviceToHost, s));
+    RE_TRY_HIP(hipStreamSynchronize(s));
+    const int32_t* c8 = (const int32_t*)(host + 16);
+    if (c8[1] != 0) return (re_status)c8[1];
+    *w_eff = c8[0];
+    RE_TRY(launch_rf_apply(s, Vin[pass], false, m, w, ldin[pass], Ri, keep, Q, ldq));
+  }
+  return RE_OK;
+}
+
+// B (ldb) = Q^T A for the w columns of Q (ldq) and FP32 A (lda).
+re_status rf_project(re_handle h, const double* Q, int64_t ldq, int64_t w, const float* A, int64_t m, int64_t n,
+                     int64_t lda, double* B, int64_t ldb) {
+  hipStream_t s = h->stream;
+  const int64_t mc = w >= 128 ? 4 : cdiv(w, 32);
+  int64_t qs = 0, qrps = 0;
+  rf_row_split(m, cdiv(w, 32 * mc) * rf_qta_col_tiles(n), &qs, &qrps);
+  RE_TRY(ensure_ws2(h, (size_t)qs * w * n * 8));
+  double* parts = (double*)h->ws2;
+  RE_TRY(launch_rf_qta(s, Q, ldq, w, A, m, n, lda, qs, qrps, parts));
+  return launch_rf_sum_parts(s, parts, qs, w, n, false, B, ldb);
+}
+
+}  // namespace
+}  // namespace re
+
+RE_API re_status re_rangefinder(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda, double eps,
+                                int32_t p, const re_adaptive* ad, double norm_a, uint64_t seed, double* Q, int64_t ldq,
+                                double* Bq, int64_t ldb, int32_t* r_out, int32_t* w_out, double* sigma_out,
+                                int32_t* k_out, uint32_t* flags_out) {
+  if (!h || !A || !ad || !Q || !Bq || !r_out || !w_out || !sigma_out) return RE_ERR_INVALID_ARG;
+  if (dt != RE_F64 && dt != RE_F32) return RE_ERR_INVALID_ARG;
+  if (dt != RE_F32 || ad->mlp) return RE_ERR_UNSUPPORTED;
+  if (!(eps > 0.0 && eps < 1.0) || m < 1 || n < 1 || lda < n || lda >= kMaxBatchLda || ((uintptr_t)A) % 4 != 0)
+    return RE_ERR_INVALID_ARG;
+  if (ad->k0 < 1 || !(ad->l_ratio >= 1.0) || ad->k_max < 0 || !isfinite(norm_a) || norm_a < 0.0)
+    return RE_ERR_INVALID_ARG;
+  int64_t kmax = m < n ? m : n;
+  if (ad->k_max > 0 && ad->k_max < kmax) kmax = ad->k_max;
+  if (kmax > RE_MAX_ADAPTIVE_K) kmax = RE_MAX_ADAPTIVE_K;
+  if (p < 2 || p >= kmax || ldq < kmax || ldb < n) return RE_ERR_INVALID_ARG;
+  const int64_t lmax = l_for(kmax, ad->l_ratio, m);
+  AdPlan pl{};
+  Carve c;
+  pl.B = c.take((size_t)m * kmax * 4);
+  pl.Xn = c.take((size_t)n * kmax * 4);
+  pl.Y = c.take((size_t)lmax * m * 4);
+  pl.C = c.take((size_t)lmax * kmax * 8);
+  pl.svd = c.take(svd_scratch_bytes(lmax, kmax));
+  pl.sigma = c.take((size_t)kmax * 8);
+  pl.info = c.take(16);
+  pl.out3 = c.take(16);
+  pl.gdesc = c.take(sizeof(GemmDesc));
+  pl.ydesc = c.take(sizeof(YDesc));
+  pl.queue = c.take(16);
+  const size_t oTail = c.take((size_t)(kmax + 1) * 8);
+  pl.total = c.off;
+  RE_TRY(ensure_ws(h, pl.total));
+  RE_TRY(ensure_host(h, 256 + (size_t)kmax * 8));
+  hipStream_t s = h->stream;
+  char* host = (char*)h->host;
+  float* B = (float*)at(h, pl.B);
+  float* Y = (float*)at(h, pl.Y);
+  double* C = (double*)at(h, pl.C);
+  double* sigma = (double*)at(h, pl.sigma);
+  int32_t* info = (int32_t*)at(h, pl.info);
+  int32_t* out4 = (int32_t*)at(h, pl.out3);
+  mark(h, 0);
+  // 1-2: rank estimation with appended sketches until the width rule finds r
+  int64_t k_old = 0, l_old = 0, k = ad->k0 < kmax ? ad->k0 : kmax;
+  const int32_t* o4 = (const int32_t*)host;
+  for (;;) {
+    const int64_t l = l_for(k, ad->l_ratio, m);
+    RE_TRY(launch_gauss_sub(s, n, k - k_old, 0, k_old, seed, kXGauss, 0, k - k_old, (float*)at(h, pl.Xn)));
+    RE_TRY(launch_gemm_f32_single(s, (const float*)A, m, n, lda, (const float*)at(h, pl.Xn), k - k_old, B + k_old, kmax,
+                                  (GemmDesc*)at(h, pl.gdesc), (unsigned*)at(h, pl.queue)));
+    RE_TRY(launch_gauss_sub(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, Y + l_old * m));
+    RE_TRY(launch_ygemm_single(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, pl.ydesc)));
+    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, pl.svd), sigma, info));
+    RE_TRY(launch_rf_width(s, sigma, k, r1_from_k((int32_t)k), n, eps, p, norm_a, info, (double*)at(h, oTail), out4));
+    RE_TRY_HIP(hipMemcpyAsync(host, out4, 16, hipMemcpyDeviceToHost, s));
+    RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)k * 8, hipMemcpyDeviceToHost, s));
+    RE_TRY_HIP(hipStreamSynchronize(s));
+    if (o4[2] != 0) return (re_status)o4[2];
+    if (o4[0] >= 0 || k >= kmax) break;
+    k_old = k;
+    l_old = l;
+    k = 2 * k < kmax ? 2 * k : kmax;
+  }
+  const int32_t r = o4[0];
+  uint32_t flags = (uint32_t)o4[3];
+  int32_t w_eff = 0;
+  mark(h, 1);
+  if (r > 0) {
+    const int64_t w = o4[1];
+    RE_TRY(rf_qr(h, B, true, m, w, kmax, Q, ldq, &w_eff));  // 3: thin QR of A X[:, :w]
+    if (w_eff < w) flags |= RE_FLAG_COLUMNS_DROPPED;
+    mark(h, 2);
+    if (w_eff > 0) RE_TRY(rf_project(h, Q, ldq, w_eff, (const float*)A, m, n, lda, Bq, ldb));  // 4: B = Q^T A
+  } else {
+    mark(h, 2);
+  }
+  mark(h, 3);
+  RE_TRY_HIP(hipStreamSynchronize(s));
+  if (h->prof) {
+    for (int i = 0; i < 3; ++i) {
+      float ms = 0.f;
+      h->rf_ms[i] = hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess ? (double)ms : -1.0;
+    }
+  }
+  *r_out = r;
+  *w_out = w_eff;
+  memcpy(sigma_out, host + 64, (size_t)k * 8);
+  if (k_out) *k_out = (int32_t)k;
+  if (flags_out) *flags_out = flags;
+  return RE_OK;
+}
+
+RE_API re_status re_thin_qr(re_handle h, const void* W, int32_t dt, int64_t m, int64_t w, int64_t ldw, double* Q,
+                            int64_t ldq, int32_t* w_out, uint32_t* flags_out) {
+  if (!h || !W || !Q || !w_out) return RE_ERR_INVALID_ARG;
+  if (dt != RE_F64 && dt != RE_F32) return RE_ERR_INVALID_ARG;
+  if (w < 1 || m < w || ldw < w || ldq < w || w > 46340 || ((uintptr_t)W) % (dt == RE_F64 ? 8 : 4) != 0)
+    return RE_ERR_INVALID_ARG;
+  int32_t we = 0;
+  RE_TRY(rf_qr(h, W, dt == RE_F32, m, w, ldw, Q, ldq, &we));
+  RE_TRY_HIP(hipStreamSynchronize(h->stream));
+  *w_out = we;
+  if (flags_out) *flags_out = we < w ? RE_FLAG_COLUMNS_DROPPED : 0u;
+  return RE_OK;
+}
+
+RE_API re_status re_project(re_handle h, const double* Q, int64_t ldq, int64_t w, const void* A, int32_t dt, int64_t m,
+                            int64_t n, int64_t lda, double* B, int64_t ldb) {
+  if (!h || !Q || !A || !B) return RE_ERR_INVALID_ARG;
+  if (dt != RE_F64 && dt != RE_F32) return RE_ERR_INVALID_ARG;
+  if (dt != RE_F32) return RE_ERR_UNSUPPORTED;
+  if (w < 1 || m < 1 || n < 1 || ldq < w || lda < n || ldb < n || ((uintptr_t)A) % 4 != 0) return RE_ERR_INVALID_ARG;
+  return rf_project(h, Q, ldq, w, (const float*)A, m, n, lda, B, ldb);
+}
+
+RE_API re_status re_rangefinder_stage_ms(re_handle h, double* ms) {
+  if (!h || !ms || !h->prof) return RE_ERR_INVALID_ARG;
+  for (int i = 0; i < 3; ++i) ms[i] = h->rf_ms[i];
+  return RE_OK;
 }
 
 RE_API re_status re_philox(re_handle h, const uint64_t* ctr, uint64_t seed, int64_t count, uint64_t* out) {
