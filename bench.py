@@ -42,6 +42,10 @@ WORKLOADS = {
                desc="learned sketch width: planted FP32 matrices (m log-uniform in [4096, 65536], n = m/4, poly / exp "
                     "/ step decay, planted rank in [10, 2000] at eps in [1e-6, 1e-2]), Gaussian sketches, pilot "
                     "k = 32, l = 1.5 k; the trained network with doubling fallback against doubling from 32"),
+    "rf": dict(m=100000, n=100000, q=0.01, k=1650, l=3300, p=10, eps=(1e-3,), x="gaussian", y="gaussian",
+               desc="rank estimation + randomized rangefinder (fixed-precision QB): FP32 100000x100000 diagonal "
+                    "s_i = 10^(-0.01 (i-1)) stored dense (slow exponential decay), r1 = 1500 (Gaussian X 1650 "
+                    "columns, Y 3300 rows), p = 10, eps 1e-3; thin QR of A X[:, :r+p], B = Q^T A"),
     "c1": dict(m=2000, n=1000, R=1000, k=40, l=60, eps=(1e-6,), x="gaussian", y="gaussian",
                desc="plain method, CPU-sized: FP64 2000x1000, step spectrum (20 x 1, then 1e-8), "
                     "Gaussian X 1000x40, Gaussian Y 60x2000, eps 1e-6"),
@@ -50,7 +54,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 TRAFFIC_SOURCES = {"c2": ("srht.hip", "common.h"), "c3": ("gemm_lp.hip", "common.h"),
-                   "c4": ("batch.hip", "batch.h", "common.h")}
+                   "c4": ("batch.hip", "batch.h", "common.h"), "rf": ("batch.hip", "batch.h", "common.h")}
 
 
 def kernel_source_digest(workload: str) -> str:
@@ -286,6 +290,131 @@ def bench_learned(args, w, dev):
     print(json.dumps(out), flush=True)
 
 
+def cpu_baseline_rf(A_dev, w, rows: int, r: int):
+    """Oracle of Algorithm 3 timed on a bounded sample: A X and Q^T A on the
+    first `rows` rows (scaled to m), Y B on `rows` columns of Y (scaled to m),
+    the Jacobi SVD of a half-size sketch (scaled by 8, its cubic cost), the
+    Householder QR of the full m x (r + p) basis."""
+    import numpy as np
+
+    import oracle
+    m, n, k, l, p = w["m"], w["n"], w["k"], w["l"], w["p"]
+    rows = min(rows, m)
+    A_s = A_dev[:rows].cpu().numpy()
+    # A X costs a fixed part (drawing X) plus a part linear in the rows:
+    # timed at rows / 2 and rows, extrapolated linearly to m
+    t0 = time.perf_counter()
+    oracle.apply_x(A_s[:rows // 2], oracle.GAUSSIAN, k, seed=0)
+    t_half = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    B = oracle.apply_x(A_s, oracle.GAUSSIAN, k, seed=0)
+    t_full = time.perf_counter() - t0
+    per_row = max(t_full - t_half, 0.0) / (rows - rows // 2)
+    t_x = max(t_full - per_row * rows, 0.0) + per_row * m
+    t0 = time.perf_counter()
+    oracle.apply_y(B, oracle.GAUSSIAN, l, seed=0)
+    t_y = (time.perf_counter() - t0) * (m / rows)
+    G = np.random.default_rng(0).standard_normal((l // 2, k // 2))
+    t0 = time.perf_counter()
+    oracle.jacobi_sv(G)
+    t_svd = (time.perf_counter() - t0) * 8
+    wd = r + p
+    W = np.random.default_rng(1).standard_normal((m, wd))
+    t0 = time.perf_counter()
+    Q, _ = oracle.rangefinder.thin_qr(W)
+    t_qr = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Q[:rows].T @ A_s.astype(np.float64)
+    t_qb = (time.perf_counter() - t0) * (m / rows)
+    total = t_x + t_y + t_svd + t_qr + t_qb
+    return {"value": 1.0 / total, "unit": "QB factorisations/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"A X timed on the first {rows // 2} and {rows} rows, extrapolated linearly to {m}; Y B and "
+                      f"Q^T A on the first {rows} rows scaled by {m / rows:g}; Jacobi SVD of a "
+                      f"{l // 2}x{k // 2} sketch scaled by 8, Householder QR of {m}x{wd}; seconds: ax {t_x:.1f}, "
+                      f"yb {t_y:.1f}, svd {t_svd:.1f}, qr {t_qr:.1f}, qta {t_qb:.1f}"}
+
+
+def bench_rf(args, w, dev):
+    """One step = Algorithm 3 end to end: rank estimation at k = round(1.1 r1),
+    the width rule, the thin QR of A X[:, :r+p] and B = Q^T A."""
+    import numpy as np
+    import torch
+
+    import paper_2105_07388_amd as re_
+
+    m, n, k = w["m"], w["n"], w["k"]
+    A = torch.zeros(m, n, dtype=torch.float32, device=dev)
+    A.diagonal().copy_(10.0 ** (-w["q"] * torch.arange(min(m, n), dtype=torch.float64, device=dev)))
+    Q = torch.empty(m, k, dtype=torch.float64, device=dev)
+    B = torch.empty(k, n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    print(f"[bench] rf: A {tuple(A.shape)} {A.dtype} resident; warmup {args.warmup}", file=sys.stderr, flush=True)
+    h = re_.Handle(dev)
+    h.set_profiling(True)
+    eps, p = w["eps"][0], w["p"]
+
+    def step(i):
+        return re_.rangefinder(A, eps, p, k0=k, k_max=k, l_ratio=w["l"] / k, seed=1000003 * (i + 1), Q=Q, B=B,
+                               handle=h)
+
+    for i in range(args.warmup):
+        step(-1 - i)
+    torch.cuda.synchronize()
+    stages, infos = [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, _, info = step(i)
+        infos.append((info["r"], info["w"], info["k"]))
+        stages.append(re_.rangefinder_stage_ms(h))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = np.mean(np.array(stages), axis=0)
+    st_mean = {"estimate": float(st[0]), "thin_qr": float(st[1]), "qta": float(st[2])}
+    r, wd, kk = infos[-1]
+    print(f"[bench] stages (ms): " + ", ".join(f"{a} {v:.3f}" for a, v in st_mean.items()) +
+          f"; (r, w, k) {sorted(set(infos))}", file=sys.stderr, flush=True)
+    # dominant kernel: the A X contraction inside the estimate, timed by the
+    # single-matrix call's own stage events at the same (k, l)
+    for i in range(2):
+        re_.rank_estimate(A, eps, k=k, l=w["l"], seed=7 + i, handle=h)
+    ax = []
+    for i in range(max(3, min(args.steps, 5))):
+        re_.rank_estimate(A, eps, k=k, l=w["l"], seed=11 + i, handle=h)
+        ax.append(h.last_stage_ms()["ax"])
+    ax_ms = float(np.mean(ax))
+    flops = 2.0 * m * n * k
+    achieved = flops / (ax_ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": load_traffic("rf"),
+            "kernel": "persistent FP32 MFMA A X (k = 1650)", "algorithmic_flops_per_launch": flops,
+            "algorithmic_bytes_per_launch": m * n * 4.0, "mean_ms": ax_ms,
+            "qta": {"achieved_tflops": 2.0 * m * n * wd / (st_mean["qta"] * 1e-3) / 1e12,
+                    "frac": 2.0 * m * n * wd / (st_mean["qta"] * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+                    "hbm_GBs": m * n * 4.0 / (st_mean["qta"] * 1e-3) / 1e9, "mean_ms": st_mean["qta"]}}
+    out = {
+        "metric": "QB factorisations/s (Algorithm 3, fixed precision)",
+        "value": args.steps / elapsed,
+        "unit": "QB factorisations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "m": m, "n": n, "k": k, "l": w["l"], "p": p, "eps": [eps], "r": r,
+                   "w": wd, "parallelism": "single GPU"},
+        "roofline": roof,
+        "stage_ms": st_mean,
+    }
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_rf(A, w, min(args.cpu_rows, 512), r)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +454,8 @@ def main():
         return bench_batched(args, w, dev)
     if args.workload == "c5":
         return bench_learned(args, w, dev)
+    if args.workload == "rf":
+        return bench_rf(args, w, dev)
     A = make_matrix(args.workload, w, dev)
     torch.cuda.synchronize()
     h = re_.Handle(dev)

@@ -151,8 +151,23 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
 
 // Workspace plan of one estimate.
 struct Plan {
-  size_t xbits, ybits, xsel, ysel, selscr, X, Y, B, C, svd, sigma, info, out3, stats, gdesc, ydesc, queue, total;
+  size_t xbits, ybits, xsel, ysel, selscr, X, Y, B, C, svd, sigma, info, out3, stats, gdesc, ydesc, queue, yparts,
+      total;
 };
+
+// Sketches the batched form accepts (one workgroup's LDS holds the small SVD).
+bool batched_fits(int64_t l, int64_t k) { return k <= 4096 && batched_svd_lds_bytes(l, k) <= 156 * 1024; }
+
+// C = Y B for FP32 B and Y: the batched form's kernel for every sketch the
+// batched form accepts (a block of a batch and the same matrix alone then give
+// the same bits), the tiled product with a split over m for wider ones.
+size_t yb_scratch(int64_t l, int64_t k, int64_t m) { return batched_fits(l, k) ? 0 : yb_parts_bytes(l, k, m); }
+
+re_status run_yb(hipStream_t s, const float* B, int64_t m, int64_t k, int64_t ldb, const float* Y, int64_t ldy,
+                 int64_t l, double* C, YDesc* yd, void* parts) {
+  if (batched_fits(l, k)) return launch_ygemm_single(s, B, m, k, ldb, Y, ldy, l, C, yd);
+  return launch_yb_tiled(s, B, m, k, ldb, Y, ldy, l, C, (double*)parts);
+}
 
 Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   Carve c;
@@ -177,6 +192,7 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   p.gdesc = c.take(sizeof(GemmDesc));
   p.ydesc = c.take(sizeof(YDesc));
   p.queue = c.take(16);
+  p.yparts = c.take(rs.yk == RE_GAUSSIAN && dt == RE_F32 ? yb_scratch(rs.l, rs.k, m) : 0);
   p.total = c.off;
   return p;
 }
@@ -237,8 +253,9 @@ re_status run_y(re_handle h, const Plan& p, void* B, int32_t bdt, int64_t m, con
   void* Y = at(h, p.Y);
   RE_TRY(launch_gauss_fill(s, fy, rs.l, m, seed, kYGauss, 1, Y));
   mark(h, RE_STAGE_YB);
-  if (bdt == RE_F32)  // the batched form's kernel, so one block of a batch matches a single call
-    return launch_ygemm_single(s, (const float*)B, m, rs.k, rs.k, (const float*)Y, m, rs.l, C, (YDesc*)at(h, p.ydesc));
+  if (bdt == RE_F32)
+    return run_yb(s, (const float*)B, m, rs.k, rs.k, (const float*)Y, m, rs.l, C, (YDesc*)at(h, p.ydesc),
+                  at(h, p.yparts));
   return launch_gemm_f64acc(s, rs.l, rs.k, m, Y, 0, m, B, 0, rs.k, C, 0, rs.k);
 }
 
@@ -619,7 +636,7 @@ RE_API re_status re_rank_estimate_batched(re_handle h, const re_block* blocks, i
   const int64_t k = sk->k, l = sk->l == 0 ? 2 * (int64_t)sk->k : sk->l;
   if (k < 1 || l < k || k > 4096) return RE_ERR_INVALID_ARG;
   if (nblocks == 0) return RE_OK;
-  if (batched_svd_lds_bytes(l, k) > 156 * 1024) return RE_ERR_UNSUPPORTED;
+  if (!batched_fits(l, k)) return RE_ERR_UNSUPPORTED;
   int64_t nmax = 0, mmax = 0, brows = 0;
   for (int b = 0; b < nblocks; ++b) {
     const re_block& bl = blocks[b];
@@ -800,8 +817,24 @@ void pilot_features(const double* s, int64_t k, int64_t m, int64_t n, double eps
 }
 
 struct AdPlan {
-  size_t B, Xn, Y, C, svd, sigma, info, out3, gdesc, ydesc, queue, feat, yout, total;
+  size_t B, Xn, Y, C, svd, sigma, info, out3, gdesc, ydesc, queue, feat, yout, yparts, total;
 };
+
+// Largest Y B scratch over the widths an adaptive run may visit (k0 doubling,
+// a proposal rounded to 8, k_max).
+size_t yb_scratch_adaptive(int64_t k0, int64_t kmax, double ratio, int64_t m) {
+  size_t most = 0;
+  for (int64_t k = 8; k <= kmax; k += 8) {
+    const size_t b = yb_scratch(l_for(k, ratio, m), k, m);
+    most = b > most ? b : most;
+  }
+  for (int64_t k = k0 < kmax ? k0 : kmax;; k = 2 * k < kmax ? 2 * k : kmax) {
+    const size_t b = yb_scratch(l_for(k, ratio, m), k, m);
+    most = b > most ? b : most;
+    if (k >= kmax) break;
+  }
+  return most;
+}
 
 }  // namespace
 }  // namespace re
@@ -835,6 +868,7 @@ RE_API re_status re_rank_adaptive(re_handle h, const void* A, int32_t dt, int64_
   p.queue = c.take(16);
   p.feat = c.take(RE_MLP_INPUTS * 4);
   p.yout = c.take(16);
+  p.yparts = c.take(yb_scratch_adaptive(ad->k0, kmax, ad->l_ratio, m));
   p.total = c.off;
   RE_TRY(ensure_ws(h, p.total));
   RE_TRY(ensure_host(h, 256 + (size_t)kmax * 8));  // out3 | sigma | features
@@ -855,7 +889,7 @@ RE_API re_status re_rank_adaptive(re_handle h, const void* A, int32_t dt, int64_
     RE_TRY(launch_gemm_f32_single(s, (const float*)A, m, n, lda, (const float*)at(h, p.Xn), k - k_old, B + k_old, kmax,
                                   (GemmDesc*)at(h, p.gdesc), (unsigned*)at(h, p.queue)));
     RE_TRY(launch_gauss_sub(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, Y + l_old * m));
-    RE_TRY(launch_ygemm_single(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, p.ydesc)));
+    RE_TRY(run_yb(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, p.ydesc), at(h, p.yparts)));
     // steps 7-8
     RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, p.svd), sigma, info));
     RE_TRY(launch_rank_count(s, sigma, k, r1_from_k((int32_t)k), eps, info, out3));
@@ -994,6 +1028,7 @@ RE_API re_status re_rangefinder(re_handle h, const void* A, int32_t dt, int64_t 
   pl.gdesc = c.take(sizeof(GemmDesc));
   pl.ydesc = c.take(sizeof(YDesc));
   pl.queue = c.take(16);
+  pl.yparts = c.take(yb_scratch_adaptive(ad->k0, kmax, ad->l_ratio, m));
   const size_t oTail = c.take((size_t)(kmax + 1) * 8);
   pl.total = c.off;
   RE_TRY(ensure_ws(h, pl.total));
@@ -1016,7 +1051,7 @@ RE_API re_status re_rangefinder(re_handle h, const void* A, int32_t dt, int64_t 
     RE_TRY(launch_gemm_f32_single(s, (const float*)A, m, n, lda, (const float*)at(h, pl.Xn), k - k_old, B + k_old, kmax,
                                   (GemmDesc*)at(h, pl.gdesc), (unsigned*)at(h, pl.queue)));
     RE_TRY(launch_gauss_sub(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, Y + l_old * m));
-    RE_TRY(launch_ygemm_single(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, pl.ydesc)));
+    RE_TRY(run_yb(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, pl.ydesc), at(h, pl.yparts)));
     RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, pl.svd), sigma, info));
     RE_TRY(launch_rf_width(s, sigma, k, r1_from_k((int32_t)k), n, eps, p, norm_a, info, (double*)at(h, oTail), out4));
     RE_TRY_HIP(hipMemcpyAsync(host, out4, 16, hipMemcpyDeviceToHost, s));

@@ -41,6 +41,13 @@ RE_RF_HIDDEN re_status launch_rf_chol(hipStream_t s, double* G, int64_t w, bool 
 // negative) if keep is given, else to c.  V as in launch_rf_gram.
 RE_RF_HIDDEN re_status launch_rf_apply(hipStream_t s, const void* V, bool v32, int64_t m, int64_t w, int64_t ldv,
                                        const double* Rinv, const int32_t* keep, double* Q, int64_t ldq);
+// C = Y B (l x k, FP64, leading dimension k) for a Gaussian Y (l x m FP32,
+// ldy) and B (m x k FP32, ldb): 64 x 64 tiles on the FP64 matrix cores, the m
+// rows split into chunks when the tiles alone cannot fill the chip, chunk
+// partials (yb_parts_bytes of scratch) summed in a fixed order.
+RE_RF_HIDDEN size_t yb_parts_bytes(int64_t l, int64_t k, int64_t m);
+RE_RF_HIDDEN re_status launch_yb_tiled(hipStream_t s, const float* B, int64_t m, int64_t k, int64_t ldb, const float* Y,
+                                       int64_t ldy, int64_t l, double* C, double* parts);
 // parts[s] (w x n) = Q[rows of chunk s]^T A[rows of chunk s], FP32 matrix-core
 // products of FP32 A with Q rounded to FP32, FP64 accumulation across every
 // 256 rows.

@@ -280,33 +280,42 @@ __global__ void __launch_bounds__(kCholThreads) k_rf_chol(double* __restrict__ G
 }
 
 // ---------------------------------------------------------------------------
-// Q = V Rinv: 64 x 64 output tiles, K = the columns of V, stopping at the last
-// column of the tile (Rinv is upper triangular).  Same wavefront layout and
-// MFMA as the Gram kernel, the V tile stored row by row (pitch 17 doubles).
+// C = A Bm over one chunk of K: 64 x 64 output tiles of the M x N product of a
+// row-major A (M x K, lda) and a row-major Bm (K x N, ldb), FP64 products of
+// the stored values (FP32 or FP64).  Chunk z = blockIdx.z covers K indices
+// [z kps, (z+1) kps) and writes its tile to out + z sstride; with `tri` the K
+// range also stops at the tile's last column (Bm upper triangular).  Column c
+// is written to column map[c] (skipped when negative) if map is given.  Same
+// wavefront layout and MFMA as the Gram kernel; the A tile is stored row by
+// row (pitch 17 doubles).
 // ---------------------------------------------------------------------------
 constexpr int kABK = 16, kAPV = kABK + 1, kAPR = 80;
 
-template <typename TI>
-__global__ void __launch_bounds__(256) k_rf_apply(const TI* __restrict__ V, int64_t m, int64_t w, int64_t ldv,
-                                                  const double* __restrict__ Rinv, const int32_t* __restrict__ keep,
-                                                  double* __restrict__ Q, int64_t ldq) {
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(256) k_nn64(const TA* __restrict__ A, int64_t M, int64_t lda,
+                                              const TB* __restrict__ Bm, int64_t ldb, int64_t N, int64_t K,
+                                              int64_t kps, int tri, const int32_t* __restrict__ map,
+                                              double* __restrict__ out, int64_t ldo, int64_t sstride) {
   __shared__ double sV[2][64 * kAPV], sR[2][kABK * kAPR];
   const int64_t c0 = (int64_t)blockIdx.x * 64, i0 = (int64_t)blockIdx.y * 64;
-  const int64_t kend = c0 + 64 < w ? c0 + 64 : w;
+  const int64_t kb = (int64_t)blockIdx.z * kps;
+  int64_t ke = kb + kps < K ? kb + kps : K;
+  if (tri && c0 + 64 < ke) ke = c0 + 64;
+  double* __restrict__ o = out + (int64_t)blockIdx.z * sstride;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int q16 = lane & 15, kq = lane >> 4, wy = wave >> 1, wx = wave & 1;
-  const int vr = tid >> 2, vk = (tid & 3) * 4;   // V loader: row, first of 4 K values
-  const int rr = tid >> 4, rc = (tid & 15) * 4;  // Rinv loader: K row, first of 4 columns
+  const int vr = tid >> 2, vk = (tid & 3) * 4;   // A loader: row, first of 4 K values
+  const int rr = tid >> 4, rc = (tid & 15) * 4;  // Bm loader: K row, first of 4 columns
   double xv[4], xr[4];
-  const bool vrow_ok = i0 + vr < m;
-  const TI* __restrict__ vrow = V + (vrow_ok ? i0 + vr : 0) * ldv;
+  const bool vrow_ok = i0 + vr < M;
+  const TA* __restrict__ vrow = A + (vrow_ok ? i0 + vr : 0) * lda;
   auto load = [&](int64_t t0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t t = t0 + vk + q;
-      xv[q] = (vrow_ok && t < kend) ? (double)vrow[t] : 0.0;
+      xv[q] = (vrow_ok && t < ke) ? (double)vrow[t] : 0.0;
       const int64_t tr = t0 + rr, c = c0 + rc + q;
-      xr[q] = (tr < kend && c < w) ? Rinv[tr * w + c] : 0.0;
+      xr[q] = (tr < ke && c < N) ? (double)Bm[tr * ldb + c] : 0.0;
     }
   };
   auto store = [&](int buf) {
@@ -321,13 +330,13 @@ __global__ void __launch_bounds__(256) k_rf_apply(const TI* __restrict__ V, int6
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const int64_t nsteps = (kend + kABK - 1) / kABK;
-  load(0);
+  const int64_t nsteps = ke > kb ? (ke - kb + kABK - 1) / kABK : 0;
+  load(kb);
   store(0);
   __syncthreads();
   for (int64_t st = 0; st < nsteps; ++st) {
     const int buf = st & 1;
-    if (st + 1 < nsteps) load((st + 1) * kABK);
+    if (st + 1 < nsteps) load(kb + (st + 1) * kABK);
 #pragma unroll
     for (int kk = 0; kk < kABK; kk += 4) {
       const double u0 = sV[buf][(wy * 32 + q16) * kAPV + kk + kq];
@@ -347,13 +356,13 @@ __global__ void __launch_bounds__(256) k_rf_apply(const TI* __restrict__ V, int6
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
       const int64_t c = c0 + wx * 32 + y * 16 + q16;
-      if (c >= w) continue;
-      const int64_t oc = keep ? (int64_t)keep[c] : c;
+      if (c >= N) continue;
+      const int64_t oc = map ? (int64_t)map[c] : c;
       if (oc < 0) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t i = i0 + wy * 32 + x * 16 + kq + 4 * r;
-        if (i < m) Q[i * ldq + oc] = acc[x][y][r];
+        if (i < M) o[i * ldo + oc] = acc[x][y][r];
       }
     }
 }
@@ -517,12 +526,38 @@ re_status launch_rf_chol(hipStream_t s, double* G, int64_t w, bool shift, int64_
 
 re_status launch_rf_apply(hipStream_t s, const void* V, bool v32, int64_t m, int64_t w, int64_t ldv, const double* Rinv,
                           const int32_t* keep, double* Q, int64_t ldq) {
-  const dim3 grid((unsigned)cdiv(w, 64), (unsigned)cdiv(m, 64));
+  const dim3 grid((unsigned)cdiv(w, 64), (unsigned)cdiv(m, 64), 1);
   if (v32)
-    hipLaunchKernelGGL(k_rf_apply<float>, grid, dim3(256), 0, s, (const float*)V, m, w, ldv, Rinv, keep, Q, ldq);
+    hipLaunchKernelGGL((k_nn64<float, double>), grid, dim3(256), 0, s, (const float*)V, m, ldv, Rinv, w, w, w, w, 1,
+                       keep, Q, ldq, (int64_t)0);
   else
-    hipLaunchKernelGGL(k_rf_apply<double>, grid, dim3(256), 0, s, (const double*)V, m, w, ldv, Rinv, keep, Q, ldq);
+    hipLaunchKernelGGL((k_nn64<double, double>), grid, dim3(256), 0, s, (const double*)V, m, ldv, Rinv, w, w, w, w, 1,
+                       keep, Q, ldq, (int64_t)0);
   RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
+
+void yb_split(int64_t l, int64_t k, int64_t m, int64_t* splits, int64_t* rows_per_split) {
+  rf_row_split(m, cdiv(l, 64) * cdiv(k, 64), splits, rows_per_split);
+}
+
+size_t yb_parts_bytes(int64_t l, int64_t k, int64_t m) {
+  int64_t sp = 0, rps = 0;
+  yb_split(l, k, m, &sp, &rps);
+  return sp > 1 ? (size_t)sp * l * k * 8 : 0;
+}
+
+re_status launch_yb_tiled(hipStream_t s, const float* B, int64_t m, int64_t k, int64_t ldb, const float* Y, int64_t ldy,
+                          int64_t l, double* C, double* parts) {
+  int64_t sp = 0, rps = 0;
+  yb_split(l, k, m, &sp, &rps);
+  if (sp > 1 && !parts) return RE_ERR_INVALID_ARG;
+  const dim3 grid((unsigned)cdiv(k, 64), (unsigned)cdiv(l, 64), (unsigned)sp);
+  double* out = sp > 1 ? parts : C;
+  hipLaunchKernelGGL((k_nn64<float, float>), grid, dim3(256), 0, s, Y, l, ldy, B, ldb, k, m, rps, 0,
+                     (const int32_t*)nullptr, out, k, sp > 1 ? l * k : (int64_t)0);
+  RE_TRY_HIP(hipGetLastError());
+  if (sp > 1) return launch_rf_sum_parts(s, parts, sp, l, k, false, C, k);
   return RE_OK;
 }
 
