@@ -990,9 +990,11 @@ re_status rf_project(re_handle h, const double* Q, int64_t ldq, int64_t w, const
   const int64_t mc = w >= 128 ? 4 : cdiv(w, 32);
   int64_t qs = 0, qrps = 0;
   rf_row_split(m, cdiv(w, 32 * mc) * rf_qta_col_tiles(n), &qs, &qrps);
-  RE_TRY(ensure_ws2(h, (size_t)qs * w * n * 8));
-  double* parts = (double*)h->ws2;
-  RE_TRY(launch_rf_qta(s, Q, ldq, w, A, m, n, lda, qs, qrps, parts));
+  Carve c;
+  const size_t oParts = c.take((size_t)qs * w * n * 8), oQ32 = c.take((size_t)m * w * 4);
+  RE_TRY(ensure_ws2(h, c.off));
+  double* parts = (double*)((char*)h->ws2 + oParts);
+  RE_TRY(launch_rf_qta(s, Q, ldq, w, A, m, n, lda, qs, qrps, (float*)((char*)h->ws2 + oQ32), parts));
   return launch_rf_sum_parts(s, parts, qs, w, n, false, B, ldb);
 }
 

@@ -48,12 +48,12 @@ RE_RF_HIDDEN re_status launch_rf_apply(hipStream_t s, const void* V, bool v32, i
 RE_RF_HIDDEN size_t yb_parts_bytes(int64_t l, int64_t k, int64_t m);
 RE_RF_HIDDEN re_status launch_yb_tiled(hipStream_t s, const float* B, int64_t m, int64_t k, int64_t ldb, const float* Y,
                                        int64_t ldy, int64_t l, double* C, double* parts);
-// parts[s] (w x n) = Q[rows of chunk s]^T A[rows of chunk s], FP32 matrix-core
-// products of FP32 A with Q rounded to FP32, FP64 accumulation across every
-// 256 rows.
+// parts[s] (w x n) = Q[rows of chunk s]^T A[rows of chunk s], FP32
+// matrix-core products of FP32 A with Q rounded to FP32 (q32: m x w floats of
+// scratch), FP64 accumulation across every 256 rows.
 RE_RF_HIDDEN int64_t rf_qta_col_tiles(int64_t n);
 RE_RF_HIDDEN re_status launch_rf_qta(hipStream_t s, const double* Q, int64_t ldq, int64_t w, const float* A,
                                      int64_t m, int64_t n, int64_t lda, int64_t splits, int64_t rows_per_split,
-                                     double* parts);
+                                     float* q32, double* parts);
 
 }  // namespace re

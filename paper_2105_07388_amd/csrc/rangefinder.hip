@@ -368,22 +368,31 @@ __global__ void __launch_bounds__(256) k_nn64(const TA* __restrict__ A, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// parts[s] (w x n) = Q[rows of chunk s]^T A[rows of chunk s].  A workgroup owns
-// 32 MC rows of the output (columns of Q) by 128 columns (of A): four
-// wavefronts, each 32 columns and MC v_mfma_f32_32x32x2f32 tiles (operand lane
-// l: row or column l % 32, K index l / 32; accumulator q of lane l: row
-// 8 (q/4) + 4 (l/32) + q%4, column l % 32).  Q is rounded to FP32 as it is
-// staged; the FP32 accumulators are added into FP64 ones every 256 rows.
-// Workgroups are spread so that the MC-row tiles sharing one column panel of
-// A sit on the same XCD (consecutive workgroup ids go round-robin over the 8
-// XCDs) and read that panel through the same L2.
+// parts[s] (w x n) = Q[rows of chunk s]^T A[rows of chunk s] for FP32 copies
+// of Q (m x w, leading dimension w) and A.  A workgroup owns 32 MC rows of the
+// output (columns of Q) by 128 columns (of A): four wavefronts, each 32
+// columns and MC v_mfma_f32_32x32x2f32 tiles (operand lane l: row or column
+// l % 32, K index l / 32; accumulator q of lane l: row 8 (q/4) + 4 (l/32) +
+// q%4, column l % 32).  K steps of 32 rows through double-buffered LDS; the
+// FP32 accumulators are added into FP64 ones every 256 rows.  Workgroups are
+// spread so that the MC-row tiles sharing one column panel of A sit on the
+// same XCD (consecutive workgroup ids go round-robin over the 8 XCDs) and
+// read that panel through the same L2.
 // ---------------------------------------------------------------------------
-constexpr int kQBK = 16, kQBJ = 128, kQFlush = 256 / kQBK;
+constexpr int kQBK = 32, kQBJ = 128, kQFlush = 256 / kQBK;
+
+__global__ void k_to_f32(const double* __restrict__ Q, int64_t ldq, int64_t m, int64_t w, float* __restrict__ out) {
+  const int64_t total = m * w;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / w, c = e - i * w;
+    out[e] = (float)Q[i * ldq + c];
+  }
+}
 
 template <int MC>
-__global__ void __launch_bounds__(256) k_rf_qta(const double* __restrict__ Q, int64_t ldq, int64_t w,
-                                               const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
-                                               int64_t rps, int64_t ctiles, int64_t ntiles, double* __restrict__ parts) {
+__global__ void __launch_bounds__(256) k_rf_qta(const float* __restrict__ Q, int64_t w, const float* __restrict__ A,
+                                               int64_t m, int64_t n, int64_t lda, int64_t rps, int64_t ctiles,
+                                               int64_t ntiles, double* __restrict__ parts) {
   constexpr int BC = 32 * MC, QPER = kQBK * BC / 256, APER = kQBK * kQBJ / 256;
   __shared__ float sQ[2][kQBK * BC], sA[2][kQBK * kQBJ];
   const int64_t per_xcd = gridDim.x / 8;
@@ -399,7 +408,7 @@ __global__ void __launch_bounds__(256) k_rf_qta(const double* __restrict__ Q, in
     for (int q = 0; q < QPER; ++q) {
       const int e = tid + 256 * q, r = e / BC, c = e % BC;
       const int64_t i = i0 + r;
-      xq[q] = (i < ie && c0 + c < w) ? (float)Q[i * ldq + c0 + c] : 0.0f;
+      xq[q] = (i < ie && c0 + c < w) ? Q[i * w + c0 + c] : 0.0f;
     }
 #pragma unroll
     for (int q = 0; q < APER; ++q) {
@@ -564,17 +573,20 @@ re_status launch_yb_tiled(hipStream_t s, const float* B, int64_t m, int64_t k, i
 int64_t rf_qta_col_tiles(int64_t n) { return cdiv(n, kQBJ); }
 
 re_status launch_rf_qta(hipStream_t s, const double* Q, int64_t ldq, int64_t w, const float* A, int64_t m, int64_t n,
-                        int64_t lda, int64_t splits, int64_t rows_per_split, double* parts) {
+                        int64_t lda, int64_t splits, int64_t rows_per_split, float* q32, double* parts) {
+  int64_t blocks = cdiv(m * w, 256);
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)blocks), dim3(256), 0, s, Q, ldq, m, w, q32);
   const int mc = w >= 128 ? 4 : (int)cdiv(w, 32);
   const int64_t ctiles = cdiv(w, 32 * mc), ntiles = ctiles * rf_qta_col_tiles(n);
   const int64_t grid = cdiv(ntiles, 8) * 8;
   const dim3 g((unsigned)grid, (unsigned)splits);
-#define RE_QTA_CASE(MC)                                                                                               \
-  if (mc == MC) {                                                                                                     \
-    hipLaunchKernelGGL(k_rf_qta<MC>, g, dim3(256), 0, s, Q, ldq, w, A, m, n, lda, rows_per_split, ctiles, ntiles,     \
-                       parts);                                                                                        \
-    RE_TRY_HIP(hipGetLastError());                                                                                    \
-    return RE_OK;                                                                                                     \
+#define RE_QTA_CASE(MC)                                                                                              \
+  if (mc == MC) {                                                                                                    \
+    hipLaunchKernelGGL(k_rf_qta<MC>, g, dim3(256), 0, s, (const float*)q32, w, A, m, n, lda, rows_per_split, ctiles, \
+                       ntiles, parts);                                                                               \
+    RE_TRY_HIP(hipGetLastError());                                                                                   \
+    return RE_OK;                                                                                                    \
   }
   RE_QTA_CASE(1)
   RE_QTA_CASE(2)
