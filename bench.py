@@ -293,7 +293,7 @@ def bench_learned(args, w, dev):
 def cpu_baseline_rf(A_dev, w, rows: int, r: int):
     """Oracle of Algorithm 3 timed on a bounded sample: A X and Q^T A on the
     first `rows` rows (scaled to m), Y B on `rows` columns of Y (scaled to m),
-    the Jacobi SVD of a half-size sketch (scaled by 8, its cubic cost), the
+    the Jacobi SVD of a quarter-size sketch (scaled by 64, its cubic cost), the
     Householder QR of the full m x (r + p) basis."""
     import numpy as np
 
@@ -314,10 +314,10 @@ def cpu_baseline_rf(A_dev, w, rows: int, r: int):
     t0 = time.perf_counter()
     oracle.apply_y(B, oracle.GAUSSIAN, l, seed=0)
     t_y = (time.perf_counter() - t0) * (m / rows)
-    G = np.random.default_rng(0).standard_normal((l // 2, k // 2))
+    G = np.random.default_rng(0).standard_normal((l // 4, k // 4))
     t0 = time.perf_counter()
     oracle.jacobi_sv(G)
-    t_svd = (time.perf_counter() - t0) * 8
+    t_svd = (time.perf_counter() - t0) * 64
     wd = r + p
     W = np.random.default_rng(1).standard_normal((m, wd))
     t0 = time.perf_counter()
@@ -330,7 +330,7 @@ def cpu_baseline_rf(A_dev, w, rows: int, r: int):
     return {"value": 1.0 / total, "unit": "QB factorisations/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"A X timed on the first {rows // 2} and {rows} rows, extrapolated linearly to {m}; Y B and "
                       f"Q^T A on the first {rows} rows scaled by {m / rows:g}; Jacobi SVD of a "
-                      f"{l // 2}x{k // 2} sketch scaled by 8, Householder QR of {m}x{wd}; seconds: ax {t_x:.1f}, "
+                      f"{l // 4}x{k // 4} sketch scaled by 64, Householder QR of {m}x{wd}; seconds: ax {t_x:.1f}, "
                       f"yb {t_y:.1f}, svd {t_svd:.1f}, qr {t_qr:.1f}, qta {t_qb:.1f}"}
 
 
@@ -411,7 +411,7 @@ def bench_rf(args, w, dev):
     }
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline_rf(A, w, min(args.cpu_rows, 512), r)
+        out["cpu_baseline"] = cpu_baseline_rf(A, w, min(args.cpu_rows, 64), r)
     print(json.dumps(out), flush=True)
 
 
