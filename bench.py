@@ -225,7 +225,8 @@ def bench_batched(args, w, dev):
 def bench_learned(args, w, dev):
     """One step = the adaptive estimate of every matrix of a fixed set of
     recipes (unseen in training), with the trained network; doubling timed on
-    the same matrices and seeds for comparison."""
+    the same matrices and seeds for comparison, each matrix under both
+    policies back to back."""
     import numpy as np
     import torch
 
@@ -241,29 +242,41 @@ def bench_learned(args, w, dev):
           f"warmup {args.warmup}", file=sys.stderr, flush=True)
     h = re_.Handle(dev)
 
-    def one_pass(mlp, seed0):
-        out = []
-        for i, (A, p) in enumerate(zip(mats, recipes)):
-            r, _, info = re_.rank_adaptive(A, p["eps"], k_max=min(A.shape[1], 4096), mlp=mlp, delta=delta,
-                                           seed=seed0 + i, handle=h)
-            out.append((r, info["rounds"], info["k"]))
-        return out
+    pol = {"learned": policy, "doubling": None}
 
+    def call(name, A, p, seed):
+        r, _, info = re_.rank_adaptive(A, p["eps"], k_max=min(A.shape[1], 4096), mlp=pol[name], delta=delta,
+                                       seed=seed, handle=h)
+        return r, info["rounds"], info["k"]
+
+    for i in range(args.warmup):
+        for j, (A, p) in enumerate(zip(mats, recipes)):
+            for name in pol:
+                call(name, A, p, 500 * (i + 1) + j)
+    torch.cuda.synchronize()
+    # paired timing: every matrix under both policies back to back (the order
+    # alternating), each call synchronised on both sides
+    tsum = {name: 0.0 for name in pol}
+    runs = {name: [] for name in pol}
+    for i in range(args.steps):
+        for j, (A, p) in enumerate(zip(mats, recipes)):
+            order = ("learned", "doubling") if (i + j) % 2 == 0 else ("doubling", "learned")
+            for name in order:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = call(name, A, p, 1000 * (i + 1) + j)
+                torch.cuda.synchronize()
+                tsum[name] += time.perf_counter() - t0
+                if i == args.steps - 1:
+                    runs[name].append(out)
     res = {}
-    for name, mlp in (("learned", policy), ("doubling", None)):
-        for i in range(args.warmup):
-            one_pass(mlp, 500 + i)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            runs = one_pass(mlp, 1000 * (i + 1))
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
+    for name in pol:
+        el = tsum[name]
         res[name] = {"estimates_per_s": len(mats) * args.steps / el, "ms_per_pass": 1e3 * el / args.steps,
-                     "mean_rounds": float(np.mean([r[1] for r in runs])),
-                     "mean_k_final": float(np.mean([r[2] for r in runs])),
-                     "rank_agreement": float(np.mean([r[0] == t for r, t in zip(runs, truth)])),
-                     "ranks": [r[0] for r in runs]}
+                     "mean_rounds": float(np.mean([r[1] for r in runs[name]])),
+                     "mean_k_final": float(np.mean([r[2] for r in runs[name]])),
+                     "rank_agreement": float(np.mean([r[0] == t for r, t in zip(runs[name], truth)])),
+                     "ranks": [r[0] for r in runs[name]]}
     same = float(np.mean([a == b for a, b in zip(res["learned"]["ranks"], res["doubling"]["ranks"])]))
     for v in res.values():
         v.pop("ranks")
