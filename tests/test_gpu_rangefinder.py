@@ -126,6 +126,13 @@ def test_wide_basis_global_factorisation(orc):
     assert got["k"] == 384 and got["w"] > 136
 
 
+def test_wide_matrix_and_capped_width(orc):
+    # m < n: k is capped by m; k0 above k_max starts at k_max
+    A = inputs.planted(700, 1900, inputs.spectrum_step(700, 30, 1.0, 1e-7), 17, torch.float32)
+    got, _, _ = _compare(orc, A, 1e-2, 8, 500, 9, k_max=64, exact=True)
+    assert got["k"] == 64 and got["r"] == 30 and got["w"] == 38
+
+
 def _geometric(m, w, cond, seed, dtype=torch.float64):
     return inputs.planted(m, w, np.geomspace(1.0, 1.0 / cond, w), seed, dtype)
 
