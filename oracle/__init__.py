@@ -7,3 +7,4 @@ from .pyoracle import *  # noqa: F401,F403
 from . import learned  # noqa: F401,E402
 from . import gap  # noqa: F401,E402
 from . import rangefinder  # noqa: F401,E402
+from . import qrdiag  # noqa: F401,E402
