@@ -142,6 +142,22 @@ re_status re_rank_estimate(re_handle h, const void* A_dev, int32_t dt, int64_t m
                            const re_sketch* sk, uint64_t seed, int32_t* r_out, double* sigma_out, int32_t* r1_out,
                            uint32_t* flags_out);
 
+/*
+ * Algorithm 1 with the alternative step 7 of Sec. 5: the estimates are the
+ * magnitudes of the diagonal of R in a QR factorisation Y A X = Q R (an
+ * unpivoted QR of a sketch whose right singular vectors are randomised is rank
+ * revealing with high probability), here from the library's shifted
+ * CholeskyQR3 in FP64 (R = R3 R2 R1, |R_jj| = |R3_jj R2_jj R1_jj|), sorted in
+ * descending order and scaled by 1/sqrt(k l); the count is step 8's.  A column
+ * of Y A X dependent on the earlier ones at FP64 precision gives 0.
+ * Arguments, outputs and errors as re_rank_estimate (sigma_out: the k sorted
+ * diagonal magnitudes); RE_ERR_UNSUPPORTED unless sk->prec = RE_PREC_NATIVE.
+ * Stage times: the QR takes the place of the SVD (RE_STAGE_SVD).
+ */
+re_status re_rank_estimate_qr(re_handle h, const void* A_dev, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                              double eps, const re_sketch* sk, uint64_t seed, int32_t* r_out, double* sigma_out,
+                              int32_t* r1_out, uint32_t* flags_out);
+
 /* One block of a batched call: caller-owned device matrix, m x n row-major
  * with leading dimension n <= lda < 2^23 (FP32, 4-byte aligned). */
 typedef struct {

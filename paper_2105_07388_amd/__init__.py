@@ -32,6 +32,7 @@ from ._binding import (  # noqa: F401
     rank_count,
     rank_estimate,
     rank_estimate_batched,
+    rank_estimate_qr,
     singular_values,
     sketch_x,
     sketch_y,

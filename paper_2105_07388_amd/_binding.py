@@ -80,6 +80,8 @@ def lib():
             "re_last_stage_ms": ([vp, vp], i32),
             "re_rank_estimate": ([vp, vp, i32, i64, i64, i64, dbl, C.POINTER(ReSketch), u64, C.POINTER(i32), vp,
                                   C.POINTER(i32), C.POINTER(C.c_uint32)], i32),
+            "re_rank_estimate_qr": ([vp, vp, i32, i64, i64, i64, dbl, C.POINTER(ReSketch), u64, C.POINTER(i32), vp,
+                                     C.POINTER(i32), C.POINTER(C.c_uint32)], i32),
             "re_rank_estimate_batched": ([vp, vp, i32, i32, dbl, C.POINTER(ReSketch), u64, vp, vp, vp], i32),
             "re_rank_adaptive": ([vp, vp, i32, i64, i64, i64, dbl, C.POINTER(ReAdaptive), u64, C.POINTER(i32), vp,
                                   C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
@@ -222,6 +224,25 @@ def rank_estimate(A: torch.Tensor, eps: float, *, k: int, l: int = 0, x: str = "
                                 C.byref(fl))
     _check(st, "re_rank_estimate")
     return r.value, sigma, {"r1": r1.value, "flags": fl.value, "k": int(k), "l": int(l) if l else 2 * int(k)}
+
+
+def rank_estimate_qr(A: torch.Tensor, eps: float, *, k: int, l: int = 0, x: str = "gaussian", y: str = "gaussian",
+                     seed: int = 0, handle: Handle | None = None):
+    """Algorithm 1 with step 7 by the diagonal of R in Y A X = Q R (Sec. 5).
+    Returns (r, d[k] (sorted |R_jj| / sqrt(k l), numpy float64), info dict)."""
+    _check_matrix(A)
+    h = handle or default_handle(A.device)
+    m, n = A.shape
+    sk = make_sketch(k, l, x, y, "native")
+    r = C.c_int32(0)
+    r1 = C.c_int32(0)
+    fl = C.c_uint32(0)
+    d = np.zeros(int(k), dtype=np.float64)
+    st = lib().re_rank_estimate_qr(h.bind(), _ptr(A), _dtype_code(A), m, n, A.stride(0), float(eps), C.byref(sk),
+                                   int(seed) % 2**64, C.byref(r), d.ctypes.data_as(C.c_void_p), C.byref(r1),
+                                   C.byref(fl))
+    _check(st, "re_rank_estimate_qr")
+    return r.value, d, {"r1": r1.value, "flags": fl.value, "k": int(k), "l": int(l) if l else 2 * int(k)}
 
 
 def rank_adaptive(A: torch.Tensor, eps: float, *, k0: int = 32, k_max: int = 0, l_ratio: float = 1.5,

@@ -152,7 +152,7 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
 // Workspace plan of one estimate.
 struct Plan {
   size_t xbits, ybits, xsel, ysel, selscr, X, Y, B, C, svd, sigma, info, out3, stats, gdesc, ydesc, queue, yparts,
-      total;
+      rdiag, total;
 };
 
 // Sketches the batched form accepts (one workgroup's LDS holds the small SVD).
@@ -193,6 +193,7 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   p.ydesc = c.take(sizeof(YDesc));
   p.queue = c.take(16);
   p.yparts = c.take(rs.yk == RE_GAUSSIAN && dt == RE_F32 ? yb_scratch(rs.l, rs.k, m) : 0);
+  p.rdiag = c.take((size_t)rs.k * 3 * 8);  // diagonals of the QR passes (step 7 by the QR diagonal)
   p.total = c.off;
   return p;
 }
@@ -941,7 +942,7 @@ namespace {
 // ldv) by shifted CholeskyQR3: the kept columns of Q go to Q (ldq), their
 // number to *w_eff.  Synchronises the stream once, before the last product.
 re_status rf_qr(re_handle h, const void* V, bool v32, int64_t m, int64_t w, int64_t ldv, double* Q, int64_t ldq,
-                int32_t* w_eff) {
+                int32_t* w_eff, double* rdiag3 = nullptr) {
   hipStream_t s = h->stream;
   int64_t gs = 0, grps = 0;
   rf_row_split(m, cdiv(w, 64) * (cdiv(w, 64) + 1) / 2, &gs, &grps);
@@ -967,7 +968,7 @@ re_status rf_qr(re_handle h, const void* V, bool v32, int64_t m, int64_t w, int6
     const bool f32 = pass == 0 && v32;
     RE_TRY(launch_rf_gram(s, Vin[pass], f32, m, w, ldin[pass], gs, grps, parts));
     RE_TRY(launch_rf_sum_parts(s, parts, gs, w, w, true, G, w));
-    RE_TRY(launch_rf_chol(s, G, w, pass == 0, m, Ri, keep, cnt));
+    RE_TRY(launch_rf_chol(s, G, w, pass == 0, m, Ri, keep, cnt, rdiag3 ? rdiag3 + pass * w : nullptr));
     if (pass < 2) {
       RE_TRY(launch_rf_apply(s, Vin[pass], f32, m, w, ldin[pass], Ri, nullptr, Vout[pass], w));
       continue;
@@ -978,7 +979,7 @@ re_status rf_qr(re_handle h, const void* V, bool v32, int64_t m, int64_t w, int6
     const int32_t* c8 = (const int32_t*)(host + 16);
     if (c8[1] != 0) return (re_status)c8[1];
     *w_eff = c8[0];
-    RE_TRY(launch_rf_apply(s, Vin[pass], false, m, w, ldin[pass], Ri, keep, Q, ldq));
+    if (Q) RE_TRY(launch_rf_apply(s, Vin[pass], false, m, w, ldin[pass], Ri, keep, Q, ldq));
   }
   return RE_OK;
 }
@@ -1000,6 +1001,56 @@ re_status rf_project(re_handle h, const double* Q, int64_t ldq, int64_t w, const
 
 }  // namespace
 }  // namespace re
+
+RE_API re_status re_rank_estimate_qr(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                                     double eps, const re_sketch* sk, uint64_t seed, int32_t* r_out, double* sigma_out,
+                                     int32_t* r1_out, uint32_t* flags_out) {
+  if (!h || !r_out || !sigma_out) return RE_ERR_INVALID_ARG;
+  if (!(eps > 0.0 && eps < 1.0)) return RE_ERR_INVALID_ARG;
+  Resolved rs;
+  RE_TRY(validate(A, dt, m, n, lda, sk, &rs));
+  if (sk->prec != RE_PREC_NATIVE) return RE_ERR_UNSUPPORTED;
+  if (rs.k > 46340) return RE_ERR_INVALID_ARG;
+  rs.fmt_x = x_fmt(dt);
+  const Plan p = plan(dt, m, n, rs);
+  RE_TRY(ensure_ws(h, p.total));
+  RE_TRY(ensure_host(h, (size_t)rs.k * 8 + 64));
+  hipStream_t s = h->stream;
+  void* B = at(h, p.B);
+  double* C = (double*)at(h, p.C);
+  double* sigma = (double*)at(h, p.sigma);
+  int32_t* out3 = (int32_t*)at(h, p.out3);
+  double* rdiag3 = (double*)at(h, p.rdiag);
+  mark(h, RE_STAGE_X_DRAW);
+  RE_TRY(run_x(h, p, A, dt, m, n, lda, rs, seed, B));
+  mark(h, RE_STAGE_Y_DRAW);
+  RE_TRY(run_y(h, p, B, dt, m, rs, seed, C));
+  mark(h, RE_STAGE_SVD);
+  int32_t w_eff = 0;
+  RE_TRY(rf_qr(h, C, false, rs.l, rs.k, rs.k, nullptr, 0, &w_eff, rdiag3));
+  RE_TRY(launch_qr_sigma(s, rdiag3, rs.k, 1.0 / sqrt((double)rs.k * (double)rs.l), sigma));
+  mark(h, RE_STAGE_RANK);
+  const int32_t r1 = r1_from_k((int32_t)rs.k);
+  RE_TRY(launch_rank_count(s, sigma, rs.k, r1, eps, nullptr, out3));
+  char* host = (char*)h->host;
+  RE_TRY_HIP(hipMemcpyAsync(host, out3, 16, hipMemcpyDeviceToHost, s));
+  RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)rs.k * 8, hipMemcpyDeviceToHost, s));
+  mark(h, RE_NUM_STAGES);
+  RE_TRY_HIP(hipStreamSynchronize(s));
+  if (h->prof) {
+    for (int i = 0; i < RE_NUM_STAGES; ++i) {
+      float ms = 0.f;
+      h->stage_ms[i] = hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess ? (double)ms : -1.0;
+    }
+  }
+  const int32_t* o3 = (const int32_t*)host;
+  if (o3[2] != 0) return (re_status)o3[2];
+  *r_out = o3[0];
+  memcpy(sigma_out, host + 64, (size_t)rs.k * 8);
+  if (r1_out) *r1_out = r1;
+  if (flags_out) *flags_out = (uint32_t)o3[1];
+  return RE_OK;
+}
 
 RE_API re_status re_rangefinder(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda, double eps,
                                 int32_t p, const re_adaptive* ad, double norm_a, uint64_t seed, double* Q, int64_t ldq,

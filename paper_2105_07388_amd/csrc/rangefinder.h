@@ -33,10 +33,14 @@ RE_RF_HIDDEN re_status launch_rf_sum_parts(hipStream_t s, const double* parts, i
                                            int64_t cols, bool upper, double* out, int64_t ldo);
 // Cholesky factor of G (+ shift for the first pass) and the inverse of the
 // factor (w x w, upper, row-major, zero rows / columns for dropped columns);
-// keep[c] = new index of column c or -1; cnt2 = {kept columns, status}.
+// keep[c] = new index of column c or -1; cnt2 = {kept columns, status};
+// rdiag (w doubles, or NULL) receives the factor's diagonal.
 RE_RF_HIDDEN size_t rf_chol_lds_bytes(int64_t w);
 RE_RF_HIDDEN re_status launch_rf_chol(hipStream_t s, double* G, int64_t w, bool shift, int64_t m, double* Rinv,
-                                      int32_t* keep, int32_t* cnt2);
+                                      int32_t* keep, int32_t* cnt2, double* rdiag);
+// sigma (k, descending) = |R3_jj R2_jj R1_jj| scale from the three passes'
+// diagonals (rdiag3: 3 x k doubles, pass-major).
+RE_RF_HIDDEN re_status launch_qr_sigma(hipStream_t s, const double* rdiag3, int64_t k, double scale, double* sigma);
 // Q (ldq) = V Rinv for the w columns; column c goes to keep[c] (skipped when
 // negative) if keep is given, else to c.  V as in launch_rf_gram.
 RE_RF_HIDDEN re_status launch_rf_apply(hipStream_t s, const void* V, bool v32, int64_t m, int64_t w, int64_t ldv,

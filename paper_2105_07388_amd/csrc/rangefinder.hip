@@ -214,7 +214,8 @@ __device__ double block_max(double v, double* red) {
 
 __global__ void __launch_bounds__(kCholThreads) k_rf_chol(double* __restrict__ G, int w, int shift, int64_t m,
                                                          int use_lds, double* __restrict__ Rinv,
-                                                         int32_t* __restrict__ keep, int32_t* __restrict__ cnt2) {
+                                                         int32_t* __restrict__ keep, int32_t* __restrict__ cnt2,
+                                                         double* __restrict__ rdiag) {
   extern __shared__ double lds[];
   __shared__ double red[kCholThreads];
   __shared__ int s_bad;
@@ -257,6 +258,8 @@ __global__ void __launch_bounds__(kCholThreads) k_rf_chol(double* __restrict__ G
     }
     __syncthreads();
   }
+  if (rdiag)
+    for (int j = tid; j < w; j += nth) rdiag[j] = R[(int64_t)j * w + j];
   if (tid == 0) {
     int cnt = 0;
     for (int j = 0; j < w; ++j) keep[j] = R[(int64_t)j * w + j] > 0.0 ? cnt++ : -1;
@@ -293,7 +296,7 @@ constexpr int64_t kCholBlkMaxW = 1100;  // kCB rows of w doubles within 138 KiB 
 
 __global__ void __launch_bounds__(kCholBlkThreads) k_rf_chol_blk(double* __restrict__ R, int w, int shift, int64_t m,
                                                              double* __restrict__ Rinv, int32_t* __restrict__ keep,
-                                                             int32_t* __restrict__ cnt2) {
+                                                             int32_t* __restrict__ cnt2, double* __restrict__ rdiag) {
   extern __shared__ double P[];  // kCB x w: the current block row (row stride w)
   __shared__ double D[kCB * kCB], Di[kCB * kCB];
   __shared__ double red[kCholThreads];
@@ -375,6 +378,8 @@ __global__ void __launch_bounds__(kCholBlkThreads) k_rf_chol_blk(double* __restr
     }
     __syncthreads();
   }
+  if (rdiag)
+    for (int j = tid; j < w; j += nth) rdiag[j] = R[(int64_t)j * w + j];
   if (tid == 0) {
     int cnt = 0;
     for (int j = 0; j < w; ++j) keep[j] = R[(int64_t)j * w + j] > 0.0 ? cnt++ : -1;
@@ -625,6 +630,26 @@ __global__ void __launch_bounds__(256) k_rf_qta(const float* __restrict__ Q, int
     }
 }
 
+// ---------------------------------------------------------------------------
+// Estimates from the diagonal of R (the alternative step 7 of Sec. 5): the
+// sketch's R = R3 R2 R1 is the product of the three passes' triangular factors,
+// so |R_jj| = |R3_jj R2_jj R1_jj|; scaled by 1/sqrt(k l) and placed in
+// descending order by counting, for each value, the values above it (ties by
+// index), which gives the same order on every run.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_qr_sigma(const double* __restrict__ rd, int64_t k, double scale,
+                                                 double* __restrict__ sigma) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  const double vj = fabs(rd[j] * rd[k + j] * rd[2 * k + j]) * scale;
+  int64_t rank = 0;
+  for (int64_t i = 0; i < k; ++i) {
+    const double vi = fabs(rd[i] * rd[k + i] * rd[2 * k + i]) * scale;
+    rank += (vi > vj) || (vi == vj && i < j);
+  }
+  sigma[rank] = vj;
+}
+
 }  // namespace
 
 re_status launch_rf_width(hipStream_t s, const double* sigma, int64_t k, int32_t r1, int64_t n, double eps, int32_t p,
@@ -673,14 +698,14 @@ re_status launch_rf_sum_parts(hipStream_t s, const double* parts, int64_t splits
 size_t rf_chol_lds_bytes(int64_t w) { return w <= kCholLdsMaxW ? (size_t)(w * w * 8) : 0; }
 
 re_status launch_rf_chol(hipStream_t s, double* G, int64_t w, bool shift, int64_t m, double* Rinv, int32_t* keep,
-                         int32_t* cnt2) {
+                         int32_t* cnt2, double* rdiag) {
   if (w < 1 || w > 46340) return RE_ERR_INVALID_ARG;  // w^2 within int range of the trailing loop
   if (w > kCholLdsMaxW && w <= kCholBlkMaxW) {
     const size_t pb = (size_t)kCB * w * 8;
     if (pb > 65536)
       RE_TRY_HIP(hipFuncSetAttribute((const void*)k_rf_chol_blk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pb));
     hipLaunchKernelGGL(k_rf_chol_blk, dim3(1), dim3(kCholBlkThreads), pb, s, G, (int)w, shift ? 1 : 0, m, Rinv, keep,
-                       cnt2);
+                       cnt2, rdiag);
     RE_TRY_HIP(hipGetLastError());
     return RE_OK;
   }
@@ -688,7 +713,7 @@ re_status launch_rf_chol(hipStream_t s, double* G, int64_t w, bool shift, int64_
   if (lds > 65536)
     RE_TRY_HIP(hipFuncSetAttribute((const void*)k_rf_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_rf_chol, dim3(1), dim3(kCholThreads), lds, s, G, (int)w, shift ? 1 : 0, m, lds ? 1 : 0, Rinv,
-                     keep, cnt2);
+                     keep, cnt2, rdiag);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
 }
@@ -731,6 +756,12 @@ re_status launch_yb_tiled(hipStream_t s, const float* B, int64_t m, int64_t k, i
 }
 
 int64_t rf_qta_col_tiles(int64_t n) { return cdiv(n, kQBJ); }
+
+re_status launch_qr_sigma(hipStream_t s, const double* rdiag3, int64_t k, double scale, double* sigma) {
+  hipLaunchKernelGGL(k_qr_sigma, dim3((unsigned)cdiv(k, 256)), dim3(256), 0, s, rdiag3, k, scale, sigma);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
 
 re_status launch_rf_qta(hipStream_t s, const double* Q, int64_t ldq, int64_t w, const float* A, int64_t m, int64_t n,
                         int64_t lda, int64_t splits, int64_t rows_per_split, float* q32, double* parts) {
