@@ -282,8 +282,9 @@ __global__ void __launch_bounds__(kCholThreads) k_rf_chol(double* __restrict__ G
   }
 }
 
-// Blocked form of the same factorisation and inverse for 136 < w <= 1100, in
-// blocks of kCB = 16 rows: the diagonal block is factored in LDS, the block
+// Blocked form of the same factorisation and inverse for 136 < w <= 2200, in
+// blocks of CB = 16 rows (8 rows above w = 1100, where 16 rows of w doubles
+// would overflow LDS): the diagonal block is factored in LDS, the block
 // row of R solved column by column (one thread per column) and kept in LDS,
 // and the trailing matrix in global memory takes one rank-16 update per
 // element (16 products per read-modify-write instead of one).  The inverse
@@ -291,14 +292,16 @@ __global__ void __launch_bounds__(kCholThreads) k_rf_chol(double* __restrict__ G
 // back substitution, then for every column c to the right
 // Rinv[I][c] = -D^-1 sum_t R[I][t] Rinv[t][c] with 16 accumulators per thread.
 // The pivot rule (shift, dependence threshold) is the unblocked one.
-constexpr int kCB = 16, kCholBlkThreads = 1024;
-constexpr int64_t kCholBlkMaxW = 1100;  // kCB rows of w doubles within 138 KiB of LDS
+constexpr int kCholBlkThreads = 1024;
+constexpr int64_t kCholBlkMaxW = 1100;   // 16-row blocks: 16 rows of w doubles within 138 KiB of LDS
+constexpr int64_t kCholBlk8MaxW = 2200;  // 8-row blocks beyond that
 
+template <int CB>
 __global__ void __launch_bounds__(kCholBlkThreads) k_rf_chol_blk(double* __restrict__ R, int w, int shift, int64_t m,
                                                              double* __restrict__ Rinv, int32_t* __restrict__ keep,
                                                              int32_t* __restrict__ cnt2, double* __restrict__ rdiag) {
-  extern __shared__ double P[];  // kCB x w: the current block row (row stride w)
-  __shared__ double D[kCB * kCB], Di[kCB * kCB];
+  extern __shared__ double P[];  // CB x w: the current block row (row stride w)
+  __shared__ double D[CB * CB], Di[CB * CB];
   __shared__ double red[kCholThreads];
   __shared__ int s_bad;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -319,51 +322,50 @@ __global__ void __launch_bounds__(kCholBlkThreads) k_rf_chol_blk(double* __restr
   const double thr = 16.0 * kU64 * (mx + s);
   for (int j = tid; j < w; j += nth) R[(int64_t)j * w + j] += s;
   __syncthreads();
-  for (int J = 0; J < w; J += kCB) {
-    const int jb = w - J < kCB ? w - J : kCB;
+  for (int J = 0; J < w; J += CB) {
+    const int jb = w - J < CB ? w - J : CB;
     // diagonal block (upper triangle) into LDS, factored in place
     if (tid < jb * jb) {
       const int i = tid / jb, j = tid % jb;
-      D[i * kCB + j] = i <= j ? R[(int64_t)(J + i) * w + J + j] : 0.0;
+      D[i * CB + j] = i <= j ? R[(int64_t)(J + i) * w + J + j] : 0.0;
     }
     __syncthreads();
     for (int j = 0; j < jb; ++j) {
-      const double d = D[j * kCB + j];
+      const double d = D[j * CB + j];
       const bool kj = isfinite(d) && d > thr;
       const double rjj = kj ? sqrt(d) : 0.0, inv = kj ? 1.0 / rjj : 0.0;
       __syncthreads();
       if (tid < jb) {
-        if (tid > j) D[j * kCB + tid] *= inv;
+        if (tid > j) D[j * CB + tid] *= inv;
         if (tid == j) {
-          D[j * kCB + j] = rjj;
+          D[j * CB + j] = rjj;
           if (!isfinite(d)) s_bad = 1;
         }
       }
       __syncthreads();
       if (tid < jb * jb) {
         const int a = tid / jb, b = tid % jb;
-        if (a > j && b >= a) D[a * kCB + b] -= D[j * kCB + a] * D[j * kCB + b];
+        if (a > j && b >= a) D[a * CB + b] -= D[j * CB + a] * D[j * CB + b];
       }
       __syncthreads();
     }
     // block row of R: forward substitution with D^T, one thread per column,
     // kept in LDS (rows past jb zero, so the update below needs no guard)
     for (int c = J + jb + tid; c < w; c += nth) {
-      for (int i = 0; i < kCB; ++i) {
-        double x = 0.0;
-        if (i < jb) {
-          double v = R[(int64_t)(J + i) * w + c];
-          for (int t = 0; t < i; ++t) v -= D[t * kCB + i] * P[t * w + c];
-          const double dii = D[i * kCB + i];
-          x = dii > 0.0 ? v / dii : 0.0;
-          R[(int64_t)(J + i) * w + c] = x;
-        }
+#pragma unroll
+      for (int i = 0; i < CB; ++i) P[i * w + c] = i < jb ? R[(int64_t)(J + i) * w + c] : 0.0;  // loads in flight together
+      for (int i = 0; i < jb; ++i) {
+        double v = P[i * w + c];
+        for (int t = 0; t < i; ++t) v -= D[t * CB + i] * P[t * w + c];
+        const double dii = D[i * CB + i];
+        const double x = dii > 0.0 ? v / dii : 0.0;
+        R[(int64_t)(J + i) * w + c] = x;
         P[i * w + c] = x;
       }
     }
     if (tid < jb * jb) {
       const int i = tid / jb, j = tid % jb;
-      if (i <= j) R[(int64_t)(J + i) * w + J + j] = D[i * kCB + j];
+      if (i <= j) R[(int64_t)(J + i) * w + J + j] = D[i * CB + j];
     }
     __syncthreads();
     // trailing matrix: rank-jb update of the upper triangle
@@ -373,7 +375,7 @@ __global__ void __launch_bounds__(kCholBlkThreads) k_rf_chol_blk(double* __restr
       if (a > b) continue;
       double acc = 0.0;
 #pragma unroll
-      for (int i = 0; i < kCB; ++i) acc += P[i * w + a] * P[i * w + b];
+      for (int i = 0; i < CB; ++i) acc += P[i * w + a] * P[i * w + b];
       R[(int64_t)a * w + b] -= acc;
     }
     __syncthreads();
@@ -386,44 +388,55 @@ __global__ void __launch_bounds__(kCholBlkThreads) k_rf_chol_blk(double* __restr
     cnt2[0] = cnt;
     cnt2[1] = s_bad ? (int32_t)RE_ERR_NONFINITE : 0;
   }
-  for (int I = ((w - 1) / kCB) * kCB; I >= 0; I -= kCB) {
-    const int ib = w - I < kCB ? w - I : kCB, W2 = w - I;
+  for (int I = ((w - 1) / CB) * CB; I >= 0; I -= CB) {
+    const int ib = w - I < CB ? w - I : CB, W2 = w - I;
     // block row of R (rows past ib zero) and the diagonal block's inverse Di
-    for (int e = tid; e < kCB * W2; e += nth) {
+    for (int e = tid; e < CB * W2; e += nth) {
       const int i = e / W2, c = I + e % W2;
       P[i * w + c] = i < ib ? R[(int64_t)(I + i) * w + c] : 0.0;
     }
     __syncthreads();
-    if (tid < kCB) {  // column tid of Di by back substitution
+    if (tid < CB) {  // column tid of Di by back substitution
       const int cc = tid;
       const bool ckept = cc < ib && P[cc * w + I + cc] > 0.0;
-      for (int i = kCB - 1; i >= 0; --i) {
+      for (int i = CB - 1; i >= 0; --i) {
         double v = 0.0;
         if (i <= cc && ckept) {
           const double rii = P[i * w + I + i];
           if (rii > 0.0) {
             v = i == cc ? 1.0 : 0.0;
-            for (int t = i + 1; t <= cc; ++t) v -= P[i * w + I + t] * Di[t * kCB + cc];
+            for (int t = i + 1; t <= cc; ++t) v -= P[i * w + I + t] * Di[t * CB + cc];
             v /= rii;
           }
         }
-        Di[i * kCB + cc] = v;
+        Di[i * CB + cc] = v;
         if (i < ib && cc < ib) Rinv[(int64_t)(I + i) * w + I + cc] = v;
       }
     }
     __syncthreads();
     for (int c = I + ib + tid; c < w; c += nth) {
-      double y[kCB];
+      double y[CB];
 #pragma unroll
-      for (int i = 0; i < kCB; ++i) y[i] = 0.0;
-      for (int t = I + ib; t <= c; ++t) {
+      for (int i = 0; i < CB; ++i) y[i] = 0.0;
+      constexpr int U = CB == 16 ? 1 : 4;  // loads in flight together; the summation order is unchanged
+      int t = I + ib;
+      for (; t + U - 1 <= c; t += U) {
+        double rv[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) rv[q] = Rinv[(int64_t)(t + q) * w + c];
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+          for (int i = 0; i < CB; ++i) y[i] += P[i * w + t + q] * rv[q];
+      }
+      for (; t <= c; ++t) {
         const double rv = Rinv[(int64_t)t * w + c];
 #pragma unroll
-        for (int i = 0; i < kCB; ++i) y[i] += P[i * w + t] * rv;
+        for (int i = 0; i < CB; ++i) y[i] += P[i * w + t] * rv;
       }
       for (int i = 0; i < ib; ++i) {
         double o = 0.0;
-        for (int j = i; j < kCB; ++j) o -= Di[i * kCB + j] * y[j];
+        for (int j = i; j < CB; ++j) o -= Di[i * CB + j] * y[j];
         Rinv[(int64_t)(I + i) * w + c] = o;
       }
     }
@@ -700,12 +713,17 @@ size_t rf_chol_lds_bytes(int64_t w) { return w <= kCholLdsMaxW ? (size_t)(w * w 
 re_status launch_rf_chol(hipStream_t s, double* G, int64_t w, bool shift, int64_t m, double* Rinv, int32_t* keep,
                          int32_t* cnt2, double* rdiag) {
   if (w < 1 || w > 46340) return RE_ERR_INVALID_ARG;  // w^2 within int range of the trailing loop
-  if (w > kCholLdsMaxW && w <= kCholBlkMaxW) {
-    const size_t pb = (size_t)kCB * w * 8;
-    if (pb > 65536)
-      RE_TRY_HIP(hipFuncSetAttribute((const void*)k_rf_chol_blk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pb));
-    hipLaunchKernelGGL(k_rf_chol_blk, dim3(1), dim3(kCholBlkThreads), pb, s, G, (int)w, shift ? 1 : 0, m, Rinv, keep,
-                       cnt2, rdiag);
+  if (w > kCholLdsMaxW && w <= kCholBlk8MaxW) {
+    const bool b16 = w <= kCholBlkMaxW;
+    const size_t pb = (size_t)(b16 ? 16 : 8) * w * 8;
+    const void* fn = b16 ? (const void*)k_rf_chol_blk<16> : (const void*)k_rf_chol_blk<8>;
+    if (pb > 65536) RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pb));
+    if (b16)
+      hipLaunchKernelGGL(k_rf_chol_blk<16>, dim3(1), dim3(kCholBlkThreads), pb, s, G, (int)w, shift ? 1 : 0, m, Rinv,
+                         keep, cnt2, rdiag);
+    else
+      hipLaunchKernelGGL(k_rf_chol_blk<8>, dim3(1), dim3(kCholBlkThreads), pb, s, G, (int)w, shift ? 1 : 0, m, Rinv,
+                         keep, cnt2, rdiag);
     RE_TRY_HIP(hipGetLastError());
     return RE_OK;
   }

@@ -141,7 +141,8 @@ def _geometric(m, w, cond, seed, dtype=torch.float64):
                                             (2048, 64, 1e6, torch.float32), (5000, 200, 1e3, torch.float64),
                                             (1000, 1, 1.0, torch.float64), (1500, 136, 1e3, torch.float64),
                                             (1500, 137, 1e3, torch.float64), (2600, 1100, 1e2, torch.float64),
-                                            (2600, 1101, 1e2, torch.float64)])
+                                            (2600, 1101, 1e2, torch.float64), (2400, 2200, 1e2, torch.float64),
+                                            (2400, 2201, 1e2, torch.float64)])
 def test_thin_qr_matches_oracle(orc, m, w, cond, dtype):
     W = _geometric(m, w, cond, 31 + w, dtype)
     Qg, flags = re_.thin_qr(W.to(DEV))
