@@ -46,6 +46,11 @@ WORKLOADS = {
                desc="rank estimation + randomized rangefinder (fixed-precision QB): FP32 100000x100000 diagonal "
                     "s_i = 10^(-0.01 (i-1)) stored dense (slow exponential decay), r1 = 1500 (Gaussian X 1650 "
                     "columns, Y 3300 rows), p = 10, eps 1e-3; thin QR of A X[:, :r+p], B = Q^T A"),
+    "qr": dict(m=65536, n=16384, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="srht", y="srht", wide_k=1650,
+               wide_l=3300,
+               desc="step 7 by the QR diagonal (Sec. 5): the plain method at scale (FP32 65536x16384, SRHT X 384, "
+                    "SRHT Y 576, eps 1e-3/1e-5) with |diag R| of Y A X in place of its singular values; also timed "
+                    "against the SVD at Gaussian k = 1650, l = 3300"),
     "c1": dict(m=2000, n=1000, R=1000, k=40, l=60, eps=(1e-6,), x="gaussian", y="gaussian",
                desc="plain method, CPU-sized: FP64 2000x1000, step spectrum (20 x 1, then 1e-8), "
                     "Gaussian X 1000x40, Gaussian Y 60x2000, eps 1e-6"),
@@ -83,7 +88,7 @@ def make_matrix(name, w, device):
     import torch
 
     from paper_2105_07388_amd import inputs
-    if name == "c2":
+    if name in ("c2", "qr"):
         return inputs.c2_matrix(w["m"], w["n"], w["R"], device=device)
     if name == "c1":
         return inputs.c1_matrix(device=device)
@@ -428,6 +433,81 @@ def bench_rf(args, w, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_qr(args, w, dev):
+    """One step = Algorithm 1 with step 7 by the QR diagonal on the plain
+    method's workload; the SVD form timed beside it, and both at a wide
+    Gaussian sketch."""
+    import numpy as np
+    import torch
+
+    import paper_2105_07388_amd as re_
+
+    A = make_matrix("c2", w, dev)
+    torch.cuda.synchronize()
+    h = re_.Handle(dev)
+    h.set_profiling(True)
+    print(f"[bench] qr: A {tuple(A.shape)} resident; warmup {args.warmup}", file=sys.stderr, flush=True)
+
+    def run(fn, k, l, x, y, steps, seed0):
+        st, ranks = [], []
+        for i in range(args.warmup):
+            fn(A, w["eps"][0], k=k, l=l, x=x, y=y, seed=seed0 + 7 + i, handle=h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            r, _, _ = fn(A, w["eps"][i % len(w["eps"])], k=k, l=l, x=x, y=y, seed=seed0 + 1000003 * (i + 1),
+                         handle=h)
+            ranks.append(r)
+            st.append(h.last_stage_ms())
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        mean = {a: float(np.mean([d[a] for d in st])) for a in st[0]}
+        return steps / el, mean, sorted(set(ranks))
+
+    def qr_fn(A, eps, **kw):
+        return re_.rank_estimate_qr(A, eps, **kw)
+
+    def svd_fn(A, eps, **kw):
+        return re_.rank_estimate(A, eps, **kw)
+
+    v_qr, st_qr, rk_qr = run(qr_fn, w["k"], w["l"], w["x"], w["y"], args.steps, 0)
+    v_svd, st_svd, rk_svd = run(svd_fn, w["k"], w["l"], w["x"], w["y"], args.steps, 0)
+    nw = max(2, min(args.steps, 3))
+    vw_qr, stw_qr, rkw_qr = run(qr_fn, w["wide_k"], w["wide_l"], "gaussian", "gaussian", nw, 5)
+    vw_svd, stw_svd, rkw_svd = run(svd_fn, w["wide_k"], w["wide_l"], "gaussian", "gaussian", nw, 5)
+    print(f"[bench] k {w['k']}: qr {st_qr['svd']:.3f} ms (ranks {rk_qr}) vs svd {st_svd['svd']:.3f} ms (ranks {rk_svd}); "
+          f"k {w['wide_k']}: qr {stw_qr['svd']:.1f} ms (ranks {rkw_qr}) vs svd {stw_svd['svd']:.1f} ms (ranks {rkw_svd})",
+          file=sys.stderr, flush=True)
+    ax_ms = st_qr["ax"]
+    alg_bytes = w["m"] * w["n"] * 4
+    achieved = alg_bytes / (ax_ms * 1e-3) / 1e9
+    out = {
+        "metric": "rank estimates/s + sketch GB/s vs HBM peak; learned vs doubling, same rank",
+        "value": v_qr,
+        "unit": "rank estimates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 / v_qr,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "m": w["m"], "n": w["n"], "k": w["k"], "l": w["l"], "eps": list(w["eps"]),
+                   "x": w["x"], "y": w["y"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic("c2"), "kernel": "A X pass",
+                     "algorithmic_bytes_per_launch": alg_bytes, "mean_ms": ax_ms},
+        "stage_ms": st_qr,
+        "step7_ms": {"k384_qr": st_qr["svd"], "k384_svd": st_svd["svd"], "k1650_qr": stw_qr["svd"],
+                     "k1650_svd": stw_svd["svd"]},
+        "svd_form_estimates_per_s": v_svd,
+        "ranks": {"k384_qr": rk_qr, "k384_svd": rk_svd, "k1650_qr": rkw_qr, "k1650_svd": rkw_svd},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -469,6 +549,8 @@ def main():
         return bench_learned(args, w, dev)
     if args.workload == "rf":
         return bench_rf(args, w, dev)
+    if args.workload == "qr":
+        return bench_qr(args, w, dev)
     A = make_matrix(args.workload, w, dev)
     torch.cuda.synchronize()
     h = re_.Handle(dev)
