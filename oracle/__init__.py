@@ -8,3 +8,4 @@ from . import learned  # noqa: F401,E402
 from . import gap  # noqa: F401,E402
 from . import rangefinder  # noqa: F401,E402
 from . import qrdiag  # noqa: F401,E402
+from . import hrtt  # noqa: F401,E402

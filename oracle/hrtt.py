@@ -1,0 +1,84 @@
+"""FP64 oracle of the hashed randomized DCT sketch (HRTT) for X, test
+infrastructure only (only tests/, the package smoke check and the benchmark's
+CPU-baseline leg may import it).
+
+Sec. 3.3: a hashed randomized trigonometric transform replaces the sampling
+matrix S of the subsampled transform S F D by a hashing matrix H (CountSketch:
+each transformed coordinate goes to one of k buckets with a random sign), the
+paper's experimental X (Sec. 3.3, Sec. 6) with F a DCT.  Here, per row a of A
+(zero-padded to N = the next power of two >= max(n, 2), as for the Hadamard
+transform):  B[i, b] = sqrt(k) sum_{j : h(j) = b} s(j) (F D a_i)_j  with D the
+random signs of the SRHT's X (Philox stream 3), F the orthonormal DCT-II of
+length N (scipy's, a library FFT serving as the transform step), h(j) in
+[0, k) and s(j) in {+1, -1} from Philox4x64-10 at counter (j, 0, 7, 0):
+h(j) = floor(w0 k / 2^64), s(j) = +1 if the lowest bit of w1 is 0.  The factor
+sqrt(k) lets every X kind share the 1/sqrt(k) scale of the estimates.
+"""
+import math
+
+import numpy as np
+import scipy.fft as sf
+
+from . import pyoracle as _o
+
+STREAM_XHASH = 7
+
+
+def npad(n):
+    return max(2, _o.next_pow2(int(n)))
+
+
+def hash_table(seed, N, k, blk=0):
+    """(bucket[N], sign[N]) of the CountSketch."""
+    b = np.zeros(N, dtype=np.int64)
+    s = np.zeros(N, dtype=np.float64)
+    for j in range(N):
+        w = _o.philox4x64_10([j, 0, STREAM_XHASH, blk], [seed, 0])
+        b[j] = (int(w[0]) * int(k)) >> 64
+        s[j] = 1.0 - 2.0 * float(int(w[1]) & 1)
+    return b, s
+
+
+def signs(seed, N, blk=0):
+    return np.array([_o.sign(seed, j, _o.STREAM_XSIGN, blk) for j in range(N)], dtype=np.float64)
+
+
+def dct_matrix(N):
+    """Orthonormal DCT-II by its definition: F[q, j] = c_q sqrt(2/N) cos(pi q (2j+1) / (2N))."""
+    q = np.arange(N)[:, None]
+    j = np.arange(N)[None, :]
+    F = math.sqrt(2.0 / N) * np.cos(np.pi * q * (2 * j + 1) / (2 * N))
+    F[0] /= math.sqrt(2.0)
+    return F
+
+
+def apply_x(A, k, seed=0, blk=0):
+    """B = A X for the HRTT X (m x k, FP64)."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    N = npad(n)
+    Z = np.zeros((m, N))
+    Z[:, :n] = A
+    Z *= signs(seed, N, blk)[None, :]
+    Yt = sf.dct(Z, type=2, norm="ortho", axis=1)
+    b, s = hash_table(seed, N, k, blk)
+    H = np.zeros((N, k))
+    H[np.arange(N), b] = s
+    return math.sqrt(k) * (Yt @ H)
+
+
+def rank_estimate(A, eps, k=40, l=None, ykind=_o.GAUSSIAN, seed=0):
+    """Algorithm 1 with the HRTT X: (r, sigma[k], r1, flags); Y Gaussian or SRHT
+    in A's storage format, as the plain oracle draws it."""
+    A = np.ascontiguousarray(A)
+    l = 2 * k if l is None else l
+    fmt = _o.FMT_F64 if A.dtype == np.float64 else _o.FMT_F32
+    B = apply_x(A, k, seed=seed)
+    Cm = _o.apply_y(B, ykind, l, fmt_y=fmt, seed=seed)
+    s, _, st = _o.jacobi_sv(Cm)
+    if st != 0:
+        raise _o.OracleError(st)
+    s = s / math.sqrt(k * l)
+    r1 = _o.r1_from_k(k)
+    r, flags = _o.rank_count(s, r1, eps)
+    return r, s, r1, flags

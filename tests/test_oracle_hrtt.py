@@ -1,0 +1,64 @@
+"""Pins of the HRTT sketch oracle (oracle/hrtt.py): the DCT step against its
+definition, the hashing step against an explicit matrix, the whole X against
+the product D F^T H^T written out, uniform buckets, the expected isometry, and
+the paper's remark that the hashed transform handles a diagonal (coherent)
+matrix where the subsampled one does not."""
+import math
+
+import numpy as np
+import pytest
+import scipy.stats as st
+
+from paper_2105_07388_amd import inputs
+
+
+def test_dct_step_is_the_orthonormal_dct(orc):
+    H = orc.hrtt
+    for N in (2, 4, 16, 64):
+        F = H.dct_matrix(N)
+        assert np.allclose(F @ F.T, np.eye(N), atol=1e-13)
+        x = np.random.default_rng(N).standard_normal(N)
+        import scipy.fft as sf
+        assert np.allclose(sf.dct(x, type=2, norm="ortho"), F @ x, atol=1e-13)
+
+
+def test_whole_x_is_the_written_out_product(orc):
+    H = orc.hrtt
+    rng = np.random.default_rng(5)
+    m, n, k, seed = 7, 13, 5, 11
+    A = rng.standard_normal((m, n))
+    N = H.npad(n)
+    D = np.diag(H.signs(seed, N))
+    b, s = H.hash_table(seed, N, k)
+    Hm = np.zeros((k, N))
+    Hm[b, np.arange(N)] = s
+    X = (D @ H.dct_matrix(N).T @ Hm.T)[:n] * math.sqrt(k)  # n x k
+    assert np.allclose(H.apply_x(A, k, seed=seed), A @ X, atol=1e-12)
+    # the hash is the published Philox draw: bucket = floor(w0 k / 2^64), sign from w1
+    w = orc.philox4x64_10([3, 0, 7, 0], [seed, 0])
+    assert b[3] == (int(w[0]) * k) >> 64 and s[3] == (1.0 if int(w[1]) % 2 == 0 else -1.0)
+
+
+def test_buckets_uniform_and_isometry_in_expectation(orc):
+    H = orc.hrtt
+    b, s = H.hash_table(1, 8192, 64)
+    counts = np.bincount(b, minlength=64)
+    assert st.chisquare(counts).pvalue > 1e-3
+    assert abs(np.mean(s)) < 4 / math.sqrt(8192)
+    # E ||Theta x||^2 = ||x||^2 for the CountSketch of an orthogonal transform
+    x = np.random.default_rng(2).standard_normal((1, 100))
+    r = [np.sum(H.apply_x(x, 16, seed=t) ** 2) / 16 / np.sum(x ** 2) for t in range(60)]
+    assert abs(np.mean(r) - 1.0) < 4 * np.std(r) / math.sqrt(60)
+
+
+def test_diagonal_matrix_hashed_beats_subsampled(orc):
+    # Sec. 3.3 / 3.4: on a diagonal (maximally coherent) matrix with a gap at 30
+    # the hashed DCT keeps the gap, while a subsampled transform can miss
+    # coordinates and understate the rank
+    n = 512
+    s = np.concatenate([np.ones(30), 1e-8 * np.ones(n - 30)])
+    A = np.diag(s)
+    r, sig, r1, fl = orc.hrtt.rank_estimate(A, 1e-4, k=64, l=128, seed=3)
+    assert r == 30
+    rs, _, _, _, _ = orc.rank_estimate(A, 1e-4, orc.SRHT, orc.GAUSSIAN, k=64, l=128, seed=3)
+    assert rs < 30
