@@ -12,6 +12,7 @@
 
 #include "batch.h"
 #include "common.h"
+#include "hrtt.h"
 #include "learned.h"
 #include "rangefinder.h"
 
@@ -130,7 +131,8 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
   if (dt != RE_F64 && dt != RE_F32) return RE_ERR_INVALID_ARG;
   if (m < 1 || n < 1 || lda < n) return RE_ERR_INVALID_ARG;
   if (((uintptr_t)A) % (dt == RE_F64 ? 8 : 4) != 0) return RE_ERR_INVALID_ARG;
-  if ((sk->x_kind != RE_GAUSSIAN && sk->x_kind != RE_SRHT) || (sk->y_kind != RE_GAUSSIAN && sk->y_kind != RE_SRHT))
+  if ((sk->x_kind != RE_GAUSSIAN && sk->x_kind != RE_SRHT && sk->x_kind != RE_HRTT) ||
+      (sk->y_kind != RE_GAUSSIAN && sk->y_kind != RE_SRHT))
     return RE_ERR_INVALID_ARG;
   if (sk->prec < RE_PREC_NATIVE || sk->prec > RE_PREC_AUTO) return RE_ERR_INVALID_ARG;
   rs->xk = sk->x_kind;
@@ -139,20 +141,21 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
   rs->l = sk->l == 0 ? 2 * (int64_t)sk->k : sk->l;
   rs->npad_n = next_pow2(n);
   rs->npad_m = next_pow2(m);
-  const int64_t kmax = rs->xk == RE_SRHT ? rs->npad_n : n;
+  const int64_t kmax = rs->xk == RE_SRHT ? rs->npad_n : rs->xk == RE_HRTT ? hrtt_npad(n) : n;
   const int64_t lmax = rs->yk == RE_SRHT ? rs->npad_m : m;
   if (rs->k < 1 || rs->l < rs->k) return RE_ERR_INVALID_ARG;
   if ((sides & 1) && rs->k > kmax) return RE_ERR_INVALID_ARG;
   if ((sides & 2) && rs->l > lmax) return RE_ERR_INVALID_ARG;
   if (rs->k > (int64_t)INT32_MAX / 2) return RE_ERR_INVALID_ARG;
-  if (sk->prec != RE_PREC_NATIVE && (dt == RE_F64 || rs->xk == RE_SRHT)) return RE_ERR_UNSUPPORTED;
+  if (sk->prec != RE_PREC_NATIVE && (dt == RE_F64 || rs->xk != RE_GAUSSIAN)) return RE_ERR_UNSUPPORTED;
+  if (rs->xk == RE_HRTT && (dt != RE_F32 || hrtt_npad(n) > kHrttMaxN)) return RE_ERR_UNSUPPORTED;
   return RE_OK;
 }
 
 // Workspace plan of one estimate.
 struct Plan {
   size_t xbits, ybits, xsel, ysel, selscr, X, Y, B, C, svd, sigma, info, out3, stats, gdesc, ydesc, queue, yparts,
-      rdiag, total;
+      rdiag, hscr, total;
 };
 
 // Sketches the batched form accepts (one workgroup's LDS holds the small SVD).
@@ -175,7 +178,7 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   const int fx = x_fmt(dt);
   const size_t be = dt == RE_F64 ? 8 : 4;
   const int64_t brows = rs.yk == RE_SRHT ? (int64_t)srht_cols_rows_alloc(m) : m;
-  p.xbits = c.take((size_t)cdiv(rs.npad_n, 32) * 4);
+  p.xbits = c.take((size_t)cdiv(rs.xk == RE_HRTT ? hrtt_npad(n) : rs.npad_n, 32) * 4);
   p.ybits = c.take((size_t)cdiv(rs.npad_m, 32) * 4);
   p.xsel = c.take((size_t)rs.k * 4);
   p.ysel = c.take((size_t)rs.l * 4);
@@ -194,6 +197,7 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   p.queue = c.take(16);
   p.yparts = c.take(rs.yk == RE_GAUSSIAN && dt == RE_F32 ? yb_scratch(rs.l, rs.k, m) : 0);
   p.rdiag = c.take((size_t)rs.k * 3 * 8);  // diagonals of the QR passes (step 7 by the QR diagonal)
+  p.hscr = c.take(rs.xk == RE_HRTT ? hrtt_scratch_bytes(n, rs.k) : 0);
   p.total = c.off;
   return p;
 }
@@ -214,6 +218,12 @@ void mark(re_handle h, int i) {
 re_status run_x(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
                 const Resolved& rs, uint64_t seed, void* B) {
   hipStream_t s = h->stream;
+  if (rs.xk == RE_HRTT) {  // hashed randomized DCT (FP32 A)
+    uint32_t* bits = (uint32_t*)at(h, p.xbits);
+    RE_TRY(launch_sign_bits(s, hrtt_npad(n), seed, kXSign, bits));
+    mark(h, RE_STAGE_AX);
+    return launch_hrtt_rows(s, (const float*)A, m, n, lda, rs.k, seed, bits, at(h, p.hscr), (float*)B, rs.k);
+  }
   if (rs.xk == RE_SRHT) {
     uint32_t* bits = (uint32_t*)at(h, p.xbits);
     int32_t* sel = (int32_t*)at(h, p.xsel);

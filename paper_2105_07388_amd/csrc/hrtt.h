@@ -1,0 +1,25 @@
+// Launchers of the hashed randomized DCT embedding (HRTT X, Sec. 3.3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rankest.h"
+
+namespace re {
+
+// Rows of the DCT held in one workgroup's LDS: N complex FP32 values.
+constexpr int64_t kHrttMaxN = 16384;
+
+// N = the transform length for n columns (next power of two, at least 2).
+__attribute__((visibility("hidden"))) int64_t hrtt_npad(int64_t n);
+// Scratch of one call: bucket codes, bucket pointers, coordinate lists, twiddles.
+__attribute__((visibility("hidden"))) size_t hrtt_scratch_bytes(int64_t n, int64_t k);
+// B (m x k FP32, ldb) = A X for the HRTT X of width k; sign_bits: the SRHT X
+// signs for N coordinates.  RE_ERR_UNSUPPORTED when N > kHrttMaxN or k > N.
+__attribute__((visibility("hidden"))) re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n,
+                                                                int64_t lda, int64_t k, uint64_t seed,
+                                                                const uint32_t* sign_bits, void* scratch, float* B,
+                                                                int64_t ldb);
+
+}  // namespace re

@@ -1,0 +1,87 @@
+"""GPU tests of the hashed randomized DCT sketch (HRTT X) against the oracle
+(oracle/hrtt.py).
+
+Tolerance of B = A X, per row: the FP32 FFT's normwise error (5 log2 N + 4) u32
+||a|| (Cooley-Tukey with accurate twiddles, Higham Thm. 24.2, plus the
+post-twiddle), through the CountSketch (norm sqrt(max bucket)), plus the
+rounding of each bucket's sum (max bucket^(3/2) u32 ||a||), times sqrt(k).
+Estimates: that error through Y, |d sigma| <= 1.1 (sqrt m + sqrt l) ||dB||_F /
+sqrt(k l).  Ranks compared on gaps.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2105_07388_amd as re_
+from paper_2105_07388_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+U32 = 2.0 ** -24
+
+
+def _row_tol(orc, n, k, seed, anorm):
+    N = orc.hrtt.npad(n)
+    lg = int(math.log2(N))
+    b, _ = orc.hrtt.hash_table(seed, N, k)
+    bmax = int(np.bincount(b, minlength=k).max())
+    return math.sqrt(k) * (math.sqrt(bmax) * (5 * lg + 4) + bmax ** 1.5) * U32 * anorm
+
+
+@pytest.mark.parametrize("m,n,k", [(300, 1000, 64), (257, 1024, 7), (64, 2049, 384), (50, 1, 1), (33, 2, 2),
+                                   (40, 3, 4), (128, 16384, 384), (90, 700, 700)])
+def test_sketch_x_matches_oracle(orc, m, n, k):
+    A = inputs.gaussian(m, n, 100 + n, torch.float32)
+    seed = 17 + k
+    Bg = re_.sketch_x(A.to(DEV), k=k, x="hrtt", seed=seed).cpu().numpy().astype(np.float64)
+    Bo = orc.hrtt.apply_x(A.numpy(), k, seed=seed)
+    err = np.linalg.norm(Bg - Bo, axis=1)
+    tol = np.array([_row_tol(orc, n, k, seed, float(np.linalg.norm(a))) for a in A.double().numpy()])
+    assert np.all(err <= tol), float(np.max(err / tol))
+
+
+def test_rank_estimate_matches_oracle_on_a_gap(orc):
+    A = inputs.planted(1500, 1000, inputs.spectrum_step(1000, 20, 1.0, 1e-8), 31, torch.float32)
+    k, l = 40, 60
+    for y, ykind in (("gaussian", orc.GAUSSIAN), ("srht", orc.SRHT)):
+        r, s, info = re_.rank_estimate(A.to(DEV), 1e-5, k=k, l=l, x="hrtt", y=y, seed=6)
+        ro, so, r1, fl = orc.hrtt.rank_estimate(A.numpy(), 1e-5, k=k, l=l, ykind=ykind, seed=6)
+        assert r == ro == 20 and info["flags"] == fl
+        dB = math.sqrt(sum(_row_tol(orc, 1000, k, 6, float(np.linalg.norm(a))) ** 2 for a in A.double().numpy()))
+        tol = 1.1 * (math.sqrt(1500) + math.sqrt(l)) * dB / math.sqrt(k * l) + 1e-12 * so[0]
+        assert np.all(np.abs(s - so) <= tol), (float(np.max(np.abs(s - so))), tol)
+
+
+def test_coherent_diagonal_matrix(orc):
+    # Sec. 3.3: the hashed transform keeps the gap of a diagonal matrix, the
+    # subsampled Hadamard transform does not (the same on both sides)
+    n = 512
+    A = torch.diag(torch.cat([torch.ones(30), 1e-8 * torch.ones(n - 30)])).float()
+    r, _, _ = re_.rank_estimate(A.to(DEV), 1e-4, k=64, l=128, x="hrtt", seed=3)
+    ro, _, _, _ = orc.hrtt.rank_estimate(A.numpy(), 1e-4, k=64, l=128, seed=3)
+    assert r == ro == 30
+    rs, _, _ = re_.rank_estimate(A.to(DEV), 1e-4, k=64, l=128, x="srht", seed=3)
+    rso, _, _, _, _ = orc.rank_estimate(A.numpy(), 1e-4, orc.SRHT, orc.GAUSSIAN, k=64, l=128, seed=3)
+    assert rs == rso < 30
+
+
+def test_repeatable_and_errors():
+    A = inputs.gaussian(400, 3000, 9, torch.float32).to(DEV)
+    b1 = re_.sketch_x(A, k=100, x="hrtt", seed=2)
+    b2 = re_.sketch_x(A, k=100, x="hrtt", seed=2)
+    assert torch.equal(b1, b2)
+    with pytest.raises(re_.RankEstError) as e:
+        re_.sketch_x(A.double(), k=10, x="hrtt")
+    assert e.value.status == re_._binding.RE_ERR_UNSUPPORTED
+    W = torch.zeros(4, 16385, device=DEV)
+    with pytest.raises(re_.RankEstError) as e:
+        re_.sketch_x(W, k=10, x="hrtt")
+    assert e.value.status == re_._binding.RE_ERR_UNSUPPORTED
+    with pytest.raises(re_.RankEstError) as e:
+        re_.rank_estimate(A, 1e-3, k=10, x="hrtt", precision="bf16")
+    assert e.value.status == re_._binding.RE_ERR_UNSUPPORTED
+    with pytest.raises(re_.RankEstError) as e:
+        re_.rank_estimate(A, 1e-3, k=10, y="hrtt")
+    assert e.value.status == re_._binding.RE_ERR_INVALID_ARG
