@@ -46,6 +46,9 @@ WORKLOADS = {
                desc="rank estimation + randomized rangefinder (fixed-precision QB): FP32 100000x100000 diagonal "
                     "s_i = 10^(-0.01 (i-1)) stored dense (slow exponential decay), r1 = 1500 (Gaussian X 1650 "
                     "columns, Y 3300 rows), p = 10, eps 1e-3; thin QR of A X[:, :r+p], B = Q^T A"),
+    "hrtt": dict(m=65536, n=16384, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="hrtt", y="srht",
+                 desc="hashed randomized DCT X (Sec. 3.3, the paper's experimental X): FP32 65536x16384, "
+                      "s_i=10^(-i/20) (R=1024) + 1e-9 noise, HRTT X 16384x384, SRHT Y 576x65536, eps 1e-3/1e-5"),
     "qr": dict(m=65536, n=16384, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="srht", y="srht", wide_k=1650,
                wide_l=3300,
                desc="step 7 by the QR diagonal (Sec. 5): the plain method at scale (FP32 65536x16384, SRHT X 384, "
@@ -59,7 +62,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 TRAFFIC_SOURCES = {"c2": ("srht.hip", "common.h"), "c3": ("gemm_lp.hip", "common.h"),
-                   "c4": ("batch.hip", "batch.h", "common.h"), "rf": ("batch.hip", "batch.h", "common.h")}
+                   "c4": ("batch.hip", "batch.h", "common.h"), "rf": ("batch.hip", "batch.h", "common.h"),
+                   "hrtt": ("hrtt.hip", "hrtt.h", "common.h")}
 
 
 def kernel_source_digest(workload: str) -> str:
@@ -88,7 +92,7 @@ def make_matrix(name, w, device):
     import torch
 
     from paper_2105_07388_amd import inputs
-    if name in ("c2", "qr"):
+    if name in ("c2", "qr", "hrtt"):
         return inputs.c2_matrix(w["m"], w["n"], w["R"], device=device)
     if name == "c1":
         return inputs.c1_matrix(device=device)
@@ -109,7 +113,7 @@ def cpu_baseline(A_dev, w, rows: int):
     yk = oracle.SRHT if w["y"] == "srht" else oracle.GAUSSIAN
     A_s = A_dev[:rows].cpu().numpy()
     t0 = time.perf_counter()
-    B = oracle.apply_x(A_s, xk, k, seed=0)
+    B = oracle.hrtt.apply_x(A_s, k, seed=0) if w["x"] == "hrtt" else oracle.apply_x(A_s, xk, k, seed=0)
     t_x = (time.perf_counter() - t0) * (m / rows)
     Bfull = np.random.default_rng(0).standard_normal((m, k))
     Bfull[:rows] = B

@@ -13,7 +13,7 @@ constexpr int64_t kHrttMaxN = 16384;
 
 // N = the transform length for n columns (next power of two, at least 2).
 __attribute__((visibility("hidden"))) int64_t hrtt_npad(int64_t n);
-// Scratch of one call: bucket codes, bucket pointers, coordinate lists, twiddles.
+// Scratch of one call: bucket codes, bucket pointers, coordinate lists.
 __attribute__((visibility("hidden"))) size_t hrtt_scratch_bytes(int64_t n, int64_t k);
 // B (m x k FP32, ldb) = A X for the HRTT X of width k; sign_bits: the SRHT X
 // signs for N coordinates.  RE_ERR_UNSUPPORTED when N > kHrttMaxN or k > N.

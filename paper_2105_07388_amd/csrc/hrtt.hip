@@ -66,72 +66,94 @@ __global__ void k_hash_fill(const int32_t* __restrict__ code, int64_t N, int64_t
   }
 }
 
-// FFT twiddles W[t] = e^{-2 pi i t / N} (t < N/2) and the DCT's post-twiddles
-// E[q] = e^{-i pi q / (2N)} (q < N), from FP64 sincospi rounded to FP32.
-__global__ void k_dct_twiddles(int64_t N, float2* __restrict__ W, float2* __restrict__ E) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= N) return;
-  double sv, cv;
-  if (t < N / 2) {
-    sincospi(2.0 * (double)t / (double)N, &sv, &cv);
-    W[t] = make_float2((float)cv, (float)-sv);
-  }
-  sincospi((double)t / (2.0 * (double)N), &sv, &cv);
-  E[t] = make_float2((float)cv, (float)-sv);
-}
-
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// Twiddles come from sincospif (FP32, within 2 ulp; the arguments t / N are
+// exact), so the FFT needs no table reads; the next row's entries are loaded
+// into registers while the current row is transformed.
 __global__ void __launch_bounds__(kHrttThreads) k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n,
                                                             int64_t lda, int lgN, const uint32_t* __restrict__ bits,
-                                                            const float2* __restrict__ W,
-                                                            const float2* __restrict__ E,
                                                             const int32_t* __restrict__ ptr,
                                                             const int32_t* __restrict__ list, int64_t k, float sk,
                                                             float* __restrict__ B, int64_t ldb) {
   extern __shared__ float2 X[];  // N complex values
+  constexpr int kPer = kHrttMaxN / kHrttThreads;  // entries of a row per thread at most
   const int N = 1 << lgN, half_n = N >> 1;
   const int tid = threadIdx.x, nth = blockDim.x;
   const float nrm = sqrtf(2.0f / (float)N), nrm0 = sqrtf(1.0f / (float)N);
-  for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
+  const float inv_n = 1.0f / (float)N;
+  // signed entries of one row in Makhoul's order: thread tid holds positions tid + q nth
+  float v[kPer];
+  auto load_row = [&](int64_t row) {
     const float* __restrict__ a = A + row * lda;
-    // signs, Makhoul's reordering, bit-reversed placement
-    for (int p = tid; p < N; p += nth) {
-      const int j = p < half_n ? 2 * p : 2 * (N - 1 - p) + 1;
-      float v = j < n ? a[j] : 0.0f;
-      if ((bits[j >> 5] >> (j & 31)) & 1u) v = -v;
-      X[__brev((unsigned)p) >> (32 - lgN)] = make_float2(v, 0.0f);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int p = tid + q * nth;
+      float x = 0.0f;
+      if (p < N) {
+        const int j = p < half_n ? 2 * p : 2 * (N - 1 - p) + 1;
+        if (j < n) x = a[j];
+        if ((bits[j >> 5] >> (j & 31)) & 1u) x = -x;
+      }
+      v[q] = x;
+    }
+  };
+  int64_t row = blockIdx.x;
+  if (row < m) load_row(row);
+  for (; row < m; row += gridDim.x) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int p = tid + q * nth;
+      if (p < N) X[__brev((unsigned)p) >> (32 - lgN)] = make_float2(v[q], 0.0f);
     }
     __syncthreads();
-    // radix-2 decimation in time: stage s joins pairs half = 2^s apart
+    if (row + gridDim.x < m) load_row(row + gridDim.x);  // in flight during the transform
+    // radix-2 decimation in time: stage s joins pairs half = 2^s apart with
+    // twiddle e^{-2 pi i pos / 2^(s+1)}
     for (int s = 0; s < lgN; ++s) {
       const int half = 1 << s;
+      const float tw = 1.0f / (float)half;  // twiddle angle step in units of pi
       for (int u = tid; u < half_n; u += nth) {
         const int pos = u & (half - 1);
         const int i0 = ((u >> s) << (s + 1)) + pos, i1 = i0 + half;
-        const float2 w = W[pos << (lgN - 1 - s)];
+        float sw, cw;
+        sincospif((float)pos * tw, &sw, &cw);
+        const float2 w = make_float2(cw, -sw);
         const float2 x0 = X[i0], x1 = cmul(X[i1], w);
         X[i0] = make_float2(x0.x + x1.x, x0.y + x1.y);
         X[i1] = make_float2(x0.x - x1.x, x0.y - x1.y);
       }
       __syncthreads();
     }
-    // DCT-II value q, kept in the real slot of X[q]
+    // DCT-II value q = c_q Re(e^{-i pi q / (2N)} V_q), kept in the real slot of X[q]
     for (int q = tid; q < N; q += nth) {
-      const float2 c = X[q], e = E[q];
-      X[q].x = (c.x * e.x - c.y * e.y) * (q ? nrm : nrm0);
+      float se, ce;
+      sincospif(0.5f * (float)q * inv_n, &se, &ce);
+      const float2 c = X[q];
+      X[q].x = (c.x * ce + c.y * se) * (q ? nrm : nrm0);
     }
     __syncthreads();
     // CountSketch: one thread per bucket over its fixed coordinate list
     for (int64_t b = tid; b < k; b += nth) {
       float acc = 0.0f;
       const int32_t p1 = ptr[b + 1];
-      for (int32_t t = ptr[b]; t < p1; ++t) {
+      int32_t t = ptr[b];
+      for (; t + 3 < p1; t += 4) {  // four list entries in flight, same summation order
+        int32_t c[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = list[t + q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float x = X[c[q] & 0x7fffffff].x;
+          acc += c[q] < 0 ? -x : x;
+        }
+      }
+      for (; t < p1; ++t) {
         const int32_t c = list[t];
-        const float v = X[c & 0x7fffffff].x;
-        acc += c < 0 ? -v : v;
+        const float x = X[c & 0x7fffffff].x;
+        acc += c < 0 ? -x : x;
       }
       B[row * ldb + b] = acc * sk;
     }
@@ -148,7 +170,7 @@ int64_t hrtt_npad(int64_t n) {
 
 size_t hrtt_scratch_bytes(int64_t n, int64_t k) {
   const int64_t N = hrtt_npad(n);
-  return (size_t)N * 4 + (size_t)(k + 1) * 4 + (size_t)N * 4 + (size_t)N * 12 + 4 * 256;
+  return (size_t)N * 4 + (size_t)(k + 1) * 4 + (size_t)N * 4 + 3 * 256;
 }
 
 re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t lda, int64_t k, uint64_t seed,
@@ -159,14 +181,11 @@ re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n, 
   int32_t* code = (int32_t*)base;
   int32_t* ptr = (int32_t*)(base + ((N * 4 + 255) / 256) * 256);
   int32_t* list = (int32_t*)((char*)ptr + (((k + 1) * 4 + 255) / 256) * 256);
-  float2* W = (float2*)((char*)list + ((N * 4 + 255) / 256) * 256);
-  float2* E = W + N / 2;
   const unsigned gN = (unsigned)cdiv(N, 256), gk = (unsigned)cdiv(k, 256);
   hipLaunchKernelGGL(k_hash_code, dim3(gN), dim3(256), 0, s, N, k, seed, code);
   hipLaunchKernelGGL(k_hash_count, dim3(gk), dim3(256), 0, s, (const int32_t*)code, N, k, ptr);
   hipLaunchKernelGGL(k_hash_scan, dim3(1), dim3(64), 0, s, ptr, k);
   hipLaunchKernelGGL(k_hash_fill, dim3(gk), dim3(256), 0, s, (const int32_t*)code, N, k, (const int32_t*)ptr, list);
-  hipLaunchKernelGGL(k_dct_twiddles, dim3(gN), dim3(256), 0, s, N, W, E);
   RE_TRY_HIP(hipGetLastError());
   int lgN = 0;
   while ((int64_t(1) << lgN) < N) ++lgN;
@@ -179,8 +198,7 @@ re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n, 
   int64_t grid = 256 * (int64_t)per_cu;
   if (grid > m) grid = m;
   hipLaunchKernelGGL(k_hrtt_rows, dim3((unsigned)grid), dim3(kHrttThreads), lds, s, A, m, n, lda, lgN, sign_bits,
-                     (const float2*)W, (const float2*)E, (const int32_t*)ptr, (const int32_t*)list, k,
-                     sqrtf((float)k), B, ldb);
+                     (const int32_t*)ptr, (const int32_t*)list, k, sqrtf((float)k), B, ldb);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
 }

@@ -1,8 +1,8 @@
 """GPU tests of the hashed randomized DCT sketch (HRTT X) against the oracle
 (oracle/hrtt.py).
 
-Tolerance of B = A X, per row: the FP32 FFT's normwise error (5 log2 N + 4) u32
-||a|| (Cooley-Tukey with accurate twiddles, Higham Thm. 24.2, plus the
+Tolerance of B = A X, per row: the FP32 FFT's normwise error (6 log2 N + 6) u32
+||a|| (Cooley-Tukey with twiddles within 2 ulp, Higham Thm. 24.2, plus the
 post-twiddle), through the CountSketch (norm sqrt(max bucket)), plus the
 rounding of each bucket's sum (max bucket^(3/2) u32 ||a||), times sqrt(k).
 Estimates: that error through Y, |d sigma| <= 1.1 (sqrt m + sqrt l) ||dB||_F /
@@ -27,7 +27,7 @@ def _row_tol(orc, n, k, seed, anorm):
     lg = int(math.log2(N))
     b, _ = orc.hrtt.hash_table(seed, N, k)
     bmax = int(np.bincount(b, minlength=k).max())
-    return math.sqrt(k) * (math.sqrt(bmax) * (5 * lg + 4) + bmax ** 1.5) * U32 * anorm
+    return math.sqrt(k) * (math.sqrt(bmax) * (6 * lg + 6) + bmax ** 1.5) * U32 * anorm
 
 
 @pytest.mark.parametrize("m,n,k", [(300, 1000, 64), (257, 1024, 7), (64, 2049, 384), (50, 1, 1), (33, 2, 2),
