@@ -8,10 +8,11 @@
 //
 // The DCT of a row is Makhoul's: v = (a_0, a_2, ..., a_3, a_1) (even entries
 // forward, odd ones backward), V = FFT_N(v), (F a)_q = c_q Re(e^{-i pi q / (2N)}
-// V_q).  One workgroup per row keeps the N complex values in LDS and runs an
-// in-place radix-2 decimation-in-time FFT over the bit-reversed sequence; each
-// bucket's sum then runs over a fixed list of its coordinates (one thread per
-// bucket), so every run gives the same bits.
+// V_q).  One workgroup per row keeps the N complex values in LDS and runs a
+// Stockham FFT of radix-16 passes (the 16-point DFTs in registers), so a row
+// of 16384 takes four passes over LDS; each bucket's sum then runs over a
+// fixed list of its coordinates (one thread per bucket), so every run gives
+// the same bits.
 #include <limits.h>
 
 #include "common.h"
@@ -70,9 +71,80 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Twiddles come from sincospif (FP32, within 2 ulp; the arguments t / N are
-// exact), so the FFT needs no table reads; the next row's entries are loaded
-// into registers while the current row is transformed.
+constexpr int brev_c(int i, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r = (r << 1) | ((i >> b) & 1);
+  return r;
+}
+
+constexpr int log2_c(int r) { return r <= 1 ? 0 : 1 + log2_c(r >> 1); }
+
+// R-point DFT (R <= 16) in registers, in place: radix-2 decimation in time
+// over values already in bit-reversed order (t[brev(r)] = input r), twiddles
+// e^{-2 pi i t / 16} written out (cos and sin of multiples of pi / 8); the
+// output is in natural order.
+template <int R>
+__device__ __forceinline__ void dft_reg(float2 (&t)[R]) {
+  constexpr float c1 = 0.923879532511286756f, s1 = 0.382683432365089772f, c2 = 0.707106781186547524f;
+  const float2 w16[8] = {make_float2(1.0f, 0.0f), make_float2(c1, -s1), make_float2(c2, -c2), make_float2(s1, -c1),
+                         make_float2(0.0f, -1.0f), make_float2(-s1, -c1), make_float2(-c2, -c2), make_float2(-c1, -s1)};
+#pragma unroll
+  for (int half = 1; half < R; half *= 2)
+#pragma unroll
+    for (int g = 0; g < R; g += 2 * half)
+#pragma unroll
+      for (int pos = 0; pos < half; ++pos) {
+        const float2 a = t[g + pos], b = cmul(t[g + pos + half], w16[pos * (16 / (2 * half))]);
+        t[g + pos] = make_float2(a.x + b.x, a.y + b.y);
+        t[g + pos + half] = make_float2(a.x - b.x, a.y - b.y);
+      }
+}
+
+// One Stockham pass of radix R over the N values in LDS (natural order in,
+// natural order out after the last pass): task j reads X[j + r N/R], turns it
+// by e^{-2 pi i (j mod Ns) r / (Ns R)}, takes the R-point DFT and writes it to
+// X[(j / Ns) Ns R + (j mod Ns) + r Ns].  All reads finish before any write.
+template <int R>
+__device__ __forceinline__ void stockham_pass(float2* X, int N, int Ns, int tid, int nth) {
+  constexpr int TASKS = R == 16 ? 1 : R == 8 ? 2 : 4;  // tasks per thread (N <= 16384, 1024 threads)
+  const int T = N / R;
+  float2 v[TASKS][R];
+#pragma unroll
+  for (int q = 0; q < TASKS; ++q) {
+    const int j = tid + q * nth;
+    if (j < T) {
+      const int kk = j & (Ns - 1);
+      constexpr int L = log2_c(R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][brev_c(r, L)] = X[j + r * T];  // bit-reversed for dft_reg
+      if (Ns > 1) {
+        const float step = 2.0f * (float)kk / (float)(Ns * R);  // exact: powers of two
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float sw, cw;
+          sincospif(step * (float)r, &sw, &cw);
+          v[q][brev_c(r, L)] = cmul(v[q][brev_c(r, L)], make_float2(cw, -sw));
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < TASKS; ++q) {
+    const int j = tid + q * nth;
+    if (j < T) {
+      dft_reg<R>(v[q]);
+      const int kk = j & (Ns - 1);
+      const int base = (j - kk) * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) X[base + r * Ns] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Twiddles come from sincospif (FP32, within 2 ulp; the arguments are exact),
+// so the FFT reads no tables.
 __global__ void __launch_bounds__(kHrttThreads) k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n,
                                                             int64_t lda, int lgN, const uint32_t* __restrict__ bits,
                                                             const int32_t* __restrict__ ptr,
@@ -84,48 +156,49 @@ __global__ void __launch_bounds__(kHrttThreads) k_hrtt_rows(const float* __restr
   const int tid = threadIdx.x, nth = blockDim.x;
   const float nrm = sqrtf(2.0f / (float)N), nrm0 = sqrtf(1.0f / (float)N);
   const float inv_n = 1.0f / (float)N;
-  // signed entries of one row in Makhoul's order: thread tid holds positions tid + q nth
-  float v[kPer];
-  auto load_row = [&](int64_t row) {
+  for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
+    // signed entries in Makhoul's order, natural positions (four loads in flight)
     const float* __restrict__ a = A + row * lda;
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int p = tid + q * nth;
-      float x = 0.0f;
-      if (p < N) {
-        const int j = p < half_n ? 2 * p : 2 * (N - 1 - p) + 1;
-        if (j < n) x = a[j];
-        if ((bits[j >> 5] >> (j & 31)) & 1u) x = -x;
-      }
-      v[q] = x;
-    }
-  };
-  int64_t row = blockIdx.x;
-  if (row < m) load_row(row);
-  for (; row < m; row += gridDim.x) {
+    for (int q0 = 0; q0 < kPer; q0 += 4) {
+      float x[4];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int p = tid + q * nth;
-      if (p < N) X[__brev((unsigned)p) >> (32 - lgN)] = make_float2(v[q], 0.0f);
+      for (int q = 0; q < 4; ++q) {
+        const int p = tid + (q0 + q) * nth;
+        x[q] = 0.0f;
+        if (p < N) {
+          const int j = p < half_n ? 2 * p : 2 * (N - 1 - p) + 1;
+          if (j < n) x[q] = a[j];
+          if ((bits[j >> 5] >> (j & 31)) & 1u) x[q] = -x[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int p = tid + (q0 + q) * nth;
+        if (p < N) X[p] = make_float2(x[q], 0.0f);
+      }
     }
     __syncthreads();
-    if (row + gridDim.x < m) load_row(row + gridDim.x);  // in flight during the transform
-    // radix-2 decimation in time: stage s joins pairs half = 2^s apart with
-    // twiddle e^{-2 pi i pos / 2^(s+1)}
-    for (int s = 0; s < lgN; ++s) {
-      const int half = 1 << s;
-      const float tw = 1.0f / (float)half;  // twiddle angle step in units of pi
-      for (int u = tid; u < half_n; u += nth) {
-        const int pos = u & (half - 1);
-        const int i0 = ((u >> s) << (s + 1)) + pos, i1 = i0 + half;
-        float sw, cw;
-        sincospif((float)pos * tw, &sw, &cw);
-        const float2 w = make_float2(cw, -sw);
-        const float2 x0 = X[i0], x1 = cmul(X[i1], w);
-        X[i0] = make_float2(x0.x + x1.x, x0.y + x1.y);
-        X[i1] = make_float2(x0.x - x1.x, x0.y - x1.y);
+    // FFT_N by Stockham passes of radix 16 while 16 divides what is left, then 8, 4 or 2
+    int Ns = 1, rem = N;
+    while (rem > 1) {
+      if (rem >= 16) {
+        stockham_pass<16>(X, N, Ns, tid, nth);
+        Ns *= 16;
+        rem >>= 4;
+      } else if (rem == 8) {
+        stockham_pass<8>(X, N, Ns, tid, nth);
+        Ns *= 8;
+        rem = 1;
+      } else if (rem == 4) {
+        stockham_pass<4>(X, N, Ns, tid, nth);
+        Ns *= 4;
+        rem = 1;
+      } else {
+        stockham_pass<2>(X, N, Ns, tid, nth);
+        Ns *= 2;
+        rem = 1;
       }
-      __syncthreads();
     }
     // DCT-II value q = c_q Re(e^{-i pi q / (2N)} V_q), kept in the real slot of X[q]
     for (int q = tid; q < N; q += nth) {
