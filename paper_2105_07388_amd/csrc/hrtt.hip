@@ -8,11 +8,20 @@
 //
 // The DCT of a row is Makhoul's: v = (a_0, a_2, ..., a_3, a_1) (even entries
 // forward, odd ones backward), V = FFT_N(v), (F a)_q = c_q Re(e^{-i pi q / (2N)}
-// V_q).  One workgroup per row keeps the N complex values in LDS and runs a
-// Stockham FFT of radix-16 passes (the 16-point DFTs in registers), so a row
-// of 16384 takes four passes over LDS; each bucket's sum then runs over a
-// fixed list of its coordinates (one thread per bucket), so every run gives
-// the same bits.
+// V_q).  v is real, so V comes from one complex FFT of half the length:
+// z_p = v_{2p} + i v_{2p+1}, Z = FFT_M(z) with M = N / 2, then
+// V_q = E_q + e^{-2 pi i q / N} O_q and V_{q+M} = E_q - e^{-2 pi i q / N} O_q,
+// where E_q = (Z_q + conj Z_{M-q}) / 2 and O_q = (Z_q - conj Z_{M-q}) / (2i) are
+// the transforms of the even and odd samples; V_{N-q} = conj V_q gives
+// (F a)_{N-q} from the same product.  A row's M complex values (64 KiB at
+// N = 16384) sit in LDS, so two rows run on each CU, one per workgroup; the
+// FFT is a Stockham one (a pass of radix 2, 4 or 8 first when lg M is not a
+// multiple of 4, fused into the loads for radix 2, then radix-16 passes with
+// the 16-point DFTs in registers and twiddles from a quarter-wave cosine
+// table).  Each thread owns a fixed chunk of the bucket-sorted coordinate
+// list, kept in registers for the whole launch: it sums its chunk's runs, and
+// each bucket then adds the run sums that fall in it, always in the same
+// order, so every run gives the same bits.
 #include <limits.h>
 
 #include "common.h"
@@ -23,53 +32,151 @@ namespace re {
 namespace {
 
 constexpr uint64_t kXHashStream = 7;
-constexpr int kHrttThreads = 1024;
+constexpr int kRowThreads = 512;
+// a thread's chunk of the list (N / 512 entries) fits the 32-bit run-end mask
+static_assert(kHrttMaxN / kRowThreads <= 32, "list chunk larger than the run-end mask");
+constexpr int kBuildThreads = 1024;
 
-// code[j] = bucket of coordinate j, bit 31 set for a negative sign.
-__global__ void k_hash_code(int64_t N, int64_t k, uint64_t seed, int32_t* __restrict__ code) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  const u64x4 w = philox((uint64_t)j, 0, kXHashStream, 0, seed);
-  const uint64_t b = __umul64hi(w.x, (uint64_t)k);
-  code[j] = (int32_t)((uint32_t)b | ((w.y & 1u) ? 0x80000000u : 0u));
-}
-
-// cnt[b] = coordinates hashed to bucket b (one thread per bucket, all N in order).
-__global__ void k_hash_count(const int32_t* __restrict__ code, int64_t N, int64_t k, int32_t* __restrict__ cnt) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= k) return;
-  int32_t c = 0;
-  for (int64_t j = 0; j < N; ++j) c += (code[j] & 0x7fffffff) == b;
-  cnt[b] = c;
-}
-
-// ptr[0..k] = exclusive prefix sums of cnt (in place: cnt has k + 1 slots).
-__global__ void k_hash_scan(int32_t* __restrict__ ptr, int64_t k) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  int32_t s = 0;
-  for (int64_t b = 0; b < k; ++b) {
-    const int32_t c = ptr[b];
-    ptr[b] = s;
-    s += c;
+// Hash lists and their run structure, one workgroup: the N codes (bucket, sign
+// in bit 31) and the k + 1 counts sit in LDS.  ptr[0..k] = first list position
+// of each bucket (ptr[k] = N); list[ptr[b] ..] = the coordinates of bucket b in
+// increasing order, the sign in bit 31.  The list is cut into chunks of C =
+// max(N / 512, 1) positions; a run is a maximal piece of a chunk inside one
+// bucket, numbered in list order.  ends[t] = bit i set where position tC + i
+// ends a run; rbase[t] = number of the first run of chunk t; runs rlo[b] ..
+// rhi[b] make up bucket b (rlo > rhi for an empty bucket); code16[p] = the list
+// entry at position p in 16 bits (coordinate, sign in bit 15).
+__global__ void __launch_bounds__(kBuildThreads) k_hash_build(int N, int k, uint64_t seed, int32_t* __restrict__ ptr,
+                                                              int32_t* __restrict__ list, uint16_t* __restrict__ code16,
+                                                              uint32_t* __restrict__ ends,
+                                                              int32_t* __restrict__ rbase, int32_t* __restrict__ rlo,
+                                                              int32_t* __restrict__ rhi) {
+  extern __shared__ int32_t sh[];
+  int32_t* code = sh;
+  int32_t* cnt = sh + N;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int j = tid; j < N; j += nth) {
+    const u64x4 w = philox((uint64_t)j, 0, kXHashStream, 0, seed);
+    const uint64_t b = __umul64hi(w.x, (uint64_t)k);
+    code[j] = (int32_t)((uint32_t)b | ((w.y & 1u) ? 0x80000000u : 0u));
   }
-  ptr[k] = s;
-}
-
-// list[ptr[b] ..] = the coordinates of bucket b in increasing order, sign bit kept.
-__global__ void k_hash_fill(const int32_t* __restrict__ code, int64_t N, int64_t k, const int32_t* __restrict__ ptr,
-                            int32_t* __restrict__ list) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= k) return;
-  int32_t p = ptr[b];
-  for (int64_t j = 0; j < N; ++j) {
-    const int32_t c = code[j];
-    if ((c & 0x7fffffff) == b) list[p++] = (int32_t)((uint32_t)j | ((uint32_t)c & 0x80000000u));
+  for (int b = tid; b <= k; b += nth) cnt[b] = 0;
+  __syncthreads();
+  for (int j = tid; j < N; j += nth) atomicAdd(&cnt[code[j] & 0x7fffffff], 1);
+  __syncthreads();
+  if (tid < 64) {  // exclusive prefix sums: a chunk per lane, then a scan across the wave
+    const int ch = (k + 63) / 64;
+    const int lo = min(k, tid * ch), hi = min(k, lo + ch);
+    int s = 0;
+    for (int b = lo; b < hi; ++b) s += cnt[b];
+    int incl = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off, 64);
+      if (tid >= off) incl += y;
+    }
+    int run = incl - s;
+    for (int b = lo; b < hi; ++b) {
+      const int c = cnt[b];
+      cnt[b] = run;
+      run += c;
+    }
+    if (tid == 63) cnt[k] = incl;
+  }
+  __syncthreads();
+  for (int b = tid; b <= k; b += nth) ptr[b] = cnt[b];
+  for (int b = tid; b < k; b += nth) {
+    int p = cnt[b];
+    const int e = cnt[b + 1];
+    if (N >= 4) {
+      for (int j = 0; j < N && p < e; j += 4) {
+        const int4 c4 = *(const int4*)(code + j);
+        const int32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if ((c[q] & 0x7fffffff) == b) {
+            list[p] = (int32_t)((uint32_t)(j + q) | ((uint32_t)c[q] & 0x80000000u));
+            code16[p++] = (uint16_t)((j + q) | (c[q] < 0 ? 0x8000 : 0));
+          }
+      }
+    } else {
+      for (int j = 0; j < N; ++j)
+        if ((code[j] & 0x7fffffff) == b) {
+          list[p] = (int32_t)((uint32_t)j | ((uint32_t)code[j] & 0x80000000u));
+          code16[p++] = (uint16_t)(j | (code[j] < 0 ? 0x8000 : 0));
+        }
+    }
+  }
+  __syncthreads();
+  // run ends: bucket ends and chunk ends, flagged in the (now free) code array
+  const int C = N >= kRowThreads ? N / kRowThreads : 1, nch = N / C;
+  int32_t* flag = code;
+  for (int j = tid; j < N; j += nth) flag[j] = (j % C) == C - 1;
+  __syncthreads();
+  for (int b = tid; b < k; b += nth)
+    if (cnt[b + 1] > cnt[b]) flag[cnt[b + 1] - 1] = 1;
+  __syncthreads();
+  // per chunk: run-end mask and run count; prefix sums of the counts (chunks <= 512)
+  __shared__ int32_t rs[kRowThreads];
+  uint32_t msk = 0;
+  if (tid < nch) {
+    for (int i = 0; i < C; ++i)
+      if (flag[tid * C + i]) msk |= 1u << i;
+    ends[tid] = msk;
+    rs[tid] = __popc(msk);
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int ch = (nch + 63) / 64;
+    const int lo = min(nch, tid * ch), hi = min(nch, lo + ch);
+    int sum = 0;
+    for (int t = lo; t < hi; ++t) sum += rs[t];
+    int incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off, 64);
+      if (tid >= off) incl += y;
+    }
+    int run = incl - sum;
+    for (int t = lo; t < hi; ++t) {
+      const int c = rs[t];
+      rs[t] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  // run number at each run end
+  if (tid < nch) {
+    rbase[tid] = rs[tid];
+    int r = rs[tid];
+    for (int i = 0; i < C; ++i)
+      if ((msk >> i) & 1u) flag[tid * C + i] = r++;
+  }
+  __syncthreads();
+  for (int b = tid; b < k; b += nth) {
+    const int s0 = cnt[b], e = cnt[b + 1];
+    if (e > s0) {
+      const int first = min(s0 - s0 % C + C - 1, e - 1);
+      rlo[b] = flag[first];
+      rhi[b] = flag[e - 1];
+    } else {
+      rlo[b] = 1;
+      rhi[b] = 0;
+    }
   }
 }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// LDS slots with one pad per 16 complex values, so that strided Stockham
+// writes spread over the banks: complex value i at pz(i), real value q (the
+// float view of the same storage) at px(q).
+__device__ __forceinline__ int pz(int i) { return i + (i >> 4); }
+__device__ __forceinline__ int px(int q) { return q + ((q >> 5) << 1); }
 
 constexpr int brev_c(int i, int bits) {
   int r = 0;
@@ -78,6 +185,14 @@ constexpr int brev_c(int i, int bits) {
 }
 
 constexpr int log2_c(int r) { return r <= 1 ? 0 : 1 + log2_c(r >> 1); }
+
+// e^{-2 pi i t / M} for 0 <= t < M as the product of two table entries:
+// tw[u] = e^{-2 pi i u / M} for u < 64 and tw[64 + v] = e^{-2 pi i 64 v / M}
+// for v < M / 64.
+__device__ __forceinline__ float2 twiddle(const float2* tw, int t) {
+  const float2 f = tw[t & 63];
+  return (t >> 6) ? cmul(f, tw[64 + (t >> 6)]) : f;
+}
 
 // R-point DFT (R <= 16) in registers, in place: radix-2 decimation in time
 // over values already in bit-reversed order (t[brev(r)] = input r), twiddles
@@ -95,142 +210,312 @@ __device__ __forceinline__ void dft_reg(float2 (&t)[R]) {
 #pragma unroll
       for (int pos = 0; pos < half; ++pos) {
         const float2 a = t[g + pos], b = cmul(t[g + pos + half], w16[pos * (16 / (2 * half))]);
-        t[g + pos] = make_float2(a.x + b.x, a.y + b.y);
-        t[g + pos + half] = make_float2(a.x - b.x, a.y - b.y);
+        t[g + pos] = cadd(a, b);
+        t[g + pos + half] = csub(a, b);
       }
 }
 
-// One Stockham pass of radix R over the N values in LDS (natural order in,
-// natural order out after the last pass): task j reads X[j + r N/R], turns it
-// by e^{-2 pi i (j mod Ns) r / (Ns R)}, takes the R-point DFT and writes it to
-// X[(j / Ns) Ns R + (j mod Ns) + r Ns].  All reads finish before any write.
-template <int R>
-__device__ __forceinline__ void stockham_pass(float2* X, int N, int Ns, int tid, int nth) {
-  constexpr int TASKS = R == 16 ? 1 : R == 8 ? 2 : 4;  // tasks per thread (N <= 16384, 1024 threads)
-  const int T = N / R;
+// One Stockham pass of radix R over the M = 2^LGM values in LDS (natural
+// order in, natural order out after the last pass), Ns = 2^LGNS: task j reads
+// Z[j + r M/R], turns it by e^{-2 pi i (j mod Ns) r / (Ns R)}, takes the
+// R-point DFT and writes it to Z[(j / Ns) Ns R + (j mod Ns) + r Ns].  All reads
+// finish before any write.
+template <int R, int LGM, int LGNS>
+__device__ __forceinline__ void fft_pass(float2* Z, const float2* tw, int tid) {
+  constexpr int L = log2_c(R), M = 1 << LGM, T = M / R, Ns = 1 << LGNS;
+  constexpr int TASKS = T > kRowThreads ? T / kRowThreads : 1;
   float2 v[TASKS][R];
 #pragma unroll
   for (int q = 0; q < TASKS; ++q) {
-    const int j = tid + q * nth;
-    if (j < T) {
+    const int j = tid + q * kRowThreads;
+    if (T >= kRowThreads || j < T) {
       const int kk = j & (Ns - 1);
-      constexpr int L = log2_c(R);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][brev_c(r, L)] = X[j + r * T];  // bit-reversed for dft_reg
-      if (Ns > 1) {
-        const float step = 2.0f * (float)kk / (float)(Ns * R);  // exact: powers of two
+      for (int r = 0; r < R; ++r) v[q][brev_c(r, L)] = Z[pz(j + r * T)];
+      if constexpr (Ns > 1) {
+        const int t1 = kk << (LGM - LGNS - L);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          float sw, cw;
-          sincospif(step * (float)r, &sw, &cw);
-          v[q][brev_c(r, L)] = cmul(v[q][brev_c(r, L)], make_float2(cw, -sw));
-        }
+        for (int r = 1; r < R; ++r) v[q][brev_c(r, L)] = cmul(v[q][brev_c(r, L)], twiddle(tw, t1 * r));
       }
     }
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < TASKS; ++q) {
-    const int j = tid + q * nth;
-    if (j < T) {
+    const int j = tid + q * kRowThreads;
+    if (T >= kRowThreads || j < T) {
       dft_reg<R>(v[q]);
       const int kk = j & (Ns - 1);
       const int base = (j - kk) * R + kk;
 #pragma unroll
-      for (int r = 0; r < R; ++r) X[base + r * Ns] = v[q][r];
+      for (int r = 0; r < R; ++r) Z[pz(base + r * Ns)] = v[q][r];
     }
   }
   __syncthreads();
 }
 
-// Twiddles come from sincospif (FP32, within 2 ulp; the arguments are exact),
-// so the FFT reads no tables.
-__global__ void __launch_bounds__(kHrttThreads) k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n,
-                                                            int64_t lda, int lgN, const uint32_t* __restrict__ bits,
-                                                            const int32_t* __restrict__ ptr,
-                                                            const int32_t* __restrict__ list, int64_t k, float sk,
-                                                            float* __restrict__ B, int64_t ldb) {
-  extern __shared__ float2 X[];  // N complex values
-  constexpr int kPer = kHrttMaxN / kHrttThreads;  // entries of a row per thread at most
-  const int N = 1 << lgN, half_n = N >> 1;
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const float nrm = sqrtf(2.0f / (float)N), nrm0 = sqrtf(1.0f / (float)N);
-  const float inv_n = 1.0f / (float)N;
+// The radix-16 passes from Ns = 2^LGNS up to M.
+template <int LGM, int LGNS>
+__device__ __forceinline__ void fft_rest(float2* Z, const float2* tw, int tid) {
+  if constexpr (LGNS < LGM) {
+    fft_pass<16, LGM, LGNS>(Z, tw, tid);
+    fft_rest<LGM, LGNS + 4>(Z, tw, tid);
+  }
+}
+
+// Entries 4p .. 4p+3 of a row, zero past n, times the signs in the nibble sg.
+__device__ __forceinline__ float4 load_quad(const float* __restrict__ a, int p, int64_t n, uint32_t sg) {
+  const int64_t j = 4 * (int64_t)p;
+  float4 x;
+  if (j + 3 < n) {
+    x = *(const float4*)(a + j);
+  } else {
+    x.x = j < n ? a[j] : 0.0f;
+    x.y = j + 1 < n ? a[j + 1] : 0.0f;
+    x.z = j + 2 < n ? a[j + 2] : 0.0f;
+    x.w = 0.0f;
+  }
+  if (sg & 1u) x.x = -x.x;
+  if (sg & 2u) x.y = -x.y;
+  if (sg & 4u) x.z = -x.z;
+  if (sg & 8u) x.w = -x.w;
+  return x;
+}
+
+// N = 2^LGN: one workgroup per row at a time (two per CU); VEC: rows are
+// 16-byte aligned and the loads are float4.  LDS: M + M/16 complex slots, the
+// twiddle table (64 + max(M / 64, 1) complex values), then one float per run.
+template <bool VEC, int LGN>
+__global__ void __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const uint32_t* __restrict__ bits,
+            const uint16_t* __restrict__ code16, const uint32_t* __restrict__ ends_g, const int32_t* __restrict__ rbase_g,
+            const int32_t* __restrict__ rlo_g, const int32_t* __restrict__ rhi_g, int k, float sk,
+            float* __restrict__ B, int64_t ldb) {
+  constexpr int N = 1 << LGN, LGM = LGN - 1, M = N >> 1;
+  constexpr int C = N >= kRowThreads ? N / kRowThreads : 1;                 // list entries per thread
+  constexpr int QUADS = (N / 4 + kRowThreads - 1) / kRowThreads;           // float4 loads per thread
+  constexpr bool FUSED = VEC && (LGM & 3) == 1 && M >= 4;                  // radix-2 pass in the loads
+  constexpr int FPAIRS = (M / 4 + kRowThreads - 1) / kRowThreads;          // fused load pairs per thread
+  constexpr int SPAIRS = M >= 2 ? (M / 2 + kRowThreads - 1) / kRowThreads : 1;  // split pairs per thread
+  constexpr int TWN = 64 + (M / 64 > 1 ? M / 64 : 1);
+  extern __shared__ float2 Z[];
+  float* Xf = (float*)Z;
+  float2* tw = Z + (M + (M >> 4));
+  float* P = (float*)(tw + TWN);
+  const int tid0 = threadIdx.x;
+  const int tid = tid0;
+
+  // set-up: twiddle table, this thread's chunk of the list and its runs, the signs of the loads
+  for (int u = tid; u < TWN; u += kRowThreads) {
+    const int t = u < 64 ? u : 64 * (u - 64);
+    double sv, cv;
+    sincospi(2.0 * (double)t / (double)M, &sv, &cv);
+    tw[u] = make_float2((float)cv, (float)-sv);
+  }
+  const bool lister = tid * C < N;
+  uint32_t ends = 0;
+  int32_t rb = 0;
+  if (lister) {
+    ends = ends_g[tid];
+    rb = rbase_g[tid];
+  }
+  uint32_t sgn = 0;
+  if constexpr (FUSED) {
+#pragma unroll
+    for (int i = 0; i < FPAIRS; ++i) {
+      const int p = tid + i * kRowThreads;
+      if ((M / 4) % kRowThreads == 0 || p < M / 4) {
+        const int p2 = M / 2 - 1 - p;
+        sgn |= ((bits[p >> 3] >> ((p & 7) * 4)) & 15u) << (8 * i);
+        sgn |= ((bits[p2 >> 3] >> ((p2 & 7) * 4)) & 15u) << (8 * i + 4);
+      }
+    }
+  } else if constexpr (VEC && N >= 4) {
+#pragma unroll
+    for (int i = 0; i < QUADS; ++i) {
+      const int p = tid + i * kRowThreads;
+      if ((N / 4) % kRowThreads == 0 || p < N / 4) sgn |= ((bits[p >> 3] >> ((p & 7) * 4)) & 15u) << (4 * i);
+    }
+  }
+  const bool one_bucket = k <= kRowThreads;
+  int32_t lo0 = 1, hi0 = 0;
+  if (one_bucket && tid < k) {
+    lo0 = rlo_g[tid];
+    hi0 = rhi_g[tid];
+  }
+  const float c = sqrtf(2.0f / (float)N), c0 = sqrtf(1.0f / (float)N);
+  __syncthreads();
+
   for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
-    // signed entries in Makhoul's order, natural positions (four loads in flight)
+    // the thread index, opaque to the optimiser here, so that the row's LDS
+    // addresses are recomputed per row instead of held (and spilled) across rows
+    int tid = tid0;
+    asm volatile("" : "+v"(tid));
     const float* __restrict__ a = A + row * lda;
+    // 1. z (or its first radix-2 pass) into LDS
+    if constexpr (FUSED) {
+      float4 x[2 * FPAIRS];
 #pragma unroll
-    for (int q0 = 0; q0 < kPer; q0 += 4) {
-      float x[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int p = tid + (q0 + q) * nth;
-        x[q] = 0.0f;
-        if (p < N) {
-          const int j = p < half_n ? 2 * p : 2 * (N - 1 - p) + 1;
-          if (j < n) x[q] = a[j];
-          if ((bits[j >> 5] >> (j & 31)) & 1u) x[q] = -x[q];
+      for (int i = 0; i < FPAIRS; ++i) {
+        const int p = tid + i * kRowThreads;
+        if ((M / 4) % kRowThreads == 0 || p < M / 4) {
+          x[2 * i] = load_quad(a, p, n, sgn >> (8 * i));
+          x[2 * i + 1] = load_quad(a, M / 2 - 1 - p, n, sgn >> (8 * i + 4));
         }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int p = tid + (q0 + q) * nth;
-        if (p < N) X[p] = make_float2(x[q], 0.0f);
+      for (int i = 0; i < FPAIRS; ++i) {
+        const int p = tid + i * kRowThreads;
+        if ((M / 4) % kRowThreads == 0 || p < M / 4) {
+          const int p2 = M / 2 - 1 - p;
+          const float4 u = x[2 * i], w = x[2 * i + 1];
+          const float2 zp = make_float2(u.x, u.z), zp_hi = make_float2(w.w, w.y);   // z_p, z_{p + M/2}
+          const float2 zq = make_float2(w.x, w.z), zq_hi = make_float2(u.w, u.y);   // z_{p2}, z_{p2 + M/2}
+          Z[pz(2 * p)] = cadd(zp, zp_hi);
+          Z[pz(2 * p + 1)] = csub(zp, zp_hi);
+          Z[pz(2 * p2)] = cadd(zq, zq_hi);
+          Z[pz(2 * p2 + 1)] = csub(zq, zq_hi);
+        }
+      }
+    } else if constexpr (VEC && N >= 4) {
+      float4 x[QUADS];
+#pragma unroll
+      for (int i = 0; i < QUADS; ++i) {
+        const int p = tid + i * kRowThreads;
+        if ((N / 4) % kRowThreads == 0 || p < N / 4) x[i] = load_quad(a, p, n, sgn >> (4 * i));
+      }
+#pragma unroll
+      for (int i = 0; i < QUADS; ++i) {
+        const int p = tid + i * kRowThreads;
+        if ((N / 4) % kRowThreads == 0 || p < N / 4) {
+          Z[pz(p)] = make_float2(x[i].x, x[i].z);
+          Z[pz(M - 1 - p)] = make_float2(x[i].w, x[i].y);
+        }
+      }
+    } else {
+      for (int t = tid; t < N; t += kRowThreads) {
+        const int64_t j = t < M ? 2 * (int64_t)t : 2 * (int64_t)(N - 1 - t) + 1;
+        float x = j < n ? a[j] : 0.0f;
+        if ((bits[j >> 5] >> (j & 31)) & 1u) x = -x;
+        Xf[px(t)] = x;
       }
     }
     __syncthreads();
-    // FFT_N by Stockham passes of radix 16 while 16 divides what is left, then 8, 4 or 2
-    int Ns = 1, rem = N;
-    while (rem > 1) {
-      if (rem >= 16) {
-        stockham_pass<16>(X, N, Ns, tid, nth);
-        Ns *= 16;
-        rem >>= 4;
-      } else if (rem == 8) {
-        stockham_pass<8>(X, N, Ns, tid, nth);
-        Ns *= 8;
-        rem = 1;
-      } else if (rem == 4) {
-        stockham_pass<4>(X, N, Ns, tid, nth);
-        Ns *= 4;
-        rem = 1;
+    // 2. Z = FFT_M(z)
+    if constexpr (FUSED) {
+      fft_rest<LGM, 1>(Z, tw, tid);
+    } else if constexpr ((LGM & 3) == 1) {
+      fft_pass<2, LGM, 0>(Z, tw, tid);
+      fft_rest<LGM, 1>(Z, tw, tid);
+    } else if constexpr ((LGM & 3) == 2) {
+      fft_pass<4, LGM, 0>(Z, tw, tid);
+      fft_rest<LGM, 2>(Z, tw, tid);
+    } else if constexpr ((LGM & 3) == 3) {
+      fft_pass<8, LGM, 0>(Z, tw, tid);
+      fft_rest<LGM, 3>(Z, tw, tid);
+    } else {
+      fft_rest<LGM, 0>(Z, tw, tid);
+    }
+    // 3. DCT-II values from Z: pairs (q, M - q) give (F a) at q, N - q, M + q and M - q
+    float out[SPAIRS][4];
+    float sp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < SPAIRS; ++i) {
+      const int q = tid + i * kRowThreads;
+      if (q >= 1 && ((M / 2) % kRowThreads == 0 || q < M / 2)) {
+        const float2 zq = Z[pz(q)], zr = Z[pz(M - q)];
+        const float2 E = make_float2(zq.x + zr.x, zq.y - zr.y);   // 2 E_q
+        const float2 O = make_float2(zq.y + zr.y, zr.x - zq.x);   // 2 O_q
+        float sw, cw2, s1, c1;
+        sincospif(2.0f * (float)q / (float)N, &sw, &cw2);
+        sincospif(0.5f * (float)q / (float)N, &s1, &c1);
+        const float2 P = cmul(make_float2(cw2, -sw), O);
+        const float2 t1 = make_float2(c1, -s1);
+        const float2 U = cmul(t1, cadd(E, P));
+        // e^{-i pi / 4} t1 for the upper half
+        const float h = 0.707106781186547524f;
+        const float2 t2 = make_float2(h * (c1 - s1), -h * (c1 + s1));
+        const float2 U2 = cmul(t2, csub(E, P));
+        const float hc = 0.5f * c;
+        out[i][0] = hc * U.x;     // q
+        out[i][1] = -hc * U.y;    // N - q
+        out[i][2] = hc * U2.x;    // M + q
+        out[i][3] = -hc * U2.y;   // M - q
+      }
+    }
+    if (tid == 0) {
+      const float2 z0 = Z[pz(0)];
+      sp[0] = c0 * (z0.x + z0.y);                          // 0
+      sp[1] = c * 0.707106781186547524f * (z0.x - z0.y);   // M
+      if constexpr (M >= 2) {
+        const float2 zh = Z[pz(M / 2)];
+        float s8, c8;
+        sincospif(0.125f, &s8, &c8);
+        const float2 Uh = cmul(make_float2(c8, -s8), make_float2(zh.x, -zh.y));
+        sp[2] = c * Uh.x;    // M / 2
+        sp[3] = -c * Uh.y;   // 3M / 2
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SPAIRS; ++i) {
+      const int q = tid + i * kRowThreads;
+      if (q >= 1 && ((M / 2) % kRowThreads == 0 || q < M / 2)) {
+        Xf[px(q)] = out[i][0];
+        Xf[px(N - q)] = out[i][1];
+        Xf[px(M + q)] = out[i][2];
+        Xf[px(M - q)] = out[i][3];
+      }
+    }
+    if (tid == 0) {
+      Xf[px(0)] = sp[0];
+      Xf[px(M)] = sp[1];
+      if constexpr (M >= 2) {
+        Xf[px(M / 2)] = sp[2];
+        Xf[px(3 * M / 2)] = sp[3];
+      }
+    }
+    __syncthreads();
+    // 4. CountSketch: the sums of this thread's runs, each stored by its number
+    if (lister) {
+      uint32_t cw[(C + 1) / 2];  // the chunk's 16-bit list entries, two a word
+      if constexpr (C % 8 == 0) {
+#pragma unroll
+        for (int i = 0; i < C / 8; ++i) {
+          const uint4 w = *(const uint4*)(code16 + tid * C + 8 * i);
+          cw[4 * i] = w.x;
+          cw[4 * i + 1] = w.y;
+          cw[4 * i + 2] = w.z;
+          cw[4 * i + 3] = w.w;
+        }
       } else {
-        stockham_pass<2>(X, N, Ns, tid, nth);
-        Ns *= 2;
-        rem = 1;
-      }
-    }
-    // DCT-II value q = c_q Re(e^{-i pi q / (2N)} V_q), kept in the real slot of X[q]
-    for (int q = tid; q < N; q += nth) {
-      float se, ce;
-      sincospif(0.5f * (float)q * inv_n, &se, &ce);
-      const float2 c = X[q];
-      X[q].x = (c.x * ce + c.y * se) * (q ? nrm : nrm0);
-    }
-    __syncthreads();
-    // CountSketch: one thread per bucket over its fixed coordinate list
-    for (int64_t b = tid; b < k; b += nth) {
-      float acc = 0.0f;
-      const int32_t p1 = ptr[b + 1];
-      int32_t t = ptr[b];
-      for (; t + 3 < p1; t += 4) {  // four list entries in flight, same summation order
-        int32_t c[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) c[q] = list[t + q];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float x = X[c[q] & 0x7fffffff].x;
-          acc += c[q] < 0 ? -x : x;
+        for (int i = 0; i < C; ++i) {
+          const uint32_t e = code16[tid * C + i];
+          cw[i >> 1] = (i & 1) ? (cw[i >> 1] | (e << 16)) : e;
         }
       }
-      for (; t < p1; ++t) {
-        const int32_t c = list[t];
-        const float x = X[c & 0x7fffffff].x;
-        acc += c < 0 ? -x : x;
+      float acc = 0.0f;
+      int r = rb;
+#pragma unroll
+      for (int i = 0; i < C; ++i) {
+        const uint32_t e = (cw[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+        const float x = Xf[px((int)(e & 0x3fffu))];
+        acc += (e & 0x8000u) ? -x : x;
+        if ((ends >> i) & 1u) {
+          P[r++] = acc;
+          acc = 0.0f;
+        }
       }
-      B[row * ldb + b] = acc * sk;
     }
     __syncthreads();
+    // 5. each bucket adds its runs in order (the next row writes Z and X, not the run sums)
+    for (int b = tid; b < k; b += kRowThreads) {
+      const int32_t lo = one_bucket ? lo0 : rlo_g[b], hi = one_bucket ? hi0 : rhi_g[b];
+      float sum = 0.0f;
+      for (int r = lo; r <= hi; ++r) sum += P[r];
+      B[row * ldb + b] = sum * sk;
+    }
   }
 }
 
@@ -241,37 +526,92 @@ int64_t hrtt_npad(int64_t n) {
   return p < 2 ? 2 : p;
 }
 
-size_t hrtt_scratch_bytes(int64_t n, int64_t k) {
-  const int64_t N = hrtt_npad(n);
-  return (size_t)N * 4 + (size_t)(k + 1) * 4 + (size_t)N * 4 + 3 * 256;
+// Scratch of one call, each piece on a 256-byte boundary: ptr (k + 1), list (N),
+// code16 (N, 16-bit), ends and rbase (512 each), rlo and rhi (k each).
+namespace {
+struct HashScratch {
+  int32_t *ptr, *list, *rbase, *rlo, *rhi;
+  uint16_t* code16;
+  uint32_t* ends;
+  size_t bytes;
+};
+HashScratch carve_hash(void* base, int64_t N, int64_t k) {
+  HashScratch h{};
+  size_t off = 0;
+  auto take = [&](int64_t count) {
+    char* p = (char*)base + off;
+    off += (size_t)((count * 4 + 255) / 256) * 256;
+    return p;
+  };
+  h.ptr = (int32_t*)take(k + 1);
+  h.list = (int32_t*)take(N);
+  h.code16 = (uint16_t*)take((N + 1) / 2);
+  h.ends = (uint32_t*)take(kRowThreads);
+  h.rbase = (int32_t*)take(kRowThreads);
+  h.rlo = (int32_t*)take(k);
+  h.rhi = (int32_t*)take(k);
+  h.bytes = off;
+  return h;
+}
+}  // namespace
+
+size_t hrtt_scratch_bytes(int64_t n, int64_t k) { return carve_hash(nullptr, hrtt_npad(n), k).bytes; }
+
+template <bool VEC>
+static const void* rows_kernel(int lgN) {
+  switch (lgN) {
+    case 1: return (const void*)k_hrtt_rows<VEC, 1>;
+    case 2: return (const void*)k_hrtt_rows<VEC, 2>;
+    case 3: return (const void*)k_hrtt_rows<VEC, 3>;
+    case 4: return (const void*)k_hrtt_rows<VEC, 4>;
+    case 5: return (const void*)k_hrtt_rows<VEC, 5>;
+    case 6: return (const void*)k_hrtt_rows<VEC, 6>;
+    case 7: return (const void*)k_hrtt_rows<VEC, 7>;
+    case 8: return (const void*)k_hrtt_rows<VEC, 8>;
+    case 9: return (const void*)k_hrtt_rows<VEC, 9>;
+    case 10: return (const void*)k_hrtt_rows<VEC, 10>;
+    case 11: return (const void*)k_hrtt_rows<VEC, 11>;
+    case 12: return (const void*)k_hrtt_rows<VEC, 12>;
+    case 13: return (const void*)k_hrtt_rows<VEC, 13>;
+    case 14: return (const void*)k_hrtt_rows<VEC, 14>;
+    default: return nullptr;
+  }
 }
 
 re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t lda, int64_t k, uint64_t seed,
                            const uint32_t* sign_bits, void* scratch, float* B, int64_t ldb) {
   const int64_t N = hrtt_npad(n);
   if (N > kHrttMaxN || k < 1 || k > N) return RE_ERR_UNSUPPORTED;
-  char* base = (char*)scratch;
-  int32_t* code = (int32_t*)base;
-  int32_t* ptr = (int32_t*)(base + ((N * 4 + 255) / 256) * 256);
-  int32_t* list = (int32_t*)((char*)ptr + (((k + 1) * 4 + 255) / 256) * 256);
-  const unsigned gN = (unsigned)cdiv(N, 256), gk = (unsigned)cdiv(k, 256);
-  hipLaunchKernelGGL(k_hash_code, dim3(gN), dim3(256), 0, s, N, k, seed, code);
-  hipLaunchKernelGGL(k_hash_count, dim3(gk), dim3(256), 0, s, (const int32_t*)code, N, k, ptr);
-  hipLaunchKernelGGL(k_hash_scan, dim3(1), dim3(64), 0, s, ptr, k);
-  hipLaunchKernelGGL(k_hash_fill, dim3(gk), dim3(256), 0, s, (const int32_t*)code, N, k, (const int32_t*)ptr, list);
+  const HashScratch h = carve_hash(scratch, N, k);
+  const size_t lds_build = (size_t)(N + k + 1) * 4;
+  if (lds_build > 65536)
+    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_hash_build, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds_build));
+  hipLaunchKernelGGL(k_hash_build, dim3(1), dim3(kBuildThreads), lds_build, s, (int)N, (int)k, seed, h.ptr, h.list,
+                     h.code16, h.ends, h.rbase, h.rlo, h.rhi);
   RE_TRY_HIP(hipGetLastError());
   int lgN = 0;
   while ((int64_t(1) << lgN) < N) ++lgN;
-  const size_t lds = (size_t)N * sizeof(float2);
-  if (lds > 65536)
-    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_hrtt_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  int per_cu = (int)((160 * 1024) / (lds + 1024));
+  const int64_t M = N / 2, twn = 64 + (M / 64 > 1 ? M / 64 : 1);
+  const size_t lds = (size_t)(M + (M >> 4) + twn) * sizeof(float2) + (size_t)(k + kRowThreads) * sizeof(float);
+  const bool vec = ((uintptr_t)A & 15) == 0 && (lda & 3) == 0;
+  const void* fn = vec ? rows_kernel<true>(lgN) : rows_kernel<false>(lgN);
+  if (fn == nullptr) return RE_ERR_UNSUPPORTED;
+  if (lds > 65536) RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int per_cu = (int)((160 * 1024) / lds);
   if (per_cu < 1) per_cu = 1;
-  if (per_cu > 2) per_cu = 2;  // 1024 threads per workgroup: two fill a CU
+  if (per_cu > 2) per_cu = 2;  // 512 threads of at most 128 VGPRs: two workgroups per CU
   int64_t grid = 256 * (int64_t)per_cu;
   if (grid > m) grid = m;
-  hipLaunchKernelGGL(k_hrtt_rows, dim3((unsigned)grid), dim3(kHrttThreads), lds, s, A, m, n, lda, lgN, sign_bits,
-                     (const int32_t*)ptr, (const int32_t*)list, k, sqrtf((float)k), B, ldb);
+  const uint16_t* ccode = h.code16;
+  const uint32_t* cends = h.ends;
+  const int32_t *crbase = h.rbase, *crlo = h.rlo, *crhi = h.rhi;
+  int ki = (int)k;
+  float sk = sqrtf((float)k);
+  void* args[] = {(void*)&A,     (void*)&m,     (void*)&n,    (void*)&lda,  (void*)&sign_bits,
+                  (void*)&ccode, (void*)&cends, (void*)&crbase, (void*)&crlo, (void*)&crhi,
+                  (void*)&ki,    (void*)&sk,    (void*)&B,    (void*)&ldb};
+  RE_TRY_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kRowThreads), args, lds, s));
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
 }
