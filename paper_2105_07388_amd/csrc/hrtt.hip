@@ -37,100 +37,75 @@ constexpr int kRowThreads = 512;
 static_assert(kHrttMaxN / kRowThreads <= 32, "list chunk larger than the run-end mask");
 constexpr int kBuildThreads = 1024;
 
-// Hash lists and their run structure, one workgroup: the N codes (bucket, sign
-// in bit 31) and the k + 1 counts sit in LDS.  ptr[0..k] = first list position
-// of each bucket (ptr[k] = N); list[ptr[b] ..] = the coordinates of bucket b in
-// increasing order, the sign in bit 31.  The list is cut into chunks of C =
+// Hash lists and their run structure, one workgroup.  Each coordinate j gets
+// the key (bucket << 15) | (j << 1) | sign; a bitonic sort of the N keys in
+// LDS puts them in (bucket, j) order.  ptr[0..k] = first list position of each
+// bucket (ptr[k] = N); list[ptr[b] ..] = the coordinates of bucket b in
+// increasing order, the sign in bit 31; code16[p] = the same entry in 16 bits
+// (coordinate, sign in bit 15).  The list is cut into chunks of C =
 // max(N / 512, 1) positions; a run is a maximal piece of a chunk inside one
 // bucket, numbered in list order.  ends[t] = bit i set where position tC + i
 // ends a run; rbase[t] = number of the first run of chunk t; runs rlo[b] ..
-// rhi[b] make up bucket b (rlo > rhi for an empty bucket); code16[p] = the list
-// entry at position p in 16 bits (coordinate, sign in bit 15).
+// rhi[b] make up bucket b (rlo > rhi for an empty bucket).
 __global__ void __launch_bounds__(kBuildThreads) k_hash_build(int N, int k, uint64_t seed, int32_t* __restrict__ ptr,
                                                               int32_t* __restrict__ list, uint16_t* __restrict__ code16,
                                                               uint32_t* __restrict__ ends,
                                                               int32_t* __restrict__ rbase, int32_t* __restrict__ rlo,
                                                               int32_t* __restrict__ rhi) {
-  extern __shared__ int32_t sh[];
-  int32_t* code = sh;
-  int32_t* cnt = sh + N;
+  extern __shared__ uint32_t key[];  // N keys, then k + 1 bucket starts
+  int32_t* sptr = (int32_t*)(key + N);
+  __shared__ uint32_t smask[kRowThreads];
+  __shared__ int32_t sbase[kRowThreads];
   const int tid = threadIdx.x, nth = blockDim.x;
   for (int j = tid; j < N; j += nth) {
     const u64x4 w = philox((uint64_t)j, 0, kXHashStream, 0, seed);
-    const uint64_t b = __umul64hi(w.x, (uint64_t)k);
-    code[j] = (int32_t)((uint32_t)b | ((w.y & 1u) ? 0x80000000u : 0u));
-  }
-  for (int b = tid; b <= k; b += nth) cnt[b] = 0;
-  __syncthreads();
-  for (int j = tid; j < N; j += nth) atomicAdd(&cnt[code[j] & 0x7fffffff], 1);
-  __syncthreads();
-  if (tid < 64) {  // exclusive prefix sums: a chunk per lane, then a scan across the wave
-    const int ch = (k + 63) / 64;
-    const int lo = min(k, tid * ch), hi = min(k, lo + ch);
-    int s = 0;
-    for (int b = lo; b < hi; ++b) s += cnt[b];
-    int incl = s;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int y = __shfl_up(incl, off, 64);
-      if (tid >= off) incl += y;
-    }
-    int run = incl - s;
-    for (int b = lo; b < hi; ++b) {
-      const int c = cnt[b];
-      cnt[b] = run;
-      run += c;
-    }
-    if (tid == 63) cnt[k] = incl;
+    const uint32_t b = (uint32_t)__umul64hi(w.x, (uint64_t)k);
+    key[j] = (b << 15) | ((uint32_t)j << 1) | (uint32_t)(w.y & 1u);
   }
   __syncthreads();
-  for (int b = tid; b <= k; b += nth) ptr[b] = cnt[b];
-  for (int b = tid; b < k; b += nth) {
-    int p = cnt[b];
-    const int e = cnt[b + 1];
-    if (N >= 4) {
-      for (int j = 0; j < N && p < e; j += 4) {
-        const int4 c4 = *(const int4*)(code + j);
-        const int32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if ((c[q] & 0x7fffffff) == b) {
-            list[p] = (int32_t)((uint32_t)(j + q) | ((uint32_t)c[q] & 0x80000000u));
-            code16[p++] = (uint16_t)((j + q) | (c[q] < 0 ? 0x8000 : 0));
-          }
-      }
-    } else {
-      for (int j = 0; j < N; ++j)
-        if ((code[j] & 0x7fffffff) == b) {
-          list[p] = (int32_t)((uint32_t)j | ((uint32_t)code[j] & 0x80000000u));
-          code16[p++] = (uint16_t)(j | (code[j] < 0 ? 0x8000 : 0));
+  for (int size = 2; size <= N; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < N / 2; i += nth) {
+        const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1)), hi = lo + stride;
+        const uint32_t a = key[lo], c = key[hi];
+        if ((a > c) == ((lo & size) == 0)) {
+          key[lo] = c;
+          key[hi] = a;
         }
+      }
+      __syncthreads();
     }
+  // list, bucket starts (every bucket from the previous key's up to this one starts here)
+  for (int p = tid; p < N; p += nth) {
+    const uint32_t kp = key[p];
+    const int b = (int)(kp >> 15), j = (int)((kp >> 1) & 0x3fffu), neg = (int)(kp & 1u);
+    list[p] = (int32_t)((uint32_t)j | (neg ? 0x80000000u : 0u));
+    code16[p] = (uint16_t)(j | (neg ? 0x8000 : 0));
+    const int bprev = p ? (int)(key[p - 1] >> 15) : -1;
+    for (int bb = bprev + 1; bb <= b; ++bb) sptr[bb] = p;
+    if (p == N - 1)
+      for (int bb = b + 1; bb <= k; ++bb) sptr[bb] = N;
   }
   __syncthreads();
-  // run ends: bucket ends and chunk ends, flagged in the (now free) code array
+  for (int b = tid; b <= k; b += nth) ptr[b] = sptr[b];
+  // runs: per chunk the run-end mask, then prefix sums of the run counts (chunks <= 512)
   const int C = N >= kRowThreads ? N / kRowThreads : 1, nch = N / C;
-  int32_t* flag = code;
-  for (int j = tid; j < N; j += nth) flag[j] = (j % C) == C - 1;
-  __syncthreads();
-  for (int b = tid; b < k; b += nth)
-    if (cnt[b + 1] > cnt[b]) flag[cnt[b + 1] - 1] = 1;
-  __syncthreads();
-  // per chunk: run-end mask and run count; prefix sums of the counts (chunks <= 512)
-  __shared__ int32_t rs[kRowThreads];
-  uint32_t msk = 0;
   if (tid < nch) {
-    for (int i = 0; i < C; ++i)
-      if (flag[tid * C + i]) msk |= 1u << i;
+    uint32_t msk = 0;
+    for (int i = 0; i < C; ++i) {
+      const int p = tid * C + i;
+      if (i == C - 1 || (key[p + 1] >> 15) != (key[p] >> 15)) msk |= 1u << i;
+    }
+    smask[tid] = msk;
     ends[tid] = msk;
-    rs[tid] = __popc(msk);
+    sbase[tid] = __popc(msk);
   }
   __syncthreads();
   if (tid < 64) {
     const int ch = (nch + 63) / 64;
     const int lo = min(nch, tid * ch), hi = min(nch, lo + ch);
     int sum = 0;
-    for (int t = lo; t < hi; ++t) sum += rs[t];
+    for (int t = lo; t < hi; ++t) sum += sbase[t];
     int incl = sum;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -139,26 +114,21 @@ __global__ void __launch_bounds__(kBuildThreads) k_hash_build(int N, int k, uint
     }
     int run = incl - sum;
     for (int t = lo; t < hi; ++t) {
-      const int c = rs[t];
-      rs[t] = run;
+      const int c = sbase[t];
+      sbase[t] = run;
       run += c;
     }
   }
   __syncthreads();
-  // run number at each run end
-  if (tid < nch) {
-    rbase[tid] = rs[tid];
-    int r = rs[tid];
-    for (int i = 0; i < C; ++i)
-      if ((msk >> i) & 1u) flag[tid * C + i] = r++;
-  }
-  __syncthreads();
+  if (tid < nch) rbase[tid] = sbase[tid];
+  // a bucket's runs: from the first run end at or after its start to its last position
   for (int b = tid; b < k; b += nth) {
-    const int s0 = cnt[b], e = cnt[b + 1];
+    const int s0 = sptr[b], e = sptr[b + 1];
     if (e > s0) {
       const int first = min(s0 - s0 % C + C - 1, e - 1);
-      rlo[b] = flag[first];
-      rhi[b] = flag[e - 1];
+      const int t0 = first / C, t1 = (e - 1) / C;
+      rlo[b] = sbase[t0] + __popc(smask[t0] & ((1u << (first % C)) - 1u));
+      rhi[b] = sbase[t1] + __popc(smask[t1] & ((1u << ((e - 1) % C)) - 1u));
     } else {
       rlo[b] = 1;
       rhi[b] = 0;
@@ -194,22 +164,35 @@ __device__ __forceinline__ float2 twiddle(const float2* tw, int t) {
   return (t >> 6) ? cmul(f, tw[64 + (t >> 6)]) : f;
 }
 
+// a e^{-2 pi i t / 16}; t is a constant once the DFT's loops are unrolled, so
+// the products by 1 and -i cost nothing and those by e^{-i pi / 4} and
+// e^{-3 i pi / 4} two multiplies.
+__device__ __forceinline__ float2 mul_w16(float2 a, int t) {
+  constexpr float c1 = 0.923879532511286756f, s1 = 0.382683432365089772f, c2 = 0.707106781186547524f;
+  switch (t) {
+    case 0: return a;
+    case 1: return cmul(a, make_float2(c1, -s1));
+    case 2: return make_float2(c2 * (a.x + a.y), c2 * (a.y - a.x));
+    case 3: return cmul(a, make_float2(s1, -c1));
+    case 4: return make_float2(a.y, -a.x);
+    case 5: return cmul(a, make_float2(-s1, -c1));
+    case 6: return make_float2(c2 * (a.y - a.x), -c2 * (a.x + a.y));
+    default: return cmul(a, make_float2(-c1, -s1));
+  }
+}
+
 // R-point DFT (R <= 16) in registers, in place: radix-2 decimation in time
-// over values already in bit-reversed order (t[brev(r)] = input r), twiddles
-// e^{-2 pi i t / 16} written out (cos and sin of multiples of pi / 8); the
+// over values already in bit-reversed order (t[brev(r)] = input r); the
 // output is in natural order.
 template <int R>
 __device__ __forceinline__ void dft_reg(float2 (&t)[R]) {
-  constexpr float c1 = 0.923879532511286756f, s1 = 0.382683432365089772f, c2 = 0.707106781186547524f;
-  const float2 w16[8] = {make_float2(1.0f, 0.0f), make_float2(c1, -s1), make_float2(c2, -c2), make_float2(s1, -c1),
-                         make_float2(0.0f, -1.0f), make_float2(-s1, -c1), make_float2(-c2, -c2), make_float2(-c1, -s1)};
 #pragma unroll
   for (int half = 1; half < R; half *= 2)
 #pragma unroll
     for (int g = 0; g < R; g += 2 * half)
 #pragma unroll
       for (int pos = 0; pos < half; ++pos) {
-        const float2 a = t[g + pos], b = cmul(t[g + pos + half], w16[pos * (16 / (2 * half))]);
+        const float2 a = t[g + pos], b = mul_w16(t[g + pos + half], pos * (16 / (2 * half)));
         t[g + pos] = cadd(a, b);
         t[g + pos + half] = csub(a, b);
       }
@@ -263,6 +246,13 @@ __device__ __forceinline__ void fft_rest(float2* Z, const float2* tw, int tid) {
   }
 }
 
+// e^{-2 pi i t / (4N)} for 0 <= t < N from ts[u] = e^{-2 pi i u / (4N)}, u < 256,
+// and ts[256 + v] = e^{-2 pi i 256 v / (4N)}.
+__device__ __forceinline__ float2 split_twiddle(const float2* ts, int t) {
+  const float2 f = ts[t & 255];
+  return (t >> 8) ? cmul(f, ts[256 + (t >> 8)]) : f;
+}
+
 // Entries 4p .. 4p+3 of a row, zero past n, times the signs in the nibble sg.
 __device__ __forceinline__ float4 load_quad(const float* __restrict__ a, int p, int64_t n, uint32_t sg) {
   const int64_t j = 4 * (int64_t)p;
@@ -284,7 +274,8 @@ __device__ __forceinline__ float4 load_quad(const float* __restrict__ a, int p, 
 
 // N = 2^LGN: one workgroup per row at a time (two per CU); VEC: rows are
 // 16-byte aligned and the loads are float4.  LDS: M + M/16 complex slots, the
-// twiddle table (64 + max(M / 64, 1) complex values), then one float per run.
+// FFT twiddles (64 + max(M / 64, 1) complex values), the split twiddles
+// (256 + max(N / 256, 1)), then one float per run.
 template <bool VEC, int LGN>
 __global__ void __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const uint32_t* __restrict__ bits,
@@ -297,11 +288,15 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
   constexpr bool FUSED = VEC && (LGM & 3) == 1 && M >= 4;                  // radix-2 pass in the loads
   constexpr int FPAIRS = (M / 4 + kRowThreads - 1) / kRowThreads;          // fused load pairs per thread
   constexpr int SPAIRS = M >= 2 ? (M / 2 + kRowThreads - 1) / kRowThreads : 1;  // split pairs per thread
+  constexpr bool QFULL = N / 4 > 0 && (N / 4) % kRowThreads == 0;  // every float4 slot in range
+  constexpr bool PFULL = M / 4 > 0 && (M / 4) % kRowThreads == 0;  // every fused pair slot in range
   constexpr int TWN = 64 + (M / 64 > 1 ? M / 64 : 1);
+  constexpr int TSN = 256 + (N / 256 > 1 ? N / 256 : 1);
   extern __shared__ float2 Z[];
   float* Xf = (float*)Z;
   float2* tw = Z + (M + (M >> 4));
-  float* P = (float*)(tw + TWN);
+  float2* ts = tw + TWN;
+  float* P = (float*)(ts + TSN);
   const int tid0 = threadIdx.x;
   const int tid = tid0;
 
@@ -311,6 +306,12 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
     double sv, cv;
     sincospi(2.0 * (double)t / (double)M, &sv, &cv);
     tw[u] = make_float2((float)cv, (float)-sv);
+  }
+  for (int u = tid; u < TSN; u += kRowThreads) {  // e^{-2 pi i t / (4N)}: 256 fine, N / 256 coarse
+    const int t = u < 256 ? u : 256 * (u - 256);
+    double sv, cv;
+    sincospi((double)t / (double)(2 * N), &sv, &cv);
+    ts[u] = make_float2((float)cv, (float)-sv);
   }
   const bool lister = tid * C < N;
   uint32_t ends = 0;
@@ -324,7 +325,7 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
 #pragma unroll
     for (int i = 0; i < FPAIRS; ++i) {
       const int p = tid + i * kRowThreads;
-      if ((M / 4) % kRowThreads == 0 || p < M / 4) {
+      if (PFULL || p < M / 4) {
         const int p2 = M / 2 - 1 - p;
         sgn |= ((bits[p >> 3] >> ((p & 7) * 4)) & 15u) << (8 * i);
         sgn |= ((bits[p2 >> 3] >> ((p2 & 7) * 4)) & 15u) << (8 * i + 4);
@@ -334,7 +335,7 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
 #pragma unroll
     for (int i = 0; i < QUADS; ++i) {
       const int p = tid + i * kRowThreads;
-      if ((N / 4) % kRowThreads == 0 || p < N / 4) sgn |= ((bits[p >> 3] >> ((p & 7) * 4)) & 15u) << (4 * i);
+      if (QFULL || p < N / 4) sgn |= ((bits[p >> 3] >> ((p & 7) * 4)) & 15u) << (4 * i);
     }
   }
   const bool one_bucket = k <= kRowThreads;
@@ -358,7 +359,7 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
 #pragma unroll
       for (int i = 0; i < FPAIRS; ++i) {
         const int p = tid + i * kRowThreads;
-        if ((M / 4) % kRowThreads == 0 || p < M / 4) {
+        if (PFULL || p < M / 4) {
           x[2 * i] = load_quad(a, p, n, sgn >> (8 * i));
           x[2 * i + 1] = load_quad(a, M / 2 - 1 - p, n, sgn >> (8 * i + 4));
         }
@@ -366,7 +367,7 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
 #pragma unroll
       for (int i = 0; i < FPAIRS; ++i) {
         const int p = tid + i * kRowThreads;
-        if ((M / 4) % kRowThreads == 0 || p < M / 4) {
+        if (PFULL || p < M / 4) {
           const int p2 = M / 2 - 1 - p;
           const float4 u = x[2 * i], w = x[2 * i + 1];
           const float2 zp = make_float2(u.x, u.z), zp_hi = make_float2(w.w, w.y);   // z_p, z_{p + M/2}
@@ -382,12 +383,12 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
 #pragma unroll
       for (int i = 0; i < QUADS; ++i) {
         const int p = tid + i * kRowThreads;
-        if ((N / 4) % kRowThreads == 0 || p < N / 4) x[i] = load_quad(a, p, n, sgn >> (4 * i));
+        if (QFULL || p < N / 4) x[i] = load_quad(a, p, n, sgn >> (4 * i));
       }
 #pragma unroll
       for (int i = 0; i < QUADS; ++i) {
         const int p = tid + i * kRowThreads;
-        if ((N / 4) % kRowThreads == 0 || p < N / 4) {
+        if (QFULL || p < N / 4) {
           Z[pz(p)] = make_float2(x[i].x, x[i].z);
           Z[pz(M - 1 - p)] = make_float2(x[i].w, x[i].y);
         }
@@ -416,25 +417,33 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
     } else {
       fft_rest<LGM, 0>(Z, tw, tid);
     }
-    // 3. DCT-II values from Z: pairs (q, M - q) give (F a) at q, N - q, M + q and M - q
+    // 3. DCT-II values from Z: pairs (q, M - q) give (F a) at q, N - q, M + q and
+    //    M - q; q = 0 gives them at 0, M, M/2 and 3M/2
+    constexpr bool SFULL = M / 2 > 0 && (M / 2) % kRowThreads == 0;  // every pair slot in range
     float out[SPAIRS][4];
-    float sp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int i = 0; i < SPAIRS; ++i) {
       const int q = tid + i * kRowThreads;
-      if (q >= 1 && ((M / 2) % kRowThreads == 0 || q < M / 2)) {
+      if (i == 0 && q == 0) {
+        const float2 z0 = Z[pz(0)];
+        out[0][0] = c0 * (z0.x + z0.y);                          // 0
+        out[0][1] = c * 0.707106781186547524f * (z0.x - z0.y);   // M
+        if constexpr (M >= 2) {
+          const float2 zh = Z[pz(M / 2)];
+          const float2 Uh = cmul(split_twiddle(ts, M / 2), make_float2(zh.x, -zh.y));  // e^{-i pi / 8}
+          out[0][2] = c * Uh.x;    // M / 2
+          out[0][3] = -c * Uh.y;   // 3M / 2
+        }
+      } else if (SFULL || q < M / 2) {
         const float2 zq = Z[pz(q)], zr = Z[pz(M - q)];
         const float2 E = make_float2(zq.x + zr.x, zq.y - zr.y);   // 2 E_q
         const float2 O = make_float2(zq.y + zr.y, zr.x - zq.x);   // 2 O_q
-        float sw, cw2, s1, c1;
-        sincospif(2.0f * (float)q / (float)N, &sw, &cw2);
-        sincospif(0.5f * (float)q / (float)N, &s1, &c1);
-        const float2 P = cmul(make_float2(cw2, -sw), O);
-        const float2 t1 = make_float2(c1, -s1);
+        const float2 t1 = split_twiddle(ts, q);            // e^{-i pi q / (2N)}
+        const float2 P = cmul(split_twiddle(ts, 4 * q), O);  // e^{-2 pi i q / N} O
         const float2 U = cmul(t1, cadd(E, P));
         // e^{-i pi / 4} t1 for the upper half
         const float h = 0.707106781186547524f;
-        const float2 t2 = make_float2(h * (c1 - s1), -h * (c1 + s1));
+        const float2 t2 = make_float2(h * (t1.x + t1.y), h * (t1.y - t1.x));
         const float2 U2 = cmul(t2, csub(E, P));
         const float hc = 0.5f * c;
         out[i][0] = hc * U.x;     // q
@@ -443,36 +452,22 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
         out[i][3] = -hc * U2.y;   // M - q
       }
     }
-    if (tid == 0) {
-      const float2 z0 = Z[pz(0)];
-      sp[0] = c0 * (z0.x + z0.y);                          // 0
-      sp[1] = c * 0.707106781186547524f * (z0.x - z0.y);   // M
-      if constexpr (M >= 2) {
-        const float2 zh = Z[pz(M / 2)];
-        float s8, c8;
-        sincospif(0.125f, &s8, &c8);
-        const float2 Uh = cmul(make_float2(c8, -s8), make_float2(zh.x, -zh.y));
-        sp[2] = c * Uh.x;    // M / 2
-        sp[3] = -c * Uh.y;   // 3M / 2
-      }
-    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < SPAIRS; ++i) {
       const int q = tid + i * kRowThreads;
-      if (q >= 1 && ((M / 2) % kRowThreads == 0 || q < M / 2)) {
+      if (i == 0 && q == 0) {
+        Xf[px(0)] = out[0][0];
+        Xf[px(M)] = out[0][1];
+        if constexpr (M >= 2) {
+          Xf[px(M / 2)] = out[0][2];
+          Xf[px(3 * M / 2)] = out[0][3];
+        }
+      } else if (SFULL || q < M / 2) {
         Xf[px(q)] = out[i][0];
         Xf[px(N - q)] = out[i][1];
         Xf[px(M + q)] = out[i][2];
         Xf[px(M - q)] = out[i][3];
-      }
-    }
-    if (tid == 0) {
-      Xf[px(0)] = sp[0];
-      Xf[px(M)] = sp[1];
-      if constexpr (M >= 2) {
-        Xf[px(M / 2)] = sp[2];
-        Xf[px(3 * M / 2)] = sp[3];
       }
     }
     __syncthreads();
@@ -583,7 +578,7 @@ re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n, 
   const int64_t N = hrtt_npad(n);
   if (N > kHrttMaxN || k < 1 || k > N) return RE_ERR_UNSUPPORTED;
   const HashScratch h = carve_hash(scratch, N, k);
-  const size_t lds_build = (size_t)(N + k + 1) * 4;
+  const size_t lds_build = (size_t)(N + k + 1) * 4;  // keys and bucket starts
   if (lds_build > 65536)
     RE_TRY_HIP(hipFuncSetAttribute((const void*)k_hash_build, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds_build));
@@ -592,8 +587,8 @@ re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n, 
   RE_TRY_HIP(hipGetLastError());
   int lgN = 0;
   while ((int64_t(1) << lgN) < N) ++lgN;
-  const int64_t M = N / 2, twn = 64 + (M / 64 > 1 ? M / 64 : 1);
-  const size_t lds = (size_t)(M + (M >> 4) + twn) * sizeof(float2) + (size_t)(k + kRowThreads) * sizeof(float);
+  const int64_t M = N / 2, twn = 64 + (M / 64 > 1 ? M / 64 : 1), tsn = 256 + (N / 256 > 1 ? N / 256 : 1);
+  const size_t lds = (size_t)(M + (M >> 4) + twn + tsn) * sizeof(float2) + (size_t)(k + kRowThreads) * sizeof(float);
   const bool vec = ((uintptr_t)A & 15) == 0 && (lda & 3) == 0;
   const void* fn = vec ? rows_kernel<true>(lgN) : rows_kernel<false>(lgN);
   if (fn == nullptr) return RE_ERR_UNSUPPORTED;

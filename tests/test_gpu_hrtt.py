@@ -42,6 +42,21 @@ def test_sketch_x_matches_oracle(orc, m, n, k):
     assert np.all(err <= tol), float(np.max(err / tol))
 
 
+@pytest.mark.parametrize("off,pad", [(1, 3), (0, 4), (2, 5)])
+def test_sketch_x_row_views(orc, off, pad):
+    # rows of a wider matrix: a pointer off the 16-byte grid or a row stride
+    # that is not a multiple of 4 takes the scalar loads, the rest the vector ones
+    m, n, k = 96, 1024, 100
+    S = inputs.gaussian(m, n + pad, 77 + off, torch.float32)
+    A = S[:, off:off + n]
+    seed = 5
+    Bg = re_.sketch_x(S.to(DEV)[:, off:off + n], k=k, x="hrtt", seed=seed).cpu().numpy().astype(np.float64)
+    Bo = orc.hrtt.apply_x(A.numpy(), k, seed=seed)
+    err = np.linalg.norm(Bg - Bo, axis=1)
+    tol = np.array([_row_tol(orc, n, k, seed, float(np.linalg.norm(a))) for a in A.double().numpy()])
+    assert np.all(err <= tol), float(np.max(err / tol))
+
+
 def test_rank_estimate_matches_oracle_on_a_gap(orc):
     A = inputs.planted(1500, 1000, inputs.spectrum_step(1000, 20, 1.0, 1e-8), 31, torch.float32)
     k, l = 40, 60
