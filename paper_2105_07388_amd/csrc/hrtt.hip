@@ -216,9 +216,18 @@ __device__ __forceinline__ void fft_pass(float2* Z, const float2* tw, int tid) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][brev_c(r, L)] = Z[pz(j + r * T)];
       if constexpr (Ns > 1) {
+        // w^r for w = e^{-2 pi i t1 / M}: the powers w^(2^b) from the table, the
+        // rest as products of at most L of them
         const int t1 = kk << (LGM - LGNS - L);
+        float2 wp[L], w[R];
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[q][brev_c(r, L)] = cmul(v[q][brev_c(r, L)], twiddle(tw, t1 * r));
+        for (int b = 0; b < L; ++b) wp[b] = twiddle(tw, t1 << b);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const int hb = log2_c(r);
+          w[r] = r == (1 << hb) ? wp[hb] : cmul(w[r - (1 << hb)], wp[hb]);
+          v[q][brev_c(r, L)] = cmul(v[q][brev_c(r, L)], w[r]);
+        }
       }
     }
   }
@@ -247,7 +256,8 @@ __device__ __forceinline__ void fft_rest(float2* Z, const float2* tw, int tid) {
 }
 
 // e^{-2 pi i t / (4N)} for 0 <= t < N from ts[u] = e^{-2 pi i u / (4N)}, u < 256,
-// and ts[256 + v] = e^{-2 pi i 256 v / (4N)}.
+// and ts[256 + v] = e^{-2 pi i 256 v / (4N)}; 64 more entries after those hold
+// e^{-2 pi i u / N}, u < 64, the fine part of e^{-2 pi i q / N}.
 __device__ __forceinline__ float2 split_twiddle(const float2* ts, int t) {
   const float2 f = ts[t & 255];
   return (t >> 8) ? cmul(f, ts[256 + (t >> 8)]) : f;
@@ -275,7 +285,7 @@ __device__ __forceinline__ float4 load_quad(const float* __restrict__ a, int p, 
 // N = 2^LGN: one workgroup per row at a time (two per CU); VEC: rows are
 // 16-byte aligned and the loads are float4.  LDS: M + M/16 complex slots, the
 // FFT twiddles (64 + max(M / 64, 1) complex values), the split twiddles
-// (256 + max(N / 256, 1)), then one float per run.
+// (256 + max(N / 256, 1) + 64), then one float per run.
 template <bool VEC, int LGN>
 __global__ void __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const uint32_t* __restrict__ bits,
@@ -291,7 +301,7 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
   constexpr bool QFULL = N / 4 > 0 && (N / 4) % kRowThreads == 0;  // every float4 slot in range
   constexpr bool PFULL = M / 4 > 0 && (M / 4) % kRowThreads == 0;  // every fused pair slot in range
   constexpr int TWN = 64 + (M / 64 > 1 ? M / 64 : 1);
-  constexpr int TSN = 256 + (N / 256 > 1 ? N / 256 : 1);
+  constexpr int TSN = 256 + (N / 256 > 1 ? N / 256 : 1) + 64;
   extern __shared__ float2 Z[];
   float* Xf = (float*)Z;
   float2* tw = Z + (M + (M >> 4));
@@ -307,8 +317,8 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
     sincospi(2.0 * (double)t / (double)M, &sv, &cv);
     tw[u] = make_float2((float)cv, (float)-sv);
   }
-  for (int u = tid; u < TSN; u += kRowThreads) {  // e^{-2 pi i t / (4N)}: 256 fine, N / 256 coarse
-    const int t = u < 256 ? u : 256 * (u - 256);
+  for (int u = tid; u < TSN; u += kRowThreads) {  // e^{-2 pi i t / (4N)}: 256 fine, N / 256 coarse, 64 at step 4
+    const int t = u < 256 ? u : u < TSN - 64 ? 256 * (u - 256) : 4 * (u - (TSN - 64));
     double sv, cv;
     sincospi((double)t / (double)(2 * N), &sv, &cv);
     ts[u] = make_float2((float)cv, (float)-sv);
@@ -439,7 +449,8 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
         const float2 E = make_float2(zq.x + zr.x, zq.y - zr.y);   // 2 E_q
         const float2 O = make_float2(zq.y + zr.y, zr.x - zq.x);   // 2 O_q
         const float2 t1 = split_twiddle(ts, q);            // e^{-i pi q / (2N)}
-        const float2 P = cmul(split_twiddle(ts, 4 * q), O);  // e^{-2 pi i q / N} O
+        const float2 wq = ts[TSN - 64 + (q & 63)];            // e^{-2 pi i q / N}: fine part
+        const float2 P = cmul((q >> 6) ? cmul(wq, ts[256 + (q >> 6)]) : wq, O);
         const float2 U = cmul(t1, cadd(E, P));
         // e^{-i pi / 4} t1 for the upper half
         const float h = 0.707106781186547524f;
@@ -587,7 +598,7 @@ re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n, 
   RE_TRY_HIP(hipGetLastError());
   int lgN = 0;
   while ((int64_t(1) << lgN) < N) ++lgN;
-  const int64_t M = N / 2, twn = 64 + (M / 64 > 1 ? M / 64 : 1), tsn = 256 + (N / 256 > 1 ? N / 256 : 1);
+  const int64_t M = N / 2, twn = 64 + (M / 64 > 1 ? M / 64 : 1), tsn = 256 + (N / 256 > 1 ? N / 256 : 1) + 64;
   const size_t lds = (size_t)(M + (M >> 4) + twn + tsn) * sizeof(float2) + (size_t)(k + kRowThreads) * sizeof(float);
   const bool vec = ((uintptr_t)A & 15) == 0 && (lda & 3) == 0;
   const void* fn = vec ? rows_kernel<true>(lgN) : rows_kernel<false>(lgN);
