@@ -221,8 +221,9 @@ re_status run_x(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m
   if (rs.xk == RE_HRTT) {  // hashed randomized DCT (FP32 A)
     uint32_t* bits = (uint32_t*)at(h, p.xbits);
     RE_TRY(launch_sign_bits(s, hrtt_npad(n), seed, kXSign, bits));
+    RE_TRY(launch_hrtt_hash(s, n, rs.k, seed, at(h, p.hscr)));
     mark(h, RE_STAGE_AX);
-    return launch_hrtt_rows(s, (const float*)A, m, n, lda, rs.k, seed, bits, at(h, p.hscr), (float*)B, rs.k);
+    return launch_hrtt_rows(s, (const float*)A, m, n, lda, rs.k, bits, at(h, p.hscr), (float*)B, rs.k);
   }
   if (rs.xk == RE_SRHT) {
     uint32_t* bits = (uint32_t*)at(h, p.xbits);

@@ -15,11 +15,15 @@ constexpr int64_t kHrttMaxN = 16384;
 __attribute__((visibility("hidden"))) int64_t hrtt_npad(int64_t n);
 // Scratch of one call: bucket codes, bucket pointers, coordinate lists.
 __attribute__((visibility("hidden"))) size_t hrtt_scratch_bytes(int64_t n, int64_t k);
-// B (m x k FP32, ldb) = A X for the HRTT X of width k; sign_bits: the SRHT X
-// signs for N coordinates.  RE_ERR_UNSUPPORTED when N > kHrttMaxN or k > N.
+// Draw the HRTT X of width k for n columns: its bucket lists and their run
+// structure into `scratch` (hrtt_scratch_bytes).  RE_ERR_UNSUPPORTED when
+// N > kHrttMaxN or k > N.
+__attribute__((visibility("hidden"))) re_status launch_hrtt_hash(hipStream_t s, int64_t n, int64_t k, uint64_t seed,
+                                                                void* scratch);
+// B (m x k FP32, ldb) = A X for the HRTT X drawn into `scratch`; sign_bits: the
+// SRHT X signs for N coordinates.
 __attribute__((visibility("hidden"))) re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n,
-                                                                int64_t lda, int64_t k, uint64_t seed,
-                                                                const uint32_t* sign_bits, void* scratch, float* B,
-                                                                int64_t ldb);
+                                                                int64_t lda, int64_t k, const uint32_t* sign_bits,
+                                                                const void* scratch, float* B, int64_t ldb);
 
 }  // namespace re

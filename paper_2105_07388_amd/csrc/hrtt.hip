@@ -584,8 +584,7 @@ static const void* rows_kernel(int lgN) {
   }
 }
 
-re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t lda, int64_t k, uint64_t seed,
-                           const uint32_t* sign_bits, void* scratch, float* B, int64_t ldb) {
+re_status launch_hrtt_hash(hipStream_t s, int64_t n, int64_t k, uint64_t seed, void* scratch) {
   const int64_t N = hrtt_npad(n);
   if (N > kHrttMaxN || k < 1 || k > N) return RE_ERR_UNSUPPORTED;
   const HashScratch h = carve_hash(scratch, N, k);
@@ -596,6 +595,14 @@ re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n, 
   hipLaunchKernelGGL(k_hash_build, dim3(1), dim3(kBuildThreads), lds_build, s, (int)N, (int)k, seed, h.ptr, h.list,
                      h.code16, h.ends, h.rbase, h.rlo, h.rhi);
   RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
+
+re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t lda, int64_t k,
+                           const uint32_t* sign_bits, const void* scratch, float* B, int64_t ldb) {
+  const int64_t N = hrtt_npad(n);
+  if (N > kHrttMaxN || k < 1 || k > N) return RE_ERR_UNSUPPORTED;
+  const HashScratch h = carve_hash((void*)scratch, N, k);
   int lgN = 0;
   while ((int64_t(1) << lgN) < N) ++lgN;
   const int64_t M = N / 2, twn = 64 + (M / 64 > 1 ? M / 64 : 1), tsn = 256 + (N / 256 > 1 ? N / 256 : 1) + 64;
