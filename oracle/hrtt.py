@@ -13,6 +13,13 @@ length N (scipy's, a library FFT serving as the transform step), h(j) in
 [0, k) and s(j) in {+1, -1} from Philox4x64-10 at counter (j, 0, 7, 0):
 h(j) = floor(w0 k / 2^64), s(j) = +1 if the lowest bit of w1 is 0.  The factor
 sqrt(k) lets every X kind share the 1/sqrt(k) scale of the estimates.
+
+The subsampled randomized DCT (SRCT, Sec. 3.3 with F a DCT, and Sec. 4) keeps
+the sampling S of the subsampled transform instead:
+B[i, b] = sqrt(N) (F D a_i)_{s_b}, with s the SRHT's X sample (the k smallest
+Philox keys of stream 5 over the N coordinates, sorted); sqrt(N) plays the part
+of the unnormalised Hadamard matrix's scale, so that E ||a X||^2 = k ||a||^2
+as for the other kinds.
 """
 import math
 
@@ -67,13 +74,27 @@ def apply_x(A, k, seed=0, blk=0):
     return math.sqrt(k) * (Yt @ H)
 
 
-def rank_estimate(A, eps, k=40, l=None, ykind=_o.GAUSSIAN, seed=0):
-    """Algorithm 1 with the HRTT X: (r, sigma[k], r1, flags); Y Gaussian or SRHT
-    in A's storage format, as the plain oracle draws it."""
+def apply_x_srct(A, k, seed=0, blk=0):
+    """B = A X for the SRCT X (m x k, FP64)."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    N = npad(n)
+    Z = np.zeros((m, N))
+    Z[:, :n] = A
+    Z *= signs(seed, N, blk)[None, :]
+    Yt = sf.dct(Z, type=2, norm="ortho", axis=1)
+    sel = _o.select(seed, N, k, _o.STREAM_XSEL, blk)
+    return math.sqrt(N) * Yt[:, sel]
+
+
+def rank_estimate(A, eps, k=40, l=None, ykind=_o.GAUSSIAN, seed=0, x="hrtt"):
+    """Algorithm 1 with the HRTT (x="hrtt") or SRCT (x="srct") X: (r, sigma[k],
+    r1, flags); Y Gaussian or SRHT in A's storage format, as the plain oracle
+    draws it."""
     A = np.ascontiguousarray(A)
     l = 2 * k if l is None else l
     fmt = _o.FMT_F64 if A.dtype == np.float64 else _o.FMT_F32
-    B = apply_x(A, k, seed=seed)
+    B = apply_x(A, k, seed=seed) if x == "hrtt" else apply_x_srct(A, k, seed=seed)
     Cm = _o.apply_y(B, ykind, l, fmt_y=fmt, seed=seed)
     s, _, st = _o.jacobi_sv(Cm)
     if st != 0:

@@ -62,3 +62,38 @@ def test_diagonal_matrix_hashed_beats_subsampled(orc):
     assert r == 30
     rs, _, _, _, _ = orc.rank_estimate(A, 1e-4, orc.SRHT, orc.GAUSSIAN, k=64, l=128, seed=3)
     assert rs < 30
+
+
+def test_srct_is_the_written_out_product(orc):
+    H = orc.hrtt
+    rng = np.random.default_rng(8)
+    m, n, k, seed = 6, 21, 9, 4
+    A = rng.standard_normal((m, n))
+    N = H.npad(n)
+    D = np.diag(H.signs(seed, N))
+    sel = orc.select(seed, N, k, orc.STREAM_XSEL)
+    S = np.zeros((k, N))
+    S[np.arange(k), sel] = 1.0
+    X = (D @ H.dct_matrix(N).T @ S.T)[:n] * math.sqrt(N)  # n x k
+    assert np.allclose(H.apply_x_srct(A, k, seed=seed), A @ X, atol=1e-12)
+    # the sample nests in k and is the SRHT's
+    assert np.array_equal(np.sort(sel), sel)
+    assert set(orc.select(seed, N, k // 2, orc.STREAM_XSEL)) <= set(sel)
+
+
+def test_srct_full_sample_is_orthogonal(orc):
+    # k = N and l = m' sample every coordinate: both embeddings are sqrt(N) resp.
+    # sqrt(m') times an orthogonal matrix, so the scaled estimates are sigma(A)
+    rng = np.random.default_rng(3)
+    m, n = 64, 32
+    A = rng.standard_normal((m, 5)) @ rng.standard_normal((5, n)) + 1e-3 * rng.standard_normal((m, n))
+    r, s, r1, fl = orc.hrtt.rank_estimate(A, 1e-2, k=n, l=m, ykind=orc.SRHT, seed=2, x="srct")
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert np.allclose(s, sv, rtol=0, atol=1e-12 * sv[0])
+    assert r == orc.rank_def(sv[:r1], 1e-2)
+
+
+def test_srct_isometry_in_expectation(orc):
+    x = np.random.default_rng(4).standard_normal((1, 100))
+    r = [np.sum(orc.hrtt.apply_x_srct(x, 16, seed=t) ** 2) / 16 / np.sum(x ** 2) for t in range(80)]
+    assert abs(np.mean(r) - 1.0) < 4 * np.std(r) / math.sqrt(80)
