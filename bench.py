@@ -49,6 +49,9 @@ WORKLOADS = {
     "hrtt": dict(m=65536, n=16384, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="hrtt", y="srht",
                  desc="hashed randomized DCT X (Sec. 3.3, the paper's experimental X): FP32 65536x16384, "
                       "s_i=10^(-i/20) (R=1024) + 1e-9 noise, HRTT X 16384x384, SRHT Y 576x65536, eps 1e-3/1e-5"),
+    "srct": dict(m=65536, n=16384, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="srct", y="srht",
+                 desc="subsampled randomized DCT X (Sec. 3.3 / Sec. 4 with F a DCT): FP32 65536x16384, "
+                      "s_i=10^(-i/20) (R=1024) + 1e-9 noise, SRCT X 16384x384, SRHT Y 576x65536, eps 1e-3/1e-5"),
     "qr": dict(m=65536, n=16384, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="srht", y="srht", wide_k=1650,
                wide_l=3300,
                desc="step 7 by the QR diagonal (Sec. 5): the plain method at scale (FP32 65536x16384, SRHT X 384, "
@@ -63,7 +66,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 TRAFFIC_SOURCES = {"c2": ("srht.hip", "common.h"), "c3": ("gemm_lp.hip", "common.h"),
                    "c4": ("batch.hip", "batch.h", "common.h"), "rf": ("batch.hip", "batch.h", "common.h"),
-                   "hrtt": ("hrtt.hip", "hrtt.h", "common.h")}
+                   "hrtt": ("hrtt.hip", "hrtt.h", "common.h"), "srct": ("hrtt.hip", "hrtt.h", "common.h")}
 
 
 def kernel_source_digest(workload: str) -> str:
@@ -92,7 +95,7 @@ def make_matrix(name, w, device):
     import torch
 
     from paper_2105_07388_amd import inputs
-    if name in ("c2", "qr", "hrtt"):
+    if name in ("c2", "qr", "hrtt", "srct"):
         return inputs.c2_matrix(w["m"], w["n"], w["R"], device=device)
     if name == "c1":
         return inputs.c1_matrix(device=device)
@@ -113,7 +116,12 @@ def cpu_baseline(A_dev, w, rows: int):
     yk = oracle.SRHT if w["y"] == "srht" else oracle.GAUSSIAN
     A_s = A_dev[:rows].cpu().numpy()
     t0 = time.perf_counter()
-    B = oracle.hrtt.apply_x(A_s, k, seed=0) if w["x"] == "hrtt" else oracle.apply_x(A_s, xk, k, seed=0)
+    if w["x"] == "hrtt":
+        B = oracle.hrtt.apply_x(A_s, k, seed=0)
+    elif w["x"] == "srct":
+        B = oracle.hrtt.apply_x_srct(A_s, k, seed=0)
+    else:
+        B = oracle.apply_x(A_s, xk, k, seed=0)
     t_x = (time.perf_counter() - t0) * (m / rows)
     Bfull = np.random.default_rng(0).standard_normal((m, k))
     Bfull[:rows] = B

@@ -53,9 +53,12 @@ typedef enum { RE_F64 = 0, RE_F32 = 1 } re_dtype;
  * the Hadamard matrix as the trigonometric transform and N = the dimension
  * zero-padded to a power of two), or (X only) a hashed randomized DCT H F D
  * (Sec. 3.3: a CountSketch H in place of the sampling S, F the orthonormal
- * DCT-II of length N = max(2, next power of two >= n); FP32 A with N <= 16384,
- * native precision; the paper's experimental X). */
-typedef enum { RE_GAUSSIAN = 0, RE_SRHT = 1, RE_HRTT = 2 } re_kind;
+ * DCT-II of length N = max(2, next power of two >= n); the paper's
+ * experimental X) or (X only) the subsampled randomized DCT sqrt(N/k) S F D
+ * (the SRHT's signs D and sample S over that N).  The two DCT kinds need FP32 A
+ * with N <= 16384 and native precision (else RE_ERR_UNSUPPORTED); as a Y they
+ * are rejected (hashed: RE_ERR_INVALID_ARG, subsampled: RE_ERR_UNSUPPORTED). */
+typedef enum { RE_GAUSSIAN = 0, RE_SRHT = 1, RE_HRTT = 2, RE_SRCT = 3 } re_kind;
 
 /* Arithmetic of the A X contraction.  NATIVE: the storage type of A.
  * BF16 / FP16: A (FP32 only) and a Gaussian X rounded to that format on the

@@ -22,7 +22,8 @@ RE_F64, RE_F32 = 0, 1
 RE_GAUSSIAN, RE_SRHT = 0, 1
 PREC = {"native": 0, "bf16": 1, "fp16": 2, "auto": 3}
 RE_HRTT = 2
-KIND = {"gaussian": RE_GAUSSIAN, "srht": RE_SRHT, "hrtt": RE_HRTT}
+RE_SRCT = 3
+KIND = {"gaussian": RE_GAUSSIAN, "srht": RE_SRHT, "hrtt": RE_HRTT, "srct": RE_SRCT}
 FLAG_NOT_CONVERGED, FLAG_ZERO, FLAG_PREC_FALLBACK, FLAG_USED_BF16, FLAG_USED_FP16 = 1, 2, 4, 8, 16
 FLAG_COLUMNS_DROPPED = 32
 MAX_ADAPTIVE_K = 5120  # RE_MAX_ADAPTIVE_K

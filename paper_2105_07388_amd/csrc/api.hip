@@ -131,9 +131,10 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
   if (dt != RE_F64 && dt != RE_F32) return RE_ERR_INVALID_ARG;
   if (m < 1 || n < 1 || lda < n) return RE_ERR_INVALID_ARG;
   if (((uintptr_t)A) % (dt == RE_F64 ? 8 : 4) != 0) return RE_ERR_INVALID_ARG;
-  if ((sk->x_kind != RE_GAUSSIAN && sk->x_kind != RE_SRHT && sk->x_kind != RE_HRTT) ||
-      (sk->y_kind != RE_GAUSSIAN && sk->y_kind != RE_SRHT))
+  if ((sk->x_kind != RE_GAUSSIAN && sk->x_kind != RE_SRHT && sk->x_kind != RE_HRTT && sk->x_kind != RE_SRCT) ||
+      (sk->y_kind != RE_GAUSSIAN && sk->y_kind != RE_SRHT && sk->y_kind != RE_SRCT))
     return RE_ERR_INVALID_ARG;
+  if (sk->y_kind == RE_SRCT) return RE_ERR_UNSUPPORTED;  // the subsampled DCT is built for X only
   if (sk->prec < RE_PREC_NATIVE || sk->prec > RE_PREC_AUTO) return RE_ERR_INVALID_ARG;
   rs->xk = sk->x_kind;
   rs->yk = sk->y_kind;
@@ -141,14 +142,15 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
   rs->l = sk->l == 0 ? 2 * (int64_t)sk->k : sk->l;
   rs->npad_n = next_pow2(n);
   rs->npad_m = next_pow2(m);
-  const int64_t kmax = rs->xk == RE_SRHT ? rs->npad_n : rs->xk == RE_HRTT ? hrtt_npad(n) : n;
+  const bool dct = rs->xk == RE_HRTT || rs->xk == RE_SRCT;
+  const int64_t kmax = rs->xk == RE_SRHT ? rs->npad_n : dct ? hrtt_npad(n) : n;
   const int64_t lmax = rs->yk == RE_SRHT ? rs->npad_m : m;
   if (rs->k < 1 || rs->l < rs->k) return RE_ERR_INVALID_ARG;
   if ((sides & 1) && rs->k > kmax) return RE_ERR_INVALID_ARG;
   if ((sides & 2) && rs->l > lmax) return RE_ERR_INVALID_ARG;
   if (rs->k > (int64_t)INT32_MAX / 2) return RE_ERR_INVALID_ARG;
   if (sk->prec != RE_PREC_NATIVE && (dt == RE_F64 || rs->xk != RE_GAUSSIAN)) return RE_ERR_UNSUPPORTED;
-  if (rs->xk == RE_HRTT && (dt != RE_F32 || hrtt_npad(n) > kHrttMaxN)) return RE_ERR_UNSUPPORTED;
+  if (dct && (dt != RE_F32 || hrtt_npad(n) > kHrttMaxN)) return RE_ERR_UNSUPPORTED;
   return RE_OK;
 }
 
@@ -178,11 +180,12 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   const int fx = x_fmt(dt);
   const size_t be = dt == RE_F64 ? 8 : 4;
   const int64_t brows = rs.yk == RE_SRHT ? (int64_t)srht_cols_rows_alloc(m) : m;
-  p.xbits = c.take((size_t)cdiv(rs.xk == RE_HRTT ? hrtt_npad(n) : rs.npad_n, 32) * 4);
+  const int64_t xn = rs.xk == RE_HRTT || rs.xk == RE_SRCT ? hrtt_npad(n) : rs.npad_n;  // X's transform length
+  p.xbits = c.take((size_t)cdiv(xn, 32) * 4);
   p.ybits = c.take((size_t)cdiv(rs.npad_m, 32) * 4);
   p.xsel = c.take((size_t)rs.k * 4);
   p.ysel = c.take((size_t)rs.l * 4);
-  p.selscr = c.take(select_scratch_bytes(rs.npad_n > rs.npad_m ? rs.npad_n : rs.npad_m));
+  p.selscr = c.take(select_scratch_bytes(xn > rs.npad_m ? xn : rs.npad_m));
   p.X = c.take(rs.xk == RE_GAUSSIAN ? (size_t)n * rs.k * (size_t)elem_size(fx) : 0);  // FP32/FP64; 2-byte formats fit too
   p.Y = c.take(rs.yk == RE_GAUSSIAN ? (size_t)rs.l * m * elem_size(fx) : 0);
   p.B = c.take((size_t)brows * rs.k * be);
@@ -224,6 +227,15 @@ re_status run_x(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m
     RE_TRY(launch_hrtt_hash(s, n, rs.k, seed, at(h, p.hscr)));
     mark(h, RE_STAGE_AX);
     return launch_hrtt_rows(s, (const float*)A, m, n, lda, rs.k, bits, at(h, p.hscr), (float*)B, rs.k);
+  }
+  if (rs.xk == RE_SRCT) {  // subsampled randomized DCT (FP32 A): the SRHT's signs and sample over N
+    const int64_t N = hrtt_npad(n);
+    uint32_t* bits = (uint32_t*)at(h, p.xbits);
+    int32_t* sel = (int32_t*)at(h, p.xsel);
+    RE_TRY(launch_sign_bits(s, N, seed, kXSign, bits));
+    RE_TRY(launch_select(s, N, rs.k, seed, kXSel, at(h, p.selscr), sel));
+    mark(h, RE_STAGE_AX);
+    return launch_srct_rows(s, (const float*)A, m, n, lda, rs.k, bits, sel, (float*)B, rs.k);
   }
   if (rs.xk == RE_SRHT) {
     uint32_t* bits = (uint32_t*)at(h, p.xbits);

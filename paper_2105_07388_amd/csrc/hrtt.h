@@ -1,4 +1,5 @@
-// Launchers of the hashed randomized DCT embedding (HRTT X, Sec. 3.3).
+// Launchers of the hashed and the subsampled randomized DCT embeddings (HRTT and
+// SRCT X, Sec. 3.3).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,5 +26,10 @@ __attribute__((visibility("hidden"))) re_status launch_hrtt_hash(hipStream_t s, 
 __attribute__((visibility("hidden"))) re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n,
                                                                 int64_t lda, int64_t k, const uint32_t* sign_bits,
                                                                 const void* scratch, float* B, int64_t ldb);
+// B (m x k FP32, ldb) = A X for the subsampled randomized DCT X:
+// B[i][b] = sqrt(N) (F D a_i)_{sel[b]}, sel the k sampled coordinates (< N).
+__attribute__((visibility("hidden"))) re_status launch_srct_rows(hipStream_t s, const float* A, int64_t m, int64_t n,
+                                                                int64_t lda, int64_t k, const uint32_t* sign_bits,
+                                                                const int32_t* sel, float* B, int64_t ldb);
 
 }  // namespace re

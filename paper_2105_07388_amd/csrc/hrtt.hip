@@ -286,12 +286,14 @@ __device__ __forceinline__ float4 load_quad(const float* __restrict__ a, int p, 
 // 16-byte aligned and the loads are float4.  LDS: M + M/16 complex slots, the
 // FFT twiddles (64 + max(M / 64, 1) complex values), the split twiddles
 // (256 + max(N / 256, 1) + 64), then one float per run.
-template <bool VEC, int LGN>
+// HASH: the CountSketch of the hashed DCT (list and runs from k_hash_build);
+// otherwise the subsampled DCT: B[i][b] = sk (F D a_i)_{sel[b]}, no run floats.
+template <bool VEC, int LGN, bool HASH>
 __global__ void __launch_bounds__(kRowThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, const uint32_t* __restrict__ bits,
             const uint16_t* __restrict__ code16, const uint32_t* __restrict__ ends_g, const int32_t* __restrict__ rbase_g,
-            const int32_t* __restrict__ rlo_g, const int32_t* __restrict__ rhi_g, int k, float sk,
-            float* __restrict__ B, int64_t ldb) {
+            const int32_t* __restrict__ rlo_g, const int32_t* __restrict__ rhi_g, const int32_t* __restrict__ sel,
+            int k, float sk, float* __restrict__ B, int64_t ldb) {
   constexpr int N = 1 << LGN, LGM = LGN - 1, M = N >> 1;
   constexpr int C = N >= kRowThreads ? N / kRowThreads : 1;                 // list entries per thread
   constexpr int QUADS = (N / 4 + kRowThreads - 1) / kRowThreads;           // float4 loads per thread
@@ -323,7 +325,7 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
     sincospi((double)t / (double)(2 * N), &sv, &cv);
     ts[u] = make_float2((float)cv, (float)-sv);
   }
-  const bool lister = tid * C < N;
+  const bool lister = HASH && tid * C < N;
   uint32_t ends = 0;
   int32_t rb = 0;
   if (lister) {
@@ -351,8 +353,12 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
   const bool one_bucket = k <= kRowThreads;
   int32_t lo0 = 1, hi0 = 0;
   if (one_bucket && tid < k) {
-    lo0 = rlo_g[tid];
-    hi0 = rhi_g[tid];
+    if constexpr (HASH) {
+      lo0 = rlo_g[tid];
+      hi0 = rhi_g[tid];
+    } else {
+      lo0 = sel[tid];
+    }
   }
   const float c = sqrtf(2.0f / (float)N), c0 = sqrtf(1.0f / (float)N);
   __syncthreads();
@@ -482,6 +488,12 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
       }
     }
     __syncthreads();
+    if constexpr (!HASH) {
+      // 4'. the sampled coordinates (the next row's loads overwrite X)
+      for (int b = tid; b < k; b += kRowThreads) B[row * ldb + b] = Xf[px(one_bucket ? lo0 : sel[b])] * sk;
+      __syncthreads();
+      continue;
+    }
     // 4. CountSketch: the sums of this thread's runs, each stored by its number
     if (lister) {
       uint32_t cw[(C + 1) / 2];  // the chunk's 16-bit list entries, two a word
@@ -563,25 +575,60 @@ HashScratch carve_hash(void* base, int64_t N, int64_t k) {
 
 size_t hrtt_scratch_bytes(int64_t n, int64_t k) { return carve_hash(nullptr, hrtt_npad(n), k).bytes; }
 
-template <bool VEC>
+template <bool VEC, bool HASH>
 static const void* rows_kernel(int lgN) {
   switch (lgN) {
-    case 1: return (const void*)k_hrtt_rows<VEC, 1>;
-    case 2: return (const void*)k_hrtt_rows<VEC, 2>;
-    case 3: return (const void*)k_hrtt_rows<VEC, 3>;
-    case 4: return (const void*)k_hrtt_rows<VEC, 4>;
-    case 5: return (const void*)k_hrtt_rows<VEC, 5>;
-    case 6: return (const void*)k_hrtt_rows<VEC, 6>;
-    case 7: return (const void*)k_hrtt_rows<VEC, 7>;
-    case 8: return (const void*)k_hrtt_rows<VEC, 8>;
-    case 9: return (const void*)k_hrtt_rows<VEC, 9>;
-    case 10: return (const void*)k_hrtt_rows<VEC, 10>;
-    case 11: return (const void*)k_hrtt_rows<VEC, 11>;
-    case 12: return (const void*)k_hrtt_rows<VEC, 12>;
-    case 13: return (const void*)k_hrtt_rows<VEC, 13>;
-    case 14: return (const void*)k_hrtt_rows<VEC, 14>;
+    case 1: return (const void*)k_hrtt_rows<VEC, 1, HASH>;
+    case 2: return (const void*)k_hrtt_rows<VEC, 2, HASH>;
+    case 3: return (const void*)k_hrtt_rows<VEC, 3, HASH>;
+    case 4: return (const void*)k_hrtt_rows<VEC, 4, HASH>;
+    case 5: return (const void*)k_hrtt_rows<VEC, 5, HASH>;
+    case 6: return (const void*)k_hrtt_rows<VEC, 6, HASH>;
+    case 7: return (const void*)k_hrtt_rows<VEC, 7, HASH>;
+    case 8: return (const void*)k_hrtt_rows<VEC, 8, HASH>;
+    case 9: return (const void*)k_hrtt_rows<VEC, 9, HASH>;
+    case 10: return (const void*)k_hrtt_rows<VEC, 10, HASH>;
+    case 11: return (const void*)k_hrtt_rows<VEC, 11, HASH>;
+    case 12: return (const void*)k_hrtt_rows<VEC, 12, HASH>;
+    case 13: return (const void*)k_hrtt_rows<VEC, 13, HASH>;
+    case 14: return (const void*)k_hrtt_rows<VEC, 14, HASH>;
     default: return nullptr;
   }
+}
+
+// One launch of the rows kernel (either variant) on all CUs, two workgroups
+// per CU when the LDS allows.
+static re_status launch_rows(hipStream_t s, bool hash, const float* A, int64_t m, int64_t n, int64_t lda, int64_t k,
+                             const uint32_t* sign_bits, const HashScratch* h, const int32_t* sel, float sk, float* B,
+                             int64_t ldb) {
+  const int64_t N = hrtt_npad(n);
+  int lgN = 0;
+  while ((int64_t(1) << lgN) < N) ++lgN;
+  const int64_t M = N / 2, twn = 64 + (M / 64 > 1 ? M / 64 : 1), tsn = 256 + (N / 256 > 1 ? N / 256 : 1) + 64;
+  const size_t lds = (size_t)(M + (M >> 4) + twn + tsn) * sizeof(float2) +
+                     (hash ? (size_t)(k + kRowThreads) * sizeof(float) : 0);
+  const bool vec = ((uintptr_t)A & 15) == 0 && (lda & 3) == 0;
+  const void* fn = hash ? (vec ? rows_kernel<true, true>(lgN) : rows_kernel<false, true>(lgN))
+                        : (vec ? rows_kernel<true, false>(lgN) : rows_kernel<false, false>(lgN));
+  if (fn == nullptr) return RE_ERR_UNSUPPORTED;
+  if (lds > 65536) RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int per_cu = (int)((160 * 1024) / lds);
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 2) per_cu = 2;  // 512 threads of at most 128 VGPRs: two workgroups per CU
+  int64_t grid = 256 * (int64_t)per_cu;
+  if (grid > m) grid = m;
+  const uint16_t* ccode = hash ? h->code16 : nullptr;
+  const uint32_t* cends = hash ? h->ends : nullptr;
+  const int32_t* crbase = hash ? h->rbase : nullptr;
+  const int32_t* crlo = hash ? h->rlo : nullptr;
+  const int32_t* crhi = hash ? h->rhi : nullptr;
+  int ki = (int)k;
+  void* args[] = {(void*)&A,     (void*)&m,     (void*)&n,      (void*)&lda,  (void*)&sign_bits,
+                  (void*)&ccode, (void*)&cends, (void*)&crbase, (void*)&crlo, (void*)&crhi,
+                  (void*)&sel,   (void*)&ki,    (void*)&sk,     (void*)&B,    (void*)&ldb};
+  RE_TRY_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kRowThreads), args, lds, s));
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
 }
 
 re_status launch_hrtt_hash(hipStream_t s, int64_t n, int64_t k, uint64_t seed, void* scratch) {
@@ -603,30 +650,14 @@ re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n, 
   const int64_t N = hrtt_npad(n);
   if (N > kHrttMaxN || k < 1 || k > N) return RE_ERR_UNSUPPORTED;
   const HashScratch h = carve_hash((void*)scratch, N, k);
-  int lgN = 0;
-  while ((int64_t(1) << lgN) < N) ++lgN;
-  const int64_t M = N / 2, twn = 64 + (M / 64 > 1 ? M / 64 : 1), tsn = 256 + (N / 256 > 1 ? N / 256 : 1) + 64;
-  const size_t lds = (size_t)(M + (M >> 4) + twn + tsn) * sizeof(float2) + (size_t)(k + kRowThreads) * sizeof(float);
-  const bool vec = ((uintptr_t)A & 15) == 0 && (lda & 3) == 0;
-  const void* fn = vec ? rows_kernel<true>(lgN) : rows_kernel<false>(lgN);
-  if (fn == nullptr) return RE_ERR_UNSUPPORTED;
-  if (lds > 65536) RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  int per_cu = (int)((160 * 1024) / lds);
-  if (per_cu < 1) per_cu = 1;
-  if (per_cu > 2) per_cu = 2;  // 512 threads of at most 128 VGPRs: two workgroups per CU
-  int64_t grid = 256 * (int64_t)per_cu;
-  if (grid > m) grid = m;
-  const uint16_t* ccode = h.code16;
-  const uint32_t* cends = h.ends;
-  const int32_t *crbase = h.rbase, *crlo = h.rlo, *crhi = h.rhi;
-  int ki = (int)k;
-  float sk = sqrtf((float)k);
-  void* args[] = {(void*)&A,     (void*)&m,     (void*)&n,    (void*)&lda,  (void*)&sign_bits,
-                  (void*)&ccode, (void*)&cends, (void*)&crbase, (void*)&crlo, (void*)&crhi,
-                  (void*)&ki,    (void*)&sk,    (void*)&B,    (void*)&ldb};
-  RE_TRY_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kRowThreads), args, lds, s));
-  RE_TRY_HIP(hipGetLastError());
-  return RE_OK;
+  return launch_rows(s, true, A, m, n, lda, k, sign_bits, &h, nullptr, sqrtf((float)k), B, ldb);
+}
+
+re_status launch_srct_rows(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t lda, int64_t k,
+                           const uint32_t* sign_bits, const int32_t* sel, float* B, int64_t ldb) {
+  const int64_t N = hrtt_npad(n);
+  if (N > kHrttMaxN || k < 1 || k > N) return RE_ERR_UNSUPPORTED;
+  return launch_rows(s, false, A, m, n, lda, k, sign_bits, nullptr, sel, sqrtf((float)N), B, ldb);
 }
 
 }  // namespace re

@@ -100,3 +100,62 @@ def test_repeatable_and_errors():
     with pytest.raises(re_.RankEstError) as e:
         re_.rank_estimate(A, 1e-3, k=10, y="hrtt")
     assert e.value.status == re_._binding.RE_ERR_INVALID_ARG
+
+
+# The subsampled randomized DCT X (SRCT): B = sqrt(N) (F D a)[sel].  The k
+# sampled entries' error is at most the whole transform's, (6 lg N + 6) u32 ||a||
+# normwise, times sqrt(N).
+def _srct_tol(n, anorm):
+    import oracle.hrtt as oh
+    N = oh.npad(n)
+    return math.sqrt(N) * (6 * math.log2(N) + 6) * U32 * anorm
+
+
+@pytest.mark.parametrize("m,n,k,off", [(300, 1000, 64, 0), (50, 1, 1, 0), (33, 2, 2, 0), (40, 3, 4, 0),
+                                       (128, 16384, 384, 0), (90, 700, 700, 0), (64, 2049, 384, 0),
+                                       (96, 1024, 100, 1)])
+def test_srct_sketch_x_matches_oracle(orc, m, n, k, off):
+    S = inputs.gaussian(m, n + off, 300 + n, torch.float32)
+    A = S[:, off:off + n]
+    seed = 23 + k
+    Bg = re_.sketch_x(S.to(DEV)[:, off:off + n], k=k, x="srct", seed=seed).cpu().numpy().astype(np.float64)
+    Bo = orc.hrtt.apply_x_srct(A.numpy(), k, seed=seed)
+    err = np.linalg.norm(Bg - Bo, axis=1)
+    tol = np.array([_srct_tol(n, float(np.linalg.norm(a))) for a in A.double().numpy()])
+    assert np.all(err <= tol), float(np.max(err / tol))
+
+
+def test_srct_full_sample_gives_the_singular_values(orc):
+    # k = N and l = m' make both embeddings orthogonal up to scale: the estimates
+    # are sigma(A) up to the FP32 transforms' rounding
+    m, n = 256, 128
+    A = inputs.planted(m, n, inputs.spectrum_step(n, 12, 1.0, 1e-3), 8, torch.float32)
+    r, s, info = re_.rank_estimate(A.to(DEV), 1e-2, k=n, l=m, x="srct", y="srht", seed=4)
+    sv = np.linalg.svd(A.double().numpy(), compute_uv=False)
+    assert r == 12
+    assert np.max(np.abs(s - sv)) <= 1e-5 * sv[0]
+
+
+def test_srct_rank_estimate_matches_oracle_on_a_gap(orc):
+    A = inputs.planted(1500, 1000, inputs.spectrum_step(1000, 20, 1.0, 1e-8), 31, torch.float32)
+    k, l = 40, 60
+    for y, ykind in (("gaussian", orc.GAUSSIAN), ("srht", orc.SRHT)):
+        r, s, info = re_.rank_estimate(A.to(DEV), 1e-5, k=k, l=l, x="srct", y=y, seed=6)
+        ro, so, r1, fl = orc.hrtt.rank_estimate(A.numpy(), 1e-5, k=k, l=l, ykind=ykind, seed=6, x="srct")
+        assert r == ro == 20 and info["flags"] == fl
+        dB = math.sqrt(sum(_srct_tol(1000, float(np.linalg.norm(a))) ** 2 for a in A.double().numpy()))
+        tol = 1.1 * (math.sqrt(1500) + math.sqrt(l)) * dB / math.sqrt(k * l) + 1e-12 * so[0]
+        assert np.all(np.abs(s - so) <= tol), (float(np.max(np.abs(s - so))), tol)
+
+
+def test_srct_repeatable_and_errors():
+    A = inputs.gaussian(400, 3000, 9, torch.float32).to(DEV)
+    assert torch.equal(re_.sketch_x(A, k=100, x="srct", seed=2), re_.sketch_x(A, k=100, x="srct", seed=2))
+    for kw, st in ((dict(x="srct", y="srct"), re_._binding.RE_ERR_UNSUPPORTED),
+                   (dict(x="srct", precision="bf16"), re_._binding.RE_ERR_UNSUPPORTED)):
+        with pytest.raises(re_.RankEstError) as e:
+            re_.rank_estimate(A, 1e-3, k=10, **kw)
+        assert e.value.status == st
+    with pytest.raises(re_.RankEstError) as e:
+        re_.sketch_x(A.double(), k=10, x="srct")
+    assert e.value.status == re_._binding.RE_ERR_UNSUPPORTED
