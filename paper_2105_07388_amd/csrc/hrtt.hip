@@ -263,9 +263,21 @@ __device__ __forceinline__ float2 split_twiddle(const float2* ts, int t) {
   return (t >> 8) ? cmul(f, ts[256 + (t >> 8)]) : f;
 }
 
-// Entries 4p .. 4p+3 of a row, zero past n, times the signs in the nibble sg.
-__device__ __forceinline__ float4 load_quad(const float* __restrict__ a, int p, int64_t n, uint32_t sg) {
+// x times the signs in the low four bits of sg (bit set: negative), by the sign bit.
+__device__ __forceinline__ float4 signed4(float4 x, uint32_t sg) {
+  x.x = __uint_as_float(__float_as_uint(x.x) ^ ((sg & 1u) << 31));
+  x.y = __uint_as_float(__float_as_uint(x.y) ^ (((sg >> 1) & 1u) << 31));
+  x.z = __uint_as_float(__float_as_uint(x.z) ^ (((sg >> 2) & 1u) << 31));
+  x.w = __uint_as_float(__float_as_uint(x.w) ^ (((sg >> 3) & 1u) << 31));
+  return x;
+}
+
+// Entries 4p .. 4p+3 of a row, zero past n (unsigned).  FULL: n covers every
+// quad, so the load has no branch and the loads of a thread stay in flight together.
+template <bool FULL>
+__device__ __forceinline__ float4 load_quad(const float* __restrict__ a, int p, int64_t n) {
   const int64_t j = 4 * (int64_t)p;
+  if (FULL) return *(const float4*)(a + j);
   float4 x;
   if (j + 3 < n) {
     x = *(const float4*)(a + j);
@@ -275,10 +287,6 @@ __device__ __forceinline__ float4 load_quad(const float* __restrict__ a, int p, 
     x.z = j + 2 < n ? a[j + 2] : 0.0f;
     x.w = 0.0f;
   }
-  if (sg & 1u) x.x = -x.x;
-  if (sg & 2u) x.y = -x.y;
-  if (sg & 4u) x.z = -x.z;
-  if (sg & 8u) x.w = -x.w;
   return x;
 }
 
@@ -363,29 +371,47 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
   const float c = sqrtf(2.0f / (float)N), c0 = sqrtf(1.0f / (float)N);
   __syncthreads();
 
+  const bool full_rows = n == N;  // every quad in range: branch-free loads
+  float4 x[FUSED ? 2 * FPAIRS : 1];
+  auto fetch = [&](const float* __restrict__ a, int t) {
+    if (full_rows) {
+#pragma unroll
+      for (int i = 0; i < FPAIRS; ++i) {
+        const int p = t + i * kRowThreads;
+        if (PFULL || p < M / 4) {
+          x[2 * i] = load_quad<true>(a, p, n);
+          x[2 * i + 1] = load_quad<true>(a, M / 2 - 1 - p, n);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < FPAIRS; ++i) {
+        const int p = t + i * kRowThreads;
+        if (PFULL || p < M / 4) {
+          x[2 * i] = load_quad<false>(a, p, n);
+          x[2 * i + 1] = load_quad<false>(a, M / 2 - 1 - p, n);
+        }
+      }
+    }
+  };
+
   for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
-    // the thread index, opaque to the optimiser here, so that the row's LDS
-    // addresses are recomputed per row instead of held (and spilled) across rows
+    // the thread index and the sign word, opaque to the optimiser here, so that
+    // the row's LDS addresses and sign masks are recomputed per row instead of
+    // held (and spilled) across rows
     int tid = tid0;
-    asm volatile("" : "+v"(tid));
+    uint32_t sg = sgn;
+    asm volatile("" : "+v"(tid), "+v"(sg));
     const float* __restrict__ a = A + row * lda;
     // 1. z (or its first radix-2 pass) into LDS
     if constexpr (FUSED) {
-      float4 x[2 * FPAIRS];
-#pragma unroll
-      for (int i = 0; i < FPAIRS; ++i) {
-        const int p = tid + i * kRowThreads;
-        if (PFULL || p < M / 4) {
-          x[2 * i] = load_quad(a, p, n, sgn >> (8 * i));
-          x[2 * i + 1] = load_quad(a, M / 2 - 1 - p, n, sgn >> (8 * i + 4));
-        }
-      }
+      fetch(a, tid);
 #pragma unroll
       for (int i = 0; i < FPAIRS; ++i) {
         const int p = tid + i * kRowThreads;
         if (PFULL || p < M / 4) {
           const int p2 = M / 2 - 1 - p;
-          const float4 u = x[2 * i], w = x[2 * i + 1];
+          const float4 u = signed4(x[2 * i], sg >> (8 * i)), w = signed4(x[2 * i + 1], sg >> (8 * i + 4));
           const float2 zp = make_float2(u.x, u.z), zp_hi = make_float2(w.w, w.y);   // z_p, z_{p + M/2}
           const float2 zq = make_float2(w.x, w.z), zq_hi = make_float2(u.w, u.y);   // z_{p2}, z_{p2 + M/2}
           Z[pz(2 * p)] = cadd(zp, zp_hi);
@@ -396,17 +422,26 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
       }
     } else if constexpr (VEC && N >= 4) {
       float4 x[QUADS];
+      if (full_rows) {
 #pragma unroll
-      for (int i = 0; i < QUADS; ++i) {
-        const int p = tid + i * kRowThreads;
-        if (QFULL || p < N / 4) x[i] = load_quad(a, p, n, sgn >> (4 * i));
+        for (int i = 0; i < QUADS; ++i) {
+          const int p = tid + i * kRowThreads;
+          if (QFULL || p < N / 4) x[i] = load_quad<true>(a, p, n);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < QUADS; ++i) {
+          const int p = tid + i * kRowThreads;
+          if (QFULL || p < N / 4) x[i] = load_quad<false>(a, p, n);
+        }
       }
 #pragma unroll
       for (int i = 0; i < QUADS; ++i) {
         const int p = tid + i * kRowThreads;
         if (QFULL || p < N / 4) {
-          Z[pz(p)] = make_float2(x[i].x, x[i].z);
-          Z[pz(M - 1 - p)] = make_float2(x[i].w, x[i].y);
+          const float4 y = signed4(x[i], sg >> (4 * i));
+          Z[pz(p)] = make_float2(y.x, y.z);
+          Z[pz(M - 1 - p)] = make_float2(y.w, y.y);
         }
       }
     } else {
@@ -433,6 +468,7 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
     } else {
       fft_rest<LGM, 0>(Z, tw, tid);
     }
+
     // 3. DCT-II values from Z: pairs (q, M - q) give (F a) at q, N - q, M + q and
     //    M - q; q = 0 gives them at 0, M, M/2 and 3M/2
     constexpr bool SFULL = M / 2 > 0 && (M / 2) % kRowThreads == 0;  // every pair slot in range
