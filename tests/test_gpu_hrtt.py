@@ -31,7 +31,8 @@ def _row_tol(orc, n, k, seed, anorm):
 
 
 @pytest.mark.parametrize("m,n,k", [(300, 1000, 64), (257, 1024, 7), (64, 2049, 384), (50, 1, 1), (33, 2, 2),
-                                   (40, 3, 4), (128, 16384, 384), (90, 700, 700)])
+                                   (40, 3, 4), (128, 16384, 384), (90, 700, 700), (70, 2048, 100), (66, 4096, 300),
+                                   (40, 8192, 1000), (48, 64, 64), (48, 512, 33)])
 def test_sketch_x_matches_oracle(orc, m, n, k):
     A = inputs.gaussian(m, n, 100 + n, torch.float32)
     seed = 17 + k
@@ -113,7 +114,8 @@ def _srct_tol(n, anorm):
 
 @pytest.mark.parametrize("m,n,k,off", [(300, 1000, 64, 0), (50, 1, 1, 0), (33, 2, 2, 0), (40, 3, 4, 0),
                                        (128, 16384, 384, 0), (90, 700, 700, 0), (64, 2049, 384, 0),
-                                       (96, 1024, 100, 1)])
+                                       (96, 1024, 100, 1), (70, 2048, 100, 0), (66, 4096, 300, 0),
+                                       (40, 8192, 1000, 0), (48, 64, 64, 0), (48, 512, 33, 0)])
 def test_srct_sketch_x_matches_oracle(orc, m, n, k, off):
     S = inputs.gaussian(m, n + off, 300 + n, torch.float32)
     A = S[:, off:off + n]
