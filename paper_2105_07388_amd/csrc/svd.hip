@@ -29,6 +29,7 @@ struct BidiagArgs {
   double* W;         // l x k working copy
   double* part;      // [2][P][k + 1] partial reductions
   double* rowbuf;    // [2][k + 1] the pivot row
+  double* red;       // [2][k + 1] reduced partials (k_bidiag_g2)
   double* d;         // k diagonal of B
   double* e;         // k - 1 superdiagonal of B
   unsigned* bar;     // grid barrier counter
@@ -285,6 +286,218 @@ __device__ bool grid_sync_coh(unsigned* bar, unsigned target, int32_t* info) {
   }
   __syncthreads();
   return ok != 0;
+}
+
+// ---- global-memory bidiagonalisation, rows held in registers --------------
+//
+// The same column steps as k_bidiag for sketches too wide for LDS, organised
+// for memory-level parallelism: one wavefront owns a row at a time and holds
+// its trailing part W[r][c .. k) in registers (lane j mod 64, up to 64 T
+// columns), so a column step reads and writes each row once: it applies both
+// reflectors and accumulates the next column's partial products x_r W[r][j]
+// from the same registers.  The P partial vectors are reduced in two levels
+// (each workgroup sums a slice of the columns over all P, then every
+// workgroup reads the reduced vector), so each column step moves 2 P (k - c)
+// partials instead of P^2 (k - c); it costs two grid barriers.  W is private
+// to the wavefront that owns each row, so only the exchanged vectors (partials,
+// reduced column, pivot row) travel by coherent stores and loads, and the
+// barriers need no cache writeback or invalidation.
+constexpr int kG2MaxP = 256;
+template <int T>
+__global__ void __launch_bounds__(kBidiagThreads) k_bidiag_g2(BidiagArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t k = a.k, l = a.l;
+  const int P = a.P, w = blockIdx.x;
+  double* wv = reinterpret_cast<double*>(smem_raw);  // [k+1] column-step coefficients w_j
+  double* vv = wv + (k + 1);                           // [k+1] row reflector v
+  double* gl = vv + (k + 1);                           // [kWaves][64 T] per-wavefront partials
+  __shared__ double s_red[kBidiagThreads];
+  __shared__ double s_scalars[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gw = w * kWaves + wave, nw = P * kWaves;  // rows r = gw (mod nw)
+  unsigned epoch = 0;
+  double rv[T], g[T];
+
+  // this wavefront's partials g (index j - 1 relative to the row segment) into
+  // LDS, then the workgroup's sum into part[par][w][0 .. n)
+  auto flush_partials = [&](int64_t par, int64_t n) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) gl[(int64_t)wave * 64 * T + lane + 64 * t] = g[t];
+    __syncthreads();
+    double* out = a.part + (par * P + w) * (k + 1);
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x)
+      st_coh(&out[j], (gl[j] + gl[64 * T + j]) + (gl[2 * 64 * T + j] + gl[3 * 64 * T + j]));
+    __syncthreads();
+  };
+
+  // copy of this workgroup's rows (non-finite input is reported) and the
+  // partials of column 0: part[j] = sum_r W[r][0] W[r][j]
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < T; ++t) g[t] = 0.0;
+  for (int64_t r = gw; r < l; r += nw) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int64_t j = lane + 64 * t;
+      rv[t] = j < k ? a.C[r * k + j] : 0.0;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int64_t j = lane + 64 * t;
+      if (j < k) {
+        bad |= !isfinite(rv[t]);
+        a.W[r * k + j] = rv[t];
+        if (r == 0) st_coh(&a.rowbuf[j], rv[t]);
+      }
+    }
+    if (bad) s_bad = 1;
+    const double x = __shfl(rv[0], 0, 64);
+#pragma unroll
+    for (int t = 0; t < T; ++t) g[t] += x * rv[t];
+  }
+  flush_partials(0, k);
+  if (s_bad) __hip_atomic_store(a.info, (int32_t)RE_ERR_NONFINITE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+
+  for (int64_t c = 0; c < k; ++c) {
+    const int64_t par = c & 1, len = k - c;
+    // ---- level 1: this workgroup's slice of the columns summed over all P partials ----
+    {
+      const int64_t S = (len + P - 1) / P, j0 = (int64_t)w * S;
+      const int64_t ns = j0 >= len ? 0 : (len - j0 < S ? len - j0 : S);
+      if (ns > kBidiagThreads) {
+        for (int64_t jj = threadIdx.x; jj < ns; jj += blockDim.x) {
+          double s = 0.0;
+          for (int p = 0; p < P; ++p) s += ld_coh(&a.part[(par * P + p) * (k + 1) + j0 + jj]);
+          st_coh(&a.red[par * (k + 1) + j0 + jj], s);
+        }
+      } else if (ns > 0) {
+        const int G = kBidiagThreads / (int)ns;  // threads per column
+        const int jj = threadIdx.x % (int)ns, gg = threadIdx.x / (int)ns;
+        double s = 0.0;
+        if (gg < G)
+          for (int p = gg; p < P; p += G) s += ld_coh(&a.part[(par * P + p) * (k + 1) + j0 + jj]);
+        s_red[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x < ns) {
+          double tot = 0.0;
+          for (int q = 0; q < G; ++q) {
+            const int idx = q * (int)ns + (int)threadIdx.x;
+            if (idx < kBidiagThreads) tot += s_red[idx];
+          }
+          st_coh(&a.red[par * (k + 1) + j0 + threadIdx.x], tot);
+        }
+      }
+    }
+    if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+    // ---- level 2: the reduced column, both reflectors (every workgroup, same arithmetic) ----
+    for (int64_t j = threadIdx.x; j < len; j += blockDim.x) wv[j] = ld_coh(&a.red[par * (k + 1) + j]);
+    for (int64_t j = threadIdx.x; j < len; j += blockDim.x) vv[j] = ld_coh(&a.rowbuf[par * (k + 1) + j]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double s0 = wv[0], x0 = vv[0];
+      const double nx = sqrt(s0);
+      double alpha = 0.0, tau = 0.0;
+      if (nx > 0.0) {
+        alpha = -copysign(nx, x0);
+        tau = 1.0 / (s0 - alpha * x0);
+      }
+      s_scalars[0] = alpha;
+      s_scalars[1] = tau;
+      s_scalars[2] = x0 - alpha;
+      if (w == 0) a.d[c] = alpha;
+    }
+    __syncthreads();
+    const double alpha = s_scalars[0], tau = s_scalars[1], u0 = s_scalars[2];
+    for (int64_t j = 1 + threadIdx.x; j < len; j += blockDim.x) {
+      const double row = vv[j];  // the pivot row, replaced by the updated row in place
+      const double wj = tau * (wv[j] - alpha * row);
+      wv[j] = wj;
+      vv[j] = row - u0 * wj;
+    }
+    __syncthreads();
+    if (len > 1) {
+      double p = 0.0;
+      for (int64_t j = 1 + threadIdx.x; j < len; j += blockDim.x) p += vv[j] * vv[j];
+      p = wave_sum(p);
+      if (lane == 0) s_red[wave] = p;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double ny2 = 0.0;
+        for (int v = 0; v < kWaves; ++v) ny2 += s_red[v];
+        const double y0 = vv[1], ny = sqrt(ny2);
+        double beta = 0.0, tau2 = 0.0;
+        if (ny > 0.0) {
+          beta = -copysign(ny, y0);
+          tau2 = 1.0 / (ny2 - beta * y0);
+        }
+        s_scalars[3] = tau2;
+        vv[1] = y0 - beta;
+        if (w == 0) a.e[c] = beta;
+      }
+      __syncthreads();
+    }
+    const double tau2 = (len > 1) ? s_scalars[3] : 0.0;
+    if (len == 1) break;
+    // ---- this wavefront's rows r > c: both reflectors, then the partials of column c + 1 ----
+#pragma unroll
+    for (int t = 0; t < T; ++t) g[t] = 0.0;
+    const int64_t par1 = par ^ 1;
+    for (int64_t r = gw; r < l; r += nw) {
+      if (r <= c) continue;
+      double* row = a.W + r * k + c;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int64_t j = lane + 64 * t;
+        rv[t] = j < len ? row[j] : 0.0;
+      }
+      const double ur = __shfl(rv[0], 0, 64);  // W[r][c]
+      double z = 0.0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int64_t j = lane + 64 * t;
+        if (j >= 1 && j < len) {
+          const double v = rv[t] - ur * wv[j];
+          rv[t] = v;
+          z += v * vv[j];
+        }
+      }
+      z = wave_sum(z) * tau2;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int64_t j = lane + 64 * t;
+        if (j >= 1 && j < len) {
+          rv[t] -= z * vv[j];
+          row[j] = rv[t];
+          if (r == c + 1) st_coh(&a.rowbuf[par1 * (k + 1) + j - 1], rv[t]);
+        }
+      }
+      const double x = __shfl(rv[0], 1, 64);  // W[r][c + 1]
+      // g[t] at lane holds the partial for j - 1 = lane + 64 t - 1: shift by one lane
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int64_t j = lane + 64 * t;
+        if (j >= 1 && j < len) g[t] += x * rv[t];
+      }
+    }
+    // g[t] belongs to index j - 1 (j = lane + 64 t): store it there
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int64_t j = lane + 64 * t;
+      if (j >= 1 && j < len) gl[(int64_t)wave * 64 * T + j - 1] = g[t];
+    }
+    __syncthreads();
+    {
+      double* out = a.part + (par1 * P + w) * (k + 1);
+      for (int64_t j = threadIdx.x; j < len - 1; j += blockDim.x)
+        st_coh(&out[j], (gl[j] + gl[64 * T + j]) + (gl[2 * 64 * T + j] + gl[3 * 64 * T + j]));
+    }
+    __syncthreads();
+    if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+  }
 }
 
 // Partials of column c from this workgroup's rows r >= c (thread per column):
@@ -884,6 +1097,17 @@ bool svd_legacy_lds() {
   return v == 1;
 }
 
+// RANKEST_SVD_LEGACY_GLOBAL=1 selects the first global-memory kernel for wide
+// sketches instead of the register-row one (comparisons).
+bool svd_legacy_global() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("RANKEST_SVD_LEGACY_GLOBAL");
+    v = (e && atoi(e) != 0) ? 1 : 0;
+  }
+  return v == 1;
+}
+
 LdsPlan lds_plan(int64_t l, int64_t k) {
   LdsPlan p{0, 0, 0};
   if (k > 1025) return p;
@@ -938,7 +1162,7 @@ RegPlan reg_plan(int64_t l, int64_t k) {
 }
 
 struct SvdLayout {
-  size_t W, part, rowbuf, d, e, bar, total;
+  size_t W, part, rowbuf, red, d, e, bar, total;
 };
 
 SvdLayout svd_layout(int64_t l, int64_t k) {
@@ -946,8 +1170,9 @@ SvdLayout svd_layout(int64_t l, int64_t k) {
   SvdLayout s{};
   size_t o = 0;
   s.W = o; o += al((size_t)l * k * 8);
-  s.part = o; o += al((size_t)2 * 64 * (k + 1) * 8);
+  s.part = o; o += al((size_t)2 * kG2MaxP * (k + 1) * 8);
   s.rowbuf = o; o += al((size_t)2 * (k + 1) * 8);
+  s.red = o; o += al((size_t)2 * (k + 1) * 8);
   s.d = o; o += al((size_t)k * 8);
   s.e = o; o += al((size_t)k * 8);
   s.bar = o; o += 256;
@@ -1051,6 +1276,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
   a.W = (double*)(base + L.W);
   a.part = (double*)(base + L.part);
   a.rowbuf = (double*)(base + L.rowbuf);
+  a.red = (double*)(base + L.red);
   a.d = (double*)(base + L.d);
   a.e = (double*)(base + L.e);
   a.bar = (unsigned*)(base + L.bar);
@@ -1118,6 +1344,23 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
       RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.bytes));
     void* params2[] = {&b2};
     RE_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(lp.P), dim3(kB2Threads), params2, (unsigned)lp.bytes, s));
+  } else if (k <= 48 * 64 && !svd_legacy_global()) {
+    // rows in registers: 32 or 48 columns per lane
+    const bool t32 = k <= 32 * 64;
+    const void* fn = t32 ? (const void*)k_bidiag_g2<32> : (const void*)k_bidiag_g2<48>;
+    const size_t lds = (size_t)(2 * (k + 1) + kWaves * 64 * (t32 ? 32 : 48)) * 8;
+    if (lds > 64 * 1024) RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int dev = 0, ncu = 0, per = 0;
+    RE_TRY_HIP(hipGetDevice(&dev));
+    RE_TRY_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    RE_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kBidiagThreads, lds));
+    int64_t P = (int64_t)ncu * (per > 0 ? per : 0);
+    if (P > kG2MaxP) P = kG2MaxP;
+    if (P > l) P = l;
+    if (P < 1) return RE_ERR_UNSUPPORTED;
+    a.P = (int)P;
+    void* params[] = {&a};
+    RE_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(a.P), dim3(kBidiagThreads), params, (unsigned)lds, s));
   } else {
     const size_t lds = (size_t)(2 * (k + 1) + kWaves * kPartChunk) * 8;
     if (lds > 160 * 1024) return RE_ERR_UNSUPPORTED;
