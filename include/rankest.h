@@ -297,6 +297,24 @@ re_status re_rank_adaptive(re_handle h, const void* A_dev, int32_t dt, int64_t m
                            const re_adaptive* ad, uint64_t seed, int32_t* r_out, double* sigma_out, int32_t* k_out,
                            int32_t* l_out, int32_t* rounds_out, int32_t* k_proposed_out, uint32_t* flags_out);
 
+/*
+ * re_rank_adaptive with the kind of Y chosen: RE_GAUSSIAN (as re_rank_adaptive)
+ * or RE_SRHT (X stays Gaussian).  Sec. 5's footnote on growing r1 with an SRTT
+ * sketch: the transform F D A X is kept and only subsampled again.  Here each
+ * new column of A X gets the signs and the first level of the Walsh-Hadamard
+ * transform along m (blocks of 256 or fewer rows) once, in place in the
+ * workspace, and every round forms the l sampled rows of the full transform
+ * from those blocks for all k columns; the samples nest in l.  The final
+ * estimate equals re_rank_estimate with Gaussian X and SRHT Y at the final
+ * (k, l) and the same seed, bit for bit.
+ *   y_kind   RE_GAUSSIAN or RE_SRHT (else RE_ERR_INVALID_ARG)
+ * Other arguments, outputs and errors as re_rank_adaptive.
+ */
+re_status re_rank_adaptive_y(re_handle h, const void* A_dev, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                             double eps, const re_adaptive* ad, int32_t y_kind, uint64_t seed, int32_t* r_out,
+                             double* sigma_out, int32_t* k_out, int32_t* l_out, int32_t* rounds_out,
+                             int32_t* k_proposed_out, uint32_t* flags_out);
+
 /* The network, FP32, on device buffers (training and inference).
  * x_dev: batch x RE_MLP_INPUTS row-major; y_dev, t_dev: batch. */
 re_status re_mlp_forward(re_handle h, const float* params_dev, const float* x_dev, int64_t batch, float* y_dev);

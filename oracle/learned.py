@@ -127,17 +127,20 @@ def l_for(k, l_ratio, m):
     return int(min(max(int(math.floor(l_ratio * k + 0.5)), k), m))
 
 
-def doubling(A, eps, seed=0, k0=32, l_ratio=1.5, kmax=None, params=None, delta=0.0):
+def doubling(A, eps, seed=0, k0=32, l_ratio=1.5, kmax=None, params=None, delta=0.0, ykind=_o.GAUSSIAN):
     """The adaptive driver: pilot at k0, then (with `params`) one round at the
     network's proposal, then doubling until r^ < r1(k) or k reaches kmax.
-    Returns dict(r, k, l, rounds, sigma, flags, k_proposed)."""
+    X is Gaussian, Y Gaussian or SRHT (`ykind`); the sketches nest in (k, l),
+    so each round is Algorithm 1 at that width (Sec. 5: rerun with a larger
+    r1 by appending to X and Y).  Returns dict(r, k, l, rounds, sigma, flags,
+    k_proposed)."""
     m, n = A.shape
     kmax = min(n, kmax or n)
     k = min(k0, kmax)
     rounds, kprop = 0, 0
     while True:
         l = l_for(k, l_ratio, m)
-        r, s, r1, flags, _ = _o.rank_estimate(A, eps, _o.GAUSSIAN, _o.GAUSSIAN, k=k, l=l, seed=seed)
+        r, s, r1, flags, _ = _o.rank_estimate(A, eps, _o.GAUSSIAN, ykind, k=k, l=l, seed=seed)
         rounds += 1
         if not (flags & _o.FLAG_NOT_CONVERGED) or k >= kmax:
             return dict(r=r, k=k, l=l, rounds=rounds, sigma=s, flags=flags, k_proposed=kprop)

@@ -88,6 +88,9 @@ def lib():
             "re_rank_adaptive": ([vp, vp, i32, i64, i64, i64, dbl, C.POINTER(ReAdaptive), u64, C.POINTER(i32), vp,
                                   C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
                                   C.POINTER(C.c_uint32)], i32),
+            "re_rank_adaptive_y": ([vp, vp, i32, i64, i64, i64, dbl, C.POINTER(ReAdaptive), i32, u64, C.POINTER(i32),
+                                    vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                    C.POINTER(C.c_uint32)], i32),
             "re_rangefinder": ([vp, vp, i32, i64, i64, i64, dbl, i32, C.POINTER(ReAdaptive), dbl, u64, vp, i64, vp,
                                 i64, C.POINTER(i32), C.POINTER(i32), vp, C.POINTER(i32), C.POINTER(C.c_uint32)], i32),
             "re_rangefinder_stage_ms": ([vp, vp], i32),
@@ -248,8 +251,10 @@ def rank_estimate_qr(A: torch.Tensor, eps: float, *, k: int, l: int = 0, x: str 
 
 
 def rank_adaptive(A: torch.Tensor, eps: float, *, k0: int = 32, k_max: int = 0, l_ratio: float = 1.5,
-                  mlp: torch.Tensor | None = None, delta: float = 0.0, seed: int = 0, handle: Handle | None = None):
-    """Rank estimate with an adaptive sketch width (FP32 A, Gaussian sketches):
+                  mlp: torch.Tensor | None = None, delta: float = 0.0, seed: int = 0, y: str = "gaussian",
+                  handle: Handle | None = None):
+    """Rank estimate with an adaptive sketch width (FP32 A, Gaussian X; Y
+    Gaussian or, with y="srht", the SRHT grown from its stored transform):
     doubling from k0, or the network's proposal after the pilot when `mlp`
     (device float32 parameter vector) is given.  Returns (r, sigma, info) with
     info = {k, l, rounds, k_proposed, flags}."""
@@ -265,9 +270,15 @@ def rank_adaptive(A: torch.Tensor, eps: float, *, k0: int = 32, k_max: int = 0, 
     sigma = np.zeros(kcap, dtype=np.float64)
     r, kk, ll, rounds, kp = (C.c_int32(0) for _ in range(5))
     fl = C.c_uint32(0)
-    st = lib().re_rank_adaptive(h.bind(), _ptr(A), _dtype_code(A), m, n, A.stride(0), float(eps), C.byref(ad),
-                                int(seed) % 2**64, C.byref(r), sigma.ctypes.data_as(C.c_void_p), C.byref(kk),
-                                C.byref(ll), C.byref(rounds), C.byref(kp), C.byref(fl))
+    if y == "gaussian":
+        st = lib().re_rank_adaptive(h.bind(), _ptr(A), _dtype_code(A), m, n, A.stride(0), float(eps), C.byref(ad),
+                                    int(seed) % 2**64, C.byref(r), sigma.ctypes.data_as(C.c_void_p), C.byref(kk),
+                                    C.byref(ll), C.byref(rounds), C.byref(kp), C.byref(fl))
+    else:
+        st = lib().re_rank_adaptive_y(h.bind(), _ptr(A), _dtype_code(A), m, n, A.stride(0), float(eps),
+                                      C.byref(ad), KIND[y], int(seed) % 2**64, C.byref(r),
+                                      sigma.ctypes.data_as(C.c_void_p), C.byref(kk), C.byref(ll), C.byref(rounds),
+                                      C.byref(kp), C.byref(fl))
     _check(st, "re_rank_adaptive")
     return r.value, sigma[:kk.value], {"k": kk.value, "l": ll.value, "rounds": rounds.value,
                                        "k_proposed": kp.value, "flags": fl.value}

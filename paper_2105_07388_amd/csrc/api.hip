@@ -841,7 +841,7 @@ void pilot_features(const double* s, int64_t k, int64_t m, int64_t n, double eps
 }
 
 struct AdPlan {
-  size_t B, Xn, Y, C, svd, sigma, info, out3, gdesc, ydesc, queue, feat, yout, yparts, total;
+  size_t B, Xn, Y, C, svd, sigma, info, out3, gdesc, ydesc, queue, feat, yout, yparts, ybits, ysel, selscr, total;
 };
 
 // Largest Y B scratch over the widths an adaptive run may visit (k0 doubling,
@@ -863,11 +863,17 @@ size_t yb_scratch_adaptive(int64_t k0, int64_t kmax, double ratio, int64_t m) {
 }  // namespace
 }  // namespace re
 
-RE_API re_status re_rank_adaptive(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
-                                  double eps, const re_adaptive* ad, uint64_t seed, int32_t* r_out, double* sigma_out,
-                                  int32_t* k_out, int32_t* l_out, int32_t* rounds_out, int32_t* k_proposed_out,
-                                  uint32_t* flags_out) {
+// The adaptive driver for a Gaussian or an SRHT Y (X Gaussian).  With the SRHT
+// Y the first level of its transform along m (signs and blocks of rows) is
+// applied once to each new column of A X and kept in place: the stored
+// F D A X of Sec. 5 (footnote on growing an SRTT sketch), from which every
+// round forms its l sampled rows for all k columns.
+static re_status adaptive_impl(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda, double eps,
+                        const re_adaptive* ad, int32_t yk, uint64_t seed, int32_t* r_out, double* sigma_out,
+                        int32_t* k_out, int32_t* l_out, int32_t* rounds_out, int32_t* k_proposed_out,
+                        uint32_t* flags_out) {
   if (!h || !A || !ad || !r_out || !sigma_out) return RE_ERR_INVALID_ARG;
+  if (yk != RE_GAUSSIAN && yk != RE_SRHT) return RE_ERR_INVALID_ARG;
   if (dt != RE_F64 && dt != RE_F32) return RE_ERR_INVALID_ARG;
   if (dt != RE_F32) return RE_ERR_UNSUPPORTED;
   if (!(eps > 0.0 && eps < 1.0) || m < 1 || n < 1 || lda < n || lda >= kMaxBatchLda || ((uintptr_t)A) % 4 != 0)
@@ -877,11 +883,16 @@ RE_API re_status re_rank_adaptive(re_handle h, const void* A, int32_t dt, int64_
   if (ad->k_max > 0 && ad->k_max < kmax) kmax = ad->k_max;
   if (kmax > RE_MAX_ADAPTIVE_K) kmax = RE_MAX_ADAPTIVE_K;
   const int64_t lmax = l_for(kmax, ad->l_ratio, m);
+  const bool srht_y = yk == RE_SRHT;
+  const int64_t npad_m = next_pow2(m);
   AdPlan p{};
   Carve c;
-  p.B = c.take((size_t)m * kmax * 4);
+  p.B = c.take((size_t)(srht_y ? (int64_t)srht_cols_rows_alloc(m) : m) * kmax * 4);
   p.Xn = c.take((size_t)n * kmax * 4);
-  p.Y = c.take((size_t)lmax * m * 4);
+  p.Y = c.take(srht_y ? 0 : (size_t)lmax * m * 4);
+  p.ybits = c.take(srht_y ? (size_t)cdiv(npad_m, 32) * 4 : 0);
+  p.ysel = c.take(srht_y ? (size_t)lmax * 4 : 0);
+  p.selscr = c.take(srht_y ? select_scratch_bytes(npad_m) : 0);
   p.C = c.take((size_t)lmax * kmax * 8);
   p.svd = c.take(svd_scratch_bytes(lmax, kmax));
   p.sigma = c.take((size_t)kmax * 8);
@@ -892,7 +903,7 @@ RE_API re_status re_rank_adaptive(re_handle h, const void* A, int32_t dt, int64_
   p.queue = c.take(16);
   p.feat = c.take(RE_MLP_INPUTS * 4);
   p.yout = c.take(16);
-  p.yparts = c.take(yb_scratch_adaptive(ad->k0, kmax, ad->l_ratio, m));
+  p.yparts = c.take(srht_y ? 0 : yb_scratch_adaptive(ad->k0, kmax, ad->l_ratio, m));
   p.total = c.off;
   RE_TRY(ensure_ws(h, p.total));
   RE_TRY(ensure_host(h, 256 + (size_t)kmax * 8));  // out3 | sigma | features
@@ -912,8 +923,17 @@ RE_API re_status re_rank_adaptive(re_handle h, const void* A, int32_t dt, int64_
     RE_TRY(launch_gauss_sub(s, n, k - k_old, 0, k_old, seed, kXGauss, 0, k - k_old, (float*)at(h, p.Xn)));
     RE_TRY(launch_gemm_f32_single(s, (const float*)A, m, n, lda, (const float*)at(h, p.Xn), k - k_old, B + k_old, kmax,
                                   (GemmDesc*)at(h, p.gdesc), (unsigned*)at(h, p.queue)));
-    RE_TRY(launch_gauss_sub(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, Y + l_old * m));
-    RE_TRY(run_yb(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, p.ydesc), at(h, p.yparts)));
+    if (srht_y) {
+      uint32_t* ybits = (uint32_t*)at(h, p.ybits);
+      int32_t* ysel = (int32_t*)at(h, p.ysel);
+      if (k_old == 0) RE_TRY(launch_sign_bits(s, npad_m, seed, kYSign, ybits));
+      RE_TRY(launch_srht_cols_lo(s, B + k_old, RE_F32, m, k - k_old, kmax, ybits));  // the new columns of F D A X
+      RE_TRY(launch_select(s, npad_m, l, seed, kYSel, at(h, p.selscr), ysel));     // nested in l
+      RE_TRY(launch_srht_cols_hi(s, B, RE_F32, m, k, kmax, ysel, l, C));
+    } else {
+      RE_TRY(launch_gauss_sub(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, Y + l_old * m));
+      RE_TRY(run_yb(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, p.ydesc), at(h, p.yparts)));
+    }
     // steps 7-8
     RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, p.svd), sigma, info));
     RE_TRY(launch_rank_count(s, sigma, k, r1_from_k((int32_t)k), eps, info, out3));
@@ -956,6 +976,22 @@ RE_API re_status re_rank_adaptive(re_handle h, const void* A, int32_t dt, int64_
       k = 2 * k < kmax ? 2 * k : kmax;
     }
   }
+}
+
+RE_API re_status re_rank_adaptive(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                                  double eps, const re_adaptive* ad, uint64_t seed, int32_t* r_out, double* sigma_out,
+                                  int32_t* k_out, int32_t* l_out, int32_t* rounds_out, int32_t* k_proposed_out,
+                                  uint32_t* flags_out) {
+  return adaptive_impl(h, A, dt, m, n, lda, eps, ad, RE_GAUSSIAN, seed, r_out, sigma_out, k_out, l_out, rounds_out,
+                       k_proposed_out, flags_out);
+}
+
+RE_API re_status re_rank_adaptive_y(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                                    double eps, const re_adaptive* ad, int32_t y_kind, uint64_t seed, int32_t* r_out,
+                                    double* sigma_out, int32_t* k_out, int32_t* l_out, int32_t* rounds_out,
+                                    int32_t* k_proposed_out, uint32_t* flags_out) {
+  return adaptive_impl(h, A, dt, m, n, lda, eps, ad, y_kind, seed, r_out, sigma_out, k_out, l_out, rounds_out,
+                       k_proposed_out, flags_out);
 }
 
 namespace re {

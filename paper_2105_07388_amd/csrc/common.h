@@ -130,6 +130,13 @@ RE_HIDDEN re_status launch_srht_rows(hipStream_t s, const void* A, int dtype, in
 RE_HIDDEN size_t srht_cols_rows_alloc(int64_t m);  // rows B must provide
 RE_HIDDEN re_status launch_srht_cols(hipStream_t s, void* B, int bdtype, int64_t m, int64_t k,
                                      const uint32_t* sign_bits, const int32_t* sel, int64_t l, double* C);
+// Its two levels separately, on k columns of a matrix with leading dimension
+// ldb: the first transforms blocks of rows in place (signs applied), the
+// second forms the l sampled rows from those blocks.
+RE_HIDDEN re_status launch_srht_cols_lo(hipStream_t s, void* B, int bdtype, int64_t m, int64_t k, int64_t ldb,
+                                        const uint32_t* sign_bits);
+RE_HIDDEN re_status launch_srht_cols_hi(hipStream_t s, const void* B, int bdtype, int64_t m, int64_t k, int64_t ldb,
+                                        const int32_t* sel, int64_t l, double* C);
 
 // Dense products for Gaussian sketches.
 // C[M x N] (ldc) = A[M x K] (lda, type ta) * B[K x N] (ldb, type tb), FP64 accumulate, output type tc.

@@ -288,8 +288,8 @@ __global__ void __launch_bounds__(512, 2) __attribute__((amdgpu_waves_per_eu(4))
 constexpr int kColTile = 64;
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_srht_cols_lo(T* __restrict__ B, int64_t m, int64_t k, int logL,
-                                                      const uint32_t* __restrict__ bits) {
+__global__ void __launch_bounds__(256) k_srht_cols_lo(T* __restrict__ B, int64_t m, int64_t k, int64_t ldb,
+                                                      int logL, const uint32_t* __restrict__ bits) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* s = reinterpret_cast<T*>(smem_raw);  // [L][kColTile]
   const int L = 1 << logL;
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(256) k_srht_cols_lo(T* __restrict__ B, int64_t
   for (int r = tr; r < L; r += rstep) {
     const int64_t row = row0 + r;
     T v = T(0);
-    if (row < m && col < k) v = apply_sign<T>(B[row * k + col], sign_neg(bits, row));
+    if (row < m && col < k) v = apply_sign<T>(B[row * ldb + col], sign_neg(bits, row));
     s[r * kColTile + tc] = v;
   }
   for (int lh = 0; lh < logL; ++lh) {
@@ -316,12 +316,12 @@ __global__ void __launch_bounds__(256) k_srht_cols_lo(T* __restrict__ B, int64_t
   }
   __syncthreads();
   if (col < k)
-    for (int r = tr; r < L; r += rstep) B[(row0 + r) * k + col] = s[r * kColTile + tc];
+    for (int r = tr; r < L; r += rstep) B[(row0 + r) * ldb + col] = s[r * kColTile + tc];
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_srht_cols_hi(const T* __restrict__ Z, int64_t nblk, int64_t k, int logL,
-                                                      const int32_t* __restrict__ sel, int64_t l,
+__global__ void __launch_bounds__(256) k_srht_cols_hi(const T* __restrict__ Z, int64_t nblk, int64_t k, int64_t ldz,
+                                                      int logL, const int32_t* __restrict__ sel, int64_t l,
                                                       double* __restrict__ C) {
   const int64_t total = l * k;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(256) k_srht_cols_hi(const T* __restrict__ Z, i
     const int64_t hi = idx >> logL, lo = idx & ((int64_t(1) << logL) - 1);
     double acc = 0.0;
     for (int64_t b = 0; b < nblk; ++b) {
-      const double z = (double)Z[((b << logL) + lo) * k + t];
+      const double z = (double)Z[((b << logL) + lo) * ldz + t];
       acc += (__popcll((unsigned long long)(hi & b)) & 1) ? -z : z;
     }
     C[e] = acc;
@@ -403,29 +403,47 @@ size_t srht_cols_rows_alloc(int64_t m) {
   return (size_t)(cdiv(m, L) * L);
 }
 
-re_status launch_srht_cols(hipStream_t s, void* B, int bdtype, int64_t m, int64_t k, const uint32_t* bits,
-                           const int32_t* sel, int64_t l, double* C) {
-  if (m <= 0 || k <= 0 || l <= 0) return RE_OK;
+re_status launch_srht_cols_lo(hipStream_t s, void* B, int bdtype, int64_t m, int64_t k, int64_t ldb,
+                              const uint32_t* bits) {
+  if (m <= 0 || k <= 0) return RE_OK;
   const int logL = cols_logL(m);
   const int64_t L = int64_t(1) << logL;
-  const int64_t nblk = cdiv(m, L);
-  const dim3 glo((unsigned)nblk, (unsigned)cdiv(k, kColTile));
-  const int64_t total = l * k;
-  const int ghi = (int)(cdiv(total, 256) < 65536 ? cdiv(total, 256) : 65536);
+  const dim3 glo((unsigned)cdiv(m, L), (unsigned)cdiv(k, kColTile));
   if (bdtype == RE_F32) {
     const size_t lds = (size_t)L * kColTile * sizeof(float);
     RE_TRY(allow_lds(k_srht_cols_lo<float>, lds));
-    hipLaunchKernelGGL(k_srht_cols_lo<float>, glo, dim3(256), lds, s, (float*)B, m, k, logL, bits);
-    hipLaunchKernelGGL(k_srht_cols_hi<float>, dim3(ghi), dim3(256), 0, s, (const float*)B, nblk, k, logL, sel, l, C);
+    hipLaunchKernelGGL(k_srht_cols_lo<float>, glo, dim3(256), lds, s, (float*)B, m, k, ldb, logL, bits);
   } else {
     const size_t lds = (size_t)L * kColTile * sizeof(double);
     RE_TRY(allow_lds(k_srht_cols_lo<double>, lds));
-    hipLaunchKernelGGL(k_srht_cols_lo<double>, glo, dim3(256), lds, s, (double*)B, m, k, logL, bits);
-    hipLaunchKernelGGL(k_srht_cols_hi<double>, dim3(ghi), dim3(256), 0, s, (const double*)B, nblk, k, logL, sel, l,
-                       C);
+    hipLaunchKernelGGL(k_srht_cols_lo<double>, glo, dim3(256), lds, s, (double*)B, m, k, ldb, logL, bits);
   }
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
+}
+
+re_status launch_srht_cols_hi(hipStream_t s, const void* B, int bdtype, int64_t m, int64_t k, int64_t ldb,
+                              const int32_t* sel, int64_t l, double* C) {
+  if (m <= 0 || k <= 0 || l <= 0) return RE_OK;
+  const int logL = cols_logL(m);
+  const int64_t nblk = cdiv(m, int64_t(1) << logL);
+  const int64_t total = l * k;
+  const int ghi = (int)(cdiv(total, 256) < 65536 ? cdiv(total, 256) : 65536);
+  if (bdtype == RE_F32)
+    hipLaunchKernelGGL(k_srht_cols_hi<float>, dim3(ghi), dim3(256), 0, s, (const float*)B, nblk, k, ldb, logL, sel, l,
+                       C);
+  else
+    hipLaunchKernelGGL(k_srht_cols_hi<double>, dim3(ghi), dim3(256), 0, s, (const double*)B, nblk, k, ldb, logL, sel,
+                       l, C);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
+
+re_status launch_srht_cols(hipStream_t s, void* B, int bdtype, int64_t m, int64_t k, const uint32_t* bits,
+                           const int32_t* sel, int64_t l, double* C) {
+  if (m <= 0 || k <= 0 || l <= 0) return RE_OK;
+  RE_TRY(launch_srht_cols_lo(s, B, bdtype, m, k, k, bits));
+  return launch_srht_cols_hi(s, B, bdtype, m, k, k, sel, l, C);
 }
 
 }  // namespace re

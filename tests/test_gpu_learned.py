@@ -131,6 +131,35 @@ def test_adaptive_limits_and_errors():
     assert ei.value.status == -1
 
 
+@pytest.mark.parametrize("m,n,rank", [(800, 400, 50), (1000, 500, 120), (3000, 1200, 250)])
+def test_adaptive_srht_y_matches_oracle_and_single_call(orc, m, n, rank):
+    # the SRHT Y grown from its stored first-level transform (Sec. 5 footnote):
+    # the final round equals one call at the final width, bit for bit
+    A = _planted32(m, n, rank, 40 + rank)
+    Ad = A.to(DEV)
+    r, s, info = re_.rank_adaptive(Ad, 1e-6, seed=5, y="srht")
+    out = orc.learned.doubling(A.numpy(), 1e-6, seed=5, ykind=orc.SRHT)
+    assert (info["k"], info["l"], info["rounds"]) == (out["k"], out["l"], out["rounds"])
+    assert r == out["r"] == rank
+    tol = 8 * 2.0**-24 * math.sqrt(n) * out["sigma"][0]
+    assert np.all(np.abs(s - out["sigma"]) <= tol)
+    r1, s1, info1 = re_.rank_estimate(Ad, 1e-6, k=info["k"], l=info["l"], x="gaussian", y="srht", seed=5)
+    assert r == r1 and np.array_equal(s, s1) and info["flags"] == info1["flags"]
+
+
+def test_adaptive_srht_y_limits_and_errors():
+    A = _planted32(300, 100, 95, 3).to(DEV)
+    r, s, info = re_.rank_adaptive(A, 1e-6, seed=1, y="srht")
+    assert info["k"] == 100 and info["flags"] & re_.FLAG_NOT_CONVERGED
+    r, s, info = re_.rank_adaptive(A, 1e-6, k_max=48, seed=1, y="srht")
+    assert info["k"] == 48 and info["rounds"] == 2
+    r1, s1, _ = re_.rank_estimate(A, 1e-6, k=48, l=info["l"], x="gaussian", y="srht", seed=1)
+    assert r == r1 and np.array_equal(s, s1)
+    with pytest.raises(re_.RankEstError) as ei:
+        re_.rank_adaptive(A, 1e-6, y="hrtt")
+    assert ei.value.status == -1
+
+
 def test_trained_policy_beats_doubling():
     """The committed network against plain doubling on unseen matrices: fewer
     rounds on average, and at least the same agreement with the planted rank."""

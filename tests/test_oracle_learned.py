@@ -93,6 +93,17 @@ def test_doubling_converges_at_first_sufficient_width(L, orc, rank, rounds, kfin
     assert k == kfinal
 
 
+@pytest.mark.parametrize("rank,rounds,kfinal", [(50, 2, 64), (120, 4, 256)])
+def test_doubling_with_an_srht_y(L, orc, rank, rounds, kfinal):
+    # the same closed form with the SRHT Y (m = 600: padded to 1024 rows), and
+    # the final round is Algorithm 1 at that width
+    A = inputs.planted(600, 400, inputs.spectrum_step(400, rank, 1.0, 1e-10), 60 + rank).numpy()
+    out = L.doubling(A, 1e-6, seed=5, ykind=orc.SRHT)
+    assert (out["rounds"], out["k"], out["r"]) == (rounds, kfinal, rank)
+    r, s, r1, fl, _ = orc.rank_estimate(A, 1e-6, orc.GAUSSIAN, orc.SRHT, k=out["k"], l=out["l"], seed=5)
+    assert r == out["r"] and np.array_equal(s, out["sigma"])
+
+
 def test_learned_round_uses_the_proposal(L):
     A = inputs.planted(600, 400, inputs.spectrum_step(400, 120, 1.0, 1e-10), 180).numpy()
     p = np.zeros(L.N_PARAMS)
