@@ -57,6 +57,10 @@ WORKLOADS = {
                desc="step 7 by the QR diagonal (Sec. 5): the plain method at scale (FP32 65536x16384, SRHT X 384, "
                     "SRHT Y 576, eps 1e-3/1e-5) with |diag R| of Y A X in place of its singular values; also timed "
                     "against the SVD at Gaussian k = 1650, l = 3300"),
+    "ady": dict(m=65536, n=16384, R=1024, k0=32, l_ratio=1.5, eps=(1e-3, 1e-5), x="gaussian", y="srht",
+                desc="adaptive width with the SRHT Y grown from its stored transform (Sec. 5 footnote): the plain-method "
+                     "matrix (FP32 65536x16384, s_i=10^(-i/20), R=1024, + 1e-9 noise), Gaussian X doubling from 32, "
+                     "l = 1.5 k, eps 1e-3/1e-5; the Gaussian Y timed on the same calls"),
     "c1": dict(m=2000, n=1000, R=1000, k=40, l=60, eps=(1e-6,), x="gaussian", y="gaussian",
                desc="plain method, CPU-sized: FP64 2000x1000, step spectrum (20 x 1, then 1e-8), "
                     "Gaussian X 1000x40, Gaussian Y 60x2000, eps 1e-6"),
@@ -95,7 +99,7 @@ def make_matrix(name, w, device):
     import torch
 
     from paper_2105_07388_amd import inputs
-    if name in ("c2", "qr", "hrtt", "srct"):
+    if name in ("c2", "qr", "hrtt", "srct", "ady"):
         return inputs.c2_matrix(w["m"], w["n"], w["R"], device=device)
     if name == "c1":
         return inputs.c1_matrix(device=device)
@@ -316,6 +320,62 @@ def bench_learned(args, w, dev):
         "doubling": res["doubling"],
         "speedup_vs_doubling": res["learned"]["estimates_per_s"] / res["doubling"]["estimates_per_s"],
         "same_rank_learned_vs_doubling": same,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_adaptive_y(args, w, dev):
+    """One step = one adaptive estimate (doubling from k0) with the SRHT Y grown
+    from its stored first-level transform, eps alternating; the same call with
+    a Gaussian Y timed back to back on the same seed for comparison."""
+    import numpy as np
+    import torch
+
+    import paper_2105_07388_amd as re_
+    A = make_matrix("ady", w, dev)
+    torch.cuda.synchronize()
+    print(f"[bench] ady: A {tuple(A.shape)} {A.dtype} resident; warmup {args.warmup}", file=sys.stderr, flush=True)
+    h = re_.Handle(dev)
+
+    def call(y, i):
+        eps = w["eps"][i % len(w["eps"])]
+        r, _, info = re_.rank_adaptive(A, eps, k0=w["k0"], l_ratio=w["l_ratio"], seed=100 + i, y=y, handle=h)
+        return r, info["rounds"], info["k"], info["l"]
+
+    for i in range(args.warmup):
+        call("srht", i)
+        call("gaussian", i)
+    torch.cuda.synchronize()
+    tsum = {"srht": 0.0, "gaussian": 0.0}
+    outs = {"srht": [], "gaussian": []}
+    for i in range(args.steps):
+        for y in (("srht", "gaussian") if i % 2 == 0 else ("gaussian", "srht")):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            outs[y].append(call(y, i))
+            torch.cuda.synchronize()
+            tsum[y] += time.perf_counter() - t0
+    res = {y: {"estimates_per_s": args.steps / tsum[y], "ms_per_estimate": 1e3 * tsum[y] / args.steps,
+               "mean_rounds": float(np.mean([o[1] for o in outs[y]])), "final_k_l": sorted(set((o[2], o[3]) for o in outs[y])),
+               "ranks": sorted(set(o[0] for o in outs[y]))} for y in tsum}
+    print(f"[bench] srht y {res['srht']}; gaussian y {res['gaussian']}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "rank estimates/s + sketch GB/s vs HBM peak; learned vs doubling, same rank",
+        "value": res["srht"]["estimates_per_s"],
+        "unit": "rank estimates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["srht"]["ms_per_estimate"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "m": w["m"], "n": w["n"], "k0": w["k0"], "eps": list(w["eps"]),
+                   "x": w["x"], "y": w["y"], "parallelism": "single GPU"},
+        "srht_y": res["srht"],
+        "gaussian_y": res["gaussian"],
     }
     print(json.dumps(out), flush=True)
 
@@ -563,6 +623,8 @@ def main():
         return bench_rf(args, w, dev)
     if args.workload == "qr":
         return bench_qr(args, w, dev)
+    if args.workload == "ady":
+        return bench_adaptive_y(args, w, dev)
     A = make_matrix(args.workload, w, dev)
     torch.cuda.synchronize()
     h = re_.Handle(dev)
