@@ -88,10 +88,13 @@ __global__ void __launch_bounds__(256 * WM) k_gemm_lp(const float* __restrict__ 
   const int64_t row0 = (int64_t)rb * BM, col0 = (int64_t)cb * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = (tid >> 6) & 3, wm = tid >> 8;
 
-  // global -> register staging of one K step
-  fx4 ra[2];
+  // global -> register staging: A DA K steps ahead (it streams from HBM; three
+  // steps where the registers allow it: four measured slower), X one step ahead (every workgroup
+  // walks the same K range, so X stays in L2)
+  constexpr int DA = WM == 2 ? 3 : 1;
+  fx4 ra0[2], ra1[2], ra2[2];
   u32x4 rx[BN * 4 / NTH];
-  auto load_tile = [&](int64_t k0) {
+  auto load_a = [&](int64_t k0, fx4 (&ra)[2]) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int r = (tid >> 3) + (NTH / 8) * i, kk = 4 * (tid & 7);
@@ -107,6 +110,8 @@ __global__ void __launch_bounds__(256 * WM) k_gemm_lp(const float* __restrict__ 
       }
       ra[i] = v;
     }
+  };
+  auto load_x = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < BN * 4 / NTH; ++i) {
       const int c = (tid >> 2) + (NTH / 4) * i, kk = 8 * (tid & 3);
@@ -126,7 +131,7 @@ __global__ void __launch_bounds__(256 * WM) k_gemm_lp(const float* __restrict__ 
       rx[i] = v;
     }
   };
-  auto store_tile = [&](int buf) {
+  auto store_tile = [&](int buf, const fx4 (&ra)[2]) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int r = (tid >> 3) + (NTH / 8) * i, kk = 4 * (tid & 7);
@@ -153,12 +158,7 @@ __global__ void __launch_bounds__(256 * WM) k_gemm_lp(const float* __restrict__ 
       for (int q = 0; q < 16; ++q) acc[mi][ni][q] = 0.f;
 
   const int64_t nsteps = (n + kBK - 1) / kBK;
-  load_tile(0);
-  store_tile(0);
-  __syncthreads();
-  for (int64_t st = 0; st < nsteps; ++st) {
-    const int buf = st & 1;
-    if (st + 1 < nsteps) load_tile((st + 1) * kBK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       // operand fragments: lane l takes row/column l % 32 and K values 8 (l / 32) .. + 7
@@ -175,10 +175,35 @@ __global__ void __launch_bounds__(256 * WM) k_gemm_lp(const float* __restrict__ 
 #pragma unroll
         for (int ni = 0; ni < NT; ++ni) acc[mi][ni] = Tr::mfma(af[mi], bf[ni], acc[mi][ni]);
     }
+  };
+  // step st computes from LDS buffer st & 1; A of steps st + 1 .. st + DA is in
+  // flight (DA = 3: set j holds the steps = j mod 3; DA = 1: one set)
+  load_a(0, ra0);
+  load_x(0);
+  if constexpr (DA == 3) {
+    if (nsteps > 1) load_a(kBK, ra1);
+    if (nsteps > 2) load_a(2 * kBK, ra2);
+  }
+  store_tile(0, ra0);
+  __syncthreads();
+  auto step = [&](int64_t st, fx4 (&ra_next)[2], fx4 (&ra_free)[2]) {
+    // ra_next holds A of step st + 1; ra_free (step st, already in LDS) takes st + DA
+    if (st + 1 < nsteps) load_x((st + 1) * kBK);
+    if (st + DA < nsteps) load_a((st + DA) * kBK, ra_free);
+    compute(st & 1);
     if (st + 1 < nsteps) {
-      store_tile(buf ^ 1);
+      store_tile((st & 1) ^ 1, ra_next);
       __syncthreads();
     }
+  };
+  if constexpr (DA == 3) {
+    for (int64_t st = 0; st < nsteps; st += 3) {
+      step(st, ra1, ra0);
+      if (st + 1 < nsteps) step(st + 1, ra2, ra1);
+      if (st + 2 < nsteps) step(st + 2, ra0, ra2);
+    }
+  } else {
+    for (int64_t st = 0; st < nsteps; ++st) step(st, ra0, ra0);
   }
   // accumulator layout of a 32x32 tile: value q of lane l is at
   // row 8 (q / 4) + 4 (l / 32) + (q % 4), column l % 32
