@@ -161,3 +161,24 @@ def test_srct_repeatable_and_errors():
     with pytest.raises(re_.RankEstError) as e:
         re_.sketch_x(A.double(), k=10, x="srct")
     assert e.value.status == re_._binding.RE_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("x", ["hrtt", "srct"])
+def test_dct_kinds_full_size_sampled_rows(orc, x):
+    # the benchmark's shape and launch configuration (512 workgroups, rows
+    # r = w + 512 t): rows at workgroup and pass boundaries against the oracle
+    m, n, k = 65536, 16384, 384
+    A = inputs.c2_matrix(device=DEV)
+    seed = 21
+    B = re_.sketch_x(A, k=k, x=x, seed=seed)
+    rows = np.array([0, 1, 511, 512, 513, 1023, 32767, 32768, 65023, 65535])
+    An = A[torch.as_tensor(rows, device=DEV)].cpu().numpy()
+    got = B[torch.as_tensor(rows, device=DEV)].cpu().numpy().astype(np.float64)
+    if x == "hrtt":
+        want = orc.hrtt.apply_x(An, k, seed=seed)
+        tol = np.array([_row_tol(orc, n, k, seed, float(np.linalg.norm(a))) for a in An.astype(np.float64)])
+    else:
+        want = orc.hrtt.apply_x_srct(An, k, seed=seed)
+        tol = np.array([_srct_tol(n, float(np.linalg.norm(a))) for a in An.astype(np.float64)])
+    err = np.linalg.norm(got - want, axis=1)
+    assert np.all(err <= tol), float(np.max(err / tol))
