@@ -172,3 +172,12 @@ def test_trained_policy_beats_doubling():
     assert out["learned"]["rank_agreement"] >= out["doubling"]["rank_agreement"] - 1.0 / 16
     if out["step_same_rank"] is not None:
         assert out["step_same_rank"] == 1.0
+
+
+def test_adaptive_srht_y_full_size_equals_single_call():
+    # the stored-transform growth on the benchmark's 65536 x 16384 matrix
+    A = inputs.c2_matrix(device=DEV)
+    for eps in (1e-3, 1e-5):
+        r, s, info = re_.rank_adaptive(A, eps, seed=31, y="srht")
+        r1, s1, info1 = re_.rank_estimate(A, eps, k=info["k"], l=info["l"], x="gaussian", y="srht", seed=31)
+        assert info["rounds"] >= 2 and r == r1 and np.array_equal(s, s1) and info["flags"] == info1["flags"]

@@ -100,3 +100,22 @@ def test_wide_sketch_uses_the_blocked_factorisation(orc):
     E = 8 * (1200 + l * k) * U64 * np.linalg.norm(Co)
     tol = E * (1 + _kappa(Co)) / math.sqrt(k * l)
     assert np.max(np.abs(d - do)) <= tol, (np.max(np.abs(d - do)), tol)
+
+
+def test_full_size_against_the_oracle(orc):
+    # the benchmark's matrix (FP32 65536 x 16384, s_i = 10^(-i/20)) with SRHT
+    # X 384 and Y 576: the leading 20 sorted |R_jj| within the first-order bound
+    # with the FP32 sketch's statistical error (2e-5 s_1, as the SVD form's
+    # full-size test), the rank up to the oracle values inside that band
+    A = inputs.c2_matrix(device=DEV)
+    An = A.cpu().numpy()
+    k, l = 384, 576
+    for eps, seed in ((1e-3, 6), (1e-5, 7)):
+        r, d, info = re_.rank_estimate_qr(A, eps, k=k, l=l, x="srht", y="srht", seed=seed)
+        ro, do, r1, fl = orc.qrdiag.rank_estimate_qr(An, eps, orc.SRHT, orc.SRHT, k=k, l=l, seed=seed)
+        Co = orc.qrdiag.sketch(An, orc.SRHT, orc.SRHT, k, l, seed=seed)
+        E = 2e-5 * do[0]
+        tol = E * (1 + _kappa(Co[:, :20]))
+        assert np.max(np.abs(d[:20] - do[:20])) <= tol, (np.max(np.abs(d[:20] - do[:20])), tol)
+        band = int(np.count_nonzero(np.abs(do[:r1] - eps * do[0]) <= E * (1 + _kappa(Co))))
+        assert abs(r - ro) <= band and info["r1"] == r1
