@@ -337,6 +337,134 @@ __global__ void __launch_bounds__(256) k_srht_cols_hi(const T* __restrict__ Z, i
   }
 }
 
+// ---------------------------------------------------------------------------
+// Y side, FP32 with L = 256 and four-column vectors: the same butterflies and
+// the same block sums as the two kernels above, in the same order (identical
+// results), arranged so that every thread issues all of its loads at once.
+//   lo: a workgroup owns 256 rows x 64 columns.  Thread (q = tid & 15,
+//       g = tid >> 4) first holds rows 16 g + i (i < 16) of columns 4q..4q+3
+//       and runs the stages over row bits 0..3 in registers; the tile passes
+//       through LDS once, after which the thread holds rows g + 16 i and runs
+//       the stages over bits 4..7.
+//   hi: a workgroup owns one low index v and 64 columns: it stages the rows
+//       b L + v of every block b in LDS, then each sample s with lo(S'_s) = v
+//       adds its signed terms over ascending b in FP64.
+// ---------------------------------------------------------------------------
+constexpr int kMaxBlkV = 512;  // blocks the hi kernel stages (m <= 131072)
+
+__device__ __forceinline__ void bfly4(fx4& x, fx4& y) {
+  const fx4 a = x, b = y;
+  x = a + b;
+  y = a - b;
+}
+
+__device__ __forceinline__ void bfly16(fx4 (&v)[16]) {
+#pragma unroll
+  for (int h = 1; h < 16; h <<= 1)
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (!(i & h)) bfly4(v[i], v[i + h]);
+}
+
+__global__ void __launch_bounds__(256) k_srht_cols_lo_v(float* __restrict__ B, int64_t m, int64_t k, int64_t ldb,
+                                                        const uint32_t* __restrict__ bits) {
+  __shared__ __align__(16) float s[256 * kColTile];
+  const int64_t row0 = (int64_t)blockIdx.x * 256;
+  const int tid = threadIdx.x, q = tid & 15, g = tid >> 4;
+  const int64_t col = (int64_t)blockIdx.y * kColTile + 4 * q;
+  const bool has = col < k;  // k % 4 == 0: all four columns or none
+  const fx4 zero = {0.f, 0.f, 0.f, 0.f};
+  fx4 v[16];
+  // sign bits of rows 16 g .. 16 g + 15 (row0 is a multiple of 256)
+  const uint32_t word = row0 + 16 * g < m ? bits[(row0 + 16 * g) >> 5] >> ((16 * g) & 16) : 0u;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int64_t row = row0 + 16 * g + i;
+    v[i] = (has && row < m) ? *reinterpret_cast<const fx4*>(B + row * ldb + col) : zero;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int64_t row = row0 + 16 * g + i;
+    if (row < m && ((word >> i) & 1u)) v[i] = -v[i];
+  }
+  bfly16(v);  // stages over row bits 0..3
+#pragma unroll
+  for (int i = 0; i < 16; ++i) *reinterpret_cast<fx4*>(s + (16 * g + i) * kColTile + 4 * q) = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = *reinterpret_cast<const fx4*>(s + (g + 16 * i) * kColTile + 4 * q);
+  bfly16(v);  // stages over row bits 4..7
+  if (has)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) *reinterpret_cast<fx4*>(B + (row0 + g + 16 * i) * ldb + col) = v[i];
+}
+
+__global__ void __launch_bounds__(256) k_srht_cols_hi_v(const float* __restrict__ Z, int nblk, int64_t k,
+                                                        int64_t ldz, const int32_t* __restrict__ sel, int64_t l,
+                                                        double* __restrict__ C) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* s = reinterpret_cast<float*>(smem_raw);  // [nblk][kColTile]
+  __shared__ int list[kMaxBlkV];
+  __shared__ int wcnt[4];
+  const int v = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t c0 = (int64_t)blockIdx.y * kColTile;
+  const int q = tid & 15, g = tid >> 4;
+  const bool has = c0 + 4 * q < k;
+  const fx4 zero = {0.f, 0.f, 0.f, 0.f};
+  // the first 256 blocks' rows are requested before the sample scan so that
+  // the scan runs under their latency
+  fx4 r[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int b = g + 16 * i;
+    r[i] = (has && b < nblk) ? *reinterpret_cast<const fx4*>(Z + ((int64_t)b * 256 + v) * ldz + c0 + 4 * q) : zero;
+  }
+  // the samples with low index v, in ascending order (distinct rows, so at
+  // most one per block: nblk <= kMaxBlkV)
+  int tot = 0;
+  for (int64_t w0 = 0; w0 < l; w0 += 256) {
+    const int64_t e = w0 + tid;
+    const bool hit = e < l && (sel[e] & 255) == v;
+    const uint64_t mask = __ballot(hit);
+    if (lane == 0) wcnt[wave] = __popcll(mask);
+    __syncthreads();
+    int pos = tot + __popcll(mask & ((1ull << lane) - 1));
+    for (int w = 0; w < wave; ++w) pos += wcnt[w];
+    if (hit && pos < kMaxBlkV) list[pos] = (int)e;
+    tot += (wcnt[0] + wcnt[1]) + (wcnt[2] + wcnt[3]);
+    __syncthreads();
+  }
+  if (tot == 0) return;  // uniform: no sample has this low index
+  if (tot > kMaxBlkV) tot = kMaxBlkV;
+  for (int b0 = 0; b0 < nblk; b0 += 256) {
+    if (b0 > 0)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int b = b0 + g + 16 * i;
+        r[i] = (has && b < nblk) ? *reinterpret_cast<const fx4*>(Z + ((int64_t)b * 256 + v) * ldz + c0 + 4 * q) : zero;
+      }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int b = b0 + g + 16 * i;
+      if (b < nblk) *reinterpret_cast<fx4*>(s + b * kColTile + 4 * q) = r[i];
+    }
+  }
+  __syncthreads();
+  for (int o = tid; o < tot * kColTile; o += 256) {
+    const int t = o & (kColTile - 1);
+    if (c0 + t >= k) continue;
+    const int64_t srow = list[o / kColTile];
+    const int64_t hi = sel[srow] >> 8;
+    double acc = 0.0;
+#pragma unroll 16
+    for (int b = 0; b < nblk; ++b) {
+      const double z = (double)s[b * kColTile + t];
+      acc += (__popcll((unsigned long long)(hi & b)) & 1) ? -z : z;
+    }
+    C[srow * k + c0 + t] = acc;
+  }
+}
+
 int lds_limit() { return 160 * 1024; }
 
 template <typename K>
@@ -409,7 +537,9 @@ re_status launch_srht_cols_lo(hipStream_t s, void* B, int bdtype, int64_t m, int
   const int logL = cols_logL(m);
   const int64_t L = int64_t(1) << logL;
   const dim3 glo((unsigned)cdiv(m, L), (unsigned)cdiv(k, kColTile));
-  if (bdtype == RE_F32) {
+  if (bdtype == RE_F32 && logL == 8 && k % 4 == 0 && ldb % 4 == 0 && ((uintptr_t)B & 15) == 0) {
+    hipLaunchKernelGGL(k_srht_cols_lo_v, glo, dim3(256), 0, s, (float*)B, m, k, ldb, bits);
+  } else if (bdtype == RE_F32) {
     const size_t lds = (size_t)L * kColTile * sizeof(float);
     RE_TRY(allow_lds(k_srht_cols_lo<float>, lds));
     hipLaunchKernelGGL(k_srht_cols_lo<float>, glo, dim3(256), lds, s, (float*)B, m, k, ldb, logL, bits);
@@ -429,7 +559,12 @@ re_status launch_srht_cols_hi(hipStream_t s, const void* B, int bdtype, int64_t 
   const int64_t nblk = cdiv(m, int64_t(1) << logL);
   const int64_t total = l * k;
   const int ghi = (int)(cdiv(total, 256) < 65536 ? cdiv(total, 256) : 65536);
-  if (bdtype == RE_F32)
+  if (bdtype == RE_F32 && logL == 8 && nblk <= kMaxBlkV && k % 4 == 0 && ldb % 4 == 0 && ((uintptr_t)B & 15) == 0) {
+    const size_t lds = (size_t)nblk * kColTile * sizeof(float);
+    RE_TRY(allow_lds(k_srht_cols_hi_v, lds));
+    hipLaunchKernelGGL(k_srht_cols_hi_v, dim3(256, (unsigned)cdiv(k, kColTile)), dim3(256), lds, s, (const float*)B,
+                       (int)nblk, k, ldb, sel, l, C);
+  } else if (bdtype == RE_F32)
     hipLaunchKernelGGL(k_srht_cols_hi<float>, dim3(ghi), dim3(256), 0, s, (const float*)B, nblk, k, ldb, logL, sel, l,
                        C);
   else
