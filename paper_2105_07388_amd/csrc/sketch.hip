@@ -78,29 +78,6 @@ __device__ __forceinline__ bool key_less(uint64_t ka, uint32_t ia, uint64_t kb, 
   return ka < kb || (ka == kb && ia < ib);
 }
 
-// In-LDS bitonic sort of n2 (a power of two) (key, idx) pairs, ascending.
-__device__ void bitonic_sort(uint64_t* key, uint32_t* idx, int n2) {
-  for (int size = 2; size <= n2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = threadIdx.x; t < (n2 >> 1); t += blockDim.x) {
-        const int lo = 2 * t - (t & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = ((lo & size) == 0);
-        const bool swap = up ? key_less(key[hi], idx[hi], key[lo], idx[lo]) : key_less(key[lo], idx[lo], key[hi], idx[hi]);
-        if (swap) {
-          const uint64_t tk = key[lo];
-          key[lo] = key[hi];
-          key[hi] = tk;
-          const uint32_t ti = idx[lo];
-          idx[lo] = idx[hi];
-          idx[hi] = ti;
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
 // Exclusive prefix sum over the workgroup of one value per thread.
 __device__ int block_exclusive_scan(int v, int* buf, int* total) {
   const int t = threadIdx.x;
@@ -119,45 +96,120 @@ __device__ int block_exclusive_scan(int v, int* buf, int* total) {
   return incl - v;
 }
 
-__global__ void __launch_bounds__(kSelThreads) k_sel_finish(int64_t npad, int64_t k, const uint64_t* __restrict__ keys,
+// Exclusive prefix sum over the workgroup of one value per thread, by
+// wavefront shuffles and one pass over the wavefront totals.
+__device__ int block_exclusive_scan_fast(int v, int* wsum) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wave; ++w) before += wsum[w];
+  (void)nw;
+  __syncthreads();
+  return before + x - v;
+}
+
+__global__ void __launch_bounds__(kSelThreads) k_sel_finish(int64_t npad, int64_t k, uint64_t thresh,
+                                                            const uint64_t* __restrict__ keys,
                                                             const ulonglong2* __restrict__ cand,
                                                             const int32_t* __restrict__ cnt, int32_t* __restrict__ out) {
-  __shared__ uint64_t skey[kSelCap];
-  __shared__ uint32_t sidx[kSelCap];
+  constexpr int NB = kSelThreads;           // buckets, one per thread
+  constexpr int PER = kSelCap / kSelThreads;  // candidates per thread
+  __shared__ int hcnt[NB], bstart[NB], bfill[NB];
+  __shared__ int slot[kSelCap];
+  __shared__ int wsum[kSelThreads / 64];
   __shared__ int scan_buf[kSelThreads];
   __shared__ unsigned hist[256];
   __shared__ uint64_t s_prefix;
   __shared__ int64_t s_rank;
   const int c = *cnt;
+  const int t = threadIdx.x;
   if (c >= k && c <= kSelCap) {
-    int n2 = 1;
-    while (n2 < c) n2 <<= 1;
-    for (int t = threadIdx.x; t < n2; t += blockDim.x) {
-      if (t < c) {
-        skey[t] = cand[t].x;
-        sidx[t] = (uint32_t)cand[t].y;
-      } else {
-        skey[t] = ~0ull;
-        sidx[t] = 0xffffffffu;
+    // Fast path: the k smallest (key, index) pairs among the c candidates,
+    // written in ascending index order.  Ranks come from a counting sort over
+    // monotone buckets (the top bits of the key below thresh, then of the
+    // index) followed by comparisons within each bucket.
+    int sh = 0;
+    while (((thresh - 1) >> sh) >= (uint64_t)NB) ++sh;
+    int shi = 0;
+    while ((uint64_t)((npad - 1) >> shi) >= (uint64_t)NB) ++shi;
+    uint64_t key[PER];
+    uint32_t idx[PER];
+    int bk[PER];
+    hcnt[t] = 0;
+    bfill[t] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = t + u * kSelThreads;
+      key[u] = 0;
+      idx[u] = 0;
+      bk[u] = 0;
+      if (i < c) {
+        const ulonglong2 e = cand[i];
+        key[u] = e.x;
+        idx[u] = (uint32_t)e.y;
+        bk[u] = (int)(e.x >> sh);
+        atomicAdd(&hcnt[bk[u]], 1);
       }
     }
     __syncthreads();
-    bitonic_sort(skey, sidx, n2);
-    int k2 = 1;
-    while (k2 < k) k2 <<= 1;
-    // keep the k smallest, then order them by index
-    uint32_t keep[kSelCap / kSelThreads];
-    int nk = 0;
-    for (int t = threadIdx.x; t < k2; t += blockDim.x) keep[nk++] = (t < k) ? sidx[t] : 0xffffffffu;
+    bstart[t] = block_exclusive_scan_fast(hcnt[t], wsum);
     __syncthreads();
-    nk = 0;
-    for (int t = threadIdx.x; t < k2; t += blockDim.x) {
-      skey[t] = keep[nk];
-      sidx[t] = keep[nk++];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = t + u * kSelThreads;
+      if (i < c) slot[bstart[bk[u]] + atomicAdd(&bfill[bk[u]], 1)] = i;
     }
     __syncthreads();
-    bitonic_sort(skey, sidx, k2);
-    for (int t = threadIdx.x; t < k; t += blockDim.x) out[t] = (int32_t)sidx[t];
+    bool keep[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = t + u * kSelThreads;
+      keep[u] = false;
+      if (i < c) {
+        int rank = bstart[bk[u]];
+        const int p1 = bstart[bk[u]] + hcnt[bk[u]];
+        for (int p = bstart[bk[u]]; p < p1; ++p) {
+          const int j = slot[p];
+          if (j == i) continue;
+          const ulonglong2 o = cand[j];
+          rank += key_less(o.x, (uint32_t)o.y, key[u], idx[u]);
+        }
+        keep[u] = rank < k;
+      }
+    }
+    __syncthreads();
+    // the kept indices in ascending order: the same counting sort over index buckets
+    hcnt[t] = 0;
+    bfill[t] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      bk[u] = (int)(idx[u] >> shi);
+      if (keep[u]) atomicAdd(&hcnt[bk[u]], 1);
+    }
+    __syncthreads();
+    bstart[t] = block_exclusive_scan_fast(hcnt[t], wsum);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+      if (keep[u]) slot[bstart[bk[u]] + atomicAdd(&bfill[bk[u]], 1)] = (int)idx[u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      if (!keep[u]) continue;
+      int pos = bstart[bk[u]];
+      const int p1 = bstart[bk[u]] + hcnt[bk[u]];
+      for (int p = bstart[bk[u]]; p < p1; ++p) pos += ((uint32_t)slot[p] < idx[u]);
+      out[pos] = (int32_t)idx[u];
+    }
     return;
   }
   // Exact path: most-significant-digit radix selection of the k-th smallest
@@ -277,7 +329,7 @@ re_status launch_select(hipStream_t s, int64_t npad, int64_t k, uint64_t seed, i
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, cnt, 1);
   hipLaunchKernelGGL(k_sel_keys, dim3(grid_for(npad, 256, 1024)), dim3(256), 0, s, npad, seed, (uint64_t)stream_id,
                      thresh, keys, cand, cnt);
-  hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(kSelThreads), 0, s, npad, k, keys, cand, cnt, idx);
+  hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(kSelThreads), 0, s, npad, k, thresh, keys, cand, cnt, idx);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
 }

@@ -932,26 +932,65 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_1wg(SmallBatch sb) {
 
 // ---- singular values of the bidiagonal by multisection on Sturm counts ----
 
-// Number of eigenvalues below x > 0 of the Golub-Kahan tridiagonal with zero
-// diagonal and off-diagonal b[0..nb), minus the k negative ones: the number
-// of singular values below x.
-// bb[j] = b[j]^2; the pivots q_j of the LDL^T factorisation of T - x I follow
-// q_j = -x - bb[j-1] / q_{j-1}, the division done as a hardware reciprocal
-// refined by one Newton step.
+// Sturm counts of the Golub-Kahan tridiagonal T of order n = nb + 1 = 2k (zero
+// diagonal, off-diagonal b[0..nb), bb[j] = b[j]^2) at a shift x > 0.  The
+// number of eigenvalues of T below x, minus its k negative ones, is the
+// number of singular values below x; by Sylvester's law of inertia it is the
+// number of negative pivots of T - x I.  Each pivot comes from the previous
+// one by a division, done as a hardware reciprocal refined by one Newton step;
+// a pivot smaller in magnitude than pivmin is replaced by -pivmin.
+__device__ __forceinline__ double sturm_step(double piv, double bbj, double x, double pivmin) {
+  double r = __builtin_amdgcn_rcp(piv);
+  r = fma(r, fma(-piv, r, 1.0), r);
+  const double nxt = fma(-bbj, r, -x);
+  return fabs(nxt) < pivmin ? -pivmin : nxt;
+}
+
+// The LDL^T pivots top-down: q_0 = -x, q_j = -x - bb[j-1] / q_{j-1}.
 __device__ int count_below(const double* bb, int nb, double x, double pivmin) {
   double q = -x;
-  int neg = 1;  // q0 = -x < 0
+  int neg = 1;  // q_0 = -x < 0
 #pragma unroll 4
   for (int j = 0; j < nb; ++j) {
-    double r = __builtin_amdgcn_rcp(q);
-    r = fma(r, fma(-q, r, 1.0), r);
-    q = fma(-bb[j], r, -x);
-    if (fabs(q) < pivmin) q = -pivmin;
+    q = sturm_step(q, bb[j], x, pivmin);
     neg += (q < 0.0);
   }
   return neg - (nb + 1) / 2;
 }
 
+// The two halves of the factorisation twisted at row r = k, which has the
+// same inertia: top-down q_0 .. q_r as above, bottom-up p_{n-1} = -x,
+// p_j = -x - bb[j] / p_{j+1} down to p_r, and the pivot of row r,
+// g = q_r + p_r + x.  Each half returns its last pivot and the negatives
+// before it (q_0 .. q_{r-1}, respectively p_{n-1} .. p_{r+1}).
+__device__ double sturm_top(const double* bb, int r, double x, double pivmin, int& neg) {
+  double q = -x;
+  int ng = 0;
+#pragma unroll 4
+  for (int j = 0; j < r; ++j) {
+    ng += (q < 0.0);
+    q = sturm_step(q, bb[j], x, pivmin);
+  }
+  neg = ng;
+  return q;
+}
+
+__device__ double sturm_bottom(const double* bb, int nb, int r, double x, double pivmin, int& neg) {
+  double p = -x;
+  int ng = 0;
+#pragma unroll 4
+  for (int j = nb - 1; j >= r; --j) {
+    ng += (p < 0.0);
+    p = sturm_step(p, bb[j], x, pivmin);
+  }
+  neg = ng;
+  return p;
+}
+
+// Singular values of the bidiagonal (d, e) by 64-way multisection on the
+// Sturm counts: a pair of wavefronts per value, one running each half of the
+// twisted factorisation (the count's dependent chain is issue-bound, so the
+// halves go to different SIMDs), meeting in LDS once per multisection round.
 __global__ void __launch_bounds__(256) k_bidiag_sv(const double* __restrict__ d, const double* __restrict__ e,
                                                    int64_t k, double scale, const int32_t* __restrict__ info,
                                                    double* __restrict__ sigma) {
@@ -959,6 +998,9 @@ __global__ void __launch_bounds__(256) k_bidiag_sv(const double* __restrict__ d,
   double* b = reinterpret_cast<double*>(smem_raw);  // 2k - 1 off-diagonal entries
   const int nb = (int)(2 * k - 1);
   double* bb = b + nb;                                // their squares
+  __shared__ double s_piv[2][64];
+  __shared__ int s_neg[2][64];
+  __shared__ double s_iv[2][2];
   double bound = 0.0, maxb2 = 0.0;
   for (int j = threadIdx.x; j < nb; j += blockDim.x) {
     b[j] = (j & 1) ? e[j >> 1] : d[j >> 1];
@@ -974,23 +1016,42 @@ __global__ void __launch_bounds__(256) k_bidiag_sv(const double* __restrict__ d,
   const bool all_zero = !(bound > 0.0);  // B = 0 (NaN is reported through info)
   bound = bound * (1.0 + 1e-14) + 1e-300;
   const double pivmin = 0x1.0p-1022 * fmax(1.0, maxb2);
-  const int lane = threadIdx.x & 63;
-  const int64_t waves = blockDim.x / 64;
-  for (int64_t jj = blockIdx.x * waves + (threadIdx.x >> 6); jj < k; jj += (int64_t)gridDim.x * waves) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int slot = wave >> 1, bottom = wave & 1;  // two values per workgroup
+  const int r = (nb + 1) >> 1;
+  for (int64_t base = 2 * (int64_t)blockIdx.x; base < k; base += 2 * (int64_t)gridDim.x) {
+    const int64_t jj = base + slot;
+    const bool act = jj < k;
     // jj-th largest singular value: #{sigma < lo} <= k-1-jj < #{sigma < hi}
     const int want = (int)(k - 1 - jj);
     double lo = 0.0, hi = bound;
     for (int it = 0; it < 9; ++it) {  // 65^9 > 2^54: below one ulp of the bound
       const double x = lo + (hi - lo) * (double)(lane + 1) * (1.0 / 65.0);
-      const int cnt = count_below(bb, nb, x, pivmin);
-      const uint64_t le = __ballot(cnt <= want);  // monotone in lane
-      const int nle = __popcll(le);               // lanes 0..nle-1 satisfy cnt <= want
-      const double nlo = nle > 0 ? lo + (hi - lo) * (double)nle * (1.0 / 65.0) : lo;
-      const double nhi = nle < 64 ? lo + (hi - lo) * (double)(nle + 1) * (1.0 / 65.0) : hi;
-      lo = nlo;
-      hi = nhi;
+      int ng = 0;
+      double piv = 0.0;
+      if (act) piv = bottom ? sturm_bottom(bb, nb, r, x, pivmin, ng) : sturm_top(bb, r, x, pivmin, ng);
+      if (bottom) {
+        s_piv[slot][lane] = piv;
+        s_neg[slot][lane] = ng;
+      }
+      __syncthreads();
+      if (!bottom && act) {
+        double g = piv + s_piv[slot][lane] + x;
+        if (fabs(g) < pivmin) g = -pivmin;
+        const int cnt = ng + s_neg[slot][lane] + (g < 0.0) - r;
+        const uint64_t le = __ballot(cnt <= want);  // monotone in lane
+        const int nle = __popcll(le);               // lanes 0..nle-1 satisfy cnt <= want
+        if (lane == 0) {
+          s_iv[slot][0] = nle > 0 ? lo + (hi - lo) * (double)nle * (1.0 / 65.0) : lo;
+          s_iv[slot][1] = nle < 64 ? lo + (hi - lo) * (double)(nle + 1) * (1.0 / 65.0) : hi;
+        }
+      }
+      __syncthreads();
+      lo = s_iv[slot][0];
+      hi = s_iv[slot][1];
     }
-    if (lane == 0) sigma[jj] = all_zero ? 0.0 : 0.5 * (lo + hi) * scale;
+    if (act && !bottom && lane == 0) sigma[jj] = all_zero ? 0.0 : 0.5 * (lo + hi) * scale;
+    __syncthreads();
   }
   (void)info;
 }
@@ -1385,9 +1446,8 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
   }
   if (lds2 > 64 * 1024)
     RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag_sv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
-  const int waves_per_block = 4;
-  const int blocks = (int)cdiv(k, waves_per_block);
-  hipLaunchKernelGGL(k_bidiag_sv, dim3(blocks), dim3(64 * waves_per_block), lds2, s, a.d, a.e, k, scale, info, sigma);
+  const int blocks = (int)cdiv(k, 2);  // two values per workgroup of four wavefronts
+  hipLaunchKernelGGL(k_bidiag_sv, dim3(blocks), dim3(256), lds2, s, a.d, a.e, k, scale, info, sigma);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
 }
