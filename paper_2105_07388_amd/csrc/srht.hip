@@ -450,18 +450,21 @@ __global__ void __launch_bounds__(256) k_srht_cols_hi_v(const float* __restrict_
     }
   }
   __syncthreads();
-  for (int o = tid; o < tot * kColTile; o += 256) {
-    const int t = o & (kColTile - 1);
-    if (c0 + t >= k) continue;
-    const int64_t srow = list[o / kColTile];
-    const int64_t hi = sel[srow] >> 8;
+  // wavefront w takes the samples w, w + 4, ...: its 64 lanes are the 64
+  // columns of one sample, so the sample's high index and the sign of each
+  // block are uniform (scalar unit); the sign goes onto the FP32 value before
+  // it is widened, which gives the same FP64 terms as negating after
+  for (int o0 = wave * kColTile; o0 < tot * kColTile; o0 += 256) {
+    const int64_t srow = list[o0 / kColTile];
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane(sel[srow] >> 8);
+    if (c0 + lane >= k) continue;
     double acc = 0.0;
 #pragma unroll 16
     for (int b = 0; b < nblk; ++b) {
-      const double z = (double)s[b * kColTile + t];
-      acc += (__popcll((unsigned long long)(hi & b)) & 1) ? -z : z;
+      const uint32_t neg = (uint32_t)(__builtin_popcount(hi & (uint32_t)b) & 1) << 31;
+      acc += (double)__uint_as_float(__float_as_uint(s[b * kColTile + lane]) ^ neg);
     }
-    C[srow * k + c0 + t] = acc;
+    C[srow * k + c0 + lane] = acc;
   }
 }
 

@@ -64,8 +64,9 @@ def test_signs_bit_exact(orc):
         assert np.array_equal(1 - 2 * d, want)
 
 
+# (65536, 5000): more candidates below the threshold than the fast path holds (4096): the exact path
 @pytest.mark.parametrize("npad,k", [(1, 1), (16, 5), (1024, 40), (16384, 384), (65536, 576), (1024, 1024),
-                                    (4096, 3000), (8192, 1)])
+                                    (4096, 3000), (8192, 1), (65536, 5000)])
 def test_select_exact(orc, npad, k):
     for seed, stream in [(3, 5), (4, 6)]:
         got = _np(re_.srht_select(npad, k, seed, stream)).astype(np.int64)
