@@ -147,6 +147,18 @@ def test_adaptive_srht_y_matches_oracle_and_single_call(orc, m, n, rank):
     assert r == r1 and np.array_equal(s, s1) and info["flags"] == info1["flags"]
 
 
+def test_adaptive_srht_y_unaligned_store_equals_single_call():
+    # k_max = 130 gives the stored transform a leading dimension that is not a
+    # multiple of 4, so the growth takes the one-element-per-thread Y kernels;
+    # the single call at the final k = 64 takes the four-column vector kernels.
+    # Both perform the same butterflies and block sums in the same order.
+    A = _planted32(2000, 800, 50, 77).to(DEV)
+    r, s, info = re_.rank_adaptive(A, 1e-6, k_max=130, seed=9, y="srht")
+    assert info["k"] == 64 and info["rounds"] == 2 and r == 50
+    r1, s1, info1 = re_.rank_estimate(A, 1e-6, k=64, l=info["l"], x="gaussian", y="srht", seed=9)
+    assert r == r1 and np.array_equal(s, s1) and info["flags"] == info1["flags"]
+
+
 def test_adaptive_srht_y_limits_and_errors():
     A = _planted32(300, 100, 95, 3).to(DEV)
     r, s, info = re_.rank_adaptive(A, 1e-6, seed=1, y="srht")
