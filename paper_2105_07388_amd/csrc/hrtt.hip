@@ -36,6 +36,7 @@ constexpr int kRowThreads = 512;
 // a thread's chunk of the list (N / 512 entries) fits the 32-bit run-end mask
 static_assert(kHrttMaxN / kRowThreads <= 32, "list chunk larger than the run-end mask");
 constexpr int kBuildThreads = 1024;
+static_assert(kHrttMaxN <= 16 * kBuildThreads, "the hash sort holds at most 16 keys per thread");
 
 // Hash lists and their run structure, one workgroup.  Each coordinate j gets
 // the key (bucket << 15) | (j << 1) | sign; a bitonic sort of the N keys in
@@ -52,29 +53,82 @@ __global__ void __launch_bounds__(kBuildThreads) k_hash_build(int N, int k, uint
                                                               uint32_t* __restrict__ ends,
                                                               int32_t* __restrict__ rbase, int32_t* __restrict__ rlo,
                                                               int32_t* __restrict__ rhi) {
-  extern __shared__ uint32_t key[];  // N keys, then k + 1 bucket starts
-  int32_t* sptr = (int32_t*)(key + N);
+  extern __shared__ uint32_t key[];  // N keys, then N + 1 words: the sort's buffer, later the k + 1 bucket starts
+  uint32_t* tmp = key + N;
+  int32_t* sptr = (int32_t*)(key + N);  // written only after the sorted keys are back in key
   __shared__ uint32_t smask[kRowThreads];
   __shared__ int32_t sbase[kRowThreads];
-  const int tid = threadIdx.x, nth = blockDim.x;
+  __shared__ int wsum[kBuildThreads / 64];
+  const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6;
   for (int j = tid; j < N; j += nth) {
     const u64x4 w = philox((uint64_t)j, 0, kXHashStream, 0, seed);
     const uint32_t b = (uint32_t)__umul64hi(w.x, (uint64_t)k);
     key[j] = (b << 15) | ((uint32_t)j << 1) | (uint32_t)(w.y & 1u);
   }
   __syncthreads();
-  for (int size = 2; size <= N; size <<= 1)
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < N / 2; i += nth) {
-        const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1)), hi = lo + stride;
-        const uint32_t a = key[lo], c = key[hi];
-        if ((a > c) == ((lo & size) == 0)) {
-          key[lo] = c;
-          key[hi] = a;
+  // Sort by (bucket, index): a stable least-significant-digit radix sort on
+  // the bucket bits, one bit per pass, of keys that start in index order.
+  // Thread t owns the E consecutive positions from t E; a pass counts its
+  // zeros, finds the zeros before it by a workgroup prefix sum and writes
+  // zeros then ones, each in their order, to the other buffer.
+  {
+    const int E = (N + nth - 1) / nth;
+    const int p0 = tid * E < N ? tid * E : N, p1 = p0 + E < N ? p0 + E : N;
+    int nbits = 0;
+    while ((1 << nbits) < k) ++nbits;
+    uint32_t* src = key;
+    uint32_t* dst = tmp;
+    const int cnt = p1 - p0;  // 0 or E (N and nth are powers of two, E <= 16)
+    for (int bit = 0; bit < nbits; ++bit) {
+      const int sh = 15 + bit;
+      // the thread's keys into registers, as 16-byte reads when E = 16
+      uint32_t v[16];
+      if (E == 16 && cnt == 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint4 x = *reinterpret_cast<const uint4*>(src + p0 + 4 * q);
+          v[4 * q] = x.x;
+          v[4 * q + 1] = x.y;
+          v[4 * q + 2] = x.z;
+          v[4 * q + 3] = x.w;
         }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = e < cnt ? src[p0 + e] : 0u;
       }
+      int z = 0;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) z += (e < cnt) & !((v[e] >> sh) & 1u);
+      int incl = z;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+      }
+      if (lane == 63) wsum[wave] = incl;
+      __syncthreads();
+      int before = 0, total = 0;
+      for (int w = 0; w < nth / 64; ++w) {
+        before += w < wave ? wsum[w] : 0;
+        total += wsum[w];
+      }
+      int zi = before + incl - z, oi = total + (p0 - (before + incl - z));
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        if (e >= cnt) break;
+        if ((v[e] >> sh) & 1u) dst[oi++] = v[e];
+        else dst[zi++] = v[e];
+      }
+      __syncthreads();  // dst complete; wsum free for the next pass
+      uint32_t* t = src;
+      src = dst;
+      dst = t;
+    }
+    if (src != key) {
+      for (int p = tid; p < N; p += nth) key[p] = src[p];
       __syncthreads();
     }
+  }
   // list, bucket starts (every bucket from the previous key's up to this one starts here)
   for (int p = tid; p < N; p += nth) {
     const uint32_t kp = key[p];
@@ -671,7 +725,7 @@ re_status launch_hrtt_hash(hipStream_t s, int64_t n, int64_t k, uint64_t seed, v
   const int64_t N = hrtt_npad(n);
   if (N > kHrttMaxN || k < 1 || k > N) return RE_ERR_UNSUPPORTED;
   const HashScratch h = carve_hash(scratch, N, k);
-  const size_t lds_build = (size_t)(N + k + 1) * 4;  // keys and bucket starts
+  const size_t lds_build = (size_t)(2 * N + 1) * 4;  // keys, then the sort buffer that later holds the k + 1 <= N + 1 bucket starts
   if (lds_build > 65536)
     RE_TRY_HIP(hipFuncSetAttribute((const void*)k_hash_build, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds_build));
