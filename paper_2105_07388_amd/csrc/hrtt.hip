@@ -39,8 +39,8 @@ constexpr int kBuildThreads = 1024;
 static_assert(kHrttMaxN <= 16 * kBuildThreads, "the hash sort holds at most 16 keys per thread");
 
 // Hash lists and their run structure, one workgroup.  Each coordinate j gets
-// the key (bucket << 15) | (j << 1) | sign; a bitonic sort of the N keys in
-// LDS puts them in (bucket, j) order.  ptr[0..k] = first list position of each
+// the key (bucket << 15) | (j << 1) | sign; a stable radix sort of the N keys
+// on their bucket bits, in LDS, puts them in (bucket, j) order.  ptr[0..k] = first list position of each
 // bucket (ptr[k] = N); list[ptr[b] ..] = the coordinates of bucket b in
 // increasing order, the sign in bit 31; code16[p] = the same entry in 16 bits
 // (coordinate, sign in bit 15).  The list is cut into chunks of C =
