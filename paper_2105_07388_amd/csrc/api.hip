@@ -166,11 +166,13 @@ bool batched_fits(int64_t l, int64_t k) { return k <= 4096 && batched_svd_lds_by
 // C = Y B for FP32 B and Y: the batched form's kernel for every sketch the
 // batched form accepts (a block of a batch and the same matrix alone then give
 // the same bits), the tiled product with a split over m for wider ones.
-size_t yb_scratch(int64_t l, int64_t k, int64_t m) { return batched_fits(l, k) ? 0 : yb_parts_bytes(l, k, m); }
+size_t yb_scratch(int64_t l, int64_t k, int64_t m) {
+  return batched_fits(l, k) ? ygemm_split_bytes(l, k, m) : yb_parts_bytes(l, k, m);
+}
 
 re_status run_yb(hipStream_t s, const float* B, int64_t m, int64_t k, int64_t ldb, const float* Y, int64_t ldy,
                  int64_t l, double* C, YDesc* yd, void* parts) {
-  if (batched_fits(l, k)) return launch_ygemm_single(s, B, m, k, ldb, Y, ldy, l, C, yd);
+  if (batched_fits(l, k)) return launch_ygemm_single(s, B, m, k, ldb, Y, ldy, l, C, yd, (double*)parts);
   return launch_yb_tiled(s, B, m, k, ldb, Y, ldy, l, C, (double*)parts);
 }
 

@@ -55,10 +55,13 @@ __attribute__((visibility("hidden"))) re_status launch_gemm_f32_single(hipStream
 __attribute__((visibility("hidden"))) re_status launch_gauss_sub(hipStream_t s, int64_t rows, int64_t cols, int64_t r0,
                                                                 int64_t c0, uint64_t seed, int stream_id, int swap_ab,
                                                                 int64_t ld, float* out);
-// C = Y[:, :m] B (l x k FP64) for one block with the batched kernel.
+// C = Y[:, :m] B (l x k FP64) for one block with the batched kernel's
+// arithmetic; with m above one group of rows it splits m over workgroups,
+// which needs ygemm_split_bytes(l, k, m) of `parts` (nullptr: no split).
 __attribute__((visibility("hidden"))) re_status launch_ygemm_single(hipStream_t s, const float* B, int64_t m, int64_t k,
                                                                    int64_t ldb, const float* Y, int64_t ldy, int64_t l,
-                                                                   double* C, YDesc* dscratch);
+                                                                   double* C, YDesc* dscratch, double* parts);
+__attribute__((visibility("hidden"))) size_t ygemm_split_bytes(int64_t l, int64_t k, int64_t m);
 __attribute__((visibility("hidden"))) re_status launch_gauss_master(hipStream_t s, const BatchHeader* hdr, int64_t nmax,
                                                                    int64_t k, int64_t l, int64_t mmax, float* X,
                                                                    float* Y);
@@ -70,6 +73,9 @@ __attribute__((visibility("hidden"))) int64_t gemm_items(int64_t m, int64_t k, i
 __attribute__((visibility("hidden"))) int gemm_col_chunks(int64_t k);
 __attribute__((visibility("hidden"))) re_status launch_ygemm_batched(hipStream_t s, const YDesc* desc, int nblk,
                                                                     const float* Y, int64_t ldy, int64_t l, int64_t k);
+__attribute__((visibility("hidden"))) re_status launch_ygemm_grid(hipStream_t s, const YDesc* desc, int nblk,
+                                                                 const float* Y, int64_t ldy, int64_t l, int64_t k,
+                                                                 unsigned groups, double* parts);
 // Batched small SVDs: C[b] (l[b] x k[b], each fitting one workgroup's LDS) ->
 // d[b], e[b]; then singular values and counts per SvDesc.
 __attribute__((visibility("hidden"))) size_t batched_svd_lds_bytes(int64_t lmax, int64_t kmax);

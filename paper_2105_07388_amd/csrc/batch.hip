@@ -197,17 +197,22 @@ __global__ void k_gauss_master(const BatchHeader* __restrict__ hdr, int64_t nmax
 // row q / 16 + 4 r, column q % 16, as measured on gfx950).  One workgroup per (block, slab of
 // 16 * waves rows of C); wavefront w owns rows 16 w .. 16 w + 15 of the slab
 // and up to six 16-column tiles; K runs over m in chunks of 16 staged in LDS
-// as FP64 (the FP32 products are exact in FP64).  The sum over m is taken in
-// the same order for every block, so a batch and a single call agree.
+// as FP64 (the FP32 products are exact in FP64).  The sum over m is a sum of
+// groups of kYGroup chunks: each group is accumulated on the matrix cores from
+// zero, in chunk order, and the group sums are added in group order.  A batch
+// runs the groups of a block one after another; a single call with many
+// groups gives each its own workgroup (gridDim.z = groups, partials to
+// `parts`) and adds the partials in the same order, so both agree.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kYKC = 16;                 // K per chunk
 constexpr int kYNT = 6, kYN = 16 * kYNT;  // column tiles per pass
 constexpr int kYApad = kYKC + 1, kYBpad = kYN + 4;
 constexpr int kYMinWaves = 4, kYMaxWaves = 9;
+constexpr int kYGroup = 32;  // chunks per group (512 rows of m)
 
 __global__ void __launch_bounds__(64 * kYMaxWaves) k_ygemm_mfma(const YDesc* __restrict__ desc,
                                                                 const float* __restrict__ Y, int64_t ldy, int64_t l,
-                                                                int64_t k) {
+                                                                int64_t k, double* __restrict__ parts) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int waves = blockDim.x >> 6, nth = blockDim.x;
   const int rows = 16 * waves;
@@ -219,6 +224,10 @@ __global__ void __launch_bounds__(64 * kYMaxWaves) k_ygemm_mfma(const YDesc* __r
   const int q16 = lane & 15, kq = lane >> 4;
   const int64_t m = d.m;
   const int64_t nchunks = (m + kYKC - 1) / kYKC;
+  const bool split = gridDim.z > 1;  // one group per workgroup, partial to parts[blockIdx.z]
+  const int64_t ch_begin = split ? (int64_t)blockIdx.z * kYGroup : 0;
+  const int64_t ch_end = split ? (ch_begin + kYGroup < nchunks ? ch_begin + kYGroup : nchunks) : nchunks;
+  double* __restrict__ out = split ? parts + (int64_t)blockIdx.z * l * k : d.C;
   // register staging: the next chunk's loads are in flight while the
   // matrix cores work on the current one
   constexpr int kPerY = 4;                          // rows * 16 / (64 * waves)
@@ -260,12 +269,13 @@ __global__ void __launch_bounds__(64 * kYMaxWaves) k_ygemm_mfma(const YDesc* __r
     f64x4 acc[kYNT];
 #pragma unroll
     for (int t = 0; t < kYNT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-    load(0);
+    bool first = true;
+    load(ch_begin * kYKC);
     store(0);
     __syncthreads();
-    for (int64_t ch = 0; ch < nchunks; ++ch) {
-      const int buf = ch & 1;
-      if (ch + 1 < nchunks) load((ch + 1) * kYKC);
+    for (int64_t ch = ch_begin; ch < ch_end; ++ch) {
+      const int buf = (ch - ch_begin) & 1;
+      if (ch + 1 < ch_end) load((ch + 1) * kYKC);
       const double* y = sY + buf * rows * kYApad + (16 * wave + q16) * kYApad;
       const double* bb = sB + buf * kYKC * kYBpad;
 #pragma unroll
@@ -275,17 +285,45 @@ __global__ void __launch_bounds__(64 * kYMaxWaves) k_ygemm_mfma(const YDesc* __r
         for (int t = 0; t < kYNT; ++t)
           acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bb[(kk + kq) * kYBpad + 16 * t + q16], acc[t], 0, 0, 0);
       }
-      if (ch + 1 < nchunks) store(buf ^ 1);
+      if ((ch + 1) % kYGroup == 0 || ch + 1 == ch_end) {
+        // a group ends: its sum goes to the thread's own outputs (first
+        // group) or is added to them
+#pragma unroll
+        for (int t = 0; t < kYNT; ++t) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t gs = s0 + 16 * wave + kq + 4 * r, gc = c0 + 16 * t + q16;
+            if (gs < l && gc < k) {
+              const gdouble o = (gdouble)out + (gs * k + gc);
+              *o = first ? acc[t][r] : *o + acc[t][r];
+            }
+          }
+          acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+        }
+        first = false;
+      }
+      if (ch + 1 < ch_end) store(buf ^ 1);
       __syncthreads();
     }
+    if (first)  // m = 0
 #pragma unroll
-    for (int t = 0; t < kYNT; ++t)
+      for (int t = 0; t < kYNT; ++t)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t gs = s0 + 16 * wave + kq + 4 * r, gc = c0 + 16 * t + q16;
-        if (gs < l && gc < k) ((gdouble)d.C)[gs * k + gc] = acc[t][r];
-      }
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gs = s0 + 16 * wave + kq + 4 * r, gc = c0 + 16 * t + q16;
+          if (gs < l && gc < k) ((gdouble)out)[gs * k + gc] = 0.0;
+        }
     __syncthreads();
+  }
+}
+
+// C = sum of the groups' partial products in group order (the order a batch
+// adds them in), for a single call split over m.
+__global__ void k_ygemm_reduce(const double* __restrict__ parts, int64_t ngroups, int64_t lk, double* __restrict__ C) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < lk; e += (int64_t)gridDim.x * blockDim.x) {
+    double t = parts[e];
+    for (int64_t g = 1; g < ngroups; ++g) t += parts[g * lk + e];
+    C[e] = t;
   }
 }
 
@@ -330,15 +368,31 @@ re_status launch_gemm_f32_single(hipStream_t s, const float* A, int64_t m, int64
   return launch_gemm_f32_persistent(s, dscratch, 1, X, k, total, queue, 4, (int)g, 32, 1);
 }
 
+int64_t ygemm_groups(int64_t m) { return cdiv(cdiv(m, kYKC), kYGroup); }
+
+// a split launch puts the groups on grid dimension z (at most 65535)
+bool ygemm_splits(int64_t m) { return ygemm_groups(m) > 1 && ygemm_groups(m) <= 65535; }
+
+size_t ygemm_split_bytes(int64_t l, int64_t k, int64_t m) {
+  return ygemm_splits(m) ? (size_t)ygemm_groups(m) * l * k * sizeof(double) : 0;
+}
+
 re_status launch_ygemm_single(hipStream_t s, const float* B, int64_t m, int64_t k, int64_t ldb, const float* Y,
-                              int64_t ldy, int64_t l, double* C, YDesc* dscratch) {
+                              int64_t ldy, int64_t l, double* C, YDesc* dscratch, double* parts) {
   YDesc d;
   d.B = B;
   d.C = C;
   d.m = m;
   d.ldb = ldb;
   hipLaunchKernelGGL(k_put_desc<YDesc>, dim3(1), dim3(64), 0, s, d, dscratch);
-  return launch_ygemm_batched(s, dscratch, 1, Y, ldy, l, k);
+  const int64_t g = ygemm_groups(m);
+  if (!ygemm_splits(m) || parts == nullptr) return launch_ygemm_batched(s, dscratch, 1, Y, ldy, l, k);
+  RE_TRY(launch_ygemm_grid(s, dscratch, 1, Y, ldy, l, k, (unsigned)g, parts));
+  const int64_t lk = l * k;
+  hipLaunchKernelGGL(k_ygemm_reduce, dim3((unsigned)(cdiv(lk, 256) < 2048 ? cdiv(lk, 256) : 2048)), dim3(256), 0, s,
+                     (const double*)parts, g, lk, C);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
 }
 
 re_status launch_gauss_sub(hipStream_t s, int64_t rows, int64_t cols, int64_t r0, int64_t c0, uint64_t seed,
@@ -371,6 +425,11 @@ int gemm_col_chunks(int64_t k) { return (int)cdiv(k, k >= 128 ? 128 : 32 * cdiv(
 
 re_status launch_ygemm_batched(hipStream_t s, const YDesc* desc, int nblk, const float* Y, int64_t ldy, int64_t l,
                                int64_t k) {
+  return launch_ygemm_grid(s, desc, nblk, Y, ldy, l, k, 1, nullptr);
+}
+
+re_status launch_ygemm_grid(hipStream_t s, const YDesc* desc, int nblk, const float* Y, int64_t ldy, int64_t l,
+                            int64_t k, unsigned groups, double* parts) {
   if (nblk <= 0 || l <= 0 || k <= 0) return RE_OK;
   int waves = (int)(cdiv(l, 16) < kYMaxWaves ? cdiv(l, 16) : kYMaxWaves);
   if (waves < kYMinWaves) waves = kYMinWaves;
@@ -378,8 +437,8 @@ re_status launch_ygemm_batched(hipStream_t s, const YDesc* desc, int nblk, const
   const size_t lds = (size_t)(2 * rows * kYApad + 2 * kYKC * kYBpad) * sizeof(double);
   if (lds > 64 * 1024)
     RE_TRY_HIP(hipFuncSetAttribute((const void*)k_ygemm_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_ygemm_mfma, dim3((unsigned)cdiv(l, rows), (unsigned)nblk), dim3(64 * waves), lds, s, desc, Y,
-                     ldy, l, k);
+  hipLaunchKernelGGL(k_ygemm_mfma, dim3((unsigned)cdiv(l, rows), (unsigned)nblk, groups), dim3(64 * waves), lds, s, desc,
+                     Y, ldy, l, k, parts);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
 }
