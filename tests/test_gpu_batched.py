@@ -128,6 +128,19 @@ def test_batched_errors():
     assert ei.value.status == -5
 
 
+def test_long_single_call_split_over_m(orc):
+    # m = 20000: the single call's Y B runs 40 groups of 512 rows on separate
+    # workgroups and adds their partials in order; the same matrix as a
+    # one-block batch adds the groups one after another.  Same bits, and the
+    # oracle's FP64 estimate within the FP32 bound.
+    A = inputs.planted(20000, 500, np.geomspace(1.0, 1e-7, 200), 41, torch.float32).to(DEV)
+    h = re_.Handle()
+    r1, s1, info = _single(A, 1e-5, 6, h)
+    r, s, fl = re_.rank_estimate_batched([A], 1e-5, k=K, l=L, seed=6, handle=h)
+    assert r[0] == r1 and np.array_equal(s[0], s1)
+    _oracle_check(orc, A, 1e-5, 6, r1, s1)
+
+
 def test_batched_full_size_sampled(orc):
     """4096 kernel blocks (m, n in [256, 4096], ~79 GB of FP32) in one call; the
     oracle checks a stratified sample: the smallest and largest blocks and a few
