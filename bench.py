@@ -691,4 +691,10 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    try:
+        main()
+    finally:
+        # release the library's handles (streams, graphs, device and pinned
+        # buffers) before the interpreter and the HIP runtime shut down
+        if "paper_2105_07388_amd" in sys.modules:
+            sys.modules["paper_2105_07388_amd"].close_all_handles()

@@ -108,6 +108,20 @@ OR_EXPORT double or_round_to(double v, int fmt) {
     }
 }
 
+/* The Gaussian embedding written out as a dense rows x cols matrix (row-major),
+ * each entry rounded to the contraction format: G[i][j] = round_fmt(gauss(i, j))
+ * for X (swap = 0); Y's entry (s, i) takes the counter (i, s), so swap = 1
+ * gives G[s][i] = round_fmt(gauss(i, s)).  Counters do not depend on the
+ * matrix size, so a smaller matrix is a leading block of a larger one. */
+OR_EXPORT void or_gauss_matrix(uint64_t seed, int64_t rows, int64_t cols, uint64_t stream, uint64_t blk, int fmt,
+                               int swap, double* G) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < rows; ++i)
+        for (int64_t j = 0; j < cols; ++j)
+            G[i * cols + j] = or_round_to(swap ? or_gauss(seed, (uint64_t)j, (uint64_t)i, stream, blk)
+                                               : or_gauss(seed, (uint64_t)i, (uint64_t)j, stream, blk), fmt);
+}
+
 /* Rademacher sign d_i = 1 - 2 * (lowest bit of the first Philox word). */
 OR_EXPORT int or_sign(uint64_t seed, uint64_t i, uint64_t stream, uint64_t blk) {
     uint64_t w[4];

@@ -61,6 +61,8 @@ def lib():
                                        vp, vp, vp, vp, vp]
         L.or_rank_estimate.restype = i32
         L.or_num_threads.restype = i32
+        L.or_gauss_matrix.argtypes = [u64, i64, i64, u64, u64, i32, i32, vp]
+        L.or_gauss_matrix.restype = None
         _lib = L
     return _lib
 
@@ -192,6 +194,51 @@ def rank_estimate(A, eps, xkind=GAUSSIAN, ykind=GAUSSIAN, k=40, l=None, prec=0, 
     _check(lib().or_rank_estimate(_ptr(A), dt, m, n, n, eps, xkind, ykind, k, l, prec, seed, blk,
                                   C.byref(r), _ptr(s), C.byref(r1), C.byref(fl), C.byref(sw)))
     return r.value, s, r1.value, fl.value, sw.value
+
+
+def gauss_matrix(seed, rows, cols, stream, fmt, swap=False, blk=0):
+    """The Gaussian embedding as a dense FP64 matrix of its rounded entries
+    (oracle.c or_gauss_matrix): X = gauss_matrix(seed, n, k, 1, fmt) and
+    Y = gauss_matrix(seed, l, m, 2, fmt, swap=True)."""
+    G = np.zeros((rows, cols), dtype=np.float64)
+    lib().or_gauss_matrix(seed, rows, cols, stream, blk, fmt, int(bool(swap)), _ptr(G))
+    return G
+
+
+def rank_estimate_gemm(A, eps, xkind=GAUSSIAN, ykind=GAUSSIAN, k=40, l=None, prec=0, seed=0, blk=0,
+                       X=None, Y=None):
+    """Algorithm 1 (Sec. 5) as rank_estimate, with the Gaussian products of
+    steps 3 and 6 taken by numpy's FP64 matrix product (a library primitive)
+    instead of oracle.c's plain loops, so that the oracle finishes at the
+    workloads' full sizes.  The embeddings are the same rounded entries
+    (gauss_matrix); an SRHT side runs oracle.c's transform.  X (n x k) and Y
+    (l x m) may be passed in as leading blocks of larger master draws.
+    Returns (r, sigma[k], r1, flags, sweeps)."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    if l is None:
+        l = 2 * k
+    dt = _a_dtype(A)
+    if xkind == GAUSSIAN:
+        if X is None:
+            X = gauss_matrix(seed, n, k, STREAM_XGAUSS, x_format(dt, prec), blk=blk)
+        B = A.astype(np.float64) @ X[:n, :k]
+    else:
+        if prec != 0:
+            raise OracleError(-2)
+        B = apply_x(A, xkind, k, seed=seed, blk=blk)
+    if ykind == GAUSSIAN:
+        if Y is None:
+            Y = gauss_matrix(seed, l, m, STREAM_YGAUSS, lib().or_y_format(dt), swap=True, blk=blk)
+        Cm = Y[:l, :m] @ B
+    else:
+        Cm = apply_y(B, ykind, l, seed=seed, blk=blk)
+    s, sw, st = jacobi_sv(Cm)
+    _check(st)
+    s = s / np.sqrt(float(k) * float(l))
+    r1 = r1_from_k(k)
+    r, fl = rank_count(s, r1, eps)
+    return r, s, r1, fl, sw
 
 
 def num_threads():

@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     FLAG_COLUMNS_DROPPED,
     FLAG_ZERO,
     Handle,
+    close_all_handles,
     RankEstError,
     default_handle,
     gap_rank,

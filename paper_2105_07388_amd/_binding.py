@@ -6,9 +6,12 @@ no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
 import threading
+import weakref
 
 import numpy as np
 import torch
@@ -141,6 +144,7 @@ class Handle:
         with torch.cuda.device(self.device):
             _check(lib().re_create(C.byref(self._h), C.c_void_p(torch.cuda.current_stream().cuda_stream)), "re_create")
         self._stream = torch.cuda.current_stream(self.device).cuda_stream
+        _live.add(self)
 
     def bind(self):
         s = torch.cuda.current_stream(self.device).cuda_stream
@@ -169,6 +173,11 @@ class Handle:
             self._h = C.c_void_p()
 
     def __del__(self):
+        # At interpreter shutdown the HIP runtime (and a profiler attached to
+        # it) may already be gone; handles still open then were released by
+        # _close_all at exit, so nothing is left to do here.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -176,6 +185,23 @@ class Handle:
 
 
 _handles: dict = {}
+_live = weakref.WeakSet()
+
+
+def _close_all():
+    """Release every open handle while the HIP runtime is still alive: Python's
+    exit hooks run before the runtime's own teardown, whereas a handle left to
+    the garbage collector may be destroyed after it."""
+    for h in list(_live):
+        try:
+            h.close()
+        except Exception:
+            pass
+    _handles.clear()
+
+
+atexit.register(_close_all)
+close_all_handles = _close_all
 
 
 def default_handle(device=None) -> Handle:

@@ -143,8 +143,11 @@ def test_long_single_call_split_over_m(orc):
 
 def test_batched_full_size_sampled(orc):
     """4096 kernel blocks (m, n in [256, 4096], ~79 GB of FP32) in one call; the
-    oracle checks a stratified sample: the smallest and largest blocks and a few
-    from the middle, plus bitwise agreement with single calls on those."""
+    oracle checks a stratified sample of 64 blocks (evenly spaced in the order of
+    block size, from the smallest to the largest), and a few of them are checked
+    bit for bit against single calls.  The oracle's Gaussian products run as FP64
+    library products on master draws of X (4096 x 96) and Y (144 x 4096), whose
+    leading blocks are each block's sketch."""
     free, _ = torch.cuda.mem_get_info()
     if free < 100 * 2**30:
         pytest.skip("needs ~100 GB of free device memory")
@@ -152,12 +155,26 @@ def test_batched_full_size_sampled(orc):
     h = re_.Handle()
     r, s, fl = re_.rank_estimate_batched(views, 1e-6, k=K, l=L, seed=77, handle=h)
     sizes = np.array([p["m"] * p["n"] for p in params])
-    order = np.argsort(sizes)
-    sample = [int(order[0]), int(order[1]), int(order[2048]), int(order[-1])]
-    for b in sample:
+    order = np.argsort(sizes, kind="stable")
+    picks = np.unique(np.round(np.linspace(0, len(order) - 1, 64)).astype(int))
+    sample = [int(order[i]) for i in picks]
+    assert len(sample) == 64 and sample[-1] == int(order[-1]) and sample[0] == int(order[0])
+    for b in (sample[0], sample[1], sample[32], sample[-1]):
         r1, s1, info = _single(views[b], 1e-6, 77, h)
         assert r[b] == r1 and np.array_equal(s[b], s1)
-    for b in sample[:3]:
-        _oracle_check(orc, views[b], 1e-6, 77, r[b], s[b])
+    X = orc.gauss_matrix(77, 4096, K, orc.STREAM_XGAUSS, orc.FMT_F32)
+    Y = orc.gauss_matrix(77, L, 4096, orc.STREAM_YGAUSS, orc.FMT_F32, swap=True)
+    worst = 0.0
+    for b in sample:
+        An = views[b].cpu().numpy()
+        r_o, s_o, r1_o, fl_o, _ = orc.rank_estimate_gemm(An, 1e-6, orc.GAUSSIAN, orc.GAUSSIAN, k=K, l=L, seed=77,
+                                                         X=X, Y=Y)
+        tol = 8 * 2.0**-24 * math.sqrt(An.shape[1]) * s_o[0]
+        err = float(np.max(np.abs(s[b] - s_o)))
+        worst = max(worst, err / tol)
+        assert err <= tol, (b, An.shape, err / s_o[0])
+        band = int(np.count_nonzero(np.abs(s_o[:r1_o] - 1e-6 * s_o[0]) <= 2 * tol))
+        assert abs(int(r[b]) - r_o) <= band, (b, int(r[b]), r_o, band)
+    print(f"batched full size: 64 stratified blocks, worst |d sigma| / tolerance {worst:.3g}")
     assert 3 <= int(np.min(r)) and int(np.max(r)) < re_.r1_from_k(K)
     del buf, views

@@ -107,3 +107,24 @@ def test_precision_form_full_size(orc):
         got = B[rows].cpu().numpy().astype(np.float64)
         bound = (U[fmt] + n * 2.0**-24) * (np.abs(Arows.astype(np.float64)) @ np.abs(X))
         assert np.all(np.abs(got - want) <= bound)
+
+
+def test_precision_form_full_size_every_sigma(orc):
+    """Every one of the 512 estimates at the workload's size (FP32 32768 x 8192,
+    Gaussian X 512 in BF16 at eps 1e-2 and FP16 at eps 1e-3, SRHT Y 768) against
+    the FP64 oracle run on the same FP32 A with the same rounded X: the error
+    stays within 2 phi_f, and the rank is 200 on both sides."""
+    A = inputs.c3_matrix(device=DEV)
+    m, n = A.shape
+    k, l = 512, 768
+    An = A.cpu().numpy()
+    phi = {f: _phi(f, A, k, m) for f in ("bf16", "fp16")}
+    for fmt, eps, seed in [("bf16", 1e-2, 11), ("fp16", 1e-3, 12)]:
+        r, s, info = re_.rank_estimate(A, eps, k=k, l=l, y="srht", precision=fmt, seed=seed)
+        ro, so, r1o, flo, _ = orc.rank_estimate_gemm(An, eps, orc.GAUSSIAN, orc.SRHT, k=k, l=l, prec=OPREC[fmt],
+                                                     seed=seed)
+        err = np.abs(s - so)
+        print(f"precision form full size, {fmt} at eps {eps}: max |d sigma| = {err.max():.3e} "
+              f"({err.max() / phi[fmt]:.3f} phi_f, {err.max() / so[0]:.3e} sigma_1), ranks {r} / {ro}")
+        assert r == ro == 200, (fmt, r, ro)
+        assert np.all(err <= 2 * phi[fmt]), (fmt, float(err.max()), phi[fmt])

@@ -73,6 +73,88 @@ def test_gauss_uses_both_words(orc):
     assert all(math.isfinite(v) for v in vals)
 
 
+def _numpy_words(seed, a, b, stream, blk=0):
+    """Philox4x64-10 words at counter (a, b, stream, blk) and key (seed, 0), taken
+    from numpy's generator: numpy returns the block at its counter + 1, so start it
+    one below (a 256-bit decrement with borrow)."""
+    c = [int(a), int(b), int(stream), int(blk)]
+    for i in range(4):
+        if c[i] > 0:
+            c[i] -= 1
+            break
+        c[i] = 2**64 - 1
+    ctr = np.array(c, dtype=np.uint64)
+    key = np.array([seed % 2**64, 0], dtype=np.uint64)
+    return np.random.Philox(key=key, counter=ctr).random_raw(4)
+
+
+def _counters(rng, count):
+    out = [(0, 0), (0, 5), (1, 0), (2**64 - 1, 3)]
+    for _ in range(count):
+        out.append((int(rng.integers(0, 2**63)), int(rng.integers(0, 1 << 20))))
+    return out
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_gauss_box_muller_bits_from_numpy_words(orc, seed):
+    """Each Gaussian entry is the Box-Muller cosine branch (Box and Muller 1958) of
+    u1 = (w0 >> 11 + 1) 2^-53 in (0, 1] and u2 = (w1 >> 11) 2^-53 in [0, 1), w the
+    numpy Philox words of its counter: swapping u1 and u2, using the sine branch,
+    the wrong words or the wrong end of a word all move the value by far more than
+    the few ulps two libm's may differ by."""
+    rng = np.random.default_rng(seed % 2**32)
+    for a, b in _counters(rng, 60):
+        for stream in (1, 2):
+            w = _numpy_words(seed, a, b, stream)
+            u1 = float((int(w[0]) >> 11) + 1) * 2.0**-53
+            u2 = float(int(w[1]) >> 11) * 2.0**-53
+            want = math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+            got = orc.gauss(seed, a, b, stream)
+            assert abs(got - want) <= 8 * 2.0**-52 * max(abs(want), 1e-3), (a, b, stream, got, want)
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_sign_and_key_bits_from_numpy_words(orc, seed):
+    """The Rademacher sign is 1 - 2 (lowest bit of the first word) and the sampling
+    key is the first word, at counter (i, 0, stream): checked bit for bit against
+    numpy's Philox, not against the oracle's own generator."""
+    rng = np.random.default_rng(seed % 2**32 + 1)
+    idx = [0, 1, 2, 31, 32, 2**64 - 1] + [int(v) for v in rng.integers(0, 2**40, 60)]
+    for i in idx:
+        for stream in (3, 4):
+            w = _numpy_words(seed, i, 0, stream)
+            assert orc.sign(seed, i, stream) == 1 - 2 * (int(w[0]) & 1), (i, stream)
+        for stream in (5, 6):
+            assert orc.select_key(seed, i, stream) == int(_numpy_words(seed, i, 0, stream)[0])
+
+
+def test_gauss_matrix_is_the_rounded_entries(orc):
+    """The dense embedding holds round_fmt(gauss(i, j)) for X and round_fmt(gauss(j, i))
+    for Y's rows, and a smaller draw is a leading block of a larger one."""
+    for fmt in (orc.FMT_F64, orc.FMT_F32, orc.FMT_BF16, orc.FMT_F16):
+        X = orc.gauss_matrix(9, 37, 11, 1, fmt)
+        for i, j in [(0, 0), (36, 10), (5, 7), (20, 0)]:
+            assert X[i, j] == orc.round_to(orc.gauss(9, i, j, 1), fmt)
+        Y = orc.gauss_matrix(9, 11, 37, 2, fmt, swap=True)
+        for s_, i in [(0, 0), (10, 36), (7, 5)]:
+            assert Y[s_, i] == orc.round_to(orc.gauss(9, i, s_, 2), fmt)
+        assert np.array_equal(orc.gauss_matrix(9, 20, 5, 1, fmt), X[:20, :5])
+
+
+@pytest.mark.parametrize("xk,yk,prec,dtype", [(0, 0, 0, np.float64), (0, 0, 0, np.float32), (0, 1, 1, np.float32),
+                                              (0, 1, 2, np.float32), (1, 0, 0, np.float32), (1, 1, 0, np.float64)])
+def test_rank_estimate_gemm_equals_plain_loops(orc, xk, yk, prec, dtype):
+    """The full-size form of the oracle (library FP64 products for the Gaussian
+    steps) gives the plain-loop oracle's estimates up to summation order and the
+    same rank, flags and r1."""
+    A = inputs.planted(500, 300, inputs.c2_spectrum(150), 12, torch.float64).numpy().astype(dtype)
+    for eps in (1e-2, 1e-4):
+        a = orc.rank_estimate(A, eps, xk, yk, k=48, l=72, prec=prec, seed=5)
+        b = orc.rank_estimate_gemm(A, eps, xk, yk, k=48, l=72, prec=prec, seed=5)
+        assert a[0] == b[0] and a[2] == b[2] and a[3] == b[3]
+        assert np.max(np.abs(a[1] - b[1])) <= 1e-13 * a[1][0]
+
+
 # --- rounding to the contraction formats ---------------------------------------------
 
 def test_round_to_fp16_matches_numpy(orc):
