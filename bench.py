@@ -141,6 +141,35 @@ def cpu_baseline(A_dev, w, rows: int):
                       f"Jacobi SVD of the {l}x{k} sketch; seconds: ax {t_x:.2f}, yb {t_y:.2f}, svd {t_svd:.2f}"}
 
 
+def sigma_error_lowprec(A_dev, w, h):
+    """Per-sigma error of the low-precision forms against the oracle: one
+    estimate per format (BF16 at the larger eps, FP16 at the smaller) on the
+    workload's matrix, and the oracle's FP64 run on the same FP32 A with the
+    same rounded X (library FP64 products).  Reported as the largest error,
+    also in units of the format's floor phi_f = (u_f / sqrt 3) ||A||_F
+    (1 / sqrt k + 1 / sqrt m) and of sigma_1."""
+    import numpy as np
+
+    import oracle
+    import paper_2105_07388_amd as re_
+    m, k, l = w["m"], w["k"], w["l"]
+    fro = float(A_dev.double().norm())
+    An = A_dev.cpu().numpy()
+    unit = {"bf16": 2.0**-8, "fp16": 2.0**-11}
+    oprec = {"bf16": 1, "fp16": 2}
+    out = {}
+    for fmt, eps in zip(w["prec"], w["eps"]):
+        seed = 77
+        r, s, _ = re_.rank_estimate(A_dev, eps, k=k, l=l, x=w["x"], y=w["y"], precision=fmt, seed=seed, handle=h)
+        ro, so, _, _, _ = oracle.rank_estimate_gemm(An, eps, oracle.GAUSSIAN, oracle.SRHT, k=k, l=l,
+                                                    prec=oprec[fmt], seed=seed)
+        phi = unit[fmt] / np.sqrt(3.0) * fro * (1 / np.sqrt(k) + 1 / np.sqrt(m))
+        err = float(np.max(np.abs(s - so)))
+        out[fmt] = {"eps": eps, "max_abs": err, "max_over_phi_f": err / phi, "max_over_sigma1": err / float(so[0]),
+                    "rank": int(r), "rank_oracle": int(ro)}
+    return out
+
+
 def cpu_baseline_batched(views, params, w, nsample: int):
     """Oracle timed on a stratified sample of blocks (sorted by size, evenly
     spaced), scaled to the whole batch by the ratio of m*n."""
@@ -687,6 +716,10 @@ def main():
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(A, w, args.cpu_rows)
+        if "prec" in w:
+            print("[bench] per-sigma error of the low-precision forms against the oracle", file=sys.stderr,
+                  flush=True)
+            out["sigma_error_vs_oracle"] = sigma_error_lowprec(A, w, h)
     print(json.dumps(out), flush=True)
 
 

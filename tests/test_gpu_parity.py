@@ -286,20 +286,19 @@ def test_errors_and_flags():
 def test_plain_method_full_size(orc):
     """The benchmark's own matrix and launch configuration: FP32 65536 x 16384,
     s_i = 10^(-i/20) + 1e-9 noise, SRHT X 384 and Y 576.  The oracle runs the
-    same estimate in FP64 on the whole matrix.  Tolerance: the FP32 sketch's
-    rounding, about u32 sqrt(log2 N) ||A||_F sqrt(k) in ||dB||_F and that times
-    sqrt(m') / sqrt(k l) in the estimates (~5e-6 s_1 here), taken four times
-    (2e-5 s_1), a statistical rather than a worst-case bound; sampled rows of
-    A X entrywise within the FWHT bound.  The spectrum has no gap at either eps
-    (ties at 61 and 101), so the ranks may differ by the oracle estimates that
-    lie inside that band around tau."""
+    same estimate in FP64 on the whole matrix.  Tolerance: the FP32-SRHT bar
+    |d sigma_i| <= 1e-5 sigma_1 (the observed maximum is about 2e-9 sigma_1: the
+    rounding errors of the FP32 sketch largely cancel in the estimates); sampled
+    rows of A X entrywise within the FWHT bound.  The spectrum has no gap at
+    either eps (ties at 61 and 101), so the ranks may differ by the oracle
+    estimates that lie inside that band around tau."""
     A = inputs.c2_matrix(device=DEV)
     An = A.cpu().numpy()
     k, l = 384, 576
     for eps, seed in ((1e-3, 3), (1e-5, 4)):
         r, s, info = re_.rank_estimate(A, eps, k=k, l=l, x="srht", y="srht", seed=seed)
         ro, so, r1, fl, _ = orc.rank_estimate(An, eps, orc.SRHT, orc.SRHT, k=k, l=l, seed=seed)
-        tol = 2e-5 * so[0]
+        tol = 1e-5 * so[0]
         print(f"plain method full size, eps {eps}: max |d sigma| / sigma_1 = {np.max(np.abs(s - so)) / so[0]:.3e}, "
               f"ranks {r} / {ro}")
         assert np.max(np.abs(s - so)) <= tol, float(np.max(np.abs(s - so)) / so[0])
