@@ -42,7 +42,8 @@ typedef enum {
   RE_ERR_NO_MEMORY = -3,     /* a workspace allocation failed */
   RE_ERR_HIP = -4,           /* a HIP runtime call failed */
   RE_ERR_NONFINITE = -5,     /* A (or the sketch) holds NaN or Inf */
-  RE_ERR_NO_CONVERGENCE = -6 /* the small SVD did not converge */
+  RE_ERR_NO_CONVERGENCE = -6, /* the small SVD did not converge */
+  RE_ERR_SCRATCH_LIMIT = -7   /* the input needs more than the fixed scratch of an allocation-free call */
 } re_status;
 
 /* Storage type of A. */
@@ -250,6 +251,27 @@ int64_t re_sketch_y_rows(int64_t m);
  * sigma_dev (device, k doubles).  C_dev is not modified. */
 re_status re_singular_values(re_handle h, const double* C_dev, int64_t l, int64_t k, double scale,
                              double* sigma_dev);
+
+/* Allocation-free form of re_singular_values, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It takes no handle and calls no hipMalloc / hipFree
+ * or allocating library routine: its working memory is a fixed static device
+ * array of RE_NOALLOC_SCRATCH_BYTES (16 MiB) per GPU, held from the first call
+ * on that GPU until the process ends.  The work is enqueued on `hip_stream`
+ * (NULL = the default stream of the current device) and the call does not
+ * synchronise.  Arguments and results as re_singular_values: C_dev device,
+ * l x k row-major FP64 (k <= l), not modified; sigma_dev device, k doubles.
+ * Returns RE_ERR_SCRATCH_LIMIT when the sketch's working set exceeds the
+ * array (l k up to about 1.9e6 at k = 384, 1.5e6 at k = 1024; see
+ * re_singular_values_noalloc_fits).  All calls on one GPU share that GPU's
+ * array and leave their contents in it: calls that overlap in time on one GPU
+ * (different streams or host threads) race and must be serialised by the
+ * caller. */
+#define RE_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+re_status re_singular_values_noalloc(void* hip_stream, const double* C_dev, int64_t l, int64_t k, double scale,
+                                     double* sigma_dev);
+/* 1 when an l x k sketch fits the allocation-free call's scratch, else 0. */
+int32_t re_singular_values_noalloc_fits(int64_t l, int64_t k);
 
 /* Algorithm 1 step 8 on device: out_dev[0] = r^, out_dev[1] = flags for the
  * descending sigma_dev[0..k) with r1 and eps (strict inequality of Def. 1). */

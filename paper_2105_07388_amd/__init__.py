@@ -35,6 +35,7 @@ from ._binding import (  # noqa: F401
     rank_estimate_batched,
     rank_estimate_qr,
     singular_values,
+    singular_values_noalloc,
     sketch_x,
     sketch_y,
     srht_select,

@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "librankest.so")
 
 RE_OK, RE_ERR_INVALID_ARG, RE_ERR_UNSUPPORTED, RE_ERR_NO_MEMORY = 0, -1, -2, -3
 RE_ERR_HIP, RE_ERR_NONFINITE, RE_ERR_NO_CONVERGENCE = -4, -5, -6
+RE_ERR_SCRATCH_LIMIT = -7
+NOALLOC_SCRATCH_BYTES = 16 << 20  # RE_NOALLOC_SCRATCH_BYTES
 RE_F64, RE_F32 = 0, 1
 RE_GAUSSIAN, RE_SRHT = 0, 1
 PREC = {"native": 0, "bf16": 1, "fp16": 2, "auto": 3}
@@ -110,6 +112,8 @@ def lib():
             "re_sketch_y": ([vp, vp, i32, i64, i64, C.POINTER(ReSketch), u64, vp], i32),
             "re_sketch_y_rows": ([i64], i64),
             "re_singular_values": ([vp, vp, i64, i64, dbl, vp], i32),
+            "re_singular_values_noalloc": ([vp, vp, i64, i64, dbl, vp], i32),
+            "re_singular_values_noalloc_fits": ([i64, i64], i32),
             "re_rank_count": ([vp, vp, i64, i32, dbl, vp], i32),
             "re_r1_from_k": ([i32], i32),
             "re_gap_rank": ([vp, i32, i32, C.POINTER(i32), C.POINTER(dbl)], i32),
@@ -522,6 +526,25 @@ def singular_values(Cm: torch.Tensor, scale: float = 1.0, handle: Handle | None 
     sigma = torch.empty(k, dtype=torch.float64, device=Cm.device)
     h = handle or default_handle(Cm.device)
     _check(lib().re_singular_values(h.bind(), _ptr(Cm), l, k, float(scale), _ptr(sigma)), "re_singular_values")
+    return sigma
+
+
+def singular_values_noalloc(Cm: torch.Tensor, sigma: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
+    """re_singular_values_noalloc on torch's current stream: the singular values
+    of the l x k FP64 device matrix Cm into the caller's k-element FP64 device
+    tensor sigma, with no device allocation inside the library (fixed per-GPU
+    scratch; overlapping calls on one GPU race).  Does not synchronise."""
+    _need_cuda(Cm, "C")
+    _need_cuda(sigma, "sigma")
+    if Cm.dtype != torch.float64 or not Cm.is_contiguous() or Cm.dim() != 2:
+        raise ValueError("C must be a contiguous 2-D float64 tensor")
+    l, k = Cm.shape
+    if sigma.dtype != torch.float64 or not sigma.is_contiguous() or sigma.numel() < k:
+        raise ValueError("sigma must be a contiguous float64 tensor of at least k elements")
+    with torch.cuda.device(Cm.device):
+        st = torch.cuda.current_stream(Cm.device).cuda_stream
+        _check(lib().re_singular_values_noalloc(C.c_void_p(st), _ptr(Cm), l, k, float(scale), _ptr(sigma)),
+               "re_singular_values_noalloc")
     return sigma
 
 

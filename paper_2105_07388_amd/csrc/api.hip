@@ -6,6 +6,7 @@
 #include <stdlib.h>
 
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1302,6 +1303,55 @@ RE_API re_status re_singular_values(re_handle h, const double* C, int64_t l, int
   return launch_svd(h->stream, C, l, k, scale, h->ws, sigma, info);
 }
 
+// ---- allocation-free singular values ------------------------------------
+// The working memory of re_singular_values_noalloc: one fixed array per GPU
+// (each device holds its own copy of a __device__ variable).  Host code uses
+// the device address obtained from hipGetSymbolAddress on each device, never
+// the name of the array itself.
+__device__ __align__(256) unsigned char scratch[RE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxNoallocDevices = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[kMaxNoallocDevices] = {};
+
+size_t noalloc_need(int64_t l, int64_t k) { return al256(svd_scratch_bytes(l, k)) + 256; }
+
+// Device address of `scratch` on the current device, looked up once per device.
+re_status noalloc_scratch(char** out) {
+  int dev = 0;
+  RE_TRY_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxNoallocDevices) return RE_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    RE_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return RE_ERR_HIP;
+    g_noalloc_ptr[dev] = (char*)p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return RE_OK;
+}
+}  // namespace
+
+RE_API int32_t re_singular_values_noalloc_fits(int64_t l, int64_t k) {
+  if (k < 1 || l < k) return 0;
+  if ((double)l * (double)k * 8.0 > (double)RE_NOALLOC_SCRATCH_BYTES) return 0;
+  return noalloc_need(l, k) <= RE_NOALLOC_SCRATCH_BYTES ? 1 : 0;
+}
+
+RE_API re_status re_singular_values_noalloc(void* hip_stream, const double* C, int64_t l, int64_t k, double scale,
+                                            double* sigma) {
+  if (!C || !sigma || k < 1 || l < k) return RE_ERR_INVALID_ARG;
+  if (!re_singular_values_noalloc_fits(l, k)) return RE_ERR_SCRATCH_LIMIT;
+  char* base = nullptr;
+  RE_TRY(noalloc_scratch(&base));
+  int32_t* info = (int32_t*)(base + al256(svd_scratch_bytes(l, k)));
+  // launch_svd clears its barrier counter and status word with a kernel before
+  // use, so what an earlier call left in the array does not matter.
+  return launch_svd((hipStream_t)hip_stream, C, l, k, scale, base, sigma, info);
+}
+
 RE_API re_status re_rank_count(re_handle h, const double* sigma, int64_t k, int32_t r1, double eps, int32_t* out) {
   if (!h || !sigma || !out || k < 1 || r1 < 1 || !(eps > 0.0 && eps < 1.0)) return RE_ERR_INVALID_ARG;
   return launch_rank_count(h->stream, sigma, k, r1, eps, nullptr, out);
@@ -1316,6 +1366,7 @@ RE_API const char* re_status_string(re_status s) {
     case RE_ERR_HIP: return "HIP runtime error";
     case RE_ERR_NONFINITE: return "non-finite values in the input or the sketch";
     case RE_ERR_NO_CONVERGENCE: return "small SVD did not complete";
+    case RE_ERR_SCRATCH_LIMIT: return "input larger than the fixed scratch of the allocation-free call";
     default: return "unknown status";
   }
 }

@@ -53,6 +53,25 @@ def test_host_only_entry_points(so):
     assert so.re_create(None, None) == -1
 
 
+def test_noalloc_limits_on_the_host(so):
+    """The allocation-free singular values reject what does not fit their fixed
+    scratch before any device work."""
+    so.re_singular_values_noalloc_fits.restype = ctypes.c_int32
+    so.re_singular_values_noalloc_fits.argtypes = [ctypes.c_int64, ctypes.c_int64]
+    fits = so.re_singular_values_noalloc_fits
+    assert fits(576, 384) == 1 and fits(768, 512) == 1 and fits(144, 96) == 1 and fits(60, 40) == 1
+    assert fits(4096, 1024) == 0 and fits(100, 200) == 0 and fits(10, 0) == 0
+    f = so.re_singular_values_noalloc
+    f.restype = ctypes.c_int32
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                  ctypes.c_void_p]
+    fake = ctypes.c_void_p(4096)  # never dereferenced: both calls are rejected on the host
+    assert f(None, fake, 4096, 1024, 1.0, fake) == -7
+    assert f(None, None, 576, 384, 1.0, fake) == -1
+    so.re_status_string.restype = ctypes.c_char_p
+    assert b"scratch" in so.re_status_string(-7)
+
+
 def test_no_oracle_in_product():
     """The product library and package never reference the oracle."""
     pkg = os.path.join(ROOT, "paper_2105_07388_amd")
