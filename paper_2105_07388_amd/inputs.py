@@ -57,6 +57,17 @@ def planted(m: int, n: int, sigma, seed: int, dtype=torch.float64, noise: float 
     return A
 
 
+def diagonal(m: int, n: int, sigma, dtype=torch.float64, device="cpu") -> torch.Tensor:
+    """The test matrices of Sec. 6: the singular values on the diagonal of an
+    m x n matrix (decreasing), stored dense."""
+    s = np.asarray(sigma, dtype=np.float64)
+    d = min(m, n, s.size)
+    A = torch.zeros(m, n, dtype=dtype, device=device)
+    idx = torch.arange(d, device=device)
+    A[idx, idx] = torch.as_tensor(s[:d], device=device).to(dtype)
+    return A
+
+
 def exact_rank(m: int, n: int, r: int, seed: int, dtype=torch.float64, device="cpu") -> torch.Tensor:
     """A = B C with Gaussian B (m x r) and C (r x n): rank exactly r (a.s.)."""
     g = _gen(seed, device)
