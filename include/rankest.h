@@ -337,6 +337,54 @@ re_status re_rank_adaptive_y(re_handle h, const void* A_dev, int32_t dt, int64_t
                              double* sigma_out, int32_t* k_out, int32_t* l_out, int32_t* rounds_out,
                              int32_t* k_proposed_out, uint32_t* flags_out);
 
+/* ------------------------------------------------------------------------
+ * Rank without a tolerance (Sec. 5 after Algorithm 1; Sec. 6.1).  With no eps
+ * the sketched spectrum itself shows where the gaps are: Sec. 6.1 grows a
+ * Gaussian X by 100 columns per round from 110 until the gap of its test
+ * matrix shows.  A gap at i (1-based, i < r1, over the estimates that are
+ * kept after discarding the oversampled ones) is a ratio s_i / s_{i+1} >=
+ * gamma (infinite when s_{i+1} = 0 < s_i).  Round j uses k_j = k0 + j dk
+ * (capped at k_max) and l_j = clamp(round(l_ratio k_j), k_j, m); its estimates
+ * are Algorithm 1's at (k_j, l_j) with the same seed, X and Y only being
+ * appended to.  The search stops after the first round whose first r1
+ * estimates reach below floor * s_1 (the spectrum has been followed down to
+ * the floor) and whose deepest gap (largest such i) is the previous round's;
+ * at k_max without that, it stops with RE_FLAG_NOT_CONVERGED; when s_1 = 0
+ * it stops at once with RE_FLAG_ZERO and r^ = 0.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t k0;      /* first width of X (Sec. 6.1: 110) */
+  int32_t dk;      /* columns appended per round (Sec. 6.1: 100) */
+  int32_t k_max;   /* largest width; 0 means min(m, n); capped at RE_MAX_ADAPTIVE_K */
+  int32_t y_kind;  /* RE_GAUSSIAN or RE_SRHT (rows appended / stored first-level transform) */
+  double l_ratio;  /* rows of Y per column of X, >= 1 */
+  double gamma;    /* gap threshold on s_i / s_{i+1}, > 1 */
+  double floor;    /* relative level s_{r1} <= floor s_1 the estimates must reach before stopping, >= 0 */
+} re_gap_search;
+
+/*
+ * The search above on an FP32 or FP64 A (device, row-major, lda >= n; 4- or
+ * 8-byte aligned), Gaussian X.  Each round draws the new columns of X (and
+ * rows of a Gaussian Y), forms only the new columns of A X (one more pass
+ * over A), then C = Y B, its singular values and the gap statistics on the
+ * device; the host reads 48 bytes and the estimates to decide.
+ *   r_out        host: the deepest gap of the last round (0: none)
+ *   ratio_out    host, may be NULL: its ratio s_r / s_{r+1}
+ *   argmax_out, argmax_ratio_out  host, may be NULL: Sec. 5's measure on the
+ *                last round, the i of the largest ratio (ties to the smallest)
+ *   sigma_out    host, k_max doubles: the last round's k estimates
+ *   k_out, l_out, rounds_out, flags_out  host, may be NULL
+ *   spectra_out  host, may be NULL: row j (stride k_max) receives round j's k_j
+ *                estimates, zero-padded, for j < spectra_cap
+ * Errors: RE_ERR_INVALID_ARG (arguments, including gamma <= 1, floor < 0,
+ * y_kind), RE_ERR_NONFINITE, RE_ERR_NO_CONVERGENCE (small SVD), RE_ERR_NO_MEMORY.
+ * Synchronises the handle's stream once per round.
+ */
+re_status re_rank_gap(re_handle h, const void* A_dev, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                      const re_gap_search* gs, uint64_t seed, int32_t* r_out, double* ratio_out, int32_t* argmax_out,
+                      double* argmax_ratio_out, double* sigma_out, int32_t* k_out, int32_t* l_out, int32_t* rounds_out,
+                      double* spectra_out, int32_t spectra_cap, uint32_t* flags_out);
+
 /* The network, FP32, on device buffers (training and inference).
  * x_dev: batch x RE_MLP_INPUTS row-major; y_dev, t_dev: batch. */
 re_status re_mlp_forward(re_handle h, const float* params_dev, const float* x_dev, int64_t batch, float* y_dev);

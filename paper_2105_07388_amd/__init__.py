@@ -34,6 +34,7 @@ from ._binding import (  # noqa: F401
     rank_estimate,
     rank_estimate_batched,
     rank_estimate_qr,
+    rank_gap,
     singular_values,
     singular_values_noalloc,
     sketch_x,

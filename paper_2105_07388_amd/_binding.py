@@ -55,6 +55,11 @@ class ReAdaptive(C.Structure):
                 ("delta", C.c_double)]
 
 
+class ReGapSearch(C.Structure):
+    _fields_ = [("k0", C.c_int32), ("dk", C.c_int32), ("k_max", C.c_int32), ("y_kind", C.c_int32),
+                ("l_ratio", C.c_double), ("gamma", C.c_double), ("floor", C.c_double)]
+
+
 MLP_INPUTS, MLP_PARAMS = 35, 6529
 
 
@@ -98,6 +103,9 @@ def lib():
                                     C.POINTER(C.c_uint32)], i32),
             "re_rangefinder": ([vp, vp, i32, i64, i64, i64, dbl, i32, C.POINTER(ReAdaptive), dbl, u64, vp, i64, vp,
                                 i64, C.POINTER(i32), C.POINTER(i32), vp, C.POINTER(i32), C.POINTER(C.c_uint32)], i32),
+            "re_rank_gap": ([vp, vp, i32, i64, i64, i64, C.POINTER(ReGapSearch), u64, C.POINTER(i32),
+                             C.POINTER(dbl), C.POINTER(i32), C.POINTER(dbl), vp, C.POINTER(i32), C.POINTER(i32),
+                             C.POINTER(i32), vp, i32, C.POINTER(C.c_uint32)], i32),
             "re_rangefinder_stage_ms": ([vp, vp], i32),
             "re_thin_qr": ([vp, vp, i32, i64, i64, i64, vp, i64, C.POINTER(i32), C.POINTER(C.c_uint32)], i32),
             "re_project": ([vp, vp, i64, i64, vp, i32, i64, i64, i64, vp, i64], i32),
@@ -312,6 +320,42 @@ def rank_adaptive(A: torch.Tensor, eps: float, *, k0: int = 32, k_max: int = 0, 
     _check(st, "re_rank_adaptive")
     return r.value, sigma[:kk.value], {"k": kk.value, "l": ll.value, "rounds": rounds.value,
                                        "k_proposed": kp.value, "flags": fl.value}
+
+
+def rank_gap(A: torch.Tensor, *, k0: int = 110, dk: int = 100, k_max: int = 0, l_ratio: float = 1.5,
+             gamma: float = 100.0, floor: float | None = None, y: str = "gaussian", seed: int = 0,
+             spectra: int = 64, handle: Handle | None = None):
+    """Rank without a tolerance (re_rank_gap): the search of Sec. 6.1 on an
+    FP32 or FP64 A with a Gaussian X grown by dk columns per round and a
+    Gaussian or SRHT Y.  floor defaults to 1e-13 (FP64 A) or 1e-5 (FP32 A).
+    Returns (r, sigma, info) with r the deepest stable gap and info = {ratio,
+    argmax, argmax_ratio, k, l, rounds, flags, spectra (one array per round,
+    the first `spectra` rounds)}."""
+    _check_matrix(A)
+    h = handle or default_handle(A.device)
+    m, n = A.shape
+    if floor is None:
+        floor = 1e-13 if A.dtype == torch.float64 else 1e-5
+    gs = ReGapSearch(int(k0), int(dk), int(k_max), KIND[y], float(l_ratio), float(gamma), float(floor))
+    kcap = min(m, n, MAX_ADAPTIVE_K) if k_max <= 0 else min(m, n, k_max, MAX_ADAPTIVE_K)
+    sigma = np.zeros(kcap, dtype=np.float64)
+    spec = np.zeros((max(int(spectra), 0), kcap), dtype=np.float64)
+    r, a, kk, ll, rounds = (C.c_int32(0) for _ in range(5))
+    q, qa = C.c_double(0.0), C.c_double(0.0)
+    fl = C.c_uint32(0)
+    st = lib().re_rank_gap(h.bind(), _ptr(A), _dtype_code(A), m, n, A.stride(0), C.byref(gs), int(seed) % 2**64,
+                           C.byref(r), C.byref(q), C.byref(a), C.byref(qa), sigma.ctypes.data_as(C.c_void_p),
+                           C.byref(kk), C.byref(ll), C.byref(rounds),
+                           spec.ctypes.data_as(C.c_void_p) if spec.size else None, spec.shape[0], C.byref(fl))
+    _check(st, "re_rank_gap")
+    widths = []
+    k = min(int(k0), kcap)
+    for _ in range(min(rounds.value, spec.shape[0])):
+        widths.append(k)
+        k = min(k + int(dk), kcap)
+    return r.value, sigma[:kk.value], {"ratio": q.value, "argmax": a.value, "argmax_ratio": qa.value, "k": kk.value,
+                                       "l": ll.value, "rounds": rounds.value, "flags": fl.value,
+                                       "spectra": [spec[j, :w].copy() for j, w in enumerate(widths)]}
 
 
 def rangefinder(A: torch.Tensor, eps: float, p: int = 10, *, k0: int = 32, k_max: int = 0, l_ratio: float = 2.0,

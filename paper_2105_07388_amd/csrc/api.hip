@@ -981,6 +981,143 @@ static re_status adaptive_impl(re_handle h, const void* A, int32_t dt, int64_t m
   }
 }
 
+// ---- rank without a tolerance: the gap search of Sec. 6.1 -----------------
+// Rounds of Algorithm 1 at k0, k0 + dk, ... with a Gaussian X whose new
+// columns (and a Gaussian Y's new rows) are drawn and applied per round; an
+// SRHT Y keeps its first-level transform of every column of A X (as the
+// adaptive driver).  After each round's small SVD the gap statistics are
+// formed on the device and the host decides whether to go on.
+static re_status gap_impl(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                          const re_gap_search* gs, uint64_t seed, int32_t* r_out, double* ratio_out,
+                          int32_t* argmax_out, double* argmax_ratio_out, double* sigma_out, int32_t* k_out,
+                          int32_t* l_out, int32_t* rounds_out, double* spectra_out, int32_t spectra_cap,
+                          uint32_t* flags_out) {
+  if (!h || !A || !gs || !r_out || !sigma_out) return RE_ERR_INVALID_ARG;
+  if (dt != RE_F64 && dt != RE_F32) return RE_ERR_INVALID_ARG;
+  const size_t be = dt == RE_F64 ? 8 : 4;
+  if (m < 1 || n < 1 || lda < n || ((uintptr_t)A) % be != 0) return RE_ERR_INVALID_ARG;
+  if (dt == RE_F32 && lda >= kMaxBatchLda) return RE_ERR_UNSUPPORTED;
+  if (gs->k0 < 1 || gs->dk < 1 || gs->k_max < 0 || !(gs->l_ratio >= 1.0) || !isfinite(gs->l_ratio)) return RE_ERR_INVALID_ARG;
+  if (!(gs->gamma > 1.0) || !(gs->floor >= 0.0) || !isfinite(gs->floor)) return RE_ERR_INVALID_ARG;
+  if (gs->y_kind != RE_GAUSSIAN && gs->y_kind != RE_SRHT) return RE_ERR_INVALID_ARG;
+  if (spectra_cap < 0 || (spectra_cap > 0 && !spectra_out)) return RE_ERR_INVALID_ARG;
+  int64_t kmax = m < n ? m : n;
+  if (gs->k_max > 0 && gs->k_max < kmax) kmax = gs->k_max;
+  if (kmax > RE_MAX_ADAPTIVE_K) kmax = RE_MAX_ADAPTIVE_K;
+  const int64_t k_first = gs->k0 < kmax ? gs->k0 : kmax;
+  const int64_t lmax = l_for(kmax, gs->l_ratio, m);
+  const bool srht_y = gs->y_kind == RE_SRHT;
+  const int64_t npad_m = next_pow2(m);
+  const int64_t xcols = k_first > gs->dk ? k_first : gs->dk;  // widest appended block of X
+  size_t yparts = 0;
+  if (!srht_y && dt == RE_F32) {
+    for (int64_t k = k_first;; k = k + gs->dk < kmax ? k + gs->dk : kmax) {
+      const size_t b = yb_scratch(l_for(k, gs->l_ratio, m), k, m);
+      yparts = b > yparts ? b : yparts;
+      if (k >= kmax) break;
+    }
+  }
+  Carve c;
+  const size_t oB = c.take((size_t)(srht_y ? (int64_t)srht_cols_rows_alloc(m) : m) * kmax * be);
+  const size_t oX = c.take((size_t)n * xcols * be);
+  const size_t oY = c.take(srht_y ? 0 : (size_t)lmax * m * be);
+  const size_t oybits = c.take(srht_y ? (size_t)cdiv(npad_m, 32) * 4 : 0);
+  const size_t oysel = c.take(srht_y ? (size_t)lmax * 4 : 0);
+  const size_t oselscr = c.take(srht_y ? select_scratch_bytes(npad_m) : 0);
+  const size_t oC = c.take((size_t)lmax * kmax * 8);
+  const size_t osvd = c.take(svd_scratch_bytes(lmax, kmax));
+  const size_t osig = c.take((size_t)kmax * 8);
+  const size_t oinfo = c.take(16);
+  const size_t ogap = c.take(sizeof(GapOut));
+  const size_t ogd = c.take(sizeof(GemmDesc));
+  const size_t oyd = c.take(sizeof(YDesc));
+  const size_t oq = c.take(16);
+  const size_t oparts = c.take(yparts);
+  RE_TRY(ensure_ws(h, c.off));
+  RE_TRY(ensure_host(h, 64 + (size_t)kmax * 8));
+  hipStream_t s = h->stream;
+  char* host = (char*)h->host;
+  char* B = at(h, oB);
+  char* Xn = at(h, oX);
+  char* Y = at(h, oY);
+  double* C = (double*)at(h, oC);
+  double* sigma = (double*)at(h, osig);
+  int32_t* info = (int32_t*)at(h, oinfo);
+  GapOut* gout = (GapOut*)at(h, ogap);
+  int64_t k_old = 0, l_old = 0, k = k_first;
+  int32_t rounds = 0, prev_g = -1;
+  for (;;) {
+    const int64_t l = l_for(k, gs->l_ratio, m), dkr = k - k_old;
+    // Algorithm 1 steps 2-3 on the appended columns only
+    if (dt == RE_F32) {
+      RE_TRY(launch_gauss_sub(s, n, dkr, 0, k_old, seed, kXGauss, 0, dkr, (float*)Xn));
+      RE_TRY(launch_gemm_f32_single(s, (const float*)A, m, n, lda, (const float*)Xn, dkr, (float*)B + k_old, kmax,
+                                    (GemmDesc*)at(h, ogd), (unsigned*)at(h, oq)));
+    } else {
+      RE_TRY(launch_gauss_sub64(s, n, dkr, 0, k_old, seed, kXGauss, 0, dkr, (double*)Xn));
+      RE_TRY(launch_gemm_f64acc(s, m, dkr, n, A, 0, lda, Xn, 0, dkr, (double*)B + k_old, 0, kmax));
+    }
+    // steps 4-6
+    if (srht_y) {
+      uint32_t* ybits = (uint32_t*)at(h, oybits);
+      int32_t* ysel = (int32_t*)at(h, oysel);
+      if (k_old == 0) RE_TRY(launch_sign_bits(s, npad_m, seed, kYSign, ybits));
+      RE_TRY(launch_srht_cols_lo(s, B + (size_t)k_old * be, dt, m, dkr, kmax, ybits));
+      RE_TRY(launch_select(s, npad_m, l, seed, kYSel, at(h, oselscr), ysel));  // nested in l
+      RE_TRY(launch_srht_cols_hi(s, B, dt, m, k, kmax, ysel, l, C));
+    } else if (dt == RE_F32) {
+      RE_TRY(launch_gauss_sub(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, (float*)Y + l_old * m));
+      RE_TRY(run_yb(s, (const float*)B, m, k, kmax, (const float*)Y, m, l, C, (YDesc*)at(h, oyd), at(h, oparts)));
+    } else {
+      RE_TRY(launch_gauss_sub64(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, (double*)Y + l_old * m));
+      RE_TRY(launch_gemm_f64acc(s, l, k, m, Y, 0, m, B, 0, kmax, C, 0, k));
+    }
+    // steps 7-8, the gap statistics in place of the count
+    const int32_t r1 = r1_from_k((int32_t)k);
+    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, osvd), sigma, info));
+    RE_TRY(launch_gap(s, sigma, k, r1, gs->gamma, gs->floor, info, gout));
+    RE_TRY_HIP(hipMemcpyAsync(host, gout, sizeof(GapOut), hipMemcpyDeviceToHost, s));
+    RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)k * 8, hipMemcpyDeviceToHost, s));
+    RE_TRY_HIP(hipStreamSynchronize(s));
+    GapOut go;
+    memcpy(&go, host, sizeof(go));
+    if (go.status != 0) return (re_status)go.status;
+    if (spectra_out && rounds < spectra_cap) {
+      double* row = spectra_out + (size_t)rounds * kmax;
+      memcpy(row, host + 64, (size_t)k * 8);
+      for (int64_t j = k; j < kmax; ++j) row[j] = 0.0;
+    }
+    ++rounds;
+    const bool zero = !(go.s1 > 0.0);
+    const bool done = !zero && go.g > 0 && go.g == prev_g && go.reached;
+    if (zero || done || k >= kmax) {
+      *r_out = zero ? 0 : go.g;
+      if (ratio_out) *ratio_out = zero ? 0.0 : go.ratio_g;
+      if (argmax_out) *argmax_out = zero ? 0 : go.a;
+      if (argmax_ratio_out) *argmax_ratio_out = zero ? 0.0 : go.ratio_a;
+      memcpy(sigma_out, host + 64, (size_t)k * 8);
+      if (k_out) *k_out = (int32_t)k;
+      if (l_out) *l_out = (int32_t)l;
+      if (rounds_out) *rounds_out = rounds;
+      if (flags_out) *flags_out = zero ? (uint32_t)RE_FLAG_ZERO : done ? 0u : (uint32_t)RE_FLAG_NOT_CONVERGED;
+      return RE_OK;
+    }
+    prev_g = go.g;
+    k_old = k;
+    l_old = l;
+    k = k + gs->dk < kmax ? k + gs->dk : kmax;
+  }
+}
+
+RE_API re_status re_rank_gap(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
+                             const re_gap_search* gs, uint64_t seed, int32_t* r_out, double* ratio_out,
+                             int32_t* argmax_out, double* argmax_ratio_out, double* sigma_out, int32_t* k_out,
+                             int32_t* l_out, int32_t* rounds_out, double* spectra_out, int32_t spectra_cap,
+                             uint32_t* flags_out) {
+  return gap_impl(h, A, dt, m, n, lda, gs, seed, r_out, ratio_out, argmax_out, argmax_ratio_out, sigma_out, k_out,
+                  l_out, rounds_out, spectra_out, spectra_cap, flags_out);
+}
+
 RE_API re_status re_rank_adaptive(re_handle h, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
                                   double eps, const re_adaptive* ad, uint64_t seed, int32_t* r_out, double* sigma_out,
                                   int32_t* k_out, int32_t* l_out, int32_t* rounds_out, int32_t* k_proposed_out,

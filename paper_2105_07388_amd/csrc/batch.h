@@ -55,6 +55,9 @@ __attribute__((visibility("hidden"))) re_status launch_gemm_f32_single(hipStream
 __attribute__((visibility("hidden"))) re_status launch_gauss_sub(hipStream_t s, int64_t rows, int64_t cols, int64_t r0,
                                                                 int64_t c0, uint64_t seed, int stream_id, int swap_ab,
                                                                 int64_t ld, float* out);
+__attribute__((visibility("hidden"))) re_status launch_gauss_sub64(hipStream_t s, int64_t rows, int64_t cols,
+                                                                  int64_t r0, int64_t c0, uint64_t seed, int stream_id,
+                                                                  int swap_ab, int64_t ld, double* out);
 // C = Y[:, :m] B (l x k FP64) for one block with the batched kernel's
 // arithmetic; with m above one group of rows it splits m over workgroups,
 // which needs ygemm_split_bytes(l, k, m) of `parts` (nullptr: no split).

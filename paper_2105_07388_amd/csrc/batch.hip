@@ -172,6 +172,16 @@ __global__ void k_gauss_sub(int64_t rows, int64_t cols, int64_t r0, int64_t c0, 
   }
 }
 
+// The same entries in FP64 (the draw is FP64 before any rounding).
+__global__ void k_gauss_sub64(int64_t rows, int64_t cols, int64_t r0, int64_t c0, uint64_t seed, uint64_t stream,
+                              int swap_ab, int64_t ld, double* __restrict__ out) {
+  const int64_t total = rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / cols, j = e - i * cols;
+    out[i * ld + j] = swap_ab ? gauss01(c0 + j, r0 + i, stream, seed) : gauss01(r0 + i, c0 + j, stream, seed);
+  }
+}
+
 // Master sketches of a batched call, seed read from the device header so the
 // captured graph serves every seed: X[i][j] (n_max x k) from counter (i, j)
 // of the X stream and Y[i][j] (l x m_max) from counter (j, i) of the Y
@@ -401,6 +411,17 @@ re_status launch_gauss_sub(hipStream_t s, int64_t rows, int64_t cols, int64_t r0
   if (total <= 0) return RE_OK;
   const int64_t g = cdiv(total, 256) < 8192 ? cdiv(total, 256) : 8192;
   hipLaunchKernelGGL(k_gauss_sub, dim3((unsigned)g), dim3(256), 0, s, rows, cols, r0, c0, seed, (uint64_t)stream_id,
+                     swap_ab, ld, out);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
+
+re_status launch_gauss_sub64(hipStream_t s, int64_t rows, int64_t cols, int64_t r0, int64_t c0, uint64_t seed,
+                             int stream_id, int swap_ab, int64_t ld, double* out) {
+  const int64_t total = rows * cols;
+  if (total <= 0) return RE_OK;
+  const int64_t g = cdiv(total, 256) < 8192 ? cdiv(total, 256) : 8192;
+  hipLaunchKernelGGL(k_gauss_sub64, dim3((unsigned)g), dim3(256), 0, s, rows, cols, r0, c0, seed, (uint64_t)stream_id,
                      swap_ab, ld, out);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;

@@ -156,6 +156,13 @@ RE_HIDDEN re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_
                                double* sigma, int32_t* info);
 RE_HIDDEN re_status launch_rank_count(hipStream_t s, const double* sigma, int64_t k, int32_t r1, double eps,
                                       const int32_t* info, int32_t* out3);
+// Gap statistics of descending estimates (search without a tolerance).
+struct GapOut {
+  int32_t g, a, reached, status;
+  double ratio_g, ratio_a, s1;
+};
+RE_HIDDEN re_status launch_gap(hipStream_t s, const double* sigma, int64_t k, int32_t r1, double gamma,
+                               double floor_rel, const int32_t* info, GapOut* out);
 RE_HIDDEN re_status launch_nonfinite_scan(hipStream_t s, const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                                           int32_t* count);
 

@@ -1095,6 +1095,73 @@ __global__ void __launch_bounds__(256) k_count(const double* __restrict__ sigma,
   out[2] = st;
 }
 
+// Gap statistics of the descending estimates for a search without a
+// tolerance (Sec. 5 after Algorithm 1, Sec. 6.1), over the 1-based i < n =
+// min(r1, k) with s_i > 0, ratio_i = s_i / s_{i+1} (infinite when s_{i+1} = 0):
+//   g      the largest i with ratio_i >= gamma (0 when none)
+//   a      the i of the largest ratio, ties to the smallest i
+//   reached  s_n <= floor s_1
+// out: int32 {g, a, reached, status}, then doubles {ratio_g, ratio_a, s_1}.
+__global__ void __launch_bounds__(256) k_gap(const double* __restrict__ sigma, int64_t k, int32_t r1, double gamma,
+                                            double floor_rel, const int32_t* __restrict__ info,
+                                            GapOut* __restrict__ out) {
+  __shared__ int64_t s_z;
+  __shared__ int64_t s_g[256];
+  __shared__ double s_q[256];
+  __shared__ int64_t s_a[256];
+  const int64_t n = r1 < k ? r1 : k;
+  if (threadIdx.x == 0) s_z = n;
+  __syncthreads();
+  // first index (0-based, below n) holding a non-positive estimate
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x)
+    if (!(sigma[j] > 0.0)) atomicMin((unsigned long long*)&s_z, (unsigned long long)j);
+  __syncthreads();
+  const int64_t z = s_z;
+  // ratios for 1 <= i <= min(n - 1, z)
+  const int64_t hi = (n - 1) < z ? (n - 1) : z;
+  int64_t g = 0, a = 0;
+  double qa = -1.0;
+  for (int64_t i = 1 + threadIdx.x; i <= hi; i += blockDim.x) {
+    const double num = sigma[i - 1], den = sigma[i];
+    const double q = den > 0.0 ? num / den : HUGE_VAL;
+    if (q >= gamma && i > g) g = i;
+    if (q > qa) {  // i increases along a thread's sequence, so strict > keeps its smallest
+      qa = q;
+      a = i;
+    }
+  }
+  s_g[threadIdx.x] = g;
+  s_q[threadIdx.x] = qa;
+  s_a[threadIdx.x] = a;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int64_t G = 0, Aix = 0;
+  double QA = -1.0;
+  for (int t = 0; t < (int)blockDim.x; ++t) {
+    if (s_g[t] > G) G = s_g[t];
+    if (s_a[t] > 0 && (s_q[t] > QA || (s_q[t] == QA && s_a[t] < Aix))) {
+      QA = s_q[t];
+      Aix = s_a[t];
+    }
+  }
+  const double s1 = n > 0 ? sigma[0] : 0.0;
+  GapOut o{};
+  o.status = info ? info[0] : 0;
+  if (o.status == 0) {
+    for (int64_t j = 0; j < k; ++j)
+      if (!isfinite(sigma[j])) o.status = RE_ERR_NONFINITE;
+  }
+  if (s1 > 0.0 && n >= 2) {
+    o.g = (int32_t)G;
+    o.a = (int32_t)Aix;
+    o.ratio_g = G > 0 ? (sigma[G] > 0.0 ? sigma[G - 1] / sigma[G] : HUGE_VAL) : 0.0;
+    o.ratio_a = Aix > 0 ? QA : 0.0;
+  }
+  o.reached = n > 0 && sigma[n - 1] <= floor_rel * s1;
+  o.s1 = s1;
+  *out = o;
+}
+
 __global__ void k_svd_init(unsigned* bar, int32_t* info) {
   if (threadIdx.x == 0) {
     bar[0] = 0;
@@ -1491,6 +1558,13 @@ re_status launch_sv_count_batched(hipStream_t s, const SvDesc* desc, int nblk, i
 re_status launch_rank_count(hipStream_t s, const double* sigma, int64_t k, int32_t r1, double eps, const int32_t* info,
                             int32_t* out3) {
   hipLaunchKernelGGL(k_count, dim3(1), dim3(256), 0, s, sigma, k, r1, eps, info, out3);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
+
+re_status launch_gap(hipStream_t s, const double* sigma, int64_t k, int32_t r1, double gamma, double floor_rel,
+                     const int32_t* info, GapOut* out) {
+  hipLaunchKernelGGL(k_gap, dim3(1), dim3(256), 0, s, sigma, k, r1, gamma, floor_rel, info, out);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
 }
