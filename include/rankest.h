@@ -378,7 +378,8 @@ typedef struct {
  *                estimates, zero-padded, for j < spectra_cap
  * Errors: RE_ERR_INVALID_ARG (arguments, including gamma <= 1, floor < 0,
  * y_kind), RE_ERR_NONFINITE, RE_ERR_NO_CONVERGENCE (small SVD), RE_ERR_NO_MEMORY.
- * Synchronises the handle's stream once per round.
+ * Synchronises the handle's stream once per round.  With profiling on
+ * (re_set_profiling), re_last_stage_ms gives each stage summed over the rounds.
  */
 re_status re_rank_gap(re_handle h, const void* A_dev, int32_t dt, int64_t m, int64_t n, int64_t lda,
                       const re_gap_search* gs, uint64_t seed, int32_t* r_out, double* ratio_out, int32_t* argmax_out,

@@ -158,7 +158,7 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
 // Workspace plan of one estimate.
 struct Plan {
   size_t xbits, ybits, xsel, ysel, selscr, X, Y, B, C, svd, sigma, info, out3, stats, gdesc, ydesc, queue, yparts,
-      rdiag, hscr, total;
+      rdiag, hscr, gparts, total;
 };
 
 // Sketches the batched form accepts (one workgroup's LDS holds the small SVD).
@@ -203,6 +203,11 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   p.queue = c.take(16);
   p.yparts = c.take(rs.yk == RE_GAUSSIAN && dt == RE_F32 ? yb_scratch(rs.l, rs.k, m) : 0);
   p.rdiag = c.take((size_t)rs.k * 3 * 8);  // diagonals of the QR passes (step 7 by the QR diagonal)
+  if (dt == RE_F64) {  // K-split partial products of the FP64 Gaussian contractions
+    const size_t gx = rs.xk == RE_GAUSSIAN ? gemm64_parts_bytes(m, rs.k, n) : 0;
+    const size_t gy = rs.yk == RE_GAUSSIAN ? gemm64_parts_bytes(rs.l, rs.k, m) : 0;
+    p.gparts = c.take(gx > gy ? gx : gy);
+  }
   p.hscr = c.take(rs.xk == RE_HRTT ? hrtt_scratch_bytes(n, rs.k) : 0);
   p.total = c.off;
   return p;
@@ -261,7 +266,10 @@ re_status run_x(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m
   if (dt == RE_F32 && lda < kMaxBatchLda)  // FP32: the matrix-core contraction shared with the batched form
     return launch_gemm_f32_single(s, (const float*)A, m, n, lda, (const float*)X, rs.k, (float*)B, rs.k,
                                   (GemmDesc*)at(h, p.gdesc), (unsigned*)at(h, p.queue));
-  return launch_gemm_f64acc(s, m, rs.k, n, A, 0, lda, X, 0, rs.k, B, 0, rs.k);
+  if (dt == RE_F32)  // rows too far apart for the persistent kernel's descriptors
+    return launch_gemm_f64acc(s, m, rs.k, n, A, 1, lda, X, 1, rs.k, B, 1, rs.k);
+  return launch_gemm64(s, m, rs.k, n, (const double*)A, lda, (const double*)X, rs.k, (double*)B, rs.k,
+                       (double*)at(h, p.gparts));
 }
 
 // Algorithm 1 steps 5-6: draw Y (RE_STAGE_Y_DRAW), form C = Y B (RE_STAGE_YB).
@@ -283,7 +291,8 @@ re_status run_y(re_handle h, const Plan& p, void* B, int32_t bdt, int64_t m, con
   if (bdt == RE_F32)
     return run_yb(s, (const float*)B, m, rs.k, rs.k, (const float*)Y, m, rs.l, C, (YDesc*)at(h, p.ydesc),
                   at(h, p.yparts));
-  return launch_gemm_f64acc(s, rs.l, rs.k, m, Y, 0, m, B, 0, rs.k, C, 0, rs.k);
+  return launch_gemm64(s, rs.l, rs.k, m, (const double*)Y, m, (const double*)B, rs.k, C, rs.k,
+                       (double*)at(h, p.gparts));
 }
 
 }  // namespace
@@ -1033,6 +1042,17 @@ static re_status gap_impl(re_handle h, const void* A, int32_t dt, int64_t m, int
   const size_t oyd = c.take(sizeof(YDesc));
   const size_t oq = c.take(16);
   const size_t oparts = c.take(yparts);
+  size_t gp = 0;  // K-split partials of the FP64 products, the largest over the rounds
+  if (dt == RE_F64) {
+    for (int64_t k = k_first, ko = 0;; ko = k, k = k + gs->dk < kmax ? k + gs->dk : kmax) {
+      const size_t gx = gemm64_parts_bytes(m, k - ko, n);
+      const size_t gy = srht_y ? 0 : gemm64_parts_bytes(l_for(k, gs->l_ratio, m), k, m);
+      gp = gx > gp ? gx : gp;
+      gp = gy > gp ? gy : gp;
+      if (k >= kmax) break;
+    }
+  }
+  const size_t ogp = c.take(gp);
   RE_TRY(ensure_ws(h, c.off));
   RE_TRY(ensure_host(h, 64 + (size_t)kmax * 8));
   hipStream_t s = h->stream;
@@ -1046,39 +1066,58 @@ static re_status gap_impl(re_handle h, const void* A, int32_t dt, int64_t m, int
   GapOut* gout = (GapOut*)at(h, ogap);
   int64_t k_old = 0, l_old = 0, k = k_first;
   int32_t rounds = 0, prev_g = -1;
+  double acc_ms[RE_NUM_STAGES] = {};  // stage times summed over the rounds (profiling)
   for (;;) {
     const int64_t l = l_for(k, gs->l_ratio, m), dkr = k - k_old;
     // Algorithm 1 steps 2-3 on the appended columns only
+    mark(h, RE_STAGE_X_DRAW);
     if (dt == RE_F32) {
       RE_TRY(launch_gauss_sub(s, n, dkr, 0, k_old, seed, kXGauss, 0, dkr, (float*)Xn));
+      mark(h, RE_STAGE_AX);
       RE_TRY(launch_gemm_f32_single(s, (const float*)A, m, n, lda, (const float*)Xn, dkr, (float*)B + k_old, kmax,
                                     (GemmDesc*)at(h, ogd), (unsigned*)at(h, oq)));
     } else {
       RE_TRY(launch_gauss_sub64(s, n, dkr, 0, k_old, seed, kXGauss, 0, dkr, (double*)Xn));
-      RE_TRY(launch_gemm_f64acc(s, m, dkr, n, A, 0, lda, Xn, 0, dkr, (double*)B + k_old, 0, kmax));
+      mark(h, RE_STAGE_AX);
+      RE_TRY(launch_gemm64(s, m, dkr, n, (const double*)A, lda, (const double*)Xn, dkr, (double*)B + k_old, kmax,
+                           (double*)at(h, ogp)));
     }
     // steps 4-6
+    mark(h, RE_STAGE_Y_DRAW);
     if (srht_y) {
       uint32_t* ybits = (uint32_t*)at(h, oybits);
       int32_t* ysel = (int32_t*)at(h, oysel);
       if (k_old == 0) RE_TRY(launch_sign_bits(s, npad_m, seed, kYSign, ybits));
-      RE_TRY(launch_srht_cols_lo(s, B + (size_t)k_old * be, dt, m, dkr, kmax, ybits));
       RE_TRY(launch_select(s, npad_m, l, seed, kYSel, at(h, oselscr), ysel));  // nested in l
+      mark(h, RE_STAGE_YB);
+      RE_TRY(launch_srht_cols_lo(s, B + (size_t)k_old * be, dt, m, dkr, kmax, ybits));
       RE_TRY(launch_srht_cols_hi(s, B, dt, m, k, kmax, ysel, l, C));
     } else if (dt == RE_F32) {
       RE_TRY(launch_gauss_sub(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, (float*)Y + l_old * m));
+      mark(h, RE_STAGE_YB);
       RE_TRY(run_yb(s, (const float*)B, m, k, kmax, (const float*)Y, m, l, C, (YDesc*)at(h, oyd), at(h, oparts)));
     } else {
       RE_TRY(launch_gauss_sub64(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, (double*)Y + l_old * m));
-      RE_TRY(launch_gemm_f64acc(s, l, k, m, Y, 0, m, B, 0, kmax, C, 0, k));
+      mark(h, RE_STAGE_YB);
+      RE_TRY(launch_gemm64(s, l, k, m, (const double*)Y, m, (const double*)B, kmax, C, k, (double*)at(h, ogp)));
     }
     // steps 7-8, the gap statistics in place of the count
     const int32_t r1 = r1_from_k((int32_t)k);
+    mark(h, RE_STAGE_SVD);
     RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, osvd), sigma, info));
+    mark(h, RE_STAGE_RANK);
     RE_TRY(launch_gap(s, sigma, k, r1, gs->gamma, gs->floor, info, gout));
     RE_TRY_HIP(hipMemcpyAsync(host, gout, sizeof(GapOut), hipMemcpyDeviceToHost, s));
     RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)k * 8, hipMemcpyDeviceToHost, s));
+    mark(h, RE_NUM_STAGES);
     RE_TRY_HIP(hipStreamSynchronize(s));
+    if (h->prof) {
+      for (int i = 0; i < RE_NUM_STAGES; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]) == hipSuccess) acc_ms[i] += (double)ms;
+      }
+      for (int i = 0; i < RE_NUM_STAGES; ++i) h->stage_ms[i] = acc_ms[i];
+    }
     GapOut go;
     memcpy(&go, host, sizeof(go));
     if (go.status != 0) return (re_status)go.status;

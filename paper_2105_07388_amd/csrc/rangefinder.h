@@ -55,6 +55,11 @@ RE_RF_HIDDEN re_status launch_yb_tiled(hipStream_t s, const float* B, int64_t m,
 // parts[s] (w x n) = Q[rows of chunk s]^T A[rows of chunk s], FP32
 // matrix-core products of FP32 A with Q rounded to FP32 (q32: m x w floats of
 // scratch), FP64 accumulation across every 256 rows.
+// FP64 C = A B on the matrix cores, K split over slices when M is short and K
+// long (parts: gemm64_parts_bytes; nullptr when that is 0).
+RE_RF_HIDDEN size_t gemm64_parts_bytes(int64_t M, int64_t N, int64_t K);
+RE_RF_HIDDEN re_status launch_gemm64(hipStream_t s, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                                     const double* B, int64_t ldb, double* C, int64_t ldc, double* parts);
 RE_RF_HIDDEN int64_t rf_qta_col_tiles(int64_t n);
 RE_RF_HIDDEN re_status launch_rf_qta(hipStream_t s, const double* Q, int64_t ldq, int64_t w, const float* A,
                                      int64_t m, int64_t n, int64_t lda, int64_t splits, int64_t rows_per_split,

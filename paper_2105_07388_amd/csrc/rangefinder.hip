@@ -773,6 +773,43 @@ re_status launch_yb_tiled(hipStream_t s, const float* B, int64_t m, int64_t k, i
   return RE_OK;
 }
 
+// FP64 C (M x N, ldc) = A (M x K) B (K x N) on the FP64 matrix cores (the
+// 64 x 64 tiles of k_nn64).  K is split into S slices only when M is short
+// (fewer than 64 row tiles) and K long, so that a short, wide product still
+// fills the chip; the slices' partial products are then summed in slice
+// order.  S depends on M and K alone, so every column of C gets the same
+// arithmetic whatever N is (a product over the appended columns of B gives
+// the bits of the same columns in a wider product).
+void gemm64_split(int64_t M, int64_t K, int64_t* splits, int64_t* rows_per_split) {
+  int64_t sp = 1;
+  if (cdiv(M, 64) < 64 && K > 4096) sp = cdiv(K, 4096) < 32 ? cdiv(K, 4096) : 32;
+  const int64_t rps = cdiv(cdiv(K, sp), kABK) * kABK;
+  *rows_per_split = rps;
+  *splits = cdiv(K, rps);
+}
+
+size_t gemm64_parts_bytes(int64_t M, int64_t N, int64_t K) {
+  int64_t sp = 0, rps = 0;
+  gemm64_split(M, K, &sp, &rps);
+  return sp > 1 ? (size_t)sp * M * N * 8 : 0;
+}
+
+re_status launch_gemm64(hipStream_t s, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
+                        int64_t ldb, double* C, int64_t ldc, double* parts) {
+  if (M <= 0 || N <= 0) return RE_OK;
+  int64_t sp = 0, rps = 0;
+  gemm64_split(M, K, &sp, &rps);
+  if (sp > 1 && !parts) return RE_ERR_INVALID_ARG;
+  if (cdiv(M, 64) > 65535 || sp > 65535) return RE_ERR_UNSUPPORTED;
+  const dim3 grid((unsigned)cdiv(N, 64), (unsigned)cdiv(M, 64), (unsigned)sp);
+  double* out = sp > 1 ? parts : C;
+  hipLaunchKernelGGL((k_nn64<double, double>), grid, dim3(256), 0, s, A, M, lda, B, ldb, N, K, rps, 0,
+                     (const int32_t*)nullptr, out, sp > 1 ? N : ldc, sp > 1 ? M * N : (int64_t)0);
+  RE_TRY_HIP(hipGetLastError());
+  if (sp > 1) return launch_rf_sum_parts(s, parts, sp, M, N, false, C, ldc);
+  return RE_OK;
+}
+
 int64_t rf_qta_col_tiles(int64_t n) { return cdiv(n, kQBJ); }
 
 re_status launch_qr_sigma(hipStream_t s, const double* rdiag3, int64_t k, double scale, double* sigma) {
