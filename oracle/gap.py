@@ -23,6 +23,8 @@ r^ is the deepest gap of the last round.
 """
 import math
 
+import numpy as np
+
 
 from . import pyoracle as _o
 
@@ -79,7 +81,16 @@ def widths(k0, dk, kmax):
 
 def estimates(A, k, l, ykind, seed):
     """Algorithm 1's k scaled estimates at (k, l) with a Gaussian X (FP64
-    library products of the rounded draws) and a Gaussian or SRHT Y."""
+    library products of the rounded draws) and a Gaussian, SRHT or (ykind =
+    "srct") subsampled randomized DCT Y."""
+    if ykind == "srct":
+        from . import hrtt
+        Xg = _o.gauss_matrix(seed, A.shape[1], k, _o.STREAM_XGAUSS, _o.x_format(_o._a_dtype(A), 0))
+        Cm = hrtt.apply_y_srct(np.asarray(A, dtype=np.float64) @ Xg, l, seed=seed)
+        s, _, st = _o.jacobi_sv(Cm)
+        if st != 0:
+            raise _o.OracleError(st)
+        return s / math.sqrt(float(k) * float(l))
     _, s, _, _, _ = _o.rank_estimate_gemm(A, 0.5, _o.GAUSSIAN, ykind, k=k, l=l, seed=seed)
     return s
 

@@ -20,6 +20,13 @@ B[i, b] = sqrt(N) (F D a_i)_{s_b}, with s the SRHT's X sample (the k smallest
 Philox keys of stream 5 over the N coordinates, sorted); sqrt(N) plays the part
 of the unnormalised Hadamard matrix's scale, so that E ||a X||^2 = k ||a||^2
 as for the other kinds.
+
+The subsampled randomized DCT as Y (SRCT Y: Sec. 4 with F a DCT; Sec. 6 uses it
+for Theta = Y) acts on the columns of B = A X (m x k, zero-padded to M = the
+next power of two >= max(m, 2)):  C[s, t] = sqrt(M) (F D_Y b_t)_{q_s}, with
+D_Y the SRHT's Y signs (Philox stream 4) and q the SRHT's Y sample (the l
+smallest stream-6 keys over the M coordinates, sorted), so E ||Y b||^2 =
+l ||b||^2 as for the Gaussian and SRHT Y.
 """
 import math
 
@@ -85,6 +92,55 @@ def apply_x_srct(A, k, seed=0, blk=0):
     Yt = sf.dct(Z, type=2, norm="ortho", axis=1)
     sel = _o.select(seed, N, k, _o.STREAM_XSEL, blk)
     return math.sqrt(N) * Yt[:, sel]
+
+
+def signs_y(seed, M, blk=0):
+    return np.array([_o.sign(seed, i, _o.STREAM_YSIGN, blk) for i in range(M)], dtype=np.float64)
+
+
+def apply_y_srct(B, l, seed=0, blk=0):
+    """C = Y B for the SRCT Y (l x k, FP64): the orthonormal DCT-II along the
+    (signed, zero-padded) columns of B, the l sampled outputs, times sqrt(M)."""
+    B = np.asarray(B, dtype=np.float64)
+    m, k = B.shape
+    M = npad(m)
+    Z = np.zeros((M, k))
+    Z[:m] = B
+    Z *= signs_y(seed, M, blk)[:, None]
+    Ft = sf.dct(Z, type=2, norm="ortho", axis=0)
+    sel = _o.select(seed, M, l, _o.STREAM_YSEL, blk)
+    return math.sqrt(M) * Ft[sel, :]
+
+
+def apply_x_any(A, x, k, seed=0):
+    """B = A X for x in gaussian / srht (oracle.c, X in A's storage format as
+    the plain oracle draws it), hrtt, srct."""
+    if x == "hrtt":
+        return apply_x(A, k, seed=seed)
+    if x == "srct":
+        return apply_x_srct(A, k, seed=seed)
+    return _o.apply_x(A, _o.SRHT if x == "srht" else _o.GAUSSIAN, k, seed=seed)
+
+
+def rank_estimate_any(A, eps, x="gaussian", y="srct", k=40, l=None, seed=0):
+    """Algorithm 1 with any X kind and a Gaussian, SRHT or SRCT Y: (r, sigma[k],
+    r1, flags).  Gaussian / SRHT Y as the plain oracle draws them (A's storage
+    format)."""
+    A = np.ascontiguousarray(A)
+    l = 2 * k if l is None else l
+    B = apply_x_any(A, x, k, seed=seed)
+    if y == "srct":
+        Cm = apply_y_srct(B, l, seed=seed)
+    else:
+        fmt = _o.FMT_F64 if A.dtype == np.float64 else _o.FMT_F32
+        Cm = _o.apply_y(B, _o.SRHT if y == "srht" else _o.GAUSSIAN, l, fmt_y=fmt, seed=seed)
+    s, _, st = _o.jacobi_sv(Cm)
+    if st != 0:
+        raise _o.OracleError(st)
+    s = s / math.sqrt(k * l)
+    r1 = _o.r1_from_k(k)
+    r, flags = _o.rank_count(s, r1, eps)
+    return r, s, r1, flags
 
 
 def rank_estimate(A, eps, k=40, l=None, ykind=_o.GAUSSIAN, seed=0, x="hrtt"):

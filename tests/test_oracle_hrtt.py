@@ -97,3 +97,57 @@ def test_srct_isometry_in_expectation(orc):
     x = np.random.default_rng(4).standard_normal((1, 100))
     r = [np.sum(orc.hrtt.apply_x_srct(x, 16, seed=t) ** 2) / 16 / np.sum(x ** 2) for t in range(80)]
     assert abs(np.mean(r) - 1.0) < 4 * np.std(r) / math.sqrt(80)
+
+
+# --- the subsampled randomized DCT as Y -------------------------------------------------
+
+def test_srct_y_is_the_written_out_product(orc):
+    """C = sqrt(M) S F D_Y [B; 0] with F the DCT-II written out, D_Y the SRHT's Y
+    signs and S the SRHT's Y sample (streams 4 and 6)."""
+    H = orc.hrtt
+    rng = np.random.default_rng(9)
+    m, k, l, seed = 37, 6, 11, 5
+    B = rng.standard_normal((m, k))
+    M = H.npad(m)
+    D = np.diag(H.signs_y(seed, M))
+    sel = orc.select(seed, M, l, orc.STREAM_YSEL)
+    S = np.zeros((l, M))
+    S[np.arange(l), sel] = 1.0
+    Y = (S @ H.dct_matrix(M) @ D)[:, :m] * math.sqrt(M)  # l x m
+    assert np.allclose(H.apply_y_srct(B, l, seed=seed), Y @ B, atol=1e-12)
+    assert np.array_equal(D.diagonal(), [orc.sign(seed, i, orc.STREAM_YSIGN) for i in range(M)])
+    assert set(orc.select(seed, M, l // 2, orc.STREAM_YSEL)) <= set(sel)
+
+
+def test_srct_y_full_sample_is_orthogonal(orc):
+    """An SRHT X with k = N and an SRCT Y with l = M sample every coordinate: both
+    are sqrt(N) resp. sqrt(M) times orthogonal maps, so the scaled estimates are
+    sigma(A) and the rank is Def. 1's."""
+    rng = np.random.default_rng(13)
+    m, n = 48, 32
+    A = rng.standard_normal((m, 4)) @ rng.standard_normal((4, n)) + 1e-3 * rng.standard_normal((m, n))
+    r, s, r1, fl = orc.hrtt.rank_estimate_any(A, 1e-2, x="srht", y="srct", k=n, l=64, seed=3)
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert np.allclose(s, sv, rtol=0, atol=1e-12 * sv[0])
+    assert r == orc.rank_def(sv[:r1], 1e-2)
+
+
+def test_srct_y_isometry_in_expectation(orc):
+    b = np.random.default_rng(6).standard_normal((100, 1))
+    r = [np.sum(orc.hrtt.apply_y_srct(b, 16, seed=t) ** 2) / 16 / np.sum(b ** 2) for t in range(80)]
+    assert abs(np.mean(r) - 1.0) < 4 * np.std(r) / math.sqrt(80)
+
+
+def test_srct_y_sees_the_coherent_block_the_srht_y_misses(orc):
+    """The diagonal A_G (400 x 400, blocks of 20) with a Gaussian X of 42
+    columns: B = A X keeps the blocks in its rows.  The subsampled Hadamard Y
+    shows fewer than 20 values of the second block (its columns below 64
+    depend on the low six bits of the sampled row only); the subsampled DCT Y,
+    Sec. 6's choice for this matrix, shows all of them and no gap inside."""
+    A = inputs.diagonal(400, 400, inputs.spectrum_gap(400, 20)).numpy()
+    s_c = orc.gap.estimates(A, 42, 63, "srct", 0)
+    s_h = orc.gap.estimates(A, 42, 63, orc.SRHT, 0)
+    assert orc.gap.deepest_gap(s_c, 38, 100.0)[0] == 20
+    assert np.count_nonzero(s_c[20:40] > 1e-6) == 20 > np.count_nonzero(s_h[20:40] > 1e-6)
+    out = orc.gap.gap_search(A, k0=22, dk=20, gamma=100.0, floor=1e-13, ykind="srct", seed=1)
+    assert out["gaps"] == [0, 20, 40, 60, 80, 80] and out["r"] == 80
