@@ -55,10 +55,12 @@ typedef enum { RE_F64 = 0, RE_F32 = 1 } re_dtype;
  * zero-padded to a power of two), or (X only) a hashed randomized DCT H F D
  * (Sec. 3.3: a CountSketch H in place of the sampling S, F the orthonormal
  * DCT-II of length N = max(2, next power of two >= n); the paper's
- * experimental X) or (X only) the subsampled randomized DCT sqrt(N/k) S F D
- * (the SRHT's signs D and sample S over that N).  The two DCT kinds need FP32 A
- * with N <= 16384 and native precision (else RE_ERR_UNSUPPORTED); as a Y they
- * are rejected (hashed: RE_ERR_INVALID_ARG, subsampled: RE_ERR_UNSUPPORTED). */
+ * experimental X) or the subsampled randomized DCT sqrt(N/k) S F D (the
+ * SRHT's signs D and sample S over that N), as X or as Y (Sec. 6 uses it for
+ * Theta = Y; along the m rows of B = A X, M = max(2, next power of two >= m),
+ * the Y stream's signs and sample, any storage type of A).  As X the two DCT
+ * kinds need FP32 A with N <= 16384 and native precision (else
+ * RE_ERR_UNSUPPORTED); the hashed DCT as a Y is rejected (RE_ERR_INVALID_ARG). */
 typedef enum { RE_GAUSSIAN = 0, RE_SRHT = 1, RE_HRTT = 2, RE_SRCT = 3 } re_kind;
 
 /* Arithmetic of the A X contraction.  NATIVE: the storage type of A.
@@ -320,8 +322,8 @@ re_status re_rank_adaptive(re_handle h, const void* A_dev, int32_t dt, int64_t m
                            int32_t* l_out, int32_t* rounds_out, int32_t* k_proposed_out, uint32_t* flags_out);
 
 /*
- * re_rank_adaptive with the kind of Y chosen: RE_GAUSSIAN (as re_rank_adaptive)
- * or RE_SRHT (X stays Gaussian).  Sec. 5's footnote on growing r1 with an SRTT
+ * re_rank_adaptive with the kind of Y chosen: RE_GAUSSIAN (as re_rank_adaptive),
+ * RE_SRHT or RE_SRCT (X stays Gaussian).  Sec. 5's footnote on growing r1 with an SRTT
  * sketch: the transform F D A X is kept and only subsampled again.  Here each
  * new column of A X gets the signs and the first level of the Walsh-Hadamard
  * transform along m (blocks of 256 or fewer rows) once, in place in the
@@ -329,7 +331,11 @@ re_status re_rank_adaptive(re_handle h, const void* A_dev, int32_t dt, int64_t m
  * from those blocks for all k columns; the samples nest in l.  The final
  * estimate equals re_rank_estimate with Gaussian X and SRHT Y at the final
  * (k, l) and the same seed, bit for bit.
- *   y_kind   RE_GAUSSIAN or RE_SRHT (else RE_ERR_INVALID_ARG)
+ *   y_kind   RE_GAUSSIAN, RE_SRHT or RE_SRCT (else RE_ERR_INVALID_ARG).  With the
+ *            subsampled DCT the kept first level is the 32-point DFTs of the
+ *            column pieces of the DCT along m (the DFT of length M split as
+ *            (M / 32) x 32), formed once per new column; each round forms the
+ *            l sampled outputs from them.
  * Other arguments, outputs and errors as re_rank_adaptive.
  */
 re_status re_rank_adaptive_y(re_handle h, const void* A_dev, int32_t dt, int64_t m, int64_t n, int64_t lda,
@@ -356,7 +362,7 @@ typedef struct {
   int32_t k0;      /* first width of X (Sec. 6.1: 110) */
   int32_t dk;      /* columns appended per round (Sec. 6.1: 100) */
   int32_t k_max;   /* largest width; 0 means min(m, n); capped at RE_MAX_ADAPTIVE_K */
-  int32_t y_kind;  /* RE_GAUSSIAN or RE_SRHT (rows appended / stored first-level transform) */
+  int32_t y_kind;  /* RE_GAUSSIAN (rows appended), RE_SRHT or RE_SRCT (stored first-level transform) */
   double l_ratio;  /* rows of Y per column of X, >= 1 */
   double gamma;    /* gap threshold on s_i / s_{i+1}, > 1 */
   double floor;    /* relative level s_{r1} <= floor s_1 the estimates must reach before stopping, >= 0 */

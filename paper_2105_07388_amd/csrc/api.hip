@@ -16,6 +16,7 @@
 #include "hrtt.h"
 #include "learned.h"
 #include "rangefinder.h"
+#include "srct_y.h"
 
 #define RE_API extern "C" __attribute__((visibility("default")))
 
@@ -135,7 +136,6 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
   if ((sk->x_kind != RE_GAUSSIAN && sk->x_kind != RE_SRHT && sk->x_kind != RE_HRTT && sk->x_kind != RE_SRCT) ||
       (sk->y_kind != RE_GAUSSIAN && sk->y_kind != RE_SRHT && sk->y_kind != RE_SRCT))
     return RE_ERR_INVALID_ARG;
-  if (sk->y_kind == RE_SRCT) return RE_ERR_UNSUPPORTED;  // the subsampled DCT is built for X only
   if (sk->prec < RE_PREC_NATIVE || sk->prec > RE_PREC_AUTO) return RE_ERR_INVALID_ARG;
   rs->xk = sk->x_kind;
   rs->yk = sk->y_kind;
@@ -145,7 +145,7 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
   rs->npad_m = next_pow2(m);
   const bool dct = rs->xk == RE_HRTT || rs->xk == RE_SRCT;
   const int64_t kmax = rs->xk == RE_SRHT ? rs->npad_n : dct ? hrtt_npad(n) : n;
-  const int64_t lmax = rs->yk == RE_SRHT ? rs->npad_m : m;
+  const int64_t lmax = rs->yk == RE_SRHT ? rs->npad_m : rs->yk == RE_SRCT ? srct_y_npad(m) : m;
   if (rs->k < 1 || rs->l < rs->k) return RE_ERR_INVALID_ARG;
   if ((sides & 1) && rs->k > kmax) return RE_ERR_INVALID_ARG;
   if ((sides & 2) && rs->l > lmax) return RE_ERR_INVALID_ARG;
@@ -158,7 +158,7 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
 // Workspace plan of one estimate.
 struct Plan {
   size_t xbits, ybits, xsel, ysel, selscr, X, Y, B, C, svd, sigma, info, out3, stats, gdesc, ydesc, queue, yparts,
-      rdiag, hscr, gparts, total;
+      rdiag, hscr, gparts, U, yord, total;
 };
 
 // Sketches the batched form accepts (one workgroup's LDS holds the small SVD).
@@ -185,10 +185,14 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   const int64_t brows = rs.yk == RE_SRHT ? (int64_t)srht_cols_rows_alloc(m) : m;
   const int64_t xn = rs.xk == RE_HRTT || rs.xk == RE_SRCT ? hrtt_npad(n) : rs.npad_n;  // X's transform length
   p.xbits = c.take((size_t)cdiv(xn, 32) * 4);
-  p.ybits = c.take((size_t)cdiv(rs.npad_m, 32) * 4);
+  const int64_t ym = rs.yk == RE_SRCT ? srct_y_npad(m) : rs.npad_m;  // Y's transform length
+  p.ybits = c.take((size_t)cdiv(ym, 32) * 4);
   p.xsel = c.take((size_t)rs.k * 4);
   p.ysel = c.take((size_t)rs.l * 4);
-  p.selscr = c.take(select_scratch_bytes(xn > rs.npad_m ? xn : rs.npad_m));
+  p.selscr = c.take(select_scratch_bytes(xn > ym ? xn : ym));
+  const int bdt = dt == RE_F64 && rs.fmt_x != kBF16 && rs.fmt_x != kF16 ? RE_F64 : RE_F32;
+  p.U = c.take(rs.yk == RE_SRCT ? srct_y_u_bytes(m, rs.k, dt == RE_F64 ? RE_F64 : bdt) : 0);
+  p.yord = c.take(rs.yk == RE_SRCT ? srct_y_order_bytes(rs.l) : 0);
   p.X = c.take(rs.xk == RE_GAUSSIAN ? (size_t)n * rs.k * (size_t)elem_size(fx) : 0);  // FP32/FP64; 2-byte formats fit too
   p.Y = c.take(rs.yk == RE_GAUSSIAN ? (size_t)rs.l * m * elem_size(fx) : 0);
   p.B = c.take((size_t)brows * rs.k * be);
@@ -283,6 +287,16 @@ re_status run_y(re_handle h, const Plan& p, void* B, int32_t bdt, int64_t m, con
     RE_TRY(launch_select(s, rs.npad_m, rs.l, seed, kYSel, at(h, p.selscr), sel));
     mark(h, RE_STAGE_YB);
     return launch_srht_cols(s, B, bdt, m, rs.k, bits, sel, rs.l, C);
+  }
+  if (rs.yk == RE_SRCT) {  // subsampled randomized DCT: the SRHT's signs and sample over M
+    const int64_t M = srct_y_npad(m);
+    uint32_t* bits = (uint32_t*)at(h, p.ybits);
+    int32_t* sel = (int32_t*)at(h, p.ysel);
+    RE_TRY(launch_sign_bits(s, M, seed, kYSign, bits));
+    RE_TRY(launch_select(s, M, rs.l, seed, kYSel, at(h, p.selscr), sel));
+    mark(h, RE_STAGE_YB);
+    RE_TRY(launch_srct_y_lo(s, B, bdt, m, rs.k, rs.k, bits, at(h, p.U), rs.k));
+    return launch_srct_y_hi(s, at(h, p.U), bdt, m, rs.k, rs.k, sel, rs.l, (int32_t*)at(h, p.yord), C);
   }
   const int fy = bdt == RE_F64 ? kF64 : kF32;
   void* Y = at(h, p.Y);
@@ -853,7 +867,8 @@ void pilot_features(const double* s, int64_t k, int64_t m, int64_t n, double eps
 }
 
 struct AdPlan {
-  size_t B, Xn, Y, C, svd, sigma, info, out3, gdesc, ydesc, queue, feat, yout, yparts, ybits, ysel, selscr, total;
+  size_t B, Xn, Y, C, svd, sigma, info, out3, gdesc, ydesc, queue, feat, yout, yparts, ybits, ysel, selscr, U, yord,
+      total;
 };
 
 // Largest Y B scratch over the widths an adaptive run may visit (k0 doubling,
@@ -885,7 +900,7 @@ static re_status adaptive_impl(re_handle h, const void* A, int32_t dt, int64_t m
                         int32_t* k_out, int32_t* l_out, int32_t* rounds_out, int32_t* k_proposed_out,
                         uint32_t* flags_out) {
   if (!h || !A || !ad || !r_out || !sigma_out) return RE_ERR_INVALID_ARG;
-  if (yk != RE_GAUSSIAN && yk != RE_SRHT) return RE_ERR_INVALID_ARG;
+  if (yk != RE_GAUSSIAN && yk != RE_SRHT && yk != RE_SRCT) return RE_ERR_INVALID_ARG;
   if (dt != RE_F64 && dt != RE_F32) return RE_ERR_INVALID_ARG;
   if (dt != RE_F32) return RE_ERR_UNSUPPORTED;
   if (!(eps > 0.0 && eps < 1.0) || m < 1 || n < 1 || lda < n || lda >= kMaxBatchLda || ((uintptr_t)A) % 4 != 0)
@@ -895,16 +910,18 @@ static re_status adaptive_impl(re_handle h, const void* A, int32_t dt, int64_t m
   if (ad->k_max > 0 && ad->k_max < kmax) kmax = ad->k_max;
   if (kmax > RE_MAX_ADAPTIVE_K) kmax = RE_MAX_ADAPTIVE_K;
   const int64_t lmax = l_for(kmax, ad->l_ratio, m);
-  const bool srht_y = yk == RE_SRHT;
-  const int64_t npad_m = next_pow2(m);
+  const bool srht_y = yk == RE_SRHT, srct_y = yk == RE_SRCT, trig_y = srht_y || srct_y;
+  const int64_t npad_m = srct_y ? srct_y_npad(m) : next_pow2(m);
   AdPlan p{};
   Carve c;
   p.B = c.take((size_t)(srht_y ? (int64_t)srht_cols_rows_alloc(m) : m) * kmax * 4);
   p.Xn = c.take((size_t)n * kmax * 4);
-  p.Y = c.take(srht_y ? 0 : (size_t)lmax * m * 4);
-  p.ybits = c.take(srht_y ? (size_t)cdiv(npad_m, 32) * 4 : 0);
-  p.ysel = c.take(srht_y ? (size_t)lmax * 4 : 0);
-  p.selscr = c.take(srht_y ? select_scratch_bytes(npad_m) : 0);
+  p.Y = c.take(trig_y ? 0 : (size_t)lmax * m * 4);
+  p.ybits = c.take(trig_y ? (size_t)cdiv(npad_m, 32) * 4 : 0);
+  p.ysel = c.take(trig_y ? (size_t)lmax * 4 : 0);
+  p.selscr = c.take(trig_y ? select_scratch_bytes(npad_m) : 0);
+  p.U = c.take(srct_y ? srct_y_u_bytes(m, kmax, RE_F32) : 0);
+  p.yord = c.take(srct_y ? srct_y_order_bytes(lmax) : 0);
   p.C = c.take((size_t)lmax * kmax * 8);
   p.svd = c.take(svd_scratch_bytes(lmax, kmax));
   p.sigma = c.take((size_t)kmax * 8);
@@ -915,7 +932,7 @@ static re_status adaptive_impl(re_handle h, const void* A, int32_t dt, int64_t m
   p.queue = c.take(16);
   p.feat = c.take(RE_MLP_INPUTS * 4);
   p.yout = c.take(16);
-  p.yparts = c.take(srht_y ? 0 : yb_scratch_adaptive(ad->k0, kmax, ad->l_ratio, m));
+  p.yparts = c.take(trig_y ? 0 : yb_scratch_adaptive(ad->k0, kmax, ad->l_ratio, m));
   p.total = c.off;
   RE_TRY(ensure_ws(h, p.total));
   RE_TRY(ensure_host(h, 256 + (size_t)kmax * 8));  // out3 | sigma | features
@@ -942,6 +959,14 @@ static re_status adaptive_impl(re_handle h, const void* A, int32_t dt, int64_t m
       RE_TRY(launch_srht_cols_lo(s, B + k_old, RE_F32, m, k - k_old, kmax, ybits));  // the new columns of F D A X
       RE_TRY(launch_select(s, npad_m, l, seed, kYSel, at(h, p.selscr), ysel));     // nested in l
       RE_TRY(launch_srht_cols_hi(s, B, RE_F32, m, k, kmax, ysel, l, C));
+    } else if (srct_y) {  // the stored first level U of the DCT along m, new columns only
+      uint32_t* ybits = (uint32_t*)at(h, p.ybits);
+      int32_t* ysel = (int32_t*)at(h, p.ysel);
+      float* U = (float*)at(h, p.U);
+      if (k_old == 0) RE_TRY(launch_sign_bits(s, npad_m, seed, kYSign, ybits));
+      RE_TRY(launch_srct_y_lo(s, B + k_old, RE_F32, m, k - k_old, kmax, ybits, U + k_old, kmax));
+      RE_TRY(launch_select(s, npad_m, l, seed, kYSel, at(h, p.selscr), ysel));  // nested in l
+      RE_TRY(launch_srct_y_hi(s, U, RE_F32, m, k, kmax, ysel, l, (int32_t*)at(h, p.yord), C));
     } else {
       RE_TRY(launch_gauss_sub(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, Y + l_old * m));
       RE_TRY(run_yb(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, p.ydesc), at(h, p.yparts)));
@@ -1008,18 +1033,18 @@ static re_status gap_impl(re_handle h, const void* A, int32_t dt, int64_t m, int
   if (dt == RE_F32 && lda >= kMaxBatchLda) return RE_ERR_UNSUPPORTED;
   if (gs->k0 < 1 || gs->dk < 1 || gs->k_max < 0 || !(gs->l_ratio >= 1.0) || !isfinite(gs->l_ratio)) return RE_ERR_INVALID_ARG;
   if (!(gs->gamma > 1.0) || !(gs->floor >= 0.0) || !isfinite(gs->floor)) return RE_ERR_INVALID_ARG;
-  if (gs->y_kind != RE_GAUSSIAN && gs->y_kind != RE_SRHT) return RE_ERR_INVALID_ARG;
+  if (gs->y_kind != RE_GAUSSIAN && gs->y_kind != RE_SRHT && gs->y_kind != RE_SRCT) return RE_ERR_INVALID_ARG;
   if (spectra_cap < 0 || (spectra_cap > 0 && !spectra_out)) return RE_ERR_INVALID_ARG;
   int64_t kmax = m < n ? m : n;
   if (gs->k_max > 0 && gs->k_max < kmax) kmax = gs->k_max;
   if (kmax > RE_MAX_ADAPTIVE_K) kmax = RE_MAX_ADAPTIVE_K;
   const int64_t k_first = gs->k0 < kmax ? gs->k0 : kmax;
   const int64_t lmax = l_for(kmax, gs->l_ratio, m);
-  const bool srht_y = gs->y_kind == RE_SRHT;
-  const int64_t npad_m = next_pow2(m);
+  const bool srht_y = gs->y_kind == RE_SRHT, srct_y = gs->y_kind == RE_SRCT, trig_y = srht_y || srct_y;
+  const int64_t npad_m = srct_y ? srct_y_npad(m) : next_pow2(m);
   const int64_t xcols = k_first > gs->dk ? k_first : gs->dk;  // widest appended block of X
   size_t yparts = 0;
-  if (!srht_y && dt == RE_F32) {
+  if (!trig_y && dt == RE_F32) {
     for (int64_t k = k_first;; k = k + gs->dk < kmax ? k + gs->dk : kmax) {
       const size_t b = yb_scratch(l_for(k, gs->l_ratio, m), k, m);
       yparts = b > yparts ? b : yparts;
@@ -1029,10 +1054,12 @@ static re_status gap_impl(re_handle h, const void* A, int32_t dt, int64_t m, int
   Carve c;
   const size_t oB = c.take((size_t)(srht_y ? (int64_t)srht_cols_rows_alloc(m) : m) * kmax * be);
   const size_t oX = c.take((size_t)n * xcols * be);
-  const size_t oY = c.take(srht_y ? 0 : (size_t)lmax * m * be);
-  const size_t oybits = c.take(srht_y ? (size_t)cdiv(npad_m, 32) * 4 : 0);
-  const size_t oysel = c.take(srht_y ? (size_t)lmax * 4 : 0);
-  const size_t oselscr = c.take(srht_y ? select_scratch_bytes(npad_m) : 0);
+  const size_t oY = c.take(trig_y ? 0 : (size_t)lmax * m * be);
+  const size_t oybits = c.take(trig_y ? (size_t)cdiv(npad_m, 32) * 4 : 0);
+  const size_t oysel = c.take(trig_y ? (size_t)lmax * 4 : 0);
+  const size_t oselscr = c.take(trig_y ? select_scratch_bytes(npad_m) : 0);
+  const size_t oU = c.take(srct_y ? srct_y_u_bytes(m, kmax, dt) : 0);
+  const size_t oyord = c.take(srct_y ? srct_y_order_bytes(lmax) : 0);
   const size_t oC = c.take((size_t)lmax * kmax * 8);
   const size_t osvd = c.take(svd_scratch_bytes(lmax, kmax));
   const size_t osig = c.take((size_t)kmax * 8);
@@ -1046,7 +1073,7 @@ static re_status gap_impl(re_handle h, const void* A, int32_t dt, int64_t m, int
   if (dt == RE_F64) {
     for (int64_t k = k_first, ko = 0;; ko = k, k = k + gs->dk < kmax ? k + gs->dk : kmax) {
       const size_t gx = gemm64_parts_bytes(m, k - ko, n);
-      const size_t gy = srht_y ? 0 : gemm64_parts_bytes(l_for(k, gs->l_ratio, m), k, m);
+      const size_t gy = trig_y ? 0 : gemm64_parts_bytes(l_for(k, gs->l_ratio, m), k, m);
       gp = gx > gp ? gx : gp;
       gp = gy > gp ? gy : gp;
       if (k >= kmax) break;
@@ -1092,6 +1119,15 @@ static re_status gap_impl(re_handle h, const void* A, int32_t dt, int64_t m, int
       mark(h, RE_STAGE_YB);
       RE_TRY(launch_srht_cols_lo(s, B + (size_t)k_old * be, dt, m, dkr, kmax, ybits));
       RE_TRY(launch_srht_cols_hi(s, B, dt, m, k, kmax, ysel, l, C));
+    } else if (srct_y) {  // the stored first level U of the DCT along m, new columns only
+      uint32_t* ybits = (uint32_t*)at(h, oybits);
+      int32_t* ysel = (int32_t*)at(h, oysel);
+      char* U = at(h, oU);
+      if (k_old == 0) RE_TRY(launch_sign_bits(s, npad_m, seed, kYSign, ybits));
+      RE_TRY(launch_select(s, npad_m, l, seed, kYSel, at(h, oselscr), ysel));  // nested in l
+      mark(h, RE_STAGE_YB);
+      RE_TRY(launch_srct_y_lo(s, B + (size_t)k_old * be, dt, m, dkr, kmax, ybits, U + (size_t)k_old * be, kmax));
+      RE_TRY(launch_srct_y_hi(s, U, dt, m, k, kmax, ysel, l, (int32_t*)at(h, oyord), C));
     } else if (dt == RE_F32) {
       RE_TRY(launch_gauss_sub(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, (float*)Y + l_old * m));
       mark(h, RE_STAGE_YB);
