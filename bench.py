@@ -53,6 +53,10 @@ WORKLOADS = {
     "srct": dict(m=65536, n=16384, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="srct", y="srht",
                  desc="subsampled randomized DCT X (Sec. 3.3 / Sec. 4 with F a DCT): FP32 65536x16384, "
                       "s_i=10^(-i/20) (R=1024) + 1e-9 noise, SRCT X 16384x384, SRHT Y 576x65536, eps 1e-3/1e-5"),
+    "paper": dict(m=65536, n=16384, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="hrtt", y="srct",
+                  desc="the paper's own sketch pair (Sec. 6: hashed randomized DCT X, subsampled randomized DCT Y): "
+                       "FP32 65536x16384, s_i=10^(-i/20) (R=1024) + 1e-9 noise, HRTT X 16384x384, SRCT Y "
+                       "576x65536, eps 1e-3/1e-5"),
     "qr": dict(m=65536, n=16384, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="srht", y="srht", wide_k=1650,
                wide_l=3300,
                desc="step 7 by the QR diagonal (Sec. 5): the plain method at scale (FP32 65536x16384, SRHT X 384, "
@@ -62,11 +66,11 @@ WORKLOADS = {
                 desc="adaptive width with the SRHT Y grown from its stored transform (Sec. 5 footnote): the plain-method "
                      "matrix (FP32 65536x16384, s_i=10^(-i/20), R=1024, + 1e-9 noise), Gaussian X doubling from 32, "
                      "l = 1.5 k, eps 1e-3/1e-5; the Gaussian Y timed on the same calls"),
-    "gap": dict(m=100000, n=100000, block=100, k0=110, dk=100, l_ratio=1.5, gamma=30.0, floor=1e-13,
-                x="gaussian", y="gaussian", eps=(None,),
+    "gap": dict(m=100000, n=100000, block=100, k0=110, dk=100, l_ratio=1.5, gamma=10.0, floor=1e-13,
+                x="gaussian", y="srct", eps=(None,),
                 desc="rank without a tolerance (Sec. 6.1): A_G of Sec. 6 (FP64 100000 x 100000 diagonal stored dense, "
                      "100 values each at 1, 1e-4, 1e-8, 1e-12, then 1e-16), Gaussian X from 110 columns, +100 per "
-                     "round, Gaussian Y with l = 1.5 k, gap ratio 30, floor 1e-13"),
+                     "round, subsampled randomized DCT Y (as Sec. 6.1) with l = 1.5 k, gap ratio 10, floor 1e-13"),
     "c1": dict(m=2000, n=1000, R=1000, k=40, l=60, eps=(1e-6,), x="gaussian", y="gaussian",
                desc="plain method, CPU-sized: FP64 2000x1000, step spectrum (20 x 1, then 1e-8), "
                     "Gaussian X 1000x40, Gaussian Y 60x2000, eps 1e-6"),
@@ -105,7 +109,7 @@ def make_matrix(name, w, device):
     import torch
 
     from paper_2105_07388_amd import inputs
-    if name in ("c2", "qr", "hrtt", "srct", "ady"):
+    if name in ("c2", "qr", "hrtt", "srct", "ady", "paper"):
         return inputs.c2_matrix(w["m"], w["n"], w["R"], device=device)
     if name == "c1":
         return inputs.c1_matrix(device=device)
@@ -136,7 +140,7 @@ def cpu_baseline(A_dev, w, rows: int):
     Bfull = np.random.default_rng(0).standard_normal((m, k))
     Bfull[:rows] = B
     t0 = time.perf_counter()
-    Cm = oracle.apply_y(Bfull, yk, l, seed=0)
+    Cm = oracle.hrtt.apply_y_srct(Bfull, l, seed=0) if w["y"] == "srct" else oracle.apply_y(Bfull, yk, l, seed=0)
     t_y = time.perf_counter() - t0
     t0 = time.perf_counter()
     oracle.jacobi_sv(Cm)
@@ -558,17 +562,23 @@ def cpu_baseline_gap(A_dev, w, rounds, rows):
         B = A_s @ X
         t_ax += (time.perf_counter() - t0) * (m / rows)
         t0 = time.perf_counter()
-        Y = oracle.gauss_matrix(0, l, rows, oracle.STREAM_YGAUSS, oracle.FMT_F64, swap=True)
-        Cm = Y @ B
-        t_y += (time.perf_counter() - t0) * (m / rows)
+        if w["y"] == "srct":  # the transform along all m rows (B padded with the rows not in the sample)
+            Bm = np.zeros((m, k))
+            Bm[:rows] = B
+            Cm = oracle.hrtt.apply_y_srct(Bm, l, seed=0)
+            t_y += time.perf_counter() - t0
+        else:
+            Y = oracle.gauss_matrix(0, l, rows, oracle.STREAM_YGAUSS, oracle.FMT_F64, swap=True)
+            Cm = Y @ B
+            t_y += (time.perf_counter() - t0) * (m / rows)
         t0 = time.perf_counter()
         oracle.jacobi_sv(Cm)
         t_svd += time.perf_counter() - t0
         k = min(k + w["dk"], min(m, n))
     total = t_ax + t_y + t_svd
     return {"value": 1.0 / total, "unit": "gap searches/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{rounds} rounds of the same schedule with A X and Y B on the first {rows} of {m} rows "
-                      f"(scaled by {m / rows:g}) and the Jacobi SVD at the full (l, k); seconds: ax {t_ax:.1f}, "
+            "sample": f"{rounds} rounds of the same schedule with A X on the first {rows} of {m} rows (scaled by "
+                      f"{m / rows:g}), Y B at full length, and the Jacobi SVD at the full (l, k); seconds: ax {t_ax:.1f}, "
                       f"yb {t_y:.1f}, svd {t_svd:.1f}"}
 
 

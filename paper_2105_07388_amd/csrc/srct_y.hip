@@ -27,7 +27,8 @@ namespace re {
 namespace {
 
 constexpr int kSrctM2 = 32;       // DFT length of level 1 (M2 = min(M, 32))
-constexpr int kSrctRows = 16;     // sampled rows per level-2 workgroup
+constexpr int kSrctRows = 8;      // sampled rows per level-2 workgroup
+constexpr int kSrctCols = 2;      // columns per lane in level 2 (a workgroup covers 128)
 constexpr int kSrctChunk = 64;    // j1 values whose weights share one LDS load
 
 __device__ __forceinline__ bool neg_bit(const uint32_t* bits, int64_t i) { return (bits[i >> 5] >> (i & 31)) & 1u; }
@@ -104,88 +105,170 @@ __global__ void __launch_bounds__(256) k_srct_y_lo(const T* __restrict__ B, int6
 
 // The sampled rows grouped by class q mod M2: order[] lists the rows s of class
 // 0, then class 1, ... (ascending s within a class); start[c] is the first
-// position of class c, start[M2] = l.  One workgroup.
-__global__ void __launch_bounds__(256) k_srct_y_classes(const int32_t* __restrict__ sel, int64_t l, int M2,
-                                                        int32_t* __restrict__ order, int32_t* __restrict__ start) {
-  __shared__ int cnt[kSrctM2 + 1];
-  if (threadIdx.x <= kSrctM2) cnt[threadIdx.x] = 0;
+// position of class c, start[M2] = l.  One workgroup: the rows go in chunks of
+// 64 (one wavefront each); a chunk's class histogram and each row's rank among
+// the earlier rows of its chunk and class come from one ballot per class, the
+// chunks' histograms are summed up per class.  LDS: (nchunk + 2) M2 ints.
+constexpr int kClsThreads = 256;
+__global__ void __launch_bounds__(kClsThreads) k_srct_y_classes(const int32_t* __restrict__ sel, int64_t l, int M2,
+                                                                int32_t* __restrict__ order,
+                                                                int32_t* __restrict__ start) {
+  extern __shared__ int32_t sh[];
+  const int nchunk = (int)((l + 63) / 64);
+  int32_t* base = sh;                  // [nchunk][M2]: rows of the class in the chunk, then in earlier chunks
+  int32_t* size = base + nchunk * M2;  // [M2]
+  int32_t* cstart = size + M2;         // [M2]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t lt = lane ? ((uint64_t)-1 >> (64 - lane)) : 0;  // lanes below this one
+  for (int z = wave; z < nchunk; z += kClsThreads / 64) {
+    const int64_t s = (int64_t)z * 64 + lane;
+    const int c = s < l ? (sel[s] & (M2 - 1)) : -1;
+    for (int cc = 0; cc < M2; ++cc) {
+      const uint64_t msk = __ballot(c == cc);
+      if (lane == 0) base[z * M2 + cc] = __popcll(msk);
+    }
+  }
   __syncthreads();
-  for (int64_t s = threadIdx.x; s < l; s += blockDim.x) atomicAdd(&cnt[sel[s] & (M2 - 1)], 1);
+  if (threadIdx.x < M2) {  // per class: exclusive prefix over the chunks
+    const int c = threadIdx.x;
+    int acc = 0;
+    for (int z = 0; z < nchunk; ++z) {
+      const int v = base[z * M2 + c];
+      base[z * M2 + c] = acc;
+      acc += v;
+    }
+    size[c] = acc;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     int acc = 0;
     for (int c = 0; c < M2; ++c) {
-      const int v = cnt[c];
+      cstart[c] = acc;
       start[c] = acc;
-      cnt[c] = acc;
-      acc += v;
+      acc += size[c];
     }
     start[M2] = acc;
-    // a stable scatter, sequential so that rows keep their order in a class
-    for (int64_t s = 0; s < l; ++s) order[cnt[sel[s] & (M2 - 1)]++] = (int32_t)s;
+  }
+  __syncthreads();
+  for (int z = wave; z < nchunk; z += kClsThreads / 64) {
+    const int64_t s = (int64_t)z * 64 + lane;
+    const int c = s < l ? (sel[s] & (M2 - 1)) : -1;
+    int rank = 0;
+    for (int cc = 0; cc < M2; ++cc) {
+      const uint64_t msk = __ballot(c == cc);
+      if (c == cc) rank = __popcll(msk & lt);
+    }
+    if (c >= 0) order[cstart[c] + base[z * M2 + c] + rank] = (int32_t)s;
   }
 }
 
 // Level 2: workgroup (class c, row group g, column tile) forms the rows
-// order[start[c] + 16 g + r], r < 16, of C for 64 columns.  The four
-// wavefronts split each chunk of 64 j1 values (16 each) and add their sums at
-// the end in a fixed order; the weights of a chunk are computed once per
-// workgroup into LDS (FP64 sin / cos of an exactly reduced angle).
+// order[start[c] + 8 g + r], r < 8, of C for 128 columns (two per lane).  The
+// four wavefronts split each chunk of 64 j1 values (16 each) and add their
+// sums at the end in a fixed order; the weights (cos phi, sin phi) of a chunk
+// are computed once per workgroup into LDS, in FP64 from the angle reduced
+// exactly modulo 2 pi (M is a power of two).
 template <typename T>
 __global__ void __launch_bounds__(256) k_srct_y_hi(const T* __restrict__ Ure, const T* __restrict__ Uim, int64_t ldu,
                                                    int64_t M, int M2, int64_t k, const int32_t* __restrict__ sel,
                                                    const int32_t* __restrict__ order,
                                                    const int32_t* __restrict__ start, double* __restrict__ C,
                                                    int64_t ldc) {
-  __shared__ double wc[kSrctRows][kSrctChunk], ws[kSrctRows][kSrctChunk];
-  __shared__ double part[4][kSrctRows][64];
+  __shared__ double2 w[kSrctRows][kSrctChunk];
+  __shared__ double part[4][kSrctRows][64 * kSrctCols];
+  __shared__ int64_t qs[kSrctRows];
   const int c = blockIdx.x % M2;
   const int g = blockIdx.x / M2;
   const int r0 = start[c] + g * kSrctRows, r1 = start[c + 1];
   if (r0 >= r1) return;  // uniform over the workgroup
   const int nr = r1 - r0 < kSrctRows ? r1 - r0 : kSrctRows;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t t = (int64_t)blockIdx.y * 64 + lane;
-  const int64_t M1 = M / M2;
-  double acc[kSrctRows];
+  const int64_t tb = (int64_t)blockIdx.y * 64 * kSrctCols + lane;
+  const int64_t M1 = M / M2, mask = 4 * M - 1;
+  if (threadIdx.x < kSrctRows) qs[threadIdx.x] = threadIdx.x < nr ? (int64_t)sel[order[r0 + threadIdx.x]] : 0;
+  double acc[kSrctCols][kSrctRows];
 #pragma unroll
-  for (int r = 0; r < kSrctRows; ++r) acc[r] = 0.0;
-  for (int64_t j0 = 0; j0 < M1; j0 += kSrctChunk) {
-    __syncthreads();
+  for (int u = 0; u < kSrctCols; ++u)
+#pragma unroll
+    for (int r = 0; r < kSrctRows; ++r) acc[u][r] = 0.0;
+  // this wavefront's 16 j1 values of a chunk, both columns, real and imaginary.
+  // The loads of a chunk are issued together, from clamped in-range addresses
+  // (values out of range are zeroed afterwards), and a chunk's loads are issued
+  // before the previous chunk is used: two register sets alternate, so the
+  // compiler can wait for the older set alone.
+  constexpr int JW = kSrctChunk / 4;
+  T ar[JW][kSrctCols], ai[JW][kSrctCols], br[JW][kSrctCols], bi[JW][kSrctCols];
+  const int64_t kc = k - 1;
+  auto fetch = [&](int64_t j0, T (&vr)[JW][kSrctCols], T (&vi)[JW][kSrctCols]) {
+#pragma unroll
+    for (int i = 0; i < JW; ++i) {
+      const int64_t j1 = j0 + wave * JW + i;
+      const int64_t o = ((j1 < M1 ? j1 : M1 - 1) * M2 + c) * ldu;
+#pragma unroll
+      for (int u = 0; u < kSrctCols; ++u) {
+        const int64_t t = tb + 64 * u;
+        vr[i][u] = Ure[o + (t < k ? t : kc)];
+        vi[i][u] = Uim[o + (t < k ? t : kc)];
+      }
+    }
+  };
+  auto weights = [&](int64_t j0) {
     for (int e = threadIdx.x; e < kSrctRows * kSrctChunk; e += 256) {
       const int r = e / kSrctChunk, jj = e % kSrctChunk;
       double cv = 0.0, sv = 0.0;
       if (r < nr && j0 + jj < M1) {
-        const int64_t q = sel[order[r0 + r]];
         // phi / pi = q (4 j1 + 1) / (2M), reduced modulo 2 exactly
-        const int64_t p = (q * (4 * (j0 + jj) + 1)) % (4 * M);
+        const int64_t p = (qs[r] * (4 * (j0 + jj) + 1)) & mask;
         sincospi((double)p / (double)(2 * M), &sv, &cv);
       }
-      wc[r][jj] = cv;
-      ws[r][jj] = sv;
+      w[r][jj] = make_double2(cv, sv);
     }
-    __syncthreads();
-    if (t < k) {
-      const int64_t jend = j0 + kSrctChunk < M1 ? j0 + kSrctChunk : M1;
-      for (int64_t j1 = j0 + wave * 16; j1 < j0 + wave * 16 + 16 && j1 < jend; ++j1) {
-        const int64_t o = (j1 * M2 + c) * ldu + t;
-        const double ur = (double)Ure[o], ui = (double)Uim[o];
-        const int jj = (int)(j1 - j0);
+  };
+  // weights of j1 >= M1 are zero, so the clamped values there add nothing; a
+  // column past k is never stored
+  auto use = [&](const T (&vr)[JW][kSrctCols], const T (&vi)[JW][kSrctCols]) {
 #pragma unroll
-        for (int r = 0; r < kSrctRows; ++r) acc[r] = fma(wc[r][jj], ur, fma(ws[r][jj], ui, acc[r]));
+    for (int i = 0; i < JW; ++i) {
+      const int jj = wave * JW + i;
+#pragma unroll
+      for (int r = 0; r < kSrctRows; ++r) {
+        const double2 wv = w[r][jj];
+#pragma unroll
+        for (int u = 0; u < kSrctCols; ++u)
+          acc[u][r] = fma(wv.x, (double)vr[i][u], fma(wv.y, (double)vi[i][u], acc[u][r]));
       }
     }
+  };
+  fetch(0, ar, ai);
+  for (int64_t j0 = 0; j0 < M1; j0 += 2 * kSrctChunk) {
+    __syncthreads();  // the previous chunk's weights are no longer read
+    weights(j0);
+    __syncthreads();
+    if (j0 + kSrctChunk < M1) fetch(j0 + kSrctChunk, br, bi);
+    use(ar, ai);
+    if (j0 + kSrctChunk >= M1) break;
+    __syncthreads();
+    weights(j0 + kSrctChunk);
+    __syncthreads();
+    if (j0 + 2 * kSrctChunk < M1) fetch(j0 + 2 * kSrctChunk, ar, ai);
+    use(br, bi);
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kSrctRows; ++r) part[wave][r][lane] = acc[r];
+  for (int u = 0; u < kSrctCols; ++u)
+#pragma unroll
+    for (int r = 0; r < kSrctRows; ++r) part[wave][r][lane + 64 * u] = acc[u][r];
   __syncthreads();
-  if (wave != 0 || t >= k) return;
+  if (wave != 0) return;
   for (int r = 0; r < nr; ++r) {
-    const double sum = ((part[0][r][lane] + part[1][r][lane]) + part[2][r][lane]) + part[3][r][lane];
     const int s = order[r0 + r];
-    const double cq = sel[s] == 0 ? 1.0 : 1.4142135623730951;  // sqrt(2) c_q
-    C[(int64_t)s * ldc + t] = cq * sum;
+    const double cq = qs[r] == 0 ? 1.0 : 1.4142135623730951;  // sqrt(2) c_q
+#pragma unroll
+    for (int u = 0; u < kSrctCols; ++u) {
+      const int64_t t = tb + 64 * u;
+      const int x = lane + 64 * u;
+      if (t < k) C[(int64_t)s * ldc + t] = cq * (((part[0][r][x] + part[1][r][x]) + part[2][r][x]) + part[3][r][x]);
+    }
   }
 }
 
@@ -240,13 +323,18 @@ re_status launch_srct_y_hi(hipStream_t s, const void* U, int bdtype, int64_t m, 
   const int M2 = srct_y_m2(M);
   int32_t* order = order_scratch;
   int32_t* start = order_scratch + l;
-  hipLaunchKernelGGL(k_srct_y_classes, dim3(1), dim3(256), 0, s, sel, l, M2, order, start);
+  const size_t cls_lds = (size_t)((cdiv(l, 64) + 2) * M2) * 4;
+  if (cls_lds > 160 * 1024) return RE_ERR_UNSUPPORTED;
+  if (cls_lds > 64 * 1024)
+    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_srct_y_classes, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)cls_lds));
+  hipLaunchKernelGGL(k_srct_y_classes, dim3(1), dim3(kClsThreads), cls_lds, s, sel, l, M2, order, start);
   RE_TRY_HIP(hipGetLastError());
-  // row groups per class: at most ceil(l / 16) for one class; empty groups exit
+  // row groups per class: at most ceil(l / 8) for one class; empty groups exit
   const int64_t groups = cdiv(l, kSrctRows);
   const int64_t gx = groups * M2;
   if (gx > INT32_MAX) return RE_ERR_UNSUPPORTED;
-  const dim3 grid((unsigned)gx, (unsigned)cdiv(k, 64));
+  const dim3 grid((unsigned)gx, (unsigned)cdiv(k, 64 * kSrctCols));
   const size_t half = (size_t)M * ldu;
   if (bdtype == RE_F64)
     hipLaunchKernelGGL(k_srct_y_hi<double>, grid, dim3(256), 0, s, (const double*)U, (const double*)U + half, ldu, M,
