@@ -258,6 +258,7 @@ struct Bidiag2Args {
   int32_t* info;
   int64_t l, k, kp;  // kp: LDS row stride in doubles (kp = 16 mod 32)
   int P, nr_max;
+  int xstride;       // launched workgroups per participant (participants: blockIdx.x % xstride == 0)
 };
 
 __device__ __forceinline__ void st_coh(double* p, double v) {
@@ -655,12 +656,17 @@ __device__ __forceinline__ double bcast_lane0(double v) {
 }
 
 template <int KPL, int NT>
-__global__ void __launch_bounds__(NT) k_bidiag_reg(Bidiag2Args a) {
+__global__ void __launch_bounds__(NT) k_bidiag_reg(Bidiag2Args a_in) {
   constexpr int NW = NT / 64;
   constexpr int SLOTS = NW < 8 ? NW : 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  // Every xstride-th workgroup takes part; with xstride = 8 and the dispatch of
+  // consecutive workgroups to the 8 XCDs in turn these all sit on one XCD.
+  // The others leave at once.
+  if (blockIdx.x % a_in.xstride != 0) return;
+  Bidiag2Args a = a_in;
   const int64_t k = a.k, l = a.l, kp = a.kp;
-  const int P = a.P, w = blockIdx.x;
+  const int P = a.P, w = blockIdx.x / a.xstride;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nr = (int)((l - w + P - 1) / P);
   double* Wl = reinterpret_cast<double*>(smem_raw);  // [nr_max][kp]
@@ -958,33 +964,88 @@ __device__ int count_below(const double* bb, int nb, double x, double pivmin) {
   return neg - (nb + 1) / 2;
 }
 
-// The two halves of the factorisation twisted at row r = k, which has the
-// same inertia: top-down q_0 .. q_r as above, bottom-up p_{n-1} = -x,
-// p_j = -x - bb[j] / p_{j+1} down to p_r, and the pivot of row r,
-// g = q_r + p_r + x.  Each half returns its last pivot and the negatives
-// before it (q_0 .. q_{r-1}, respectively p_{n-1} .. p_{r+1}).
-__device__ double sturm_top(const double* bb, int r, double x, double pivmin, int& neg) {
-  double q = -x;
-  int ng = 0;
-#pragma unroll 4
-  for (int j = 0; j < r; ++j) {
-    ng += (q < 0.0);
-    q = sturm_step(q, bb[j], x, pivmin);
+// The factorisation twisted at row r = k has the same inertia: top-down
+// pivots q_0 .. q_r as above, bottom-up p_{n-1} = -x, p_j = -x - bb[j] /
+// p_{j+1} down to p_r, and the pivot of row r, g = q_r + p_r + x.
+// The same two halves through the leading (trailing) principal minors of
+// T - x I instead of the pivots: D_0 = 1, D_1 = -x, D_{j+1} = -x D_j - bb[j-1]
+// D_{j-1}, so q_j = D_{j+1} / D_j and the negative pivots are the sign changes
+// of D_0 .. D_r.  One FMA per step is on the dependent chain (bb D_{j-1} is
+// formed a step ahead) instead of a reciprocal and its Newton correction.
+// Each FMA rounds once, which is a relative perturbation of x and of bb[j-1]
+// as in the pivot form's error analysis.  The entries come prescaled by a
+// power of two so that x <= 2 and bb <= 4: a step grows the pair (D_{j-1},
+// D_j) by at most 6x, and shrinks it by no more than x, which the
+// multisection keeps above 2^-60 of the bound; the pair is renormalised by a
+// power of two every four steps.  Returns the negatives among q_0 .. q_{r-1}
+// and the last pivot q_r.
+__device__ __forceinline__ void renorm(double& a, double& b) {
+  const double mx = fmax(fabs(a), fabs(b));
+  if (mx > 0.0) {
+    const int e = __builtin_amdgcn_frexp_exp(mx);
+    a = __builtin_ldexp(a, -e);
+    b = __builtin_ldexp(b, -e);
   }
-  neg = ng;
-  return q;
 }
 
-__device__ double sturm_bottom(const double* bb, int nb, int r, double x, double pivmin, int& neg) {
-  double p = -x;
-  int ng = 0;
-#pragma unroll 4
-  for (int j = nb - 1; j >= r; --j) {
-    ng += (p < 0.0);
-    p = sturm_step(p, bb[j], x, pivmin);
+__device__ double minors_top(const double* bb, int r, double x, int& neg) {
+  double D0 = 1.0, D1 = -x;
+  int ng = r > 0 ? 1 : 0;  // q_0 = -x < 0
+  if (r == 0) {
+    neg = 0;
+    return -x;
+  }
+  int j = 1;
+  for (; j + 3 < r; j += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double D2 = fma(-x, D1, -bb[j + u - 1] * D0);
+      ng += (D2 < 0.0) != (D1 < 0.0);
+      D0 = D1;
+      D1 = D2;
+    }
+    renorm(D0, D1);
+  }
+  for (; j < r; ++j) {
+    const double D2 = fma(-x, D1, -bb[j - 1] * D0);
+    ng += (D2 < 0.0) != (D1 < 0.0);
+    D0 = D1;
+    D1 = D2;
   }
   neg = ng;
-  return p;
+  // q_r = -x - bb[r-1] D_{r-1} / D_r; a zero D_r (q_{r-1} = 0) gives q_r -> +inf
+  return D1 != 0.0 ? -x - bb[r - 1] * (D0 / D1) : HUGE_VAL;
+}
+
+// Bottom half: E_{n} = 1, E_{n-1} = -x, E_j = -x E_{j+1} - bb[j] E_{j+2}, p_j =
+// E_j / E_{j+1}; the negatives among p_{n-1} .. p_{r+1} and the pivot p_r.
+__device__ double minors_bottom(const double* bb, int nb, int r, double x, int& neg) {
+  const int n = nb + 1;
+  double E0 = 1.0, E1 = -x;  // E_{j+2}, E_{j+1} for j = n - 2
+  int ng = n - 1 > r ? 1 : 0;  // p_{n-1} = -x < 0
+  if (n - 1 <= r) {
+    neg = 0;
+    return -x;
+  }
+  int j = n - 2;
+  for (; j - 3 > r; j -= 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double E2 = fma(-x, E1, -bb[j - u] * E0);
+      ng += (E2 < 0.0) != (E1 < 0.0);
+      E0 = E1;
+      E1 = E2;
+    }
+    renorm(E0, E1);
+  }
+  for (; j > r; --j) {
+    const double E2 = fma(-x, E1, -bb[j] * E0);
+    ng += (E2 < 0.0) != (E1 < 0.0);
+    E0 = E1;
+    E1 = E2;
+  }
+  neg = ng;
+  return E1 != 0.0 ? -x - bb[r] * (E0 / E1) : HUGE_VAL;
 }
 
 // Singular values of the bidiagonal (d, e) by 64-way multisection on the
@@ -1001,21 +1062,25 @@ __global__ void __launch_bounds__(256) k_bidiag_sv(const double* __restrict__ d,
   __shared__ double s_piv[2][64];
   __shared__ int s_neg[2][64];
   __shared__ double s_iv[2][2];
-  double bound = 0.0, maxb2 = 0.0;
-  for (int j = threadIdx.x; j < nb; j += blockDim.x) {
-    b[j] = (j & 1) ? e[j >> 1] : d[j >> 1];
-    bb[j] = b[j] * b[j];
-  }
+  double bound = 0.0;
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) b[j] = (j & 1) ? e[j >> 1] : d[j >> 1];
   __syncthreads();
   for (int j = 0; j < nb; ++j) {  // every thread, same order
     const double left = j > 0 ? fabs(b[j - 1]) : 0.0;
     bound = fmax(bound, fabs(b[j]) + left);
-    maxb2 = fmax(maxb2, b[j] * b[j]);
   }
   bound = fmax(bound, nb > 0 ? fabs(b[nb - 1]) : 0.0);
   const bool all_zero = !(bound > 0.0);  // B = 0 (NaN is reported through info)
   bound = bound * (1.0 + 1e-14) + 1e-300;
-  const double pivmin = 0x1.0p-1022 * fmax(1.0, maxb2);
+  // the counts run on the entries scaled by 2^-eb (bound < 2^eb), exactly
+  const int eb = __builtin_amdgcn_frexp_exp(bound);
+  const double xs = __builtin_ldexp(1.0, -eb);
+  __syncthreads();
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+    const double bs = __builtin_ldexp(b[j], -eb);
+    bb[j] = bs * bs;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int slot = wave >> 1, bottom = wave & 1;  // two values per workgroup
   const int r = (nb + 1) >> 1;
@@ -1029,15 +1094,15 @@ __global__ void __launch_bounds__(256) k_bidiag_sv(const double* __restrict__ d,
       const double x = lo + (hi - lo) * (double)(lane + 1) * (1.0 / 65.0);
       int ng = 0;
       double piv = 0.0;
-      if (act) piv = bottom ? sturm_bottom(bb, nb, r, x, pivmin, ng) : sturm_top(bb, r, x, pivmin, ng);
+      if (act) piv = bottom ? minors_bottom(bb, nb, r, x * xs, ng) : minors_top(bb, r, x * xs, ng);
       if (bottom) {
         s_piv[slot][lane] = piv;
         s_neg[slot][lane] = ng;
       }
       __syncthreads();
       if (!bottom && act) {
-        double g = piv + s_piv[slot][lane] + x;
-        if (fabs(g) < pivmin) g = -pivmin;
+        double g = piv + s_piv[slot][lane] + x * xs;  // the twisted pivot, scaled entries
+        if (fabs(g) < 0x1.0p-1020) g = -0x1.0p-1020;
         const int cnt = ng + s_neg[slot][lane] + (g < 0.0) - r;
         const uint64_t le = __ballot(cnt <= want);  // monotone in lane
         const int nle = __popcll(le);               // lanes 0..nle-1 satisfy cnt <= want
@@ -1194,6 +1259,19 @@ size_t small_lds_bytes(int64_t l, int64_t k) {
 // Rows per workgroup at most `svd_rows_target()` (fewer rows shorten the
 // per-column update; more workgroups lengthen the reduction), overridable
 // with RANKEST_SVD_ROWS for tuning.
+// Placement of the bidiagonalisation's workgroups (RANKEST_SVD_XCD, default
+// 1): all on one XCD (launched eight times over, every eighth workgroup taking
+// part), which shortens the device-scope exchanges between them by about 6 %
+// at 576 x 384; 0 = consecutive workgroups.
+bool svd_one_xcd() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = getenv("RANKEST_SVD_XCD");
+    v = e ? (atoi(e) != 0) : 1;
+  }
+  return v == 1;
+}
+
 int svd_rows_target() {
   static int v = -1;
   if (v < 0) {
@@ -1441,6 +1519,12 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     b2.kp = lds_stride(k);
     b2.P = rp.P;
     b2.nr_max = rp.nr_max;
+    // all participants on one XCD when eight workgroups per participant fit
+    // the device at once (one per CU), else consecutive workgroups
+    int dev = 0, ncu = 0;
+    RE_TRY_HIP(hipGetDevice(&dev));
+    RE_TRY_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    b2.xstride = svd_one_xcd() && 8 * rp.P <= ncu ? 8 : 1;
     const bool t512 = rp.nt == 512;
     const void* fn = rp.kpl == 1   ? (t512 ? (const void*)k_bidiag_reg<1, 512> : (const void*)k_bidiag_reg<1, 1024>)
                      : rp.kpl == 2 ? (t512 ? (const void*)k_bidiag_reg<2, 512> : (const void*)k_bidiag_reg<2, 1024>)
@@ -1452,7 +1536,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     if (rp.bytes > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rp.bytes));
     void* params2[] = {&b2};
-    RE_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(rp.P), dim3(rp.nt), params2, (unsigned)rp.bytes, s));
+    RE_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(rp.P * b2.xstride), dim3(rp.nt), params2, (unsigned)rp.bytes, s));
   } else if (lp.P > 0) {
     Bidiag2Args b2;
     b2.C = C;
@@ -1467,6 +1551,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     b2.kp = lds_stride(k);
     b2.P = lp.P;
     b2.nr_max = lp.nr_max;
+    b2.xstride = 1;
     const void* fn = (const void*)k_bidiag_lds;
     if (lp.bytes > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.bytes));

@@ -153,7 +153,7 @@ def test_srct_rank_estimate_matches_oracle_on_a_gap(orc):
 def test_srct_repeatable_and_errors():
     A = inputs.gaussian(400, 3000, 9, torch.float32).to(DEV)
     assert torch.equal(re_.sketch_x(A, k=100, x="srct", seed=2), re_.sketch_x(A, k=100, x="srct", seed=2))
-    for kw, st in ((dict(x="srct", y="srct"), re_._binding.RE_ERR_UNSUPPORTED),
+    for kw, st in ((dict(x="srct", y="hrtt"), re_._binding.RE_ERR_INVALID_ARG),
                    (dict(x="srct", precision="bf16"), re_._binding.RE_ERR_UNSUPPORTED)):
         with pytest.raises(re_.RankEstError) as e:
             re_.rank_estimate(A, 1e-3, k=10, **kw)
