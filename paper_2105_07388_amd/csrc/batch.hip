@@ -380,11 +380,18 @@ re_status launch_gemm_f32_single(hipStream_t s, const float* A, int64_t m, int64
 
 int64_t ygemm_groups(int64_t m) { return cdiv(cdiv(m, kYKC), kYGroup); }
 
-// a split launch puts the groups on grid dimension z (at most 65535)
-bool ygemm_splits(int64_t m) { return ygemm_groups(m) > 1 && ygemm_groups(m) <= 65535; }
+// a split launch puts the groups on grid dimension z (at most 65535); it is
+// taken only while its partial products (groups x l x k doubles) take no more
+// memory than B itself (m x k floats), i.e. for l up to about 256: wider Y
+// would make the scratch several times B.  The unsplit launch adds the groups
+// in the same order in one workgroup and gives the same bits.
+bool ygemm_splits(int64_t l, int64_t k, int64_t m) {
+  const int64_t g = ygemm_groups(m);
+  return g > 1 && g <= 65535 && (double)g * l * k * sizeof(double) <= (double)m * k * sizeof(float);
+}
 
 size_t ygemm_split_bytes(int64_t l, int64_t k, int64_t m) {
-  return ygemm_splits(m) ? (size_t)ygemm_groups(m) * l * k * sizeof(double) : 0;
+  return ygemm_splits(l, k, m) ? (size_t)ygemm_groups(m) * l * k * sizeof(double) : 0;
 }
 
 re_status launch_ygemm_single(hipStream_t s, const float* B, int64_t m, int64_t k, int64_t ldb, const float* Y,
@@ -396,7 +403,7 @@ re_status launch_ygemm_single(hipStream_t s, const float* B, int64_t m, int64_t 
   d.ldb = ldb;
   hipLaunchKernelGGL(k_put_desc<YDesc>, dim3(1), dim3(64), 0, s, d, dscratch);
   const int64_t g = ygemm_groups(m);
-  if (!ygemm_splits(m) || parts == nullptr) return launch_ygemm_batched(s, dscratch, 1, Y, ldy, l, k);
+  if (!ygemm_splits(l, k, m) || parts == nullptr) return launch_ygemm_batched(s, dscratch, 1, Y, ldy, l, k);
   RE_TRY(launch_ygemm_grid(s, dscratch, 1, Y, ldy, l, k, (unsigned)g, parts));
   const int64_t lk = l * k;
   hipLaunchKernelGGL(k_ygemm_reduce, dim3((unsigned)(cdiv(lk, 256) < 2048 ? cdiv(lk, 256) : 2048)), dim3(256), 0, s,

@@ -141,6 +141,21 @@ def test_long_single_call_split_over_m(orc):
     _oracle_check(orc, A, 1e-5, 6, r1, s1)
 
 
+def test_wide_y_single_call_unsplit(orc):
+    """k = 8 and l = 300 on m = 20000: the split over m would need partials of
+    40 x 300 x 8 doubles, more than B itself, so the single call keeps one
+    workgroup per block (the unsplit launch): the same bits as the one-block
+    batch, and the oracle's estimate within the FP32 bound."""
+    A = inputs.planted(20000, 500, np.geomspace(1.0, 1e-7, 200), 43, torch.float32).to(DEV)
+    h = re_.Handle()
+    r1, s1, info = re_.rank_estimate(A, 1e-5, k=8, l=300, seed=9, handle=h)
+    r, s, fl = re_.rank_estimate_batched([A], 1e-5, k=8, l=300, seed=9, handle=h)
+    assert r[0] == r1 and np.array_equal(s[0], s1)
+    ro, so, r1o, flo, _ = orc.rank_estimate_gemm(A.cpu().numpy(), 1e-5, orc.GAUSSIAN, orc.GAUSSIAN, k=8, l=300,
+                                                 seed=9)
+    assert np.max(np.abs(s1 - so)) <= 8 * 2.0**-24 * math.sqrt(500) * so[0]
+
+
 def test_batched_full_size_sampled(orc):
     """4096 kernel blocks (m, n in [256, 4096], ~79 GB of FP32) in one call; the
     oracle checks a stratified sample of 64 blocks (evenly spaced in the order of
