@@ -84,10 +84,15 @@ TRAFFIC_SOURCES = {"c2": ("srht.hip", "common.h"), "c3": ("gemm_lp.hip", "common
 
 
 def kernel_source_digest(workload: str) -> str:
+    """sha256 (16 hex) of the sources the measured kernel is compiled from;
+    of common.h only the device code above its host-side declarations counts."""
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES.get(workload, ("srht.hip", "common.h")):
         with open(os.path.join(ROOT, "paper_2105_07388_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+            data = fh.read()
+        if f == "common.h":
+            data = data[:data.index(b"// Host-side helpers")]
+        h.update(data)
     return h.hexdigest()[:16]
 
 

@@ -123,6 +123,7 @@ struct Resolved {
   int64_t k, l, npad_n, npad_m;
   int fmt_x = -1;     // contraction format of a Gaussian X (kF64, kF32, kBF16, kF16)
   int scale_exp = 0;  // FP16: A is scaled by 2^scale_exp before rounding
+  bool lowprec = false;  // a BF16 / FP16 contraction may run (its X tiles need room)
 };
 
 // Checks the arguments of one estimate; `sides` selects which embedding's
@@ -193,7 +194,9 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
   const int bdt = dt == RE_F64 && rs.fmt_x != kBF16 && rs.fmt_x != kF16 ? RE_F64 : RE_F32;
   p.U = c.take(rs.yk == RE_SRCT ? srct_y_u_bytes(m, rs.k, dt == RE_F64 ? RE_F64 : bdt) : 0);
   p.yord = c.take(rs.yk == RE_SRCT ? srct_y_order_bytes(rs.l) : 0);
-  p.X = c.take(rs.xk == RE_GAUSSIAN ? (size_t)n * rs.k * (size_t)elem_size(fx) : 0);  // FP32/FP64; 2-byte formats fit too
+  size_t xb = rs.xk == RE_GAUSSIAN ? (size_t)n * rs.k * (size_t)elem_size(fx) : 0;  // FP32 / FP64 X
+  if (rs.xk == RE_GAUSSIAN && rs.lowprec && gemm_lp_x_bytes(n, rs.k) > xb) xb = gemm_lp_x_bytes(n, rs.k);
+  p.X = c.take(xb);
   p.Y = c.take(rs.yk == RE_GAUSSIAN ? (size_t)rs.l * m * elem_size(fx) : 0);
   p.B = c.take((size_t)brows * rs.k * be);
   p.C = c.take((size_t)rs.l * rs.k * 8);
@@ -259,8 +262,7 @@ re_status run_x(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m
   }
   void* X = at(h, p.X);
   if (rs.fmt_x == kBF16 || rs.fmt_x == kF16) {
-    // X^T (k x n) so that each column of X is contiguous along K
-    RE_TRY(launch_gauss_fill(s, rs.fmt_x, rs.k, n, seed, kXGauss, 1, X));
+    RE_TRY(launch_gemm_lp_x(s, rs.fmt_x, n, rs.k, seed, X));
     mark(h, RE_STAGE_AX);
     return launch_gemm_lp(s, rs.fmt_x, (const float*)A, m, n, lda, X, rs.k, rs.scale_exp, (float*)B);
   }
@@ -439,6 +441,7 @@ RE_API re_status re_rank_estimate(re_handle h, const void* A, int32_t dt, int64_
   Resolved rs;
   RE_TRY(validate(A, dt, m, n, lda, sk, &rs));
   rs.fmt_x = x_fmt(dt);
+  rs.lowprec = sk->prec != RE_PREC_NATIVE;
   const Plan p = plan(dt, m, n, rs);
   RE_TRY(ensure_ws(h, p.total));
   RE_TRY(ensure_host(h, (size_t)rs.k * 8 + 64));
@@ -1477,6 +1480,7 @@ RE_API re_status re_sketch_x(re_handle h, const void* A, int32_t dt, int64_t m, 
   RE_TRY(validate(A, dt, m, n, lda, sk, &rs, 1));
   if (sk->prec == RE_PREC_AUTO) return RE_ERR_INVALID_ARG;  // the stage call needs an explicit format
   rs.fmt_x = sk->prec == RE_PREC_BF16 ? kBF16 : sk->prec == RE_PREC_FP16 ? kF16 : x_fmt(dt);
+  rs.lowprec = rs.fmt_x == kBF16 || rs.fmt_x == kF16;
   const Plan p = plan(dt, m, n, rs);
   RE_TRY(ensure_ws(h, p.total));
   if (rs.fmt_x == kF16) {

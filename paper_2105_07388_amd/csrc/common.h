@@ -143,10 +143,14 @@ RE_HIDDEN re_status launch_srht_cols_hi(hipStream_t s, const void* B, int bdtype
 RE_HIDDEN re_status launch_gemm_f64acc(hipStream_t s, int64_t M, int64_t N, int64_t K, const void* A, int ta,
                                        int64_t lda, const void* B, int tb, int64_t ldb, void* C, int tc, int64_t ldc);
 
-// Low-precision contraction B = 2^-s round_fmt(2^s A) Xt^T, fmt BF16 or F16,
-// Xt is k x n (row t holds column t of X), FP32 accumulation and output.
+// Low-precision contraction B = 2^-s round_fmt(2^s A) X, fmt BF16 or F16,
+// FP32 accumulation and output.  X is held in step-major tiles written by
+// launch_gemm_lp_x (gemm_lp_x_bytes(n, k) bytes): Gaussian entries of stream
+// kXGauss rounded to fmt.
+RE_HIDDEN size_t gemm_lp_x_bytes(int64_t n, int64_t k);
+RE_HIDDEN re_status launch_gemm_lp_x(hipStream_t s, int fmt, int64_t n, int64_t k, uint64_t seed, void* Xtiles);
 RE_HIDDEN re_status launch_gemm_lp(hipStream_t s, int fmt, const float* A, int64_t m, int64_t n, int64_t lda,
-                                   const void* Xt, int64_t k, int scale_exp, float* B);
+                                   const void* Xtiles, int64_t k, int scale_exp, float* B);
 // Sampled sum of squares, largest magnitude and sample count of A (3 doubles).
 RE_HIDDEN re_status launch_sample_stats(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t lda, double* out3);
 
