@@ -90,7 +90,9 @@ enum {
   RE_FLAG_PREC_FALLBACK = 4u, /* AUTO could not use a low-precision format */
   RE_FLAG_USED_BF16 = 8u,     /* the A X contraction ran in BF16 */
   RE_FLAG_USED_FP16 = 16u,    /* the A X contraction ran in FP16 */
-  RE_FLAG_COLUMNS_DROPPED = 32u /* re_rangefinder: columns of A X dependent at FP64 precision were left out of Q */
+  RE_FLAG_COLUMNS_DROPPED = 32u, /* re_rangefinder: columns of A X dependent at FP64 precision were left out of Q */
+  RE_FLAG_PREC_BELOW_FLOOR = 64u /* a forced BF16 / FP16 contraction: its error floor phi_f exceeds eps*sigma_1/4, so
+                                    estimates near the threshold are not resolved (AUTO would have moved on) */
 };
 
 typedef struct re_handle_s* re_handle;
@@ -124,6 +126,22 @@ enum {
 /* enable != 0: record HIP events on the handle's stream around each stage of
  * every later re_rank_estimate call (adds seven event records per call). */
 re_status re_set_profiling(re_handle h, int32_t enable);
+
+/* Limits for callers that must bound the library, and hooks for tests of the
+ * error paths:
+ *   max_workspace_bytes  > 0: no workspace of the handle (device workspaces
+ *                        and the pinned host staging) may grow past this many
+ *                        bytes; a call that needs more returns
+ *                        RE_ERR_NO_MEMORY, as a failed allocation would,
+ *                        and leaves the handle usable.  0 removes the cap.
+ *   barrier_polls        polls of a grid barrier of the multi-workgroup small
+ *                        SVD (sketches too large for one workgroup) before it
+ *                        gives up and the call returns RE_ERR_NO_CONVERGENCE;
+ *                        0 restores the default (2^26); a negative value
+ *                        gives up at the first poll, which makes that error
+ *                        happen on purpose (every workgroup still exits).
+ * Errors: RE_ERR_INVALID_ARG for a NULL handle or a negative byte cap. */
+re_status re_set_limits(re_handle h, int64_t max_workspace_bytes, int64_t barrier_polls);
 
 /* Durations in milliseconds of the stages of the last re_rank_estimate call
  * (ms: host array of RE_NUM_STAGES doubles, indexed by RE_STAGE_*).
@@ -250,7 +268,10 @@ int64_t re_sketch_y_rows(int64_t m);
 
 /* Algorithm 1 step 7: the k singular values of the l x k FP64 row-major
  * device matrix C_dev (k <= l), multiplied by `scale`, descending, into
- * sigma_dev (device, k doubles).  C_dev is not modified. */
+ * sigma_dev (device, k doubles).  C_dev is not modified.  Synchronises the
+ * handle's stream to read the device status: RE_ERR_NONFINITE when C_dev
+ * holds NaN/Inf, RE_ERR_NO_CONVERGENCE when a grid barrier of the
+ * multi-workgroup bidiagonalisation gives up (see re_set_limits). */
 re_status re_singular_values(re_handle h, const double* C_dev, int64_t l, int64_t k, double scale,
                              double* sigma_dev);
 
@@ -268,7 +289,8 @@ re_status re_singular_values(re_handle h, const double* C_dev, int64_t l, int64_
  * re_singular_values_noalloc_fits).  All calls on one GPU share that GPU's
  * array and leave their contents in it: calls that overlap in time on one GPU
  * (different streams or host threads) race and must be serialised by the
- * caller. */
+ * caller.  Being asynchronous, it does not report the device status
+ * (NaN/Inf in C_dev): sigma_dev is then undefined. */
 #define RE_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
 re_status re_singular_values_noalloc(void* hip_stream, const double* C_dev, int64_t l, int64_t k, double scale,
                                      double* sigma_dev);

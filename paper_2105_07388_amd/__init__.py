@@ -12,6 +12,7 @@ from ._binding import (  # noqa: F401
     FLAG_USED_BF16,
     FLAG_USED_FP16,
     FLAG_COLUMNS_DROPPED,
+    FLAG_PREC_BELOW_FLOOR,
     FLAG_ZERO,
     Handle,
     close_all_handles,

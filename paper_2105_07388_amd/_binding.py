@@ -31,6 +31,7 @@ RE_SRCT = 3
 KIND = {"gaussian": RE_GAUSSIAN, "srht": RE_SRHT, "hrtt": RE_HRTT, "srct": RE_SRCT}
 FLAG_NOT_CONVERGED, FLAG_ZERO, FLAG_PREC_FALLBACK, FLAG_USED_BF16, FLAG_USED_FP16 = 1, 2, 4, 8, 16
 FLAG_COLUMNS_DROPPED = 32
+FLAG_PREC_BELOW_FLOOR = 64
 MAX_ADAPTIVE_K = 5120  # RE_MAX_ADAPTIVE_K
 FMT = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 FMT_DTYPE = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float16}
@@ -89,6 +90,7 @@ def lib():
             "re_set_stream": ([vp, vp], i32),
             "re_workspace_bytes": ([vp, C.POINTER(C.c_size_t)], i32),
             "re_set_profiling": ([vp, i32], i32),
+            "re_set_limits": ([vp, i64, i64], i32),
             "re_last_stage_ms": ([vp, vp], i32),
             "re_rank_estimate": ([vp, vp, i32, i64, i64, i64, dbl, C.POINTER(ReSketch), u64, C.POINTER(i32), vp,
                                   C.POINTER(i32), C.POINTER(C.c_uint32)], i32),
@@ -172,6 +174,12 @@ class Handle:
 
     def set_profiling(self, enable: bool = True):
         _check(lib().re_set_profiling(self._h, int(bool(enable))), "re_set_profiling")
+
+    def set_limits(self, max_workspace_bytes: int = 0, barrier_polls: int = 0):
+        """Cap on each of the handle's workspaces (0: none) and the polls of the
+        small SVD's grid barriers before RE_ERR_NO_CONVERGENCE (0: default,
+        negative: at the first poll)."""
+        _check(lib().re_set_limits(self._h, int(max_workspace_bytes), int(barrier_polls)), "re_set_limits")
 
     def last_stage_ms(self) -> dict:
         """Per-stage durations (ms) of the last rank_estimate on this handle (HIP events)."""

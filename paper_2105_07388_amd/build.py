@@ -54,5 +54,49 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     return LIB
 
 
+# Host-code sanitizer build (AddressSanitizer + UndefinedBehaviorSanitizer on
+# the host side only; the GPU code is compiled as usual) linked with the C
+# driver tests/host_sanitizer_driver.cpp into one executable.
+SAN_BUILD = os.path.join(BUILD, "hostsan")
+SAN_BIN = os.path.join(HERE, "_hostsan", "host_sanitizer_driver")
+SAN_DRIVER = os.path.join(ROOT, "tests", "host_sanitizer_driver.cpp")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+SAN_HOST_FLAGS = ["-fno-gpu-sanitize", "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-g"]
+
+
+def _compile_san(src, verbose):
+    obj = os.path.join(SAN_BUILD, os.path.basename(src) + ".o")
+    cmd = ["hipcc", *FLAGS, *SAN_FLAGS, "-c", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError(f"hipcc failed on {src}")
+    return obj
+
+
+def build_host_sanitized(verbose: bool = False, jobs: int = 8) -> str:
+    """Compile every csrc/ unit with the host-side sanitizers and link the
+    driver; returns the executable's path."""
+    os.makedirs(SAN_BUILD, exist_ok=True)
+    os.makedirs(os.path.dirname(SAN_BIN), exist_ok=True)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda s: _compile_san(s, verbose), sources()))
+    drv = os.path.join(SAN_BUILD, "driver.o")
+    cmd = ["hipcc", *SAN_HOST_FLAGS, "-std=c++17", "-I", INCLUDE, "-c", SAN_DRIVER, "-o", drv]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    tmp = SAN_BIN + ".tmp"
+    cmd = ["hipcc", *SAN_HOST_FLAGS, f"--offload-arch={ARCH}", "-o", tmp, drv, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SAN_BIN)
+    return SAN_BIN
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

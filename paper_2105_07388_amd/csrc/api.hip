@@ -42,6 +42,9 @@ struct re_handle_s {
   void* ws2 = nullptr;
   size_t ws2_bytes = 0;
   double rf_ms[3] = {};
+  // re_set_limits: cap on each workspace (0: none) and the small SVD's barrier polls (0: default)
+  size_t ws_cap = 0;
+  long spin_limit = 0;
 };
 
 namespace re {
@@ -51,6 +54,7 @@ size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
 re_status ensure_ws(re_handle h, size_t bytes) {
   if (bytes <= h->ws_bytes) return RE_OK;
+  if (h->ws_cap && bytes > h->ws_cap) return RE_ERR_NO_MEMORY;
   RE_TRY_HIP(hipStreamSynchronize(h->stream));
   if (h->ws) (void)hipFree(h->ws);
   h->ws = nullptr;
@@ -67,6 +71,7 @@ re_status ensure_ws(re_handle h, size_t bytes) {
 
 re_status ensure_ws2(re_handle h, size_t bytes) {
   if (bytes <= h->ws2_bytes) return RE_OK;
+  if (h->ws_cap && bytes > h->ws_cap) return RE_ERR_NO_MEMORY;
   RE_TRY_HIP(hipStreamSynchronize(h->stream));
   if (h->ws2) (void)hipFree(h->ws2);
   h->ws2 = nullptr;
@@ -83,6 +88,7 @@ re_status ensure_ws2(re_handle h, size_t bytes) {
 
 re_status ensure_host(re_handle h, size_t bytes) {
   if (bytes <= h->host_bytes) return RE_OK;
+  if (h->ws_cap && bytes > h->ws_cap) return RE_ERR_NO_MEMORY;
   RE_TRY_HIP(hipStreamSynchronize(h->stream));
   if (h->host) (void)hipHostFree(h->host);
   h->host = nullptr;
@@ -337,6 +343,13 @@ RE_API re_status re_set_profiling(re_handle h, int32_t enable) {
   return RE_OK;
 }
 
+RE_API re_status re_set_limits(re_handle h, int64_t max_workspace_bytes, int64_t barrier_polls) {
+  if (!h || max_workspace_bytes < 0) return RE_ERR_INVALID_ARG;
+  h->ws_cap = (size_t)max_workspace_bytes;
+  h->spin_limit = (long)barrier_polls;
+  return RE_OK;
+}
+
 RE_API re_status re_last_stage_ms(re_handle h, double* ms) {
   if (!h || !ms || !h->prof) return RE_ERR_INVALID_ARG;
   for (int i = 0; i < RE_NUM_STAGES; ++i) ms[i] = h->stage_ms[i];
@@ -411,7 +424,7 @@ re_status run_once(re_handle h, const Plan& p, const void* A, int32_t dt, int64_
   RE_TRY(run_y(h, p, B, dt, m, rs, seed, C));
   const double scale = 1.0 / sqrt((double)rs.k * (double)rs.l);
   mark(h, RE_STAGE_SVD);
-  RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info));
+  RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info, h->spin_limit));
   mark(h, RE_STAGE_RANK);
   RE_TRY(launch_rank_count(h->stream, sigma, rs.k, r1, eps, info, out3));
   char* host = (char*)h->host;
@@ -474,11 +487,16 @@ RE_API re_status re_rank_estimate(re_handle h, const void* A, int32_t dt, int64_
       }
       last = run_once(h, p, A, dt, m, n, lda, eps, rs, seed);
       const int32_t* o3 = (const int32_t*)host;
-      if (sk->prec != RE_PREC_AUTO || rs.fmt_x == kF32) break;
+      if (rs.fmt_x == kF32) break;
       if (last != RE_OK) return last;
       const double s1 = ((const double*)(host + 64))[0];
       const double phi = unit_roundoff(rs.fmt_x) / sqrt(3.0) * frob * shape;
-      if (o3[2] == 0 && phi <= eps * s1 / 4.0) break;  // accepted
+      const bool resolved = o3[2] == 0 && phi <= eps * s1 / 4.0;
+      if (sk->prec != RE_PREC_AUTO) {  // a forced format: report a floor above the threshold
+        if (o3[2] == 0 && !resolved) extra |= RE_FLAG_PREC_BELOW_FLOOR;
+        break;
+      }
+      if (resolved) break;  // accepted
       if (t + 1 == ntries - 1) extra |= RE_FLAG_PREC_FALLBACK;
     }
     RE_TRY(last);
@@ -975,7 +993,7 @@ static re_status adaptive_impl(re_handle h, const void* A, int32_t dt, int64_t m
       RE_TRY(run_yb(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, p.ydesc), at(h, p.yparts)));
     }
     // steps 7-8
-    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, p.svd), sigma, info));
+    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, p.svd), sigma, info, h->spin_limit));
     RE_TRY(launch_rank_count(s, sigma, k, r1_from_k((int32_t)k), eps, info, out3));
     RE_TRY_HIP(hipMemcpyAsync(host, out3, 16, hipMemcpyDeviceToHost, s));
     RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)k * 8, hipMemcpyDeviceToHost, s));
@@ -1143,7 +1161,7 @@ static re_status gap_impl(re_handle h, const void* A, int32_t dt, int64_t m, int
     // steps 7-8, the gap statistics in place of the count
     const int32_t r1 = r1_from_k((int32_t)k);
     mark(h, RE_STAGE_SVD);
-    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, osvd), sigma, info));
+    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, osvd), sigma, info, h->spin_limit));
     mark(h, RE_STAGE_RANK);
     RE_TRY(launch_gap(s, sigma, k, r1, gs->gamma, gs->floor, info, gout));
     RE_TRY_HIP(hipMemcpyAsync(host, gout, sizeof(GapOut), hipMemcpyDeviceToHost, s));
@@ -1382,7 +1400,7 @@ RE_API re_status re_rangefinder(re_handle h, const void* A, int32_t dt, int64_t 
                                   (GemmDesc*)at(h, pl.gdesc), (unsigned*)at(h, pl.queue)));
     RE_TRY(launch_gauss_sub(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, Y + l_old * m));
     RE_TRY(run_yb(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, pl.ydesc), at(h, pl.yparts)));
-    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, pl.svd), sigma, info));
+    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, pl.svd), sigma, info, h->spin_limit));
     RE_TRY(launch_rf_width(s, sigma, k, r1_from_k((int32_t)k), n, eps, p, norm_a, info, (double*)at(h, oTail), out4));
     RE_TRY_HIP(hipMemcpyAsync(host, out4, 16, hipMemcpyDeviceToHost, s));
     RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)k * 8, hipMemcpyDeviceToHost, s));
@@ -1515,8 +1533,13 @@ RE_API re_status re_singular_values(re_handle h, const double* C, int64_t l, int
   if (!h || !C || !sigma || k < 1 || l < k) return RE_ERR_INVALID_ARG;
   const size_t need = al256(svd_scratch_bytes(l, k)) + 256;
   RE_TRY(ensure_ws(h, need));
+  RE_TRY(ensure_host(h, 64));
   int32_t* info = (int32_t*)((char*)h->ws + al256(svd_scratch_bytes(l, k)));
-  return launch_svd(h->stream, C, l, k, scale, h->ws, sigma, info);
+  RE_TRY(launch_svd(h->stream, C, l, k, scale, h->ws, sigma, info, h->spin_limit));
+  // the device status (NaN / Inf in C, a grid barrier that gave up)
+  RE_TRY_HIP(hipMemcpyAsync(h->host, info, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  RE_TRY_HIP(hipStreamSynchronize(h->stream));
+  return (re_status) * (const int32_t*)h->host;
 }
 
 // ---- allocation-free singular values ------------------------------------

@@ -84,10 +84,15 @@ __device__ __forceinline__ double round_fmt(double v, int fmt) {
 // ---------------------------------------------------------------------------
 // Host-side helpers.
 // ---------------------------------------------------------------------------
+// On failure the runtime's per-thread last error is read (and so cleared),
+// so that a later call's hipGetLastError() check does not see it again.
 #define RE_TRY_HIP(expr)                          \
   do {                                            \
     hipError_t _e = (expr);                       \
-    if (_e != hipSuccess) return RE_ERR_HIP;      \
+    if (_e != hipSuccess) {                       \
+      (void)hipGetLastError();                    \
+      return RE_ERR_HIP;                          \
+    }                                             \
   } while (0)
 
 #define RE_TRY(expr)                              \
@@ -156,8 +161,10 @@ RE_HIDDEN re_status launch_sample_stats(hipStream_t s, const float* A, int64_t m
 
 // Small dense SVD of an l x k FP64 row-major matrix: singular values, descending.
 RE_HIDDEN size_t svd_scratch_bytes(int64_t l, int64_t k);
+// spin_limit: polls of a grid barrier before it reports RE_ERR_NO_CONVERGENCE
+// (0: the default; negative: give up at the first poll).
 RE_HIDDEN re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, double scale, void* scratch,
-                               double* sigma, int32_t* info);
+                               double* sigma, int32_t* info, long spin_limit = 0);
 RE_HIDDEN re_status launch_rank_count(hipStream_t s, const double* sigma, int64_t k, int32_t r1, double eps,
                                       const int32_t* info, int32_t* out3);
 // Gap statistics of descending estimates (search without a tolerance).

@@ -646,8 +646,9 @@ struct HashScratch {
 HashScratch carve_hash(void* base, int64_t N, int64_t k) {
   HashScratch h{};
   size_t off = 0;
+  // with base == nullptr only the size is wanted: no pointer is formed
   auto take = [&](int64_t count) {
-    char* p = (char*)base + off;
+    char* p = base ? (char*)base + off : nullptr;
     off += (size_t)((count * 4 + 255) / 256) * 256;
     return p;
   };

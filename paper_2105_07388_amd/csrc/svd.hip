@@ -36,6 +36,7 @@ struct BidiagArgs {
   int32_t* info;     // status (0 ok, RE_ERR_*)
   int64_t l, k;
   int P;
+  long spin_limit;   // polls of a grid barrier before it gives up (< 0: at once)
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -78,9 +79,12 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
 }
 
 // Grid barrier over the P workgroups of the bidiagonalisation.  The counter
-// grows monotonically; a bounded wait turns a missing workgroup into an error
-// instead of a hang.
-__device__ bool grid_barrier(unsigned* bar, unsigned target, int32_t* info) {
+// grows monotonically; a bounded wait (at most `limit` polls; a negative limit
+// fails at once, a test hook) turns a missing workgroup into an error instead
+// of a hang.
+__device__ __forceinline__ bool barrier_gives_up(long& spins, long limit) { return limit < 0 || ++spins > limit; }
+
+__device__ bool grid_barrier(unsigned* bar, unsigned target, int32_t* info, long limit) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   __shared__ int ok;
@@ -90,7 +94,7 @@ __device__ bool grid_barrier(unsigned* bar, unsigned target, int32_t* info) {
     ok = 1;
     while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1l << 26)) {
+      if (barrier_gives_up(spins, limit)) {
         ok = 0;
         __hip_atomic_store(info, (int32_t)RE_ERR_NO_CONVERGENCE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
@@ -159,7 +163,7 @@ __global__ void __launch_bounds__(kBidiagThreads) k_bidiag(BidiagArgs a) {
   __syncthreads();
   if (s_bad) __hip_atomic_store(a.info, (int32_t)RE_ERR_NONFINITE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   column_partials(a, 0, w, gacc);
-  if (!grid_barrier(a.bar, (unsigned)a.P * ++epoch, a.info)) return;
+  if (!grid_barrier(a.bar, (unsigned)a.P * ++epoch, a.info, a.spin_limit)) return;
 
   for (int64_t c = 0; c < k; ++c) {
     const int64_t par = c & 1, len = k - c;
@@ -233,7 +237,7 @@ __global__ void __launch_bounds__(kBidiagThreads) k_bidiag(BidiagArgs a) {
     __syncthreads();
     if (c + 1 < k) {
       column_partials(a, c + 1, w, gacc);
-      if (!grid_barrier(a.bar, (unsigned)a.P * ++epoch, a.info)) return;
+      if (!grid_barrier(a.bar, (unsigned)a.P * ++epoch, a.info, a.spin_limit)) return;
     }
   }
 }
@@ -259,6 +263,7 @@ struct Bidiag2Args {
   int64_t l, k, kp;  // kp: LDS row stride in doubles (kp = 16 mod 32)
   int P, nr_max;
   int xstride;       // launched workgroups per participant (participants: blockIdx.x % xstride == 0)
+  long spin_limit;   // polls of a grid barrier before it gives up (< 0: at once)
 };
 
 __device__ __forceinline__ void st_coh(double* p, double v) {
@@ -268,7 +273,7 @@ __device__ __forceinline__ double ld_coh(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ bool grid_sync_coh(unsigned* bar, unsigned target, int32_t* info) {
+__device__ bool grid_sync_coh(unsigned* bar, unsigned target, int32_t* info, long limit) {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's coherent stores are complete
   __syncthreads();
   __shared__ int ok;
@@ -278,7 +283,7 @@ __device__ bool grid_sync_coh(unsigned* bar, unsigned target, int32_t* info) {
     ok = 1;
     while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1l << 26)) {
+      if (barrier_gives_up(spins, limit)) {
         ok = 0;
         __hip_atomic_store(info, (int32_t)RE_ERR_NO_CONVERGENCE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
@@ -361,7 +366,7 @@ __global__ void __launch_bounds__(kBidiagThreads) k_bidiag_g2(BidiagArgs a) {
   }
   flush_partials(0, k);
   if (s_bad) __hip_atomic_store(a.info, (int32_t)RE_ERR_NONFINITE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+  if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info, a.spin_limit)) return;
 
   for (int64_t c = 0; c < k; ++c) {
     const int64_t par = c & 1, len = k - c;
@@ -393,7 +398,7 @@ __global__ void __launch_bounds__(kBidiagThreads) k_bidiag_g2(BidiagArgs a) {
         }
       }
     }
-    if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+    if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info, a.spin_limit)) return;
     // ---- level 2: the reduced column, both reflectors (every workgroup, same arithmetic) ----
     for (int64_t j = threadIdx.x; j < len; j += blockDim.x) wv[j] = ld_coh(&a.red[par * (k + 1) + j]);
     for (int64_t j = threadIdx.x; j < len; j += blockDim.x) vv[j] = ld_coh(&a.rowbuf[par * (k + 1) + j]);
@@ -497,7 +502,7 @@ __global__ void __launch_bounds__(kBidiagThreads) k_bidiag_g2(BidiagArgs a) {
         st_coh(&out[j], (gl[j] + gl[64 * T + j]) + (gl[2 * 64 * T + j] + gl[3 * 64 * T + j]));
     }
     __syncthreads();
-    if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+    if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info, a.spin_limit)) return;
   }
 }
 
@@ -551,7 +556,7 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_lds(Bidiag2Args a) {
   if (s_bad) __hip_atomic_store(a.info, (int32_t)RE_ERR_NONFINITE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   unsigned epoch = 0;
   partials_lds(a, Wl, nr, 0, w);
-  if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+  if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info, a.spin_limit)) return;
 
   for (int64_t c = 0; c < k; ++c) {
     const int64_t par = c & 1, len = k - c;
@@ -634,7 +639,7 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_lds(Bidiag2Args a) {
     __syncthreads();
     if (c + 1 < k) {
       partials_lds(a, Wl, nr, c + 1, w);
-      if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+      if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info, a.spin_limit)) return;
     }
   }
 }
@@ -688,7 +693,7 @@ __global__ void __launch_bounds__(NT) k_bidiag_reg(Bidiag2Args a_in) {
   if (s_bad) __hip_atomic_store(a.info, (int32_t)RE_ERR_NONFINITE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   unsigned epoch = 0;
   partials_lds(a, Wl, nr, 0, w);
-  if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+  if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info, a.spin_limit)) return;
 
   for (int64_t c = 0; c < k; ++c) {
     const int64_t par = c & 1, len = k - c;
@@ -808,7 +813,7 @@ __global__ void __launch_bounds__(NT) k_bidiag_reg(Bidiag2Args a_in) {
         st_coh(&a.part[(par1 * P + w) * (k + 1) + j], s);
         if (owner) st_coh(&a.rowbuf[par1 * (k + 1) + j], Wl[(int64_t)iown * kp + c + 1 + j]);
       }
-      if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info)) return;
+      if (!grid_sync_coh(a.bar, (unsigned)P * ++epoch, a.info, a.spin_limit)) return;
     }
   }
 }
@@ -1471,9 +1476,27 @@ __global__ void __launch_bounds__(256) k_count_batched(const SvDesc* __restrict_
 
 size_t svd_scratch_bytes(int64_t l, int64_t k) { return svd_layout(l, k).total; }
 
+namespace {
+// Launch of a kernel whose workgroups meet at grid barriers.  A cooperative
+// launch makes the runtime guarantee that they are resident together; when
+// it refuses (on this platform, while another process that has made
+// cooperative launches on the device is alive, later processes' cooperative
+// launches fail), a plain launch is used instead: these grids hold at most
+// one workgroup per CU, so on a device not filled by other work they are
+// resident together as well, and otherwise the bounded barrier wait ends the
+// call with RE_ERR_NO_CONVERGENCE rather than a hang.
+re_status launch_grid(const void* fn, dim3 grid, dim3 block, void** params, unsigned lds, hipStream_t s) {
+  if (hipLaunchCooperativeKernel(fn, grid, block, params, lds, s) == hipSuccess) return RE_OK;
+  (void)hipGetLastError();
+  RE_TRY_HIP(hipLaunchKernel(fn, grid, block, params, lds, s));
+  return RE_OK;
+}
+}  // namespace
+
 re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, double scale, void* scratch,
-                     double* sigma, int32_t* info) {
+                     double* sigma, int32_t* info, long spin_limit) {
   if (k <= 0) return RE_OK;
+  const long spins = spin_limit == 0 ? (1l << 26) : spin_limit;
   if (k > l) return RE_ERR_INVALID_ARG;
   const SvdLayout L = svd_layout(l, k);
   char* base = (char*)scratch;
@@ -1490,6 +1513,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
   a.l = l;
   a.k = k;
   a.P = choose_P(l);
+  a.spin_limit = spins;
   hipLaunchKernelGGL(k_svd_init, dim3(1), dim3(64), 0, s, a.bar, info);
   const LdsPlan lp = lds_plan(l, k);
   const size_t one_bytes = small_lds_bytes(l, k);
@@ -1514,6 +1538,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     b2.e = a.e;
     b2.bar = a.bar;
     b2.info = info;
+    b2.spin_limit = spins;
     b2.l = l;
     b2.k = k;
     b2.kp = lds_stride(k);
@@ -1536,7 +1561,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     if (rp.bytes > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rp.bytes));
     void* params2[] = {&b2};
-    RE_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(rp.P * b2.xstride), dim3(rp.nt), params2, (unsigned)rp.bytes, s));
+    RE_TRY(launch_grid(fn, dim3(rp.P * b2.xstride), dim3(rp.nt), params2, (unsigned)rp.bytes, s));
   } else if (lp.P > 0) {
     Bidiag2Args b2;
     b2.C = C;
@@ -1546,6 +1571,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     b2.e = a.e;
     b2.bar = a.bar;
     b2.info = info;
+    b2.spin_limit = spins;
     b2.l = l;
     b2.k = k;
     b2.kp = lds_stride(k);
@@ -1556,7 +1582,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     if (lp.bytes > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.bytes));
     void* params2[] = {&b2};
-    RE_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(lp.P), dim3(kB2Threads), params2, (unsigned)lp.bytes, s));
+    RE_TRY(launch_grid(fn, dim3(lp.P), dim3(kB2Threads), params2, (unsigned)lp.bytes, s));
   } else if (k <= 48 * 64 && !svd_legacy_global()) {
     // rows in registers: 32 or 48 columns per lane
     const bool t32 = k <= 32 * 64;
@@ -1573,14 +1599,14 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     if (P < 1) return RE_ERR_UNSUPPORTED;
     a.P = (int)P;
     void* params[] = {&a};
-    RE_TRY_HIP(hipLaunchCooperativeKernel(fn, dim3(a.P), dim3(kBidiagThreads), params, (unsigned)lds, s));
+    RE_TRY(launch_grid(fn, dim3(a.P), dim3(kBidiagThreads), params, (unsigned)lds, s));
   } else {
     const size_t lds = (size_t)(2 * (k + 1) + kWaves * kPartChunk) * 8;
     if (lds > 160 * 1024) return RE_ERR_UNSUPPORTED;
     if (lds > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     void* params[] = {&a};
-    RE_TRY_HIP(hipLaunchCooperativeKernel((const void*)k_bidiag, dim3(a.P), dim3(kBidiagThreads), params, (unsigned)lds, s));
+    RE_TRY(launch_grid((const void*)k_bidiag, dim3(a.P), dim3(kBidiagThreads), params, (unsigned)lds, s));
   }
   const size_t lds2 = (size_t)(4 * k) * 8;
   if (lds2 > 160 * 1024) return RE_ERR_UNSUPPORTED;
