@@ -195,10 +195,11 @@ class Handle:
     def __del__(self):
         # At interpreter shutdown the HIP runtime (and a profiler attached to
         # it) may already be gone; handles still open then were released by
-        # _close_all at exit, so nothing is left to do here.
-        if sys.is_finalizing():
-            return
+        # _close_all at exit, so nothing is left to do here.  Late in the
+        # shutdown even module globals such as `sys` may already be None.
         try:
+            if sys.is_finalizing():
+                return
             self.close()
         except Exception:
             pass

@@ -130,3 +130,24 @@ def test_gap_rank_definition(orc):
     s = s[:37] + [v * 1e-4 for v in s[37:]]
     r, q = G.gap_rank(s, 54)
     assert r == 37 and abs(q - 10.0 ** (1 / 20) * 1e4) < 1e-6 * q
+
+
+def test_evaluation_acceptance_rule():
+    """Sec. 1.1's goal for an estimate of the eps-rank, on a hand-checked
+    spectrum: r^ is acceptable when sigma_{r^+1} < 10 eps sigma_1 and
+    sigma_{r^} > 0.1 eps sigma_1; step spectra need the exact planted rank."""
+    from paper_2105_07388_amd import learned
+    s = np.array([1.0, 0.2, 0.05, 3e-3, 1.5e-3, 5e-4, 2e-4, 9e-5, 1e-6])
+    eps = 1e-3
+    # sigma_{r+1} < 1e-2 needs r >= 3 (sigma_4 = 1.5e-3); sigma_r > 1e-4 needs r <= 7 (sigma_7 = 2e-4, sigma_8 = 9e-5)
+    got = [learned.acceptable(s, r, eps) for r in range(0, 10)]
+    assert got == [False, False, False, True, True, True, True, True, False, False]
+    # r = 0 only when sigma_1 is already below 10 eps
+    assert learned.acceptable(np.array([1.0, 1e-9]), 1, 1e-3) and not learned.acceptable(np.array([1.0]), 0, 1e-3)
+    p = dict(R=40, r=12, eps=1e-4, decay="step", m=400, n=100, seed=3)
+    assert learned.agrees(p, 12) and not learned.agrees(p, 11) and not learned.agrees(p, 13)
+    p = dict(p, decay="exp")
+    sig = __import__("paper_2105_07388_amd").inputs.learned_spectrum(p)
+    ok = [r for r in range(0, 41) if learned.agrees(p, r)]
+    assert 12 in ok and ok == list(range(ok[0], ok[-1] + 1))
+    assert sig[ok[0]] < 10 * p["eps"] and sig[ok[-1] - 1] > 0.1 * p["eps"]
