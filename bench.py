@@ -747,6 +747,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--loop-blocks", type=int, default=256, help="c4: blocks timed through the single-matrix call")
     ap.add_argument("--cpu-blocks", type=int, default=12, help="c4: blocks in the oracle's timed sample")
+    ap.add_argument("--inflight", type=int, default=2,
+                    help="single-matrix workloads: estimates in flight (one handle, HIP stream and host thread each; "
+                         "the value is their joint throughput, one-at-a-time figures are reported beside it)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="before timing, copy a buffer of this many GiB once (a plain copy kernel of known size that "
                          "calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -786,20 +789,27 @@ def main():
         return bench_gap(args, w, dev)
     A = make_matrix(args.workload, w, dev)
     torch.cuda.synchronize()
-    h = re_.Handle(dev)
-    h.set_profiling(True)
-    print(f"[bench] {args.workload}: A {tuple(A.shape)} {A.dtype} resident; warmup {args.warmup}", file=sys.stderr,
-          flush=True)
+    nfl = max(1, args.inflight)
+    hs = [re_.Handle(dev) for _ in range(nfl)]
+    sts = [torch.cuda.Stream(dev) for _ in range(nfl)]
+    for hh in hs:
+        hh.set_profiling(True)
+    h = hs[0]
+    print(f"[bench] {args.workload}: A {tuple(A.shape)} {A.dtype} resident; warmup {args.warmup}; {nfl} in flight",
+          file=sys.stderr, flush=True)
 
-    def step(i):
+    def step(i, t=0):
         eps = w["eps"][i % len(w["eps"])]
         prec = w.get("prec", ("native",))[i % len(w.get("prec", ("native",)))]
-        return re_.rank_estimate(A, eps, k=w["k"], l=w["l"], x=w["x"], y=w["y"], precision=prec,
-                                 seed=1000003 * (i + 1), handle=h)
+        with torch.cuda.stream(sts[t]):
+            return re_.rank_estimate(A, eps, k=w["k"], l=w["l"], x=w["x"], y=w["y"], precision=prec,
+                                     seed=1000003 * (i + 1), handle=hs[t])
 
     for i in range(args.warmup):
-        step(-1 - i)
+        for t in range(nfl):
+            step(-1 - i, t)
     torch.cuda.synchronize()
+    # one estimate at a time (its stage times give the kernels' own durations)
     stages = []
     ranks = []
     t0 = time.perf_counter()
@@ -808,7 +818,32 @@ def main():
         ranks.append(r)
         stages.append(h.last_stage_ms())
     torch.cuda.synchronize()
+    elapsed1 = time.perf_counter() - t0
+    # the same steps with nfl estimates in flight: thread t runs steps t, t + nfl, ...
+    ranks_fl = [None] * args.steps
+    errors = []
+
+    def worker(t):
+        try:
+            for i in range(t, args.steps, nfl):
+                ranks_fl[i] = step(i, t)[0]
+        except Exception as exc:  # surfaced after the join
+            errors.append(exc)
+
+    import threading
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(nfl)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if errors:
+        raise errors[0]
+    if ranks_fl != ranks:
+        raise RuntimeError(f"ranks with {nfl} in flight differ from one at a time: {ranks_fl} vs {ranks}")
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     st_mean = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
@@ -839,9 +874,10 @@ def main():
         "dtype": "/".join(w["prec"]) if "prec" in w else ("f32" if elem == 4 else "f64"),
         "data": "synthetic",
         "config": {"workload": w["desc"], "m": w["m"], "n": w["n"], "k": w["k"], "l": w["l"], "eps": list(w["eps"]),
-                   "x": w["x"], "y": w["y"], "parallelism": "single GPU"},
+                   "x": w["x"], "y": w["y"], "in_flight": nfl, "parallelism": "single GPU"},
         "roofline": roof,
         "stage_ms": st_mean,
+        "one_in_flight": {"value": args.steps / elapsed1, "ms_per_step": 1e3 * elapsed1 / args.steps},
     }
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

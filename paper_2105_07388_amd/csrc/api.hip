@@ -6,6 +6,7 @@
 #include <stdlib.h>
 
 #include <map>
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <string>
@@ -45,6 +46,7 @@ struct re_handle_s {
   // re_set_limits: cap on each workspace (0: none) and the small SVD's barrier polls (0: default)
   size_t ws_cap = 0;
   long spin_limit = 0;
+  int xcd = 0;  // XCD of the multi-workgroup small SVD: handles created in turn take XCDs in turn
 };
 
 namespace re {
@@ -331,6 +333,8 @@ RE_API re_status re_create(re_handle* h, void* hip_stream) {
     return RE_ERR_HIP;
   }
   p->stream = (hipStream_t)hip_stream;
+  static std::atomic<unsigned> next_xcd{0};
+  p->xcd = (int)(next_xcd.fetch_add(1, std::memory_order_relaxed) & 7u);
   *h = p;
   return RE_OK;
 }
@@ -424,7 +428,7 @@ re_status run_once(re_handle h, const Plan& p, const void* A, int32_t dt, int64_
   RE_TRY(run_y(h, p, B, dt, m, rs, seed, C));
   const double scale = 1.0 / sqrt((double)rs.k * (double)rs.l);
   mark(h, RE_STAGE_SVD);
-  RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info, h->spin_limit));
+  RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info, h->spin_limit, h->xcd));
   mark(h, RE_STAGE_RANK);
   RE_TRY(launch_rank_count(h->stream, sigma, rs.k, r1, eps, info, out3));
   char* host = (char*)h->host;
@@ -993,7 +997,7 @@ static re_status adaptive_impl(re_handle h, const void* A, int32_t dt, int64_t m
       RE_TRY(run_yb(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, p.ydesc), at(h, p.yparts)));
     }
     // steps 7-8
-    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, p.svd), sigma, info, h->spin_limit));
+    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, p.svd), sigma, info, h->spin_limit, h->xcd));
     RE_TRY(launch_rank_count(s, sigma, k, r1_from_k((int32_t)k), eps, info, out3));
     RE_TRY_HIP(hipMemcpyAsync(host, out3, 16, hipMemcpyDeviceToHost, s));
     RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)k * 8, hipMemcpyDeviceToHost, s));
@@ -1161,7 +1165,7 @@ static re_status gap_impl(re_handle h, const void* A, int32_t dt, int64_t m, int
     // steps 7-8, the gap statistics in place of the count
     const int32_t r1 = r1_from_k((int32_t)k);
     mark(h, RE_STAGE_SVD);
-    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, osvd), sigma, info, h->spin_limit));
+    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, osvd), sigma, info, h->spin_limit, h->xcd));
     mark(h, RE_STAGE_RANK);
     RE_TRY(launch_gap(s, sigma, k, r1, gs->gamma, gs->floor, info, gout));
     RE_TRY_HIP(hipMemcpyAsync(host, gout, sizeof(GapOut), hipMemcpyDeviceToHost, s));
@@ -1400,7 +1404,7 @@ RE_API re_status re_rangefinder(re_handle h, const void* A, int32_t dt, int64_t 
                                   (GemmDesc*)at(h, pl.gdesc), (unsigned*)at(h, pl.queue)));
     RE_TRY(launch_gauss_sub(s, l - l_old, m, l_old, 0, seed, kYGauss, 1, m, Y + l_old * m));
     RE_TRY(run_yb(s, B, m, k, kmax, Y, m, l, C, (YDesc*)at(h, pl.ydesc), at(h, pl.yparts)));
-    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, pl.svd), sigma, info, h->spin_limit));
+    RE_TRY(launch_svd(s, C, l, k, 1.0 / sqrt((double)k * (double)l), at(h, pl.svd), sigma, info, h->spin_limit, h->xcd));
     RE_TRY(launch_rf_width(s, sigma, k, r1_from_k((int32_t)k), n, eps, p, norm_a, info, (double*)at(h, oTail), out4));
     RE_TRY_HIP(hipMemcpyAsync(host, out4, 16, hipMemcpyDeviceToHost, s));
     RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)k * 8, hipMemcpyDeviceToHost, s));
@@ -1535,7 +1539,7 @@ RE_API re_status re_singular_values(re_handle h, const double* C, int64_t l, int
   RE_TRY(ensure_ws(h, need));
   RE_TRY(ensure_host(h, 64));
   int32_t* info = (int32_t*)((char*)h->ws + al256(svd_scratch_bytes(l, k)));
-  RE_TRY(launch_svd(h->stream, C, l, k, scale, h->ws, sigma, info, h->spin_limit));
+  RE_TRY(launch_svd(h->stream, C, l, k, scale, h->ws, sigma, info, h->spin_limit, h->xcd));
   // the device status (NaN / Inf in C, a grid barrier that gave up)
   RE_TRY_HIP(hipMemcpyAsync(h->host, info, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
   RE_TRY_HIP(hipStreamSynchronize(h->stream));

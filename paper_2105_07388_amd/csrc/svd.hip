@@ -262,7 +262,8 @@ struct Bidiag2Args {
   int32_t* info;
   int64_t l, k, kp;  // kp: LDS row stride in doubles (kp = 16 mod 32)
   int P, nr_max;
-  int xstride;       // launched workgroups per participant (participants: blockIdx.x % xstride == 0)
+  int xstride;       // launched workgroups per participant (participants: blockIdx.x % xstride == xoff)
+  int xoff;
   long spin_limit;   // polls of a grid barrier before it gives up (< 0: at once)
 };
 
@@ -665,10 +666,10 @@ __global__ void __launch_bounds__(NT) k_bidiag_reg(Bidiag2Args a_in) {
   constexpr int NW = NT / 64;
   constexpr int SLOTS = NW < 8 ? NW : 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  // Every xstride-th workgroup takes part; with xstride = 8 and the dispatch of
+  // Every xstride-th workgroup (from xoff) takes part; with xstride = 8 and the dispatch of
   // consecutive workgroups to the 8 XCDs in turn these all sit on one XCD.
   // The others leave at once.
-  if (blockIdx.x % a_in.xstride != 0) return;
+  if ((int)(blockIdx.x % a_in.xstride) != a_in.xoff) return;
   Bidiag2Args a = a_in;
   const int64_t k = a.k, l = a.l, kp = a.kp;
   const int P = a.P, w = blockIdx.x / a.xstride;
@@ -1494,7 +1495,7 @@ re_status launch_grid(const void* fn, dim3 grid, dim3 block, void** params, unsi
 }  // namespace
 
 re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, double scale, void* scratch,
-                     double* sigma, int32_t* info, long spin_limit) {
+                     double* sigma, int32_t* info, long spin_limit, int xcd) {
   if (k <= 0) return RE_OK;
   const long spins = spin_limit == 0 ? (1l << 26) : spin_limit;
   if (k > l) return RE_ERR_INVALID_ARG;
@@ -1550,6 +1551,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     RE_TRY_HIP(hipGetDevice(&dev));
     RE_TRY_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     b2.xstride = svd_one_xcd() && 8 * rp.P <= ncu ? 8 : 1;
+    b2.xoff = b2.xstride == 8 ? (xcd & 7) : 0;
     const bool t512 = rp.nt == 512;
     const void* fn = rp.kpl == 1   ? (t512 ? (const void*)k_bidiag_reg<1, 512> : (const void*)k_bidiag_reg<1, 1024>)
                      : rp.kpl == 2 ? (t512 ? (const void*)k_bidiag_reg<2, 512> : (const void*)k_bidiag_reg<2, 1024>)
@@ -1578,6 +1580,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     b2.P = lp.P;
     b2.nr_max = lp.nr_max;
     b2.xstride = 1;
+    b2.xoff = 0;
     const void* fn = (const void*)k_bidiag_lds;
     if (lp.bytes > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.bytes));
