@@ -5,6 +5,7 @@
 // H is the unnormalised Sylvester-ordered Walsh-Hadamard matrix,
 // H[p][q] = (-1)^popcount(p & q); N, M are n, m rounded up to powers of two.
 #include <stdlib.h>
+#include <string.h>
 
 #include "common.h"
 
@@ -280,6 +281,99 @@ __global__ void __launch_bounds__(512, 2) __attribute__((amdgpu_waves_per_eu(4))
 }
 
 // ---------------------------------------------------------------------------
+// X side, FP32 rows of any N = 2^P with 11 <= P <= 15 (zero-padded when
+// n < N): the scheme above with NT = N / 32 threads of 32 values each.
+//   load     thread t reads float4 chunks at 4 t + (N / 8) j (j < 8): its
+//            register bits are q's bits {0, 1, P-3, P-2, P-1};
+//   phase 1  those five stages in registers;
+//   LDS      f(q) = q ^ (((q >> 7) & SWM) << 2) with SWM covering
+//            min(P - 10, 4) bits: the bits 7.. that phase 2 takes from t;
+//   phase 2  thread t holds the 32 positions whose bits {2..6} vary (its
+//            other bits: {0, 1} from t bits 0-1, {7 .. P-4} from t bits
+//            2 .. P-9, {P-3 .. P-1} from the top three bits of t): five stages;
+//   output   bits {7 .. P-4} are finished only for the k sampled outputs,
+//            each a signed sum of its 2^(P-10) partial values.
+// ---------------------------------------------------------------------------
+template <int P, bool PADDED>
+__global__ void __launch_bounds__(1 << (P - 5)) k_srht_rows_reg(const float* __restrict__ A, int64_t m, int64_t n,
+                                                               int64_t lda, const uint32_t* __restrict__ bits,
+                                                               const int32_t* __restrict__ sel, int k,
+                                                               float* __restrict__ B) {
+  constexpr int N = 1 << P, NT = N >> 5, CS = N >> 3;
+  constexpr int NB = P - 10;                      // unresolved bits 7 .. P-4
+  constexpr int SWB = NB < 4 ? NB : 4, SWM = (1 << SWB) - 1;
+  __shared__ __align__(16) float lds[N];
+  const int t = threadIdx.x;
+  uint32_t msk = 0;  // bit 4 j + c: sign of position CS j + 4 t + c
+#pragma unroll
+  for (int j = 0; j < 8; ++j) msk |= ((bits[(CS >> 5) * j + (t >> 3)] >> (4 * (t & 7))) & 15u) << (4 * j);
+  const int wa = (4 * t) ^ (((t >> 5) & SWM) << 2);  // phase-1 store of chunk j at wa + CS j
+  const int base = (t & 3) + 128 * ((t >> 2) & ((1 << NB) - 1)) + CS * (t >> (P - 8));
+  const int sw = (t >> 2) & SWM;
+  int ra[16];  // phase-2 value u = 16 h + i lives at ra[i] + 64 h
+#pragma unroll
+  for (int i = 0; i < 16; ++i) ra[i] = base + 4 * (i ^ sw);
+  for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
+    const float* src = A + row * lda + 4 * t;
+    float x[32];
+    asm volatile("" : "+v"(msk));
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      fx4 v;
+      if constexpr (PADDED) {
+        const int64_t q0 = 4 * t + (int64_t)CS * j;
+        if (q0 + 3 < n) {
+          v = *reinterpret_cast<const fx4*>(src + CS * j);
+        } else {
+          v = fx4{0.f, 0.f, 0.f, 0.f};
+          for (int c = 0; c < 4; ++c)
+            if (q0 + c < n) v[c] = src[CS * j + c];
+        }
+      } else {
+        v = ld_stream(src + CS * j);
+      }
+      x[4 * j + 0] = v.x;
+      x[4 * j + 1] = v.y;
+      x[4 * j + 2] = v.z;
+      x[4 * j + 3] = v.w;
+    }
+#pragma unroll
+    for (int e = 0; e < 32; ++e) x[e] = __uint_as_float(__float_as_uint(x[e]) ^ ((msk << (31 - e)) & 0x80000000u));
+    fwht32(x);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      *reinterpret_cast<float4*>(&lds[wa + CS * j]) = make_float4(x[4 * j], x[4 * j + 1], x[4 * j + 2], x[4 * j + 3]);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[16 * h + i] = lds[ra[i] + 64 * h];
+    fwht32(x);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) lds[ra[i] + 64 * h] = x[16 * h + i];
+    __syncthreads();
+    for (int s = t; s < k; s += NT) {
+      const int p = sel[s];
+      const int pl = p & ~(((1 << NB) - 1) << 7), ph = (p >> 7) & ((1 << NB) - 1);
+      float v[1 << NB];
+#pragma unroll
+      for (int b = 0; b < (1 << NB); ++b) {
+        const float val = lds[(pl ^ ((b & SWM) << 2)) + 128 * b];
+        v[b] = __uint_as_float(__float_as_uint(val) ^ ((uint32_t)(__popc(ph & b) & 1) << 31));
+      }
+#pragma unroll
+      for (int w = (1 << NB) >> 1; w > 0; w >>= 1)
+#pragma unroll
+        for (int b = 0; b < w; ++b) v[b] += v[b + w];
+      B[row * k + s] = v[0];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Y side.  H_M = H_{M/L} (x) H_L with the row index split (hi, lo):
 //   lo pass: every block of L consecutive rows is signed and transformed over
 //            its L rows, in place (rows past m read as zero);
@@ -491,6 +585,16 @@ static int num_cus() {
   return cus;
 }
 
+// RANKEST_SRHT_ROWS=lds sends every FP32 row transform to the one-row-per-
+// workgroup LDS kernel (a reference for the register-tiled ones).
+static bool srht_rows_lds_forced() {
+  static const bool forced = [] {
+    const char* v = getenv("RANKEST_SRHT_ROWS");
+    return v && strcmp(v, "lds") == 0;
+  }();
+  return forced;
+}
+
 re_status launch_srht_rows(hipStream_t s, const void* A, int dtype, int64_t m, int64_t n, int64_t lda,
                            const uint32_t* bits, const int32_t* sel, int64_t k, void* B) {
   const int64_t N = next_pow2(n);
@@ -507,6 +611,26 @@ re_status launch_srht_rows(hipStream_t s, const void* A, int dtype, int64_t m, i
       hipLaunchKernelGGL(k_srht_rows_n14, dim3((unsigned)(m < g ? m : g)), dim3(256), 0, s, (const float*)A, m, lda,
                          bits, sel, (int)k, (float*)B);
     RE_TRY_HIP(hipGetLastError());
+    return RE_OK;
+  }
+  if (dtype == RE_F32 && logN >= 11 && logN <= 15 && lda % 4 == 0 && ((uintptr_t)A % 16) == 0 &&
+      k <= INT32_MAX && !srht_rows_lds_forced()) {
+    const bool pad = n != N;
+    const void* fn = nullptr;
+    switch (logN) {
+      case 11: fn = pad ? (const void*)k_srht_rows_reg<11, true> : (const void*)k_srht_rows_reg<11, false>; break;
+      case 12: fn = pad ? (const void*)k_srht_rows_reg<12, true> : (const void*)k_srht_rows_reg<12, false>; break;
+      case 13: fn = pad ? (const void*)k_srht_rows_reg<13, true> : (const void*)k_srht_rows_reg<13, false>; break;
+      case 14: fn = pad ? (const void*)k_srht_rows_reg<14, true> : (const void*)k_srht_rows_reg<14, false>; break;
+      default: fn = pad ? (const void*)k_srht_rows_reg<15, true> : (const void*)k_srht_rows_reg<15, false>; break;
+    }
+    const int nt = 1 << (logN - 5);
+    int per = 0;
+    RE_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, nt, 0));
+    const int64_t g = (int64_t)(per > 0 ? per : 1) * num_cus();
+    const int kk = (int)k;
+    void* args[] = {(void*)&A, (void*)&m, (void*)&n, (void*)&lda, (void*)&bits, (void*)&sel, (void*)&kk, (void*)&B};
+    RE_TRY_HIP(hipLaunchKernel(fn, dim3((unsigned)(m < g ? m : g)), dim3(nt), args, 0, s));
     return RE_OK;
   }
   if (dtype == RE_F32) {

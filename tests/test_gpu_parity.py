@@ -79,7 +79,11 @@ def _row_tol(A, N):
     return math.log2(max(N, 2)) * 2.0**-24 * np.abs(A.astype(np.float64)).sum(axis=1)[:, None] * 1.01 + 1e-30
 
 
-@pytest.mark.parametrize("m,n,k", [(37, 1000, 40), (64, 16384, 384), (5, 3, 2), (130, 4096, 200), (3, 32768, 17)])
+@pytest.mark.parametrize("m,n,k", [(37, 1000, 40), (64, 16384, 384), (5, 3, 2), (130, 4096, 200), (3, 32768, 17),
+                                   # the register-tiled row transforms, N = 2^11 .. 2^15, exact and zero-padded,
+                                   # k above and below the thread count
+                                   (200, 2048, 100), (90, 3000, 256), (77, 8192, 384), (41, 12000, 500),
+                                   (33, 20000, 512), (40, 32768, 1024), (9, 16000, 384), (5, 2049, 7)])
 def test_srht_x_fp32(orc, m, n, k):
     A = inputs.gaussian(m, n, m + n, dtype=torch.float32)
     B = _np(re_.sketch_x(A.to(DEV), k=k, x="srht", y="srht", l=k, seed=8))
@@ -88,10 +92,12 @@ def test_srht_x_fp32(orc, m, n, k):
     assert np.all(np.abs(B - want) <= _row_tol(A.numpy(), N))
 
 
-def test_srht_x_integer_exact(orc):
-    A = inputs.small_integers(50, 16384, 3, -100, 100)
-    B = _np(re_.sketch_x(A.to(DEV), k=384, x="srht", y="srht", l=384, seed=1))
-    assert np.array_equal(B.astype(np.float64), orc.apply_x(A.numpy(), orc.SRHT, 384, seed=1))
+@pytest.mark.parametrize("m,n,k", [(50, 16384, 384), (40, 2048, 300), (30, 8192, 384), (20, 32768, 700),
+                                   (25, 5000, 96)])
+def test_srht_x_integer_exact(orc, m, n, k):
+    A = inputs.small_integers(m, n, 3, -100, 100)
+    B = _np(re_.sketch_x(A.to(DEV), k=k, x="srht", y="srht", l=k, seed=1))
+    assert np.array_equal(B.astype(np.float64), orc.apply_x(A.numpy(), orc.SRHT, k, seed=1))
 
 
 def test_srht_x_fp64(orc):
