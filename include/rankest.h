@@ -52,7 +52,8 @@ typedef enum { RE_F64 = 0, RE_F32 = 1 } re_dtype;
 /* Random embedding families (Sec. 3.3, Sec. 4): a Gaussian embedding, or a
  * subsampled randomized Hadamard transform sqrt(N/k) S H D (Eq. (Theta), with
  * the Hadamard matrix as the trigonometric transform and N = the dimension
- * zero-padded to a power of two), or (X only) a hashed randomized DCT H F D
+ * zero-padded to a power of two, any N up to 2^30 for either storage type),
+ * or (X only) a hashed randomized DCT H F D
  * (Sec. 3.3: a CountSketch H in place of the sampling S, F the orthonormal
  * DCT-II of length N = max(2, next power of two >= n); the paper's
  * experimental X) or the subsampled randomized DCT sqrt(N/k) S F D (the

@@ -51,6 +51,63 @@ __global__ void __launch_bounds__(256) k_srht_rows_lds(const TA* __restrict__ A,
   }
 }
 
+// Rows longer than the LDS holds, N' = 2^(logN + logH): one work item per
+// (row, c < 2^logH) builds v_c[j] = sum_h (-1)^popcount(c & h) (d .* a)[h N + j]
+// (the Kronecker split H_N' = H_{2^logH} (x) H_N), transforms it in LDS and
+// writes the sampled outputs at positions c N + p.  Item u is (row, c) with
+// row = 8 (u / 2^(logH+3)) + u mod 8 and c = (u / 8) mod 2^logH: the items of a
+// row are 8 apart, so under a grid that is a multiple of 8 (workgroup b runs on
+// XCD b mod 8) they run side by side on one XCD and share its L2.
+__device__ __forceinline__ bool sub_item(int64_t u, int64_t m, int logH, int64_t& row, int& c) {
+  const int64_t slot = u >> 3;
+  c = (int)(slot & ((1 << logH) - 1));
+  row = ((slot >> logH) << 3) | (u & 7);
+  return row < m;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_srht_rows_lds_sub(const T* __restrict__ A, int64_t m, int64_t n, int64_t lda,
+                                                           int logN, int logH, const uint32_t* __restrict__ bits,
+                                                           const int32_t* __restrict__ sel, int64_t k,
+                                                           T* __restrict__ B) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* s = reinterpret_cast<T*>(smem_raw);
+  const int N = 1 << logN;
+  const int64_t items = (((m + 7) >> 3) << 3) << logH;
+  for (int64_t u = blockIdx.x; u < items; u += gridDim.x) {
+    int64_t i;
+    int c;
+    if (!sub_item(u, m, logH, i, c)) continue;  // uniform over the workgroup
+    const T* a = A + i * lda;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+      T acc = T(0);
+      for (int h = 0; h < (1 << logH); ++h) {
+        const int64_t q = ((int64_t)h << logN) + j;
+        if (q >= n) break;
+        const T v = apply_sign<T>(a[q], sign_neg(bits, q));
+        acc += (__popc(c & h) & 1) ? -v : v;
+      }
+      s[j] = acc;
+    }
+    for (int lh = 0; lh < logN; ++lh) {
+      __syncthreads();
+      const int h = 1 << lh;
+      for (int p = threadIdx.x; p < (N >> 1); p += blockDim.x) {
+        const int j = ((p >> lh) << (lh + 1)) | (p & (h - 1));
+        const T x = s[j], y = s[j + h];
+        s[j] = x + y;
+        s[j + h] = x - y;
+      }
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < k; t += blockDim.x) {
+      const int p = sel[t];
+      if ((p >> logN) == c) B[i * k + t] = s[p & (N - 1)];
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // X side, N = 2^14 FP32 rows (the streaming pass that dominates the method):
 // 256 threads, 64 values per thread, no padding (n = N).
@@ -293,52 +350,99 @@ __global__ void __launch_bounds__(512, 2) __attribute__((amdgpu_waves_per_eu(4))
 //            2 .. P-9, {P-3 .. P-1} from the top three bits of t): five stages;
 //   output   bits {7 .. P-4} are finished only for the k sampled outputs,
 //            each a signed sum of its 2^(P-10) partial values.
+//
+// Longer rows (SUB, N' = 2^(P + logH) > 2^15): H_N' = H_{2^logH} (x) H_N, so
+// the sampled output at position c N + p (c < 2^logH, p < N) is entry p of
+// H_N v_c, v_c[j] = sum_h (-1)^popcount(c & h) (d .* a)[h N + j].  Each work
+// item is one (row, c): it accumulates v_c chunk by chunk (reading the whole
+// row), transforms it as above and keeps the samples that fall in chunk c.
+// The 2^logH items of a row are numbered 8 apart, so with a grid that is a
+// multiple of 8 they run side by side on one XCD and all but the first read
+// of the row are served from that XCD's L2.
 // ---------------------------------------------------------------------------
-template <int P, bool PADDED>
+template <int P, bool PADDED, bool SUB>
 __global__ void __launch_bounds__(1 << (P - 5)) k_srht_rows_reg(const float* __restrict__ A, int64_t m, int64_t n,
                                                                int64_t lda, const uint32_t* __restrict__ bits,
                                                                const int32_t* __restrict__ sel, int k,
-                                                               float* __restrict__ B) {
+                                                               float* __restrict__ B, int logH) {
   constexpr int N = 1 << P, NT = N >> 5, CS = N >> 3;
   constexpr int NB = P - 10;                      // unresolved bits 7 .. P-4
   constexpr int SWB = NB < 4 ? NB : 4, SWM = (1 << SWB) - 1;
   __shared__ __align__(16) float lds[N];
   const int t = threadIdx.x;
   uint32_t msk = 0;  // bit 4 j + c: sign of position CS j + 4 t + c
+  if constexpr (!SUB) {
 #pragma unroll
-  for (int j = 0; j < 8; ++j) msk |= ((bits[(CS >> 5) * j + (t >> 3)] >> (4 * (t & 7))) & 15u) << (4 * j);
+    for (int j = 0; j < 8; ++j) msk |= ((bits[(CS >> 5) * j + (t >> 3)] >> (4 * (t & 7))) & 15u) << (4 * j);
+  }
   const int wa = (4 * t) ^ (((t >> 5) & SWM) << 2);  // phase-1 store of chunk j at wa + CS j
   const int base = (t & 3) + 128 * ((t >> 2) & ((1 << NB) - 1)) + CS * (t >> (P - 8));
   const int sw = (t >> 2) & SWM;
   int ra[16];  // phase-2 value u = 16 h + i lives at ra[i] + 64 h
 #pragma unroll
   for (int i = 0; i < 16; ++i) ra[i] = base + 4 * (i ^ sw);
-  for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
-    const float* src = A + row * lda + 4 * t;
-    float x[32];
-    asm volatile("" : "+v"(msk));
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      fx4 v;
-      if constexpr (PADDED) {
-        const int64_t q0 = 4 * t + (int64_t)CS * j;
-        if (q0 + 3 < n) {
-          v = *reinterpret_cast<const fx4*>(src + CS * j);
-        } else {
-          v = fx4{0.f, 0.f, 0.f, 0.f};
-          for (int c = 0; c < 4; ++c)
-            if (q0 + c < n) v[c] = src[CS * j + c];
-        }
-      } else {
-        v = ld_stream(src + CS * j);
-      }
-      x[4 * j + 0] = v.x;
-      x[4 * j + 1] = v.y;
-      x[4 * j + 2] = v.z;
-      x[4 * j + 3] = v.w;
+  const int64_t items = SUB ? (((m + 7) >> 3) << 3) << logH : m;
+  for (int64_t u = blockIdx.x; u < items; u += gridDim.x) {
+    int64_t row = u;
+    int cc = 0;  // SUB: which chunk of the long row's outputs this item produces
+    if constexpr (SUB) {
+      if (!sub_item(u, m, logH, row, cc)) continue;  // uniform over the workgroup
     }
+    float x[32];
+    if constexpr (!SUB) {
+      const float* src = A + row * lda + 4 * t;
+      asm volatile("" : "+v"(msk));
 #pragma unroll
-    for (int e = 0; e < 32; ++e) x[e] = __uint_as_float(__float_as_uint(x[e]) ^ ((msk << (31 - e)) & 0x80000000u));
+      for (int j = 0; j < 8; ++j) {
+        fx4 v;
+        if constexpr (PADDED) {
+          const int64_t q0 = 4 * t + (int64_t)CS * j;
+          if (q0 + 3 < n) {
+            v = *reinterpret_cast<const fx4*>(src + CS * j);
+          } else {
+            v = fx4{0.f, 0.f, 0.f, 0.f};
+            for (int c = 0; c < 4; ++c)
+              if (q0 + c < n) v[c] = src[CS * j + c];
+          }
+        } else {
+          v = ld_stream(src + CS * j);
+        }
+        x[4 * j + 0] = v.x;
+        x[4 * j + 1] = v.y;
+        x[4 * j + 2] = v.z;
+        x[4 * j + 3] = v.w;
+      }
+#pragma unroll
+      for (int e = 0; e < 32; ++e) x[e] = __uint_as_float(__float_as_uint(x[e]) ^ ((msk << (31 - e)) & 0x80000000u));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 32; ++e) x[e] = 0.0f;
+      for (int h = 0; h < (1 << logH); ++h) {
+        const int64_t qh = (int64_t)h << P;  // chunk h of the long row
+        if (qh >= n) break;                  // the rest is padding
+        const float* src = A + row * lda + qh + 4 * t;
+        uint32_t mh = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          mh |= ((bits[(qh >> 5) + (CS >> 5) * j + (t >> 3)] >> (4 * (t & 7))) & 15u) << (4 * j);
+        if (__popc(cc & h) & 1) mh = ~mh;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          fx4 v;
+          const int64_t q0 = qh + 4 * t + (int64_t)CS * j;
+          if (!PADDED || q0 + 3 < n) {
+            v = *reinterpret_cast<const fx4*>(src + CS * j);
+          } else {
+            v = fx4{0.f, 0.f, 0.f, 0.f};
+            for (int c = 0; c < 4; ++c)
+              if (q0 + c < n) v[c] = src[CS * j + c];
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            x[4 * j + c] += __uint_as_float(__float_as_uint(v[c]) ^ ((mh << (31 - (4 * j + c))) & 0x80000000u));
+        }
+      }
+    }
     fwht32(x);
 #pragma unroll
     for (int j = 0; j < 8; ++j)
@@ -355,7 +459,11 @@ __global__ void __launch_bounds__(1 << (P - 5)) k_srht_rows_reg(const float* __r
       for (int i = 0; i < 16; ++i) lds[ra[i] + 64 * h] = x[16 * h + i];
     __syncthreads();
     for (int s = t; s < k; s += NT) {
-      const int p = sel[s];
+      int p = sel[s];
+      if constexpr (SUB) {
+        if ((p >> P) != cc) continue;
+        p &= N - 1;
+      }
       const int pl = p & ~(((1 << NB) - 1) << 7), ph = (p >> 7) & ((1 << NB) - 1);
       float v[1 << NB];
 #pragma unroll
@@ -613,24 +721,59 @@ re_status launch_srht_rows(hipStream_t s, const void* A, int dtype, int64_t m, i
     RE_TRY_HIP(hipGetLastError());
     return RE_OK;
   }
-  if (dtype == RE_F32 && logN >= 11 && logN <= 15 && lda % 4 == 0 && ((uintptr_t)A % 16) == 0 &&
-      k <= INT32_MAX && !srht_rows_lds_forced()) {
+  if (logN > 30) return RE_ERR_UNSUPPORTED;  // sampled positions are 32-bit
+  // 16-byte aligned FP32 rows of N >= 2^11: the register-tiled transform,
+  // over sub-rows of 2^15 with their chunk sums when N is longer.
+  if (dtype == RE_F32 && logN >= 11 && lda % 4 == 0 && ((uintptr_t)A % 16) == 0 && k <= INT32_MAX &&
+      !srht_rows_lds_forced()) {
     const bool pad = n != N;
+    const int P = logN < 15 ? logN : 15;
+    const int logH = logN - P;
     const void* fn = nullptr;
-    switch (logN) {
-      case 11: fn = pad ? (const void*)k_srht_rows_reg<11, true> : (const void*)k_srht_rows_reg<11, false>; break;
-      case 12: fn = pad ? (const void*)k_srht_rows_reg<12, true> : (const void*)k_srht_rows_reg<12, false>; break;
-      case 13: fn = pad ? (const void*)k_srht_rows_reg<13, true> : (const void*)k_srht_rows_reg<13, false>; break;
-      case 14: fn = pad ? (const void*)k_srht_rows_reg<14, true> : (const void*)k_srht_rows_reg<14, false>; break;
-      default: fn = pad ? (const void*)k_srht_rows_reg<15, true> : (const void*)k_srht_rows_reg<15, false>; break;
+    switch (P) {
+      case 11: fn = pad ? (const void*)k_srht_rows_reg<11, true, false> : (const void*)k_srht_rows_reg<11, false, false>; break;
+      case 12: fn = pad ? (const void*)k_srht_rows_reg<12, true, false> : (const void*)k_srht_rows_reg<12, false, false>; break;
+      case 13: fn = pad ? (const void*)k_srht_rows_reg<13, true, false> : (const void*)k_srht_rows_reg<13, false, false>; break;
+      case 14: fn = pad ? (const void*)k_srht_rows_reg<14, true, false> : (const void*)k_srht_rows_reg<14, false, false>; break;
+      default:
+        if (logH == 0)
+          fn = pad ? (const void*)k_srht_rows_reg<15, true, false> : (const void*)k_srht_rows_reg<15, false, false>;
+        else
+          fn = pad ? (const void*)k_srht_rows_reg<15, true, true> : (const void*)k_srht_rows_reg<15, false, true>;
+        break;
     }
-    const int nt = 1 << (logN - 5);
+    const int nt = 1 << (P - 5);
     int per = 0;
     RE_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, nt, 0));
-    const int64_t g = (int64_t)(per > 0 ? per : 1) * num_cus();
+    const int64_t items = logH ? ((m + 7) / 8 * 8) << logH : m;
+    int64_t g = (int64_t)(per > 0 ? per : 1) * num_cus();
+    if (logH) g = g < 8 ? 8 : g / 8 * 8;  // a multiple of 8 keeps a row's items on one XCD
+    if (items < g) g = items;
     const int kk = (int)k;
-    void* args[] = {(void*)&A, (void*)&m, (void*)&n, (void*)&lda, (void*)&bits, (void*)&sel, (void*)&kk, (void*)&B};
-    RE_TRY_HIP(hipLaunchKernel(fn, dim3((unsigned)(m < g ? m : g)), dim3(nt), args, 0, s));
+    void* args[] = {(void*)&A, (void*)&m, (void*)&n, (void*)&lda, (void*)&bits, (void*)&sel, (void*)&kk, (void*)&B,
+                    (void*)&logH};
+    RE_TRY_HIP(hipLaunchKernel(fn, dim3((unsigned)g), dim3(nt), args, 0, s));
+    return RE_OK;
+  }
+  // Everything else: one row (or, past the LDS, one (row, chunk) item) per
+  // workgroup with the row staged in LDS: up to 2^15 FP32 or 2^14 FP64 values.
+  const int maxLog = dtype == RE_F32 ? 15 : 14;
+  if (logN > maxLog) {
+    const int logH = logN - maxLog;
+    const size_t lds = (size_t)(1 << maxLog) * (dtype == RE_F32 ? sizeof(float) : sizeof(double));
+    const int64_t items = ((m + 7) / 8 * 8) << logH;
+    int64_t g = 8192;
+    if (items < g) g = items;
+    if (dtype == RE_F32) {
+      RE_TRY(allow_lds(k_srht_rows_lds_sub<float>, lds));
+      hipLaunchKernelGGL(k_srht_rows_lds_sub<float>, dim3((unsigned)g), dim3(256), lds, s, (const float*)A, m, n, lda,
+                         maxLog, logH, bits, sel, k, (float*)B);
+    } else {
+      RE_TRY(allow_lds(k_srht_rows_lds_sub<double>, lds));
+      hipLaunchKernelGGL(k_srht_rows_lds_sub<double>, dim3((unsigned)g), dim3(256), lds, s, (const double*)A, m, n,
+                         lda, maxLog, logH, bits, sel, k, (double*)B);
+    }
+    RE_TRY_HIP(hipGetLastError());
     return RE_OK;
   }
   if (dtype == RE_F32) {

@@ -75,8 +75,16 @@ def test_select_exact(orc, npad, k):
 
 # --- AX -----------------------------------------------------------------------------------------
 
-def _row_tol(A, N):
-    return math.log2(max(N, 2)) * 2.0**-24 * np.abs(A.astype(np.float64)).sum(axis=1)[:, None] * 1.01 + 1e-30
+def _row_tol(A, N, levels=None):
+    levels = math.log2(max(N, 2)) if levels is None else levels
+    return levels * 2.0**-24 * np.abs(A.astype(np.float64)).sum(axis=1)[:, None] * 1.01 + 1e-30
+
+
+def _long_row_levels(N, sub):
+    """Rounding levels of a row longer than one transform of length sub: the
+    N / sub chunk sums are accumulated one after another (N / sub - 1
+    additions), then log2(sub) butterfly stages."""
+    return N // sub - 1 + math.log2(sub)
 
 
 @pytest.mark.parametrize("m,n,k", [(37, 1000, 40), (64, 16384, 384), (5, 3, 2), (130, 4096, 200), (3, 32768, 17),
@@ -98,6 +106,47 @@ def test_srht_x_integer_exact(orc, m, n, k):
     A = inputs.small_integers(m, n, 3, -100, 100)
     B = _np(re_.sketch_x(A.to(DEV), k=k, x="srht", y="srht", l=k, seed=1))
     assert np.array_equal(B.astype(np.float64), orc.apply_x(A.numpy(), orc.SRHT, k, seed=1))
+
+
+# rows past 2^15 (FP32) / 2^14 (FP64): chunk sums over H = N / 2^15 (or 2^14) sub-rows,
+# exact and zero-padded N, H = 2 .. 8, k above and below the thread count
+@pytest.mark.parametrize("m,n,k", [(24, 40000, 384), (16, 65536, 1500), (9, 70000, 600), (4, 140000, 300),
+                                   (11, 65537, 33)])
+def test_srht_x_fp32_long_rows(orc, m, n, k):
+    A = inputs.gaussian(m, n, m + n, dtype=torch.float32)
+    B = _np(re_.sketch_x(A.to(DEV), k=k, x="srht", y="srht", l=k, seed=8))
+    want = orc.apply_x(A.numpy(), orc.SRHT, k, seed=8)
+    N = 1 << (n - 1).bit_length()
+    assert np.all(np.abs(B - want) <= _row_tol(A.numpy(), N, _long_row_levels(N, 1 << 15)))
+
+
+@pytest.mark.parametrize("m,n,k", [(12, 65536, 700), (7, 100000, 256)])
+def test_srht_x_long_rows_integer_exact(orc, m, n, k):
+    A = inputs.small_integers(m, n, 5, -100, 100)
+    B = _np(re_.sketch_x(A.to(DEV), k=k, x="srht", y="srht", l=k, seed=4))
+    assert np.array_equal(B.astype(np.float64), orc.apply_x(A.numpy(), orc.SRHT, k, seed=4))
+
+
+def test_srht_x_fp32_long_rows_unaligned_view(orc):
+    """A row stride that is not a multiple of 4 takes the LDS chunk-sum kernel."""
+    m, n, k = 10, 40000, 200
+    Abig = inputs.gaussian(m, n + 1, 77, dtype=torch.float32)
+    A = Abig[:, :n]
+    B = _np(re_.sketch_x(Abig.to(DEV)[:, :n], k=k, x="srht", y="srht", l=k, seed=6))
+    want = orc.apply_x(np.ascontiguousarray(A.numpy()), orc.SRHT, k, seed=6)
+    N = 1 << (n - 1).bit_length()
+    assert np.all(np.abs(B - want) <= _row_tol(A.numpy(), N, _long_row_levels(N, 1 << 15)))
+
+
+@pytest.mark.parametrize("m,n,k", [(6, 20000, 128), (5, 40000, 300), (3, 16385, 17)])
+def test_srht_x_fp64_long_rows(orc, m, n, k):
+    A = inputs.gaussian(m, n, 3 + n, dtype=torch.float64)
+    B = _np(re_.sketch_x(A.to(DEV), k=k, x="srht", y="srht", l=k, seed=2))
+    want = orc.apply_x(A.numpy(), orc.SRHT, k, seed=2)
+    N = 1 << (n - 1).bit_length()
+    # both sides round in FP64: the GPU's chunk sums and stages plus the oracle's log2(N) stages
+    tol = (_long_row_levels(N, 1 << 14) + math.log2(N)) * 2.0**-53 * np.abs(A.numpy()).sum(axis=1)[:, None] * 1.01
+    assert np.all(np.abs(B - want) <= tol)
 
 
 def test_srht_x_fp64(orc):
