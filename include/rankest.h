@@ -60,8 +60,9 @@ typedef enum { RE_F64 = 0, RE_F32 = 1 } re_dtype;
  * SRHT's signs D and sample S over that N), as X or as Y (Sec. 6 uses it for
  * Theta = Y; along the m rows of B = A X, M = max(2, next power of two >= m),
  * the Y stream's signs and sample, any storage type of A).  As X the two DCT
- * kinds need FP32 A with N <= 16384 and native precision (else
- * RE_ERR_UNSUPPORTED); the hashed DCT as a Y is rejected (RE_ERR_INVALID_ARG). */
+ * kinds need FP32 A with N <= 2^20, k <= 16384 for the hashed DCT when
+ * N > 16384, and native precision (else RE_ERR_UNSUPPORTED); the hashed DCT
+ * as a Y is rejected (RE_ERR_INVALID_ARG). */
 typedef enum { RE_GAUSSIAN = 0, RE_SRHT = 1, RE_HRTT = 2, RE_SRCT = 3 } re_kind;
 
 /* Arithmetic of the A X contraction.  NATIVE: the storage type of A.

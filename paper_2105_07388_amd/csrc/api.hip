@@ -160,14 +160,14 @@ re_status validate(const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
   if ((sides & 2) && rs->l > lmax) return RE_ERR_INVALID_ARG;
   if (rs->k > (int64_t)INT32_MAX / 2) return RE_ERR_INVALID_ARG;
   if (sk->prec != RE_PREC_NATIVE && (dt == RE_F64 || rs->xk != RE_GAUSSIAN)) return RE_ERR_UNSUPPORTED;
-  if (dct && (dt != RE_F32 || hrtt_npad(n) > kHrttMaxN)) return RE_ERR_UNSUPPORTED;
+  if (dct && (dt != RE_F32 || !dct_x_supported(n, rs->k, rs->xk == RE_HRTT))) return RE_ERR_UNSUPPORTED;
   return RE_OK;
 }
 
 // Workspace plan of one estimate.
 struct Plan {
   size_t xbits, ybits, xsel, ysel, selscr, X, Y, B, C, svd, sigma, info, out3, stats, gdesc, ydesc, queue, yparts,
-      rdiag, hscr, gparts, U, yord, total;
+      rdiag, hscr, gparts, U, yord, dctws, total;
 };
 
 // Sketches the batched form accepts (one workgroup's LDS holds the small SVD).
@@ -224,6 +224,7 @@ Plan plan(int32_t dt, int64_t m, int64_t n, const Resolved& rs) {
     p.gparts = c.take(gx > gy ? gx : gy);
   }
   p.hscr = c.take(rs.xk == RE_HRTT ? hrtt_scratch_bytes(n, rs.k) : 0);
+  p.dctws = c.take(rs.xk == RE_HRTT || rs.xk == RE_SRCT ? dct_long_ws_bytes(m, n, rs.xk == RE_HRTT) : 0);
   p.total = c.off;
   return p;
 }
@@ -249,7 +250,8 @@ re_status run_x(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m
     RE_TRY(launch_sign_bits(s, hrtt_npad(n), seed, kXSign, bits));
     RE_TRY(launch_hrtt_hash(s, n, rs.k, seed, at(h, p.hscr)));
     mark(h, RE_STAGE_AX);
-    return launch_hrtt_rows(s, (const float*)A, m, n, lda, rs.k, bits, at(h, p.hscr), (float*)B, rs.k);
+    return launch_hrtt_rows(s, (const float*)A, m, n, lda, rs.k, bits, at(h, p.hscr), (float*)B, rs.k,
+                            at(h, p.dctws));
   }
   if (rs.xk == RE_SRCT) {  // subsampled randomized DCT (FP32 A): the SRHT's signs and sample over N
     const int64_t N = hrtt_npad(n);
@@ -258,7 +260,7 @@ re_status run_x(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m
     RE_TRY(launch_sign_bits(s, N, seed, kXSign, bits));
     RE_TRY(launch_select(s, N, rs.k, seed, kXSel, at(h, p.selscr), sel));
     mark(h, RE_STAGE_AX);
-    return launch_srct_rows(s, (const float*)A, m, n, lda, rs.k, bits, sel, (float*)B, rs.k);
+    return launch_srct_rows(s, (const float*)A, m, n, lda, rs.k, bits, sel, (float*)B, rs.k, at(h, p.dctws));
   }
   if (rs.xk == RE_SRHT) {
     uint32_t* bits = (uint32_t*)at(h, p.xbits);

@@ -48,11 +48,14 @@ static_assert(kHrttMaxN <= 16 * kBuildThreads, "the hash sort holds at most 16 k
 // bucket, numbered in list order.  ends[t] = bit i set where position tC + i
 // ends a run; rbase[t] = number of the first run of chunk t; runs rlo[b] ..
 // rhi[b] make up bucket b (rlo > rhi for an empty bucket).
+// Longer transforms are cut into chunks of N coordinates: workgroup c builds
+// the lists of coordinates c N .. c N + N - 1 (local indices in list and
+// code16) into the arrays at byte offset c * chunk_bytes.
 __global__ void __launch_bounds__(kBuildThreads) k_hash_build(int N, int k, uint64_t seed, int32_t* __restrict__ ptr,
                                                               int32_t* __restrict__ list, uint16_t* __restrict__ code16,
                                                               uint32_t* __restrict__ ends,
                                                               int32_t* __restrict__ rbase, int32_t* __restrict__ rlo,
-                                                              int32_t* __restrict__ rhi) {
+                                                              int32_t* __restrict__ rhi, size_t chunk_bytes) {
   extern __shared__ uint32_t key[];  // N keys, then N + 1 words: the sort's buffer, later the k + 1 bucket starts
   uint32_t* tmp = key + N;
   int32_t* sptr = (int32_t*)(key + N);  // written only after the sorted keys are back in key
@@ -60,8 +63,19 @@ __global__ void __launch_bounds__(kBuildThreads) k_hash_build(int N, int k, uint
   __shared__ int32_t sbase[kRowThreads];
   __shared__ int wsum[kBuildThreads / 64];
   const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t j0 = (uint64_t)blockIdx.x * (uint64_t)N;
+  {
+    const size_t off = (size_t)blockIdx.x * chunk_bytes;
+    ptr = (int32_t*)((char*)ptr + off);
+    list = (int32_t*)((char*)list + off);
+    code16 = (uint16_t*)((char*)code16 + off);
+    ends = (uint32_t*)((char*)ends + off);
+    rbase = (int32_t*)((char*)rbase + off);
+    rlo = (int32_t*)((char*)rlo + off);
+    rhi = (int32_t*)((char*)rhi + off);
+  }
   for (int j = tid; j < N; j += nth) {
-    const u64x4 w = philox((uint64_t)j, 0, kXHashStream, 0, seed);
+    const u64x4 w = philox(j0 + (uint64_t)j, 0, kXHashStream, 0, seed);
     const uint32_t b = (uint32_t)__umul64hi(w.x, (uint64_t)k);
     key[j] = (b << 15) | ((uint32_t)j << 1) | (uint32_t)(w.y & 1u);
   }
@@ -627,6 +641,216 @@ k_hrtt_rows(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda, cons
   }
 }
 
+// ---------------------------------------------------------------------------
+// Rows longer than one workgroup's LDS (N > 16384): Makhoul's DCT through a
+// four-step split of the M = N / 2 point complex FFT, M = M1 M2 with
+// M2 = 8192.  With p = p2 + M2 p1 and q = q1 + M1 q2,
+//   Z_q = sum_p2 e^{-2 pi i p2 q2 / M2} [ e^{-2 pi i p2 q1 / M}
+//         sum_p1 e^{-2 pi i p1 q1 / M1} z_{p2 + M2 p1} ],
+// so one work item per (row, q1) reads the whole row, forms the bracket for
+// its q1 (an M1-term sum and a twiddle per p2), runs the 8192-point FFT in
+// LDS and writes Z_{q1 + M1 q2} for every q2 to W (natural order, M complex
+// values per row).  The items of a row are numbered 8 apart, so under a grid
+// that is a multiple of 8 they share one XCD's L2 while they read the row.
+// Then the DCT values come from the pairs (Z_q, Z_{M-q}) as in the one-row
+// kernel: sampled (SRCT) straight into B, or (HRTT) all N into T, whose
+// chunked bucket lists give the CountSketch sums.
+// ---------------------------------------------------------------------------
+constexpr int kLongLgM2 = 13, kLongM2 = 1 << kLongLgM2;
+constexpr int kLongPairs = kLongM2 / 2 / kRowThreads;  // (p2, M2 - 1 - p2) pairs per thread
+
+// Entries 4p .. 4p+3 of a row of n >= 1 entries, zero past n, without branches:
+// every load reads an entry in range (the index clamped to n - 1).
+__device__ __forceinline__ float4 clamped_quad(const float* __restrict__ a, int p, int n) {
+  const int j = 4 * p;
+  float v[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float x = a[j + c < n ? j + c : n - 1];
+    v[c] = j + c < n ? x : 0.0f;
+  }
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// LDS: M2 + M2/16 complex slots, the FFT twiddles (64 + M2/64), then
+// e^{-2 pi i t / M} as 256 fine and M/256 coarse factors.
+template <bool VEC>
+__global__ void __launch_bounds__(kRowThreads) k_dct_long_fft(const float* __restrict__ A, int64_t rows, int64_t n,
+                                                              int64_t lda, int lgM, const uint32_t* __restrict__ bits,
+                                                              float2* __restrict__ W) {
+  constexpr int M2 = kLongM2, LGM2 = kLongLgM2, TWN = 64 + M2 / 64;
+  const int M = 1 << lgM, lgM1 = lgM - LGM2, M1 = 1 << lgM1;
+  extern __shared__ float2 Z[];
+  float2* tw = Z + (M2 + (M2 >> 4));
+  float2* tf = tw + TWN;
+  float2* tc = tf + 256;
+  const int tid0 = threadIdx.x;
+  for (int u = tid0; u < TWN; u += kRowThreads) {
+    const int t = u < 64 ? u : 64 * (u - 64);
+    double sv, cv;
+    sincospi(2.0 * (double)t / (double)M2, &sv, &cv);
+    tw[u] = make_float2((float)cv, (float)-sv);
+  }
+  for (int u = tid0; u < 256 + (M >> 8); u += kRowThreads) {
+    const int t = u < 256 ? u : 256 * (u - 256);
+    double sv, cv;
+    sincospi(2.0 * (double)t / (double)M, &sv, &cv);
+    tf[u] = make_float2((float)cv, (float)-sv);  // tc = tf + 256 continues the same array
+  }
+  __syncthreads();
+  auto cis = [&](int t) {  // e^{-2 pi i t / M}
+    t &= M - 1;
+    const float2 f = tf[t & 255];
+    return (t >> 8) ? cmul(f, tc[t >> 8]) : f;
+  };
+  const int64_t items = (((rows + 7) >> 3) << 3) << lgM1;
+  for (int64_t u = blockIdx.x; u < items; u += gridDim.x) {
+    const int64_t slot = u >> 3;
+    const int q1 = (int)(slot & (M1 - 1));
+    const int64_t row = ((slot >> lgM1) << 3) | (u & 7);
+    if (row >= rows) continue;  // uniform over the workgroup
+    // the thread index, opaque to the optimiser here, so that the item's LDS
+    // addresses are recomputed per item instead of held (and spilled) across items
+    int tid = tid0;
+    asm volatile("" : "+v"(tid));
+    const float* __restrict__ a = A + row * lda;
+    // thread t owns p2 = t + 512 i and M2 - 1 - p2; quad p gives z_p = (x0, x2) and
+    // z_{M-1-p} = (x3, x1), and M - 1 - (p2 + M2 p1) = (M2 - 1 - p2) + M2 (M1 - 1 - p1)
+    constexpr int G = 4;  // pairs per group: eight loads in flight
+#pragma unroll
+    for (int g0 = 0; g0 < kLongPairs; g0 += G) {
+      float2 lo[G], hi[G];  // brackets at p2 and at M2 - 1 - p2
+#pragma unroll
+      for (int e = 0; e < G; ++e) lo[e] = hi[e] = make_float2(0.0f, 0.0f);
+#pragma unroll 1
+      for (int p1 = 0; p1 < (M1 >> 1); ++p1) {
+        const float2 wf = cis(p1 * q1 * M2), wb = cis((M1 - 1 - p1) * q1 * M2);  // e^{-2 pi i p1' q1 / M1}
+        const float* __restrict__ ap = a + 4 * (int64_t)M2 * p1;
+        const int64_t np = n - 4 * (int64_t)M2 * p1;  // the entries left from this chunk on
+        const uint32_t* __restrict__ bp = bits + (M2 >> 3) * p1;
+        if (VEC && np >= 4 * (int64_t)M2) {  // the whole chunk in range: unchecked float4 loads
+          float4 xa[G], xb[G];
+#pragma unroll
+          for (int e = 0; e < G; ++e) {
+            const int p2 = tid + (g0 + e) * kRowThreads, p2b = M2 - 1 - p2;
+            xa[e] = signed4(*(const float4*)(ap + 4 * p2), bp[p2 >> 3] >> ((p2 & 7) * 4));
+            xb[e] = signed4(*(const float4*)(ap + 4 * p2b), bp[p2b >> 3] >> ((p2b & 7) * 4));
+          }
+#pragma unroll
+          for (int e = 0; e < G; ++e) {
+            lo[e] = cadd(lo[e], cadd(cmul(wf, make_float2(xa[e].x, xa[e].z)), cmul(wb, make_float2(xb[e].w, xb[e].y))));
+            hi[e] = cadd(hi[e], cadd(cmul(wf, make_float2(xb[e].x, xb[e].z)), cmul(wb, make_float2(xa[e].w, xa[e].y))));
+          }
+        } else if (np > 0) {  // the chunk holding the end of the row (or unaligned rows): one quad at a time
+          const int nl = (int)(np < 4 * (int64_t)M2 ? np : 4 * (int64_t)M2);
+#pragma unroll
+          for (int e = 0; e < G; ++e) {
+            const int p2 = tid + (g0 + e) * kRowThreads, p2b = M2 - 1 - p2;
+            const float4 xa = signed4(clamped_quad(ap, p2, nl), bp[p2 >> 3] >> ((p2 & 7) * 4));
+            const float4 xb = signed4(clamped_quad(ap, p2b, nl), bp[p2b >> 3] >> ((p2b & 7) * 4));
+            lo[e] = cadd(lo[e], cadd(cmul(wf, make_float2(xa.x, xa.z)), cmul(wb, make_float2(xb.w, xb.y))));
+            hi[e] = cadd(hi[e], cadd(cmul(wf, make_float2(xb.x, xb.z)), cmul(wb, make_float2(xa.w, xa.y))));
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < G; ++e) {
+        const int p2 = tid + (g0 + e) * kRowThreads;
+        Z[pz(p2)] = cmul(cis(p2 * q1), lo[e]);
+        Z[pz(M2 - 1 - p2)] = cmul(cis((M2 - 1 - p2) * q1), hi[e]);
+      }
+    }
+    __syncthreads();
+    fft_pass<2, LGM2, 0>(Z, tw, tid);
+    fft_rest<LGM2, 1>(Z, tw, tid);
+    float2* __restrict__ w = W + row * (int64_t)M;
+    for (int q2 = tid; q2 < M2; q2 += kRowThreads) w[q1 + (q2 << lgM1)] = Z[pz(q2)];
+    __syncthreads();
+  }
+}
+
+// DCT-II value j of a row from Z (Makhoul): with q = j mod M and r = (M - q) mod M,
+// E = (Z_q + conj Z_r) / 2, O = (Z_q - conj Z_r) / (2i), V_j = E +- e^{-2 pi i q / N} O
+// (+ for j < M), (F a)_j = c_j Re(e^{-i pi j / (2N)} V_j).  The two unit factors
+// depend on j only: t1 = e^{-i pi j / (2N)}, t2 = +- t1 e^{-2 pi i q / N}.
+struct DctTw {
+  float2 t1, t2;
+  int q, r;
+  float c;
+};
+
+__device__ __forceinline__ DctTw dct_tw(int64_t j, int lgN) {
+  const int64_t N = int64_t(1) << lgN, M = N >> 1;
+  DctTw d;
+  d.q = (int)(j & (M - 1));
+  d.r = (int)((M - d.q) & (M - 1));
+  double s1, c1, s2, c2;
+  sincospi((double)j / (double)(2 * N), &s1, &c1);
+  sincospi((double)j / (double)(2 * N) + 2.0 * (double)d.q / (double)N, &s2, &c2);
+  const double sg = j < M ? 1.0 : -1.0;
+  d.t1 = make_float2((float)c1, (float)-s1);
+  d.t2 = make_float2((float)(sg * c2), (float)(-sg * s2));
+  d.c = j == 0 ? (float)sqrt(1.0 / (double)N) : (float)sqrt(2.0 / (double)N);
+  return d;
+}
+
+__device__ __forceinline__ float dct_value(const float2* __restrict__ z, const DctTw& d) {
+  const float2 zq = z[d.q], zr = z[d.r];
+  const float2 E = make_float2(0.5f * (zq.x + zr.x), 0.5f * (zq.y - zr.y));
+  const float2 O = make_float2(0.5f * (zq.y + zr.y), 0.5f * (zr.x - zq.x));
+  // Re(t1 E + t2 O)
+  return d.c * ((d.t1.x * E.x - d.t1.y * E.y) + (d.t2.x * O.x - d.t2.y * O.y));
+}
+
+// SRCT: B[i][b] = sk (F D a_i)_{sel[b]} for the rows of W; thread (b, row group).
+__global__ void __launch_bounds__(256) k_dct_long_sample(const float2* __restrict__ W, int64_t rows, int lgN,
+                                                        const int32_t* __restrict__ sel, int64_t k, float sk,
+                                                        float* __restrict__ B, int64_t ldb) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= k) return;
+  const DctTw d = dct_tw(sel[b], lgN);
+  const int64_t M = int64_t(1) << (lgN - 1);
+  for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) B[i * ldb + b] = sk * dct_value(W + i * M, d);
+}
+
+// HRTT, first part: T[i][j] = (F D a_i)_j for every j (coalesced in j).
+__global__ void __launch_bounds__(256) k_dct_long_values(const float2* __restrict__ W, int64_t rows, int lgN,
+                                                        float* __restrict__ T) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t N = int64_t(1) << lgN, M = N >> 1;
+  if (j >= N) return;
+  const DctTw d = dct_tw(j, lgN);
+  for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) T[i * N + j] = dct_value(W + i * M, d);
+}
+
+// HRTT, second part: B[i][b] = sk sum over the chunks c, in order, of the
+// bucket's list entries of chunk c (increasing coordinate), each T[i][c NC + j]
+// with its sign: the coordinates of bucket b in increasing order.
+__global__ void __launch_bounds__(256) k_dct_long_buckets(const float* __restrict__ T, int64_t rows, int64_t N,
+                                                         int chunks, const int32_t* __restrict__ ptr,
+                                                         const uint16_t* __restrict__ code16, size_t chunk_bytes,
+                                                         int64_t k, float sk, float* __restrict__ B, int64_t ldb) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= k) return;
+  constexpr int NC = (int)kHrttMaxN;
+  for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) {
+    const float* __restrict__ t = T + i * N;
+    float acc = 0.0f;
+    for (int c = 0; c < chunks; ++c) {
+      const int32_t* pc = (const int32_t*)((const char*)ptr + (size_t)c * chunk_bytes);
+      const uint16_t* cc = (const uint16_t*)((const char*)code16 + (size_t)c * chunk_bytes);
+      const float* tc = t + (int64_t)c * NC;
+      for (int p = pc[b]; p < pc[b + 1]; ++p) {
+        const uint32_t e = cc[p];
+        const float x = tc[e & 0x3fffu];
+        acc += (e & 0x8000u) ? -x : x;
+      }
+    }
+    B[i * ldb + b] = sk * acc;
+  }
+}
+
 }  // namespace
 
 int64_t hrtt_npad(int64_t n) {
@@ -664,7 +888,30 @@ HashScratch carve_hash(void* base, int64_t N, int64_t k) {
 }
 }  // namespace
 
-size_t hrtt_scratch_bytes(int64_t n, int64_t k) { return carve_hash(nullptr, hrtt_npad(n), k).bytes; }
+// Coordinates per hash chunk and the chunk count of a transform of length N.
+static int64_t hash_chunk(int64_t N) { return N < kHrttMaxN ? N : kHrttMaxN; }
+static int64_t hash_chunks(int64_t N) { return N / hash_chunk(N); }
+
+size_t hrtt_scratch_bytes(int64_t n, int64_t k) {
+  const int64_t N = hrtt_npad(n);
+  return (size_t)hash_chunks(N) * carve_hash(nullptr, hash_chunk(N), k).bytes;
+}
+
+// Rows of one pass of the long-row path and its workspace: W (rows x N / 2
+// complex) and, for the hashed DCT, T (rows x N).
+static int64_t long_rows(int64_t m, int64_t N, bool hash) {
+  const int64_t per = N * 4 * (hash ? 2 : 1);
+  int64_t r = (kDctLongWsBytes / per) / 8 * 8;
+  if (r < 8) r = 8;
+  const int64_t m8 = (m + 7) / 8 * 8;
+  return r < m8 ? r : m8;
+}
+
+size_t dct_long_ws_bytes(int64_t m, int64_t n, bool hash) {
+  const int64_t N = hrtt_npad(n);
+  if (N <= kHrttMaxN) return 0;
+  return (size_t)long_rows(m, N, hash) * (size_t)N * 4 * (hash ? 2 : 1);
+}
 
 template <bool VEC, bool HASH>
 static const void* rows_kernel(int lgN) {
@@ -722,32 +969,93 @@ static re_status launch_rows(hipStream_t s, bool hash, const float* A, int64_t m
   return RE_OK;
 }
 
+bool dct_x_supported(int64_t n, int64_t k, bool hash) {
+  const int64_t N = hrtt_npad(n);
+  if (N > kDctMaxN || k < 1 || k > N) return false;
+  return !(hash && N > kHrttMaxN && k > kHrttMaxN);  // a chunk's bucket starts live in its build's LDS
+}
+
 re_status launch_hrtt_hash(hipStream_t s, int64_t n, int64_t k, uint64_t seed, void* scratch) {
   const int64_t N = hrtt_npad(n);
-  if (N > kHrttMaxN || k < 1 || k > N) return RE_ERR_UNSUPPORTED;
-  const HashScratch h = carve_hash(scratch, N, k);
-  const size_t lds_build = (size_t)(2 * N + 1) * 4;  // keys, then the sort buffer that later holds the k + 1 <= N + 1 bucket starts
+  if (!dct_x_supported(n, k, true)) return RE_ERR_UNSUPPORTED;
+  const int64_t NC = hash_chunk(N);
+  const HashScratch h = carve_hash(scratch, NC, k);
+  const size_t lds_build = (size_t)(2 * NC + 1) * 4;  // keys, then the sort buffer that later holds the k + 1 <= NC + 1 bucket starts
   if (lds_build > 65536)
     RE_TRY_HIP(hipFuncSetAttribute((const void*)k_hash_build, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds_build));
-  hipLaunchKernelGGL(k_hash_build, dim3(1), dim3(kBuildThreads), lds_build, s, (int)N, (int)k, seed, h.ptr, h.list,
-                     h.code16, h.ends, h.rbase, h.rlo, h.rhi);
+  hipLaunchKernelGGL(k_hash_build, dim3((unsigned)hash_chunks(N)), dim3(kBuildThreads), lds_build, s, (int)NC, (int)k,
+                     seed, h.ptr, h.list, h.code16, h.ends, h.rbase, h.rlo, h.rhi, h.bytes);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
 }
 
+// Rows past 16384 coordinates: for each block of rows, the four-step FFT
+// items into W, then the sampled values (SRCT) or all values into T and the
+// bucket sums (HRTT).
+static re_status launch_long(hipStream_t s, bool hash, const float* A, int64_t m, int64_t n, int64_t lda, int64_t k,
+                             const uint32_t* sign_bits, const HashScratch* h, const int32_t* sel, float sk, float* B,
+                             int64_t ldb, void* ws) {
+  const int64_t N = hrtt_npad(n), M = N / 2;
+  int lgN = 0;
+  while ((int64_t(1) << lgN) < N) ++lgN;
+  const int lgM = lgN - 1, lgM1 = lgM - kLongLgM2;
+  if (ws == nullptr) return RE_ERR_INVALID_ARG;
+  const int64_t R = long_rows(m, N, hash);
+  float2* W = (float2*)ws;
+  float* T = (float*)((char*)ws + (size_t)R * (size_t)M * sizeof(float2));
+  const bool vec = ((uintptr_t)A & 15) == 0 && (lda & 3) == 0;
+  const void* fn = vec ? (const void*)k_dct_long_fft<true> : (const void*)k_dct_long_fft<false>;
+  const size_t lds = (size_t)(kLongM2 + kLongM2 / 16 + 64 + kLongM2 / 64 + 256 + (M >> 8)) * sizeof(float2);
+  if (lds > 65536) RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int per = 0;
+  RE_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kRowThreads, lds));
+  int cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                               hipSuccess || cus <= 0)
+    cus = 256;
+  int64_t g = (int64_t)(per > 0 ? per : 1) * cus;
+  g = g < 8 ? 8 : g / 8 * 8;  // a multiple of 8 keeps a row's items on one XCD
+  const int chunks = (int)hash_chunks(N);
+  for (int64_t r0 = 0; r0 < m; r0 += R) {
+    int64_t rows = m - r0 < R ? m - r0 : R;
+    int lgMv = lgM;
+    const float* Ar = A + r0 * lda;
+    const int64_t items = ((rows + 7) / 8 * 8) << lgM1;
+    const unsigned grid = (unsigned)(items < g ? items : g);
+    void* args[] = {(void*)&Ar, (void*)&rows, (void*)&n, (void*)&lda, (void*)&lgMv, (void*)&sign_bits, (void*)&W};
+    RE_TRY_HIP(hipLaunchKernel(fn, dim3(grid), dim3(kRowThreads), args, lds, s));
+    const unsigned gy = (unsigned)((rows + 15) / 16);
+    if (!hash) {
+      hipLaunchKernelGGL(k_dct_long_sample, dim3((unsigned)cdiv(k, 256), gy), dim3(256), 0, s, (const float2*)W, rows,
+                         lgN, sel, k, sk, B + r0 * ldb, ldb);
+    } else {
+      hipLaunchKernelGGL(k_dct_long_values, dim3((unsigned)(N / 256), gy), dim3(256), 0, s, (const float2*)W, rows,
+                         lgN, T);
+      hipLaunchKernelGGL(k_dct_long_buckets, dim3((unsigned)cdiv(k, 256), (unsigned)rows), dim3(256), 0, s,
+                         (const float*)T, rows,
+                         N, chunks, (const int32_t*)h->ptr, (const uint16_t*)h->code16, h->bytes, k, sk,
+                         B + r0 * ldb, ldb);
+    }
+    RE_TRY_HIP(hipGetLastError());
+  }
+  return RE_OK;
+}
+
 re_status launch_hrtt_rows(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t lda, int64_t k,
-                           const uint32_t* sign_bits, const void* scratch, float* B, int64_t ldb) {
+                           const uint32_t* sign_bits, const void* scratch, float* B, int64_t ldb, void* ws) {
   const int64_t N = hrtt_npad(n);
-  if (N > kHrttMaxN || k < 1 || k > N) return RE_ERR_UNSUPPORTED;
-  const HashScratch h = carve_hash((void*)scratch, N, k);
+  if (!dct_x_supported(n, k, true)) return RE_ERR_UNSUPPORTED;
+  const HashScratch h = carve_hash((void*)scratch, hash_chunk(N), k);
+  if (N > kHrttMaxN) return launch_long(s, true, A, m, n, lda, k, sign_bits, &h, nullptr, sqrtf((float)k), B, ldb, ws);
   return launch_rows(s, true, A, m, n, lda, k, sign_bits, &h, nullptr, sqrtf((float)k), B, ldb);
 }
 
 re_status launch_srct_rows(hipStream_t s, const float* A, int64_t m, int64_t n, int64_t lda, int64_t k,
-                           const uint32_t* sign_bits, const int32_t* sel, float* B, int64_t ldb) {
+                           const uint32_t* sign_bits, const int32_t* sel, float* B, int64_t ldb, void* ws) {
   const int64_t N = hrtt_npad(n);
-  if (N > kHrttMaxN || k < 1 || k > N) return RE_ERR_UNSUPPORTED;
+  if (!dct_x_supported(n, k, false)) return RE_ERR_UNSUPPORTED;
+  if (N > kHrttMaxN) return launch_long(s, false, A, m, n, lda, k, sign_bits, nullptr, sel, sqrtf((float)N), B, ldb, ws);
   return launch_rows(s, false, A, m, n, lda, k, sign_bits, nullptr, sel, sqrtf((float)N), B, ldb);
 }
 

@@ -91,9 +91,13 @@ def test_repeatable_and_errors():
     with pytest.raises(re_.RankEstError) as e:
         re_.sketch_x(A.double(), k=10, x="hrtt")
     assert e.value.status == re_._binding.RE_ERR_UNSUPPORTED
-    W = torch.zeros(4, 16385, device=DEV)
+    W = torch.zeros(2, (1 << 20) + 1, device=DEV)  # N = 2^21: past the longest transform
     with pytest.raises(re_.RankEstError) as e:
         re_.sketch_x(W, k=10, x="hrtt")
+    assert e.value.status == re_._binding.RE_ERR_UNSUPPORTED
+    W = torch.zeros(2, 20000, device=DEV)  # chunked bucket lists hold at most 16384 buckets
+    with pytest.raises(re_.RankEstError) as e:
+        re_.sketch_x(W, k=16385, x="hrtt")
     assert e.value.status == re_._binding.RE_ERR_UNSUPPORTED
     with pytest.raises(re_.RankEstError) as e:
         re_.rank_estimate(A, 1e-3, k=10, x="hrtt", precision="bf16")
@@ -182,3 +186,60 @@ def test_dct_kinds_full_size_sampled_rows(orc, x):
         tol = np.array([_srct_tol(n, float(np.linalg.norm(a))) for a in An.astype(np.float64)])
     err = np.linalg.norm(got - want, axis=1)
     assert np.all(err <= tol), float(np.max(err / tol))
+
+
+# --- rows past 16384 coordinates: the four-step split M = M1 x 8192 ---------------------------
+# The M1-term bracket sums (M1 - 1 additions and a table twiddle of at most 2 ulp
+# per term, normwise (M1 + 8) u32 relative) come on top of the FFT's bound, so
+# the per-row tolerances take 6 lg N + 14 + M1 in place of 6 lg N + 6.
+
+def _long_levels(N):
+    M1 = max(1, N // 2 // 8192)
+    return 6 * math.log2(N) + 14 + M1
+
+
+@pytest.mark.parametrize("m,n,k,off", [(24, 20000, 384, 0), (16, 32768, 512, 0), (8, 65536, 300, 0),
+                                       (5, 70000, 100, 0), (6, 131072, 2000, 0), (7, 40000, 64, 1),
+                                       (70, 600000, 40, 0)])
+def test_srct_long_rows_match_oracle(orc, m, n, k, off):
+    """(70, 600000): N = 2^20, two passes of rows through the workspace; off = 1:
+    a row stride and pointer off the 16-byte grid (clamped scalar loads)."""
+    S = inputs.gaussian(m, n + off, 500 + n, torch.float32)
+    A = S[:, off:off + n]
+    seed = 31 + k
+    Bg = re_.sketch_x(S.to(DEV)[:, off:off + n], k=k, x="srct", seed=seed).cpu().numpy().astype(np.float64)
+    Bo = orc.hrtt.apply_x_srct(np.ascontiguousarray(A.numpy()), k, seed=seed)
+    N = orc.hrtt.npad(n)
+    err = np.linalg.norm(Bg - Bo, axis=1)
+    tol = math.sqrt(N) * _long_levels(N) * U32 * np.linalg.norm(A.double().numpy(), axis=1)
+    assert np.all(err <= tol), float(np.max(err / tol))
+
+
+@pytest.mark.parametrize("m,n,k,off", [(24, 20000, 384, 0), (12, 65536, 1000, 0), (5, 100000, 64, 0),
+                                       (9, 40000, 333, 2), (3, 32768, 16384, 0)])
+def test_hrtt_long_rows_match_oracle(orc, m, n, k, off):
+    S = inputs.gaussian(m, n + off, 700 + n, torch.float32)
+    A = S[:, off:off + n]
+    seed = 41 + k
+    Bg = re_.sketch_x(S.to(DEV)[:, off:off + n], k=k, x="hrtt", seed=seed).cpu().numpy().astype(np.float64)
+    Bo = orc.hrtt.apply_x(np.ascontiguousarray(A.numpy()), k, seed=seed)
+    N = orc.hrtt.npad(n)
+    b, _ = orc.hrtt.hash_table(seed, N, k)
+    bmax = int(np.bincount(b, minlength=k).max())
+    err = np.linalg.norm(Bg - Bo, axis=1)
+    tol = (math.sqrt(k) * (math.sqrt(bmax) * _long_levels(N) + bmax ** 1.5) * U32
+           * np.linalg.norm(A.double().numpy(), axis=1))
+    assert np.all(err <= tol), float(np.max(err / tol))
+
+
+def test_long_rows_repeatable_and_rank_on_a_gap(orc):
+    """Bit-identical repeats, and the rank of a planted gap through both DCT kinds at n = 65536."""
+    m, n, r = 600, 65536, 12
+    s = np.concatenate([np.ones(r), 1e-7 * np.ones(64 - r)])
+    A = inputs.planted(m, n, s, 3, torch.float32, 0.0, DEV)
+    for x in ("srct", "hrtt"):
+        b1 = re_.sketch_x(A, k=48, x=x, seed=7)
+        b2 = re_.sketch_x(A, k=48, x=x, seed=7)
+        assert torch.equal(b1, b2)
+        rk, sig, _ = re_.rank_estimate(A, 1e-4, k=48, l=72, x=x, seed=7)
+        assert rk == r, (x, rk, sig[:16])
