@@ -747,7 +747,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--loop-blocks", type=int, default=256, help="c4: blocks timed through the single-matrix call")
     ap.add_argument("--cpu-blocks", type=int, default=12, help="c4: blocks in the oracle's timed sample")
-    ap.add_argument("--inflight", type=int, default=2,
+    ap.add_argument("--inflight", type=int, default=4,
                     help="single-matrix workloads: estimates in flight (one handle, HIP stream and host thread each; "
                          "the value is their joint throughput, one-at-a-time figures are reported beside it)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -821,12 +821,15 @@ def main():
     elapsed1 = time.perf_counter() - t0
     # the same steps with nfl estimates in flight: thread t runs steps t, t + nfl, ...
     ranks_fl = [None] * args.steps
+    relaunched = [0] * args.steps
     errors = []
 
     def worker(t):
         try:
             for i in range(t, args.steps, nfl):
-                ranks_fl[i] = step(i, t)[0]
+                r, _, info = step(i, t)
+                ranks_fl[i] = r
+                relaunched[i] = int(bool(info["flags"] & re_.FLAG_SVD_RELAUNCHED))
         except Exception as exc:  # surfaced after the join
             errors.append(exc)
 
@@ -878,6 +881,7 @@ def main():
         "roofline": roof,
         "stage_ms": st_mean,
         "one_in_flight": {"value": args.steps / elapsed1, "ms_per_step": 1e3 * elapsed1 / args.steps},
+        "svd_relaunched": sum(relaunched),
     }
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -13,6 +13,7 @@ from ._binding import (  # noqa: F401
     FLAG_USED_FP16,
     FLAG_COLUMNS_DROPPED,
     FLAG_PREC_BELOW_FLOOR,
+    FLAG_SVD_RELAUNCHED,
     FLAG_ZERO,
     Handle,
     close_all_handles,

@@ -32,6 +32,7 @@ KIND = {"gaussian": RE_GAUSSIAN, "srht": RE_SRHT, "hrtt": RE_HRTT, "srct": RE_SR
 FLAG_NOT_CONVERGED, FLAG_ZERO, FLAG_PREC_FALLBACK, FLAG_USED_BF16, FLAG_USED_FP16 = 1, 2, 4, 8, 16
 FLAG_COLUMNS_DROPPED = 32
 FLAG_PREC_BELOW_FLOOR = 64
+FLAG_SVD_RELAUNCHED = 128
 MAX_ADAPTIVE_K = 5120  # RE_MAX_ADAPTIVE_K
 FMT = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 FMT_DTYPE = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float16}

@@ -46,6 +46,7 @@ struct re_handle_s {
   // re_set_limits: cap on each workspace (0: none) and the small SVD's barrier polls (0: default)
   size_t ws_cap = 0;
   long spin_limit = 0;
+  bool relaunched = false;  // the last estimate's small SVD was run again cooperatively
   int xcd = 0;  // XCD of the multi-workgroup small SVD: handles created in turn take XCDs in turn
 };
 
@@ -414,10 +415,25 @@ RE_API re_status re_gap_rank(const double* sigma, int32_t k, int32_t r1, int32_t
 namespace re {
 namespace {
 
+// Estimates of the plain method between their launch and their final
+// synchronisation, over all handles of the process.  Up to kPlainInFlight of
+// them let the small SVD take the plain launch (see launch_svd): with more,
+// a steady stream of other estimates' kernels could keep its late
+// participants waiting, and the cooperative form is used.
+std::atomic<int> g_in_flight{0};
+constexpr int kPlainInFlight = 4;
+
+struct InFlight {
+  int n;
+  InFlight() : n(g_in_flight.fetch_add(1) + 1) {}
+  ~InFlight() { g_in_flight.fetch_sub(1); }
+};
+
 // One pass of Algorithm 1 with the formats in rs; results left in the
 // handle's pinned staging buffer (16 bytes of r, flags, status; then sigma).
 re_status run_once(re_handle h, const Plan& p, const void* A, int32_t dt, int64_t m, int64_t n, int64_t lda,
                    double eps, const Resolved& rs, uint64_t seed) {
+  const InFlight fl;
   void* B = at(h, p.B);
   double* C = (double*)at(h, p.C);
   double* sigma = (double*)at(h, p.sigma);
@@ -430,7 +446,9 @@ re_status run_once(re_handle h, const Plan& p, const void* A, int32_t dt, int64_
   RE_TRY(run_y(h, p, B, dt, m, rs, seed, C));
   const double scale = 1.0 / sqrt((double)rs.k * (double)rs.l);
   mark(h, RE_STAGE_SVD);
-  RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info, h->spin_limit, h->xcd));
+  bool plain = false;
+  RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info, h->spin_limit, h->xcd,
+                    fl.n <= kPlainInFlight, &plain));
   mark(h, RE_STAGE_RANK);
   RE_TRY(launch_rank_count(h->stream, sigma, rs.k, r1, eps, info, out3));
   char* host = (char*)h->host;
@@ -438,6 +456,16 @@ re_status run_once(re_handle h, const Plan& p, const void* A, int32_t dt, int64_
   RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)rs.k * 8, hipMemcpyDeviceToHost, h->stream));
   mark(h, RE_NUM_STAGES);
   RE_TRY_HIP(hipStreamSynchronize(h->stream));
+  if (plain && ((const int32_t*)host)[2] == RE_ERR_NO_CONVERGENCE) {
+    // a participant of the plain launch waited past its poll limit: the same
+    // step again, cooperative (C is intact; the SVD starts from it afresh)
+    RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info, h->spin_limit, h->xcd));
+    RE_TRY(launch_rank_count(h->stream, sigma, rs.k, r1, eps, info, out3));
+    RE_TRY_HIP(hipMemcpyAsync(host, out3, 16, hipMemcpyDeviceToHost, h->stream));
+    RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)rs.k * 8, hipMemcpyDeviceToHost, h->stream));
+    RE_TRY_HIP(hipStreamSynchronize(h->stream));
+    h->relaunched = true;
+  }
   if (h->prof) {
     for (int i = 0; i < RE_NUM_STAGES; ++i) {
       float ms = 0.f;
@@ -466,6 +494,7 @@ RE_API re_status re_rank_estimate(re_handle h, const void* A, int32_t dt, int64_
   RE_TRY(ensure_host(h, (size_t)rs.k * 8 + 64));
   const char* host = (const char*)h->host;
   uint32_t extra = 0;
+  h->relaunched = false;
   if (sk->prec == RE_PREC_NATIVE) {
     RE_TRY(run_once(h, p, A, dt, m, n, lda, eps, rs, seed));
   } else {
@@ -514,6 +543,7 @@ RE_API re_status re_rank_estimate(re_handle h, const void* A, int32_t dt, int64_
   *r_out = o3[0];
   memcpy(sigma_out, host + 64, (size_t)rs.k * 8);
   if (r1_out) *r1_out = r1_from_k((int32_t)rs.k);
+  if (h->relaunched) extra |= RE_FLAG_SVD_RELAUNCHED;
   if (flags_out) *flags_out = (uint32_t)o3[1] | extra;
   return RE_OK;
 }

@@ -14,6 +14,8 @@
 // of u ||C|| of its exact value.
 #include <stdlib.h>
 
+#include <string.h>
+
 #include "common.h"
 #include "batch.h"
 
@@ -1486,8 +1488,41 @@ namespace {
 // one workgroup per CU, so on a device not filled by other work they are
 // resident together as well, and otherwise the bounded barrier wait ends the
 // call with RE_ERR_NO_CONVERGENCE rather than a hang.
-re_status launch_grid(const void* fn, dim3 grid, dim3 block, void** params, unsigned lds, hipStream_t s) {
-  if (hipLaunchCooperativeKernel(fn, grid, block, params, lds, s) == hipSuccess) return RE_OK;
+// Launch form of the multi-workgroup kernels, whose participants wait for one
+// another at grid barriers.  The cooperative form guarantees that they are
+// resident together, but this runtime runs cooperative kernels one at a time
+// (also across streams), so estimates in flight on other streams cannot
+// overlap their small SVDs.  Where the caller allows it, the form pinned to
+// one XCD with at most 16 participants (one workgroup per CU; XCDs handed to
+// handles in turn) takes a plain launch instead.  The other kernels never wait
+// on it, so its participants do become resident, but under a steady stream of
+// other kernels a late participant can wait long for a free CU: the plain form
+// therefore polls at most 2^15 times per barrier (tens of milliseconds,
+// far above a column step's microseconds), and its caller redoes a give-up
+// with the cooperative form.  RANKEST_SVD_LAUNCH=coop or =plain forces one
+// form for every launch (for comparisons).
+static int svd_launch_override() {
+  static const int v = [] {
+    const char* e = getenv("RANKEST_SVD_LAUNCH");
+    if (!e) return 0;
+    return strcmp(e, "coop") == 0 ? 1 : strcmp(e, "plain") == 0 ? 2 : 0;
+  }();
+  return v;
+}
+
+// RANKEST_SVD_PLAIN_POLLS overrides the plain form's poll limit (a negative
+// value gives up at the first poll: a test of the cooperative redo).
+static long plain_polls() {
+  static const long v = [] {
+    const char* e = getenv("RANKEST_SVD_PLAIN_POLLS");
+    return e ? atol(e) : (1l << 15);
+  }();
+  return v;
+}
+
+re_status launch_grid(const void* fn, dim3 grid, dim3 block, void** params, unsigned lds, hipStream_t s,
+                      bool plain = false) {
+  if (!plain && hipLaunchCooperativeKernel(fn, grid, block, params, lds, s) == hipSuccess) return RE_OK;
   (void)hipGetLastError();
   RE_TRY_HIP(hipLaunchKernel(fn, grid, block, params, lds, s));
   return RE_OK;
@@ -1495,7 +1530,8 @@ re_status launch_grid(const void* fn, dim3 grid, dim3 block, void** params, unsi
 }  // namespace
 
 re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, double scale, void* scratch,
-                     double* sigma, int32_t* info, long spin_limit, int xcd) {
+                     double* sigma, int32_t* info, long spin_limit, int xcd, bool allow_plain, bool* used_plain) {
+  if (used_plain) *used_plain = false;
   if (k <= 0) return RE_OK;
   const long spins = spin_limit == 0 ? (1l << 26) : spin_limit;
   if (k > l) return RE_ERR_INVALID_ARG;
@@ -1562,8 +1598,12 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
                                     : (const void*)k_bidiag_reg<16, 512>;
     if (rp.bytes > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rp.bytes));
+    const int ov = svd_launch_override();
+    const bool plain = ov == 2 || (ov == 0 && allow_plain && b2.xstride == 8 && rp.P <= 16);
+    if (plain && spin_limit == 0) b2.spin_limit = plain_polls();
+    if (used_plain) *used_plain = plain;
     void* params2[] = {&b2};
-    RE_TRY(launch_grid(fn, dim3(rp.P * b2.xstride), dim3(rp.nt), params2, (unsigned)rp.bytes, s));
+    RE_TRY(launch_grid(fn, dim3(rp.P * b2.xstride), dim3(rp.nt), params2, (unsigned)rp.bytes, s, plain));
   } else if (lp.P > 0) {
     Bidiag2Args b2;
     b2.C = C;
@@ -1585,7 +1625,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     if (lp.bytes > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp.bytes));
     void* params2[] = {&b2};
-    RE_TRY(launch_grid(fn, dim3(lp.P), dim3(kB2Threads), params2, (unsigned)lp.bytes, s));
+    RE_TRY(launch_grid(fn, dim3(lp.P), dim3(kB2Threads), params2, (unsigned)lp.bytes, s, svd_launch_override() == 2));
   } else if (k <= 48 * 64 && !svd_legacy_global()) {
     // rows in registers: 32 or 48 columns per lane
     const bool t32 = k <= 32 * 64;
@@ -1602,14 +1642,14 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     if (P < 1) return RE_ERR_UNSUPPORTED;
     a.P = (int)P;
     void* params[] = {&a};
-    RE_TRY(launch_grid(fn, dim3(a.P), dim3(kBidiagThreads), params, (unsigned)lds, s));
+    RE_TRY(launch_grid(fn, dim3(a.P), dim3(kBidiagThreads), params, (unsigned)lds, s, svd_launch_override() == 2));
   } else {
     const size_t lds = (size_t)(2 * (k + 1) + kWaves * kPartChunk) * 8;
     if (lds > 160 * 1024) return RE_ERR_UNSUPPORTED;
     if (lds > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     void* params[] = {&a};
-    RE_TRY(launch_grid((const void*)k_bidiag, dim3(a.P), dim3(kBidiagThreads), params, (unsigned)lds, s));
+    RE_TRY(launch_grid((const void*)k_bidiag, dim3(a.P), dim3(kBidiagThreads), params, (unsigned)lds, s, svd_launch_override() == 2));
   }
   const size_t lds2 = (size_t)(4 * k) * 8;
   if (lds2 > 160 * 1024) return RE_ERR_UNSUPPORTED;

@@ -135,3 +135,67 @@ def test_small_svd_in_a_second_process_while_this_one_holds_the_device():
     assert r.returncode == 0, r.stderr[-2000:]
     s_there = np.array(json.loads(r.stdout.strip().splitlines()[-1]))
     assert np.array_equal(s_there, s_here)
+
+
+def test_estimates_in_flight_on_several_streams_match_one_at_a_time():
+    """Handles on their own streams and host threads, their multi-workgroup
+    small SVDs (576 x 384, pinned to the handles' XCDs, plain launches) running
+    side by side: every estimate equals the same estimate run alone."""
+    import threading
+    A = _matrix(8192, 2048, 21)
+    seeds = list(range(100, 112))
+    ref = {}
+    h0 = re_.Handle()
+    for sd in seeds:
+        ref[sd] = re_.rank_estimate(A, 1e-3, k=384, l=576, x="srht", y="srht", seed=sd, handle=h0)
+    torch.cuda.synchronize()
+    n = 4
+    hs = [re_.Handle() for _ in range(n)]
+    sts = [torch.cuda.Stream() for _ in range(n)]
+    got = [dict() for _ in range(n)]
+    errs = []
+
+    def work(t):
+        try:
+            with torch.cuda.stream(sts[t]):
+                for sd in seeds[t::n]:
+                    got[t][sd] = re_.rank_estimate(A, 1e-3, k=384, l=576, x="srht", y="srht", seed=sd, handle=hs[t])
+        except Exception as e:  # reported below, on the main thread
+            errs.append(e)
+
+    th = [threading.Thread(target=work, args=(t,)) for t in range(n)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    torch.cuda.synchronize()
+    assert not errs, errs
+    for t in range(n):
+        for sd, (r, s, _) in got[t].items():
+            assert r == ref[sd][0] and np.array_equal(s, ref[sd][1]), sd
+
+
+def test_plain_svd_give_up_is_redone_cooperatively():
+    """A plain-launched small SVD whose barrier gives up (forced here: a poll
+    limit below zero for the plain form, set before the library loads, in a
+    child process) is run again with the cooperative form: same estimate, and
+    the flag says so."""
+    import json
+    import os
+    import subprocess
+    import sys
+    A = _matrix(4096, 1024, 22)
+    r0, s0, info0 = re_.rank_estimate(A, 1e-3, k=384, l=576, x="srht", y="srht", seed=8, handle=re_.Handle())
+    assert not info0["flags"] & re_.FLAG_SVD_RELAUNCHED
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys, json, numpy as np; sys.path.insert(0, %r); import paper_2105_07388_amd as re_; "
+            "from paper_2105_07388_amd import inputs; "
+            "s = np.geomspace(1.0, 1e-6, 1024); A = inputs.planted(4096, 1024, s, 22, __import__('torch').float32, 0.0, 'cuda'); "
+            "r, sig, info = re_.rank_estimate(A, 1e-3, k=384, l=576, x='srht', y='srht', seed=8); "
+            "print(json.dumps([r, sig.tolist(), info['flags']]))" % root)
+    env = dict(os.environ, RANKEST_SVD_PLAIN_POLLS="-1")
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, env=env)
+    assert res.returncode == 0, res.stderr[-2000:]
+    r1, s1, fl = json.loads(res.stdout.strip().splitlines()[-1])
+    assert fl & re_.FLAG_SVD_RELAUNCHED
+    assert r1 == r0 and np.array_equal(np.array(s1), s0)
