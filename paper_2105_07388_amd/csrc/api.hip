@@ -47,7 +47,7 @@ struct re_handle_s {
   size_t ws_cap = 0;
   long spin_limit = 0;
   bool relaunched = false;  // the last estimate's small SVD was run again cooperatively
-  int xcd = 0;  // XCD of the multi-workgroup small SVD: handles created in turn take XCDs in turn
+  int xcd = 7;  // XCD of the multi-workgroup small SVD: handles created in turn take XCDs 7, 6, ..., 0 in turn
 };
 
 namespace re {
@@ -336,8 +336,11 @@ RE_API re_status re_create(re_handle* h, void* hip_stream) {
     return RE_ERR_HIP;
   }
   p->stream = (hipStream_t)hip_stream;
+  // XCDs in turn from the last one down: workgroup 0 of every launch, and so
+  // every one-workgroup kernel of every stream, runs on XCD 0, which the
+  // small SVDs of up to seven handles thus avoid
   static std::atomic<unsigned> next_xcd{0};
-  p->xcd = (int)(next_xcd.fetch_add(1, std::memory_order_relaxed) & 7u);
+  p->xcd = (int)(7u - (next_xcd.fetch_add(1, std::memory_order_relaxed) & 7u));
   *h = p;
   return RE_OK;
 }
@@ -491,7 +494,7 @@ RE_API re_status re_rank_estimate(re_handle h, const void* A, int32_t dt, int64_
   rs.lowprec = sk->prec != RE_PREC_NATIVE;
   const Plan p = plan(dt, m, n, rs);
   RE_TRY(ensure_ws(h, p.total));
-  RE_TRY(ensure_host(h, (size_t)rs.k * 8 + 64));
+  RE_TRY(ensure_host(h, (size_t)rs.k * 8 + 64 + 32));  // r, flags, status; sigma; the sampled statistics
   const char* host = (const char*)h->host;
   uint32_t extra = 0;
   h->relaunched = false;
@@ -501,8 +504,8 @@ RE_API re_status re_rank_estimate(re_handle h, const void* A, int32_t dt, int64_
     // sampled ||A||_F^2 and max |a|: FP16 scale and the AUTO acceptance test
     double* st = (double*)at(h, p.stats);
     RE_TRY(launch_sample_stats(h->stream, (const float*)A, m, n, lda, st));
-    double stats[3];
-    RE_TRY_HIP(hipMemcpyAsync(stats, st, sizeof(stats), hipMemcpyDeviceToHost, h->stream));
+    double* stats = (double*)((char*)h->host + 64 + (size_t)rs.k * 8);  // pinned: the copy stays asynchronous
+    RE_TRY_HIP(hipMemcpyAsync(stats, st, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     RE_TRY_HIP(hipStreamSynchronize(h->stream));
     const double frob = sqrt(stats[0] * ((double)m * (double)n / (stats[2] > 0 ? stats[2] : 1.0)));
     const double amax = stats[1];
@@ -1540,8 +1543,9 @@ RE_API re_status re_sketch_x(re_handle h, const void* A, int32_t dt, int64_t m, 
   if (rs.fmt_x == kF16) {
     double* st = (double*)at(h, p.stats);
     RE_TRY(launch_sample_stats(h->stream, (const float*)A, m, n, lda, st));
-    double stats[3];
-    RE_TRY_HIP(hipMemcpyAsync(stats, st, sizeof(stats), hipMemcpyDeviceToHost, h->stream));
+    RE_TRY(ensure_host(h, 32));
+    double* stats = (double*)h->host;  // pinned: the copy stays asynchronous
+    RE_TRY_HIP(hipMemcpyAsync(stats, st, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     RE_TRY_HIP(hipStreamSynchronize(h->stream));
     if (stats[1] > 0.0) {
       int e2 = 0;

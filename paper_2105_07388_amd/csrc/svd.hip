@@ -1493,7 +1493,7 @@ namespace {
 // resident together, but this runtime runs cooperative kernels one at a time
 // (also across streams), so estimates in flight on other streams cannot
 // overlap their small SVDs.  Where the caller allows it, the form pinned to
-// one XCD with at most 16 participants (one workgroup per CU; XCDs handed to
+// one XCD (at most 32 participants, one workgroup per CU; XCDs handed to
 // handles in turn) takes a plain launch instead.  The other kernels never wait
 // on it, so its participants do become resident, but under a steady stream of
 // other kernels a late participant can wait long for a free CU: the plain form
@@ -1599,7 +1599,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     if (rp.bytes > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rp.bytes));
     const int ov = svd_launch_override();
-    const bool plain = ov == 2 || (ov == 0 && allow_plain && b2.xstride == 8 && rp.P <= 16);
+    const bool plain = ov == 2 || (ov == 0 && allow_plain && b2.xstride == 8);
     if (plain && spin_limit == 0) b2.spin_limit = plain_polls();
     if (used_plain) *used_plain = plain;
     void* params2[] = {&b2};
