@@ -96,8 +96,9 @@ enum {
   RE_FLAG_PREC_BELOW_FLOOR = 64u, /* a forced BF16 / FP16 contraction: its error floor phi_f exceeds eps*sigma_1/4, so
                                     estimates near the threshold are not resolved (AUTO would have moved on) */
   RE_FLAG_SVD_RELAUNCHED = 128u  /* re_rank_estimate: the small SVD, launched without the cooperative form so
-                                    that estimates on other streams could overlap it, waited past its poll limit
-                                    for a free CU and was run again cooperatively (same result, more time) */
+                                    that estimates on other streams could overlap it, waited past its short poll
+                                    limit for a free CU and was run again with the default limit (same result,
+                                    more time) */
 };
 
 typedef struct re_handle_s* re_handle;

@@ -451,7 +451,7 @@ re_status run_once(re_handle h, const Plan& p, const void* A, int32_t dt, int64_
   mark(h, RE_STAGE_SVD);
   bool plain = false;
   RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info, h->spin_limit, h->xcd,
-                    fl.n <= kPlainInFlight, &plain));
+                    fl.n <= kPlainInFlight ? 1 : 0, &plain));
   mark(h, RE_STAGE_RANK);
   RE_TRY(launch_rank_count(h->stream, sigma, rs.k, r1, eps, info, out3));
   char* host = (char*)h->host;
@@ -460,9 +460,10 @@ re_status run_once(re_handle h, const Plan& p, const void* A, int32_t dt, int64_
   mark(h, RE_NUM_STAGES);
   RE_TRY_HIP(hipStreamSynchronize(h->stream));
   if (plain && ((const int32_t*)host)[2] == RE_ERR_NO_CONVERGENCE) {
-    // a participant of the plain launch waited past its poll limit: the same
-    // step again, cooperative (C is intact; the SVD starts from it afresh)
-    RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info, h->spin_limit, h->xcd));
+    // a participant of the plain launch waited past its short poll limit: the
+    // same step again, plain under the default limit (C is intact; the SVD
+    // starts from it afresh)
+    RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info, h->spin_limit, h->xcd, 2));
     RE_TRY(launch_rank_count(h->stream, sigma, rs.k, r1, eps, info, out3));
     RE_TRY_HIP(hipMemcpyAsync(host, out3, 16, hipMemcpyDeviceToHost, h->stream));
     RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)rs.k * 8, hipMemcpyDeviceToHost, h->stream));

@@ -166,12 +166,12 @@ RE_HIDDEN size_t svd_scratch_bytes(int64_t l, int64_t k);
 // eight) that holds the workgroups of the multi-workgroup bidiagonalisation,
 // so that sketches of different streams need not share one.  allow_plain:
 // the bidiagonalisation pinned to one XCD may take a plain launch (the
-// cooperative form runs one kernel at a time device-wide); *used_plain (if
-// given) tells whether it did, so that a caller can redo a give-up with the
-// cooperative form (C is left untouched).
+// cooperative form runs one kernel at a time device-wide), 1 with a short
+// barrier poll limit, 2 with the default one; *used_plain (if given) tells
+// whether it did, so that a caller can redo a give-up (C is left untouched).
 RE_HIDDEN re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, double scale, void* scratch,
                                double* sigma, int32_t* info, long spin_limit = 0, int xcd = 0,
-                               bool allow_plain = false, bool* used_plain = nullptr);
+                               int allow_plain = 0, bool* used_plain = nullptr);
 RE_HIDDEN re_status launch_rank_count(hipStream_t s, const double* sigma, int64_t k, int32_t r1, double eps,
                                       const int32_t* info, int32_t* out3);
 // Gap statistics of descending estimates (search without a tolerance).

@@ -1499,7 +1499,9 @@ namespace {
 // other kernels a late participant can wait long for a free CU: the plain form
 // therefore polls at most 2^15 times per barrier (tens of milliseconds,
 // far above a column step's microseconds), and its caller redoes a give-up
-// with the cooperative form.  RANKEST_SVD_LAUNCH=coop or =plain forces one
+// with a plain launch under the default limit (not the cooperative form:
+// processes that mixed cooperative launches into plain ones in flight on
+// other streams ended with a segmentation fault at exit).  RANKEST_SVD_LAUNCH=coop or =plain forces one
 // form for every launch (for comparisons).
 static int svd_launch_override() {
   static const int v = [] {
@@ -1530,7 +1532,7 @@ re_status launch_grid(const void* fn, dim3 grid, dim3 block, void** params, unsi
 }  // namespace
 
 re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, double scale, void* scratch,
-                     double* sigma, int32_t* info, long spin_limit, int xcd, bool allow_plain, bool* used_plain) {
+                     double* sigma, int32_t* info, long spin_limit, int xcd, int allow_plain, bool* used_plain) {
   if (used_plain) *used_plain = false;
   if (k <= 0) return RE_OK;
   const long spins = spin_limit == 0 ? (1l << 26) : spin_limit;
@@ -1599,8 +1601,8 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     if (rp.bytes > 64 * 1024)
       RE_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rp.bytes));
     const int ov = svd_launch_override();
-    const bool plain = ov == 2 || (ov == 0 && allow_plain && b2.xstride == 8);
-    if (plain && spin_limit == 0) b2.spin_limit = plain_polls();
+    const bool plain = ov == 2 || (ov == 0 && allow_plain != 0 && b2.xstride == 8);
+    if (plain && spin_limit == 0 && allow_plain == 1) b2.spin_limit = plain_polls();
     if (used_plain) *used_plain = plain;
     void* params2[] = {&b2};
     RE_TRY(launch_grid(fn, dim3(rp.P * b2.xstride), dim3(rp.nt), params2, (unsigned)rp.bytes, s, plain));

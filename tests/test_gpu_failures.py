@@ -175,11 +175,11 @@ def test_estimates_in_flight_on_several_streams_match_one_at_a_time():
             assert r == ref[sd][0] and np.array_equal(s, ref[sd][1]), sd
 
 
-def test_plain_svd_give_up_is_redone_cooperatively():
-    """A plain-launched small SVD whose barrier gives up (forced here: a poll
-    limit below zero for the plain form, set before the library loads, in a
-    child process) is run again with the cooperative form: same estimate, and
-    the flag says so."""
+def test_plain_svd_give_up_is_redone():
+    """A plain-launched small SVD whose barrier gives up at its short poll limit
+    (forced here: a limit below zero, set before the library loads, in a child
+    process) is run again under the default limit: same estimate, and the flag
+    says so."""
     import json
     import os
     import subprocess
