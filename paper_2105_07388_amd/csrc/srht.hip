@@ -710,7 +710,14 @@ re_status launch_srht_rows(hipStream_t s, const void* A, int dtype, int64_t m, i
   const int grid = (int)(m < 8192 ? m : 8192);
   if (m <= 0) return RE_OK;
   if (dtype == RE_F32 && n == kN14 && lda % 4 == 0 && ((uintptr_t)A % 16) == 0 && k <= INT32_MAX) {
-    const int64_t g = 2 * (int64_t)num_cus();
+    // 32 workgroups per CU's worth (8192 on 256 CUs), each striding over the
+    // rows (8 rows apiece at m = 65536): against two per CU, each holding its
+    // CU for the whole pass, the pass itself is about 1 % faster and the
+    // kernels of estimates in flight on other streams find CUs as workgroups
+    // retire (joint rate 678 against 631 estimates/s at four in flight).
+    // RANKEST_N14W_GRID sets another workgroup count (tuning).
+    static const int64_t grid_env = getenv("RANKEST_N14W_GRID") ? atoll(getenv("RANKEST_N14W_GRID")) : 0;
+    const int64_t g = grid_env > 0 ? grid_env : 32 * (int64_t)num_cus();
     static const int variant = getenv("RANKEST_FWHT14") ? atoi(getenv("RANKEST_FWHT14")) : 1;
     if (variant == 1)
       hipLaunchKernelGGL(k_srht_rows_n14w, dim3((unsigned)(m < g ? m : g)), dim3(512), 0, s, (const float*)A, m, lda,
