@@ -276,6 +276,15 @@ __device__ __forceinline__ double ld_coh(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The exchange between participants goes only through agent-scope atomic
+// stores and loads (st_coh / ld_coh), which bypass the non-coherent caches;
+// a wave's vmcnt(0) waits for its stores' acknowledgements, so they are
+// visible device-wide before the workgroup barrier and the counter increment
+// that follows it, and the loads after the spin are issued only once the
+// counter has reached the target.  Release / acquire orders on the counter
+// would add an L2 writeback and invalidate per barrier: measured at 576 x 384,
+// 2.68 ms against 2.05 ms for the bidiagonalisation, and the rate of four
+// estimates in flight fell from 682 to 543 per second.
 __device__ bool grid_sync_coh(unsigned* bar, unsigned target, int32_t* info, long limit) {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's coherent stores are complete
   __syncthreads();
