@@ -158,25 +158,27 @@ def cpu_baseline(A_dev, w, rows: int):
     # shapes), threaded BLAS sgemm for the Gaussian products, LAPACK for the SVD.
     be_x, be_y = t_x, t_y
     rng = np.random.default_rng(0)
+    ft = np.float64 if A_s.dtype == np.float64 else np.float32  # the storage type of A, as the GPU path
+    gemm = "BLAS dgemm" if ft == np.float64 else "BLAS sgemm"
     if w["x"] == "gaussian":
-        X = rng.standard_normal((n, k), dtype=np.float32)
-        A32 = np.ascontiguousarray(A_s, dtype=np.float32)
+        X = rng.standard_normal((n, k)).astype(ft)
+        Af = np.ascontiguousarray(A_s, dtype=ft)
         t0 = time.perf_counter()
-        _ = A32 @ X
+        _ = Af @ X
         be_x = (time.perf_counter() - t0) * (m / rows)
     if w["y"] == "gaussian":
-        Y = rng.standard_normal((l, m), dtype=np.float32)
-        B32 = Bfull.astype(np.float32)
+        Y = rng.standard_normal((l, m)).astype(ft)
+        Bf = Bfull.astype(ft)
         t0 = time.perf_counter()
-        _ = Y @ B32
+        _ = Y @ Bf
         be_y = time.perf_counter() - t0
     t0 = time.perf_counter()
     np.linalg.svd(Cm, compute_uv=False)
     be_svd = time.perf_counter() - t0
     best = {"value": 1.0 / (be_x + be_y + be_svd), "unit": "rank estimates/s", "cores": oracle.num_threads(),
             "kind": "best_effort",
-            "sample": f"same sample; {'BLAS sgemm' if w['x'] == 'gaussian' else 'the oracle transform'} for A X, "
-                      f"{'BLAS sgemm' if w['y'] == 'gaussian' else 'the oracle transform'} for Y B, LAPACK SVD; "
+            "sample": f"same sample; {gemm if w['x'] == 'gaussian' else 'the oracle transform'} for A X, "
+                      f"{gemm if w['y'] == 'gaussian' else 'the oracle transform'} for Y B, LAPACK SVD; "
                       f"seconds: ax {be_x:.2f}, yb {be_y:.2f}, svd {be_svd:.3f}"}
     return {"value": 1.0 / total, "unit": "rank estimates/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"A X on the first {rows} of {m} rows scaled by {m / rows:g}, Y B on a full {m}x{k} B, "
