@@ -257,10 +257,51 @@ def bench_batched(args, w, dev):
     torch.cuda.synchronize()
     ranks = None
     t0 = time.perf_counter()
+    ranks_one = []
     for i in range(args.steps):  # graph replays
         ranks, _, _ = re_.rank_estimate_batched(table, eps, k=k, l=l, seed=1000003 * (i + 1), handle=h)
+        ranks_one.append(ranks.copy())
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed1 = time.perf_counter() - t0
+    # the same batches with several in flight: one handle (its own graph and
+    # workspace), HIP stream and host thread each, thread t running batches t,
+    # t + nfl, ...; the ranks must equal the one-at-a-time ranks batch by batch
+    nfl = max(1, args.inflight)
+    elapsed = elapsed1
+    if nfl > 1:
+        import threading
+        hs = [h] + [re_.Handle(dev) for _ in range(nfl - 1)]
+        sts = [torch.cuda.Stream(dev) for _ in range(nfl)]
+        for t in range(1, nfl):
+            with torch.cuda.stream(sts[t]):
+                re_.rank_estimate_batched(table, eps, k=k, l=l, seed=7, handle=hs[t])
+        ranks_fl = [None] * args.steps
+        errors = []
+
+        def worker(t):
+            try:
+                with torch.cuda.stream(sts[t]):
+                    for i in range(t, args.steps, nfl):
+                        r_i, _, _ = re_.rank_estimate_batched(table, eps, k=k, l=l, seed=1000003 * (i + 1),
+                                                              handle=hs[t])
+                        ranks_fl[i] = r_i.copy()
+            except Exception as exc:  # surfaced after the join
+                errors.append(exc)
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        threads = [threading.Thread(target=worker, args=(t,)) for t in range(nfl)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        if errors:
+            raise errors[0]
+        for i in range(args.steps):
+            if not np.array_equal(ranks_fl[i], ranks_one[i]):
+                raise RuntimeError(f"batch {i}: ranks with {nfl} in flight differ from one at a time")
     # stage times: the same launches issued directly with HIP events between them
     h.set_profiling(True)
     stages = []
@@ -305,11 +346,12 @@ def bench_batched(args, w, dev):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w["desc"], "nblocks": nb, "k": k, "l": l, "eps": [eps], "x": "gaussian",
-                   "y": "gaussian", "entries": mn, "parallelism": "single GPU"},
+                   "y": "gaussian", "entries": mn, "in_flight": nfl, "parallelism": "single GPU"},
         "roofline": roof,
         "stage_ms": st_mean,
         "per_block_loop": {"value": nb / t_loop, "unit": "rank estimates/s",
                            "sample": f"{nloop} blocks through the single-matrix call, scaled by total m*n"},
+        "one_in_flight": {"value": nb * args.steps / elapsed1, "ms_per_step": 1e3 * elapsed1 / args.steps},
     }
     if not args.no_cpu:
         print("[bench] timing the CPU oracle on a sample of blocks", file=sys.stderr, flush=True)
