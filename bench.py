@@ -73,6 +73,16 @@ WORKLOADS = {
                 desc="rank without a tolerance (Sec. 6.1): A_G of Sec. 6 (FP64 100000 x 100000 diagonal stored dense, "
                      "100 values each at 1, 1e-4, 1e-8, 1e-12, then 1e-16), Gaussian X from 110 columns, +100 per "
                      "round, subsampled randomized DCT Y (as Sec. 6.1) with l = 1.5 k, gap ratio 10, floor 1e-13"),
+    "srht_long": dict(m=16384, n=65536, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="srht", y="srht",
+                      desc="rows past 2^15 with an SRHT X: FP32 16384x65536, s_i=10^(-i/20) (R=1024) + 1e-9 "
+                           "noise, SRHT X 65536x384 (two chunks of 2^15 per row), SRHT Y 576x16384, eps 1e-3/1e-5"),
+    "srct_long": dict(m=16384, n=65536, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="srct", y="srht",
+                      desc="rows past 16384 with a subsampled DCT X: FP32 16384x65536, s_i=10^(-i/20) (R=1024) + "
+                           "1e-9 noise, SRCT X 65536x384 (four-step FFT, M1 = 4), SRHT Y 576x16384, eps 1e-3/1e-5"),
+    "hrtt_long": dict(m=16384, n=65536, R=1024, k=384, l=576, eps=(1e-3, 1e-5), x="hrtt", y="srht",
+                      desc="rows past 16384 with a hashed DCT X: FP32 16384x65536, s_i=10^(-i/20) (R=1024) + 1e-9 "
+                           "noise, HRTT X 65536x384 (four-step FFT, chunked bucket lists), SRHT Y 576x16384, "
+                           "eps 1e-3/1e-5"),
     "c1": dict(m=2000, n=1000, R=1000, k=40, l=60, eps=(1e-6,), x="gaussian", y="gaussian",
                desc="plain method, CPU-sized: FP64 2000x1000, step spectrum (20 x 1, then 1e-8), "
                     "Gaussian X 1000x40, Gaussian Y 60x2000, eps 1e-6"),
@@ -116,7 +126,7 @@ def make_matrix(name, w, device):
     import torch
 
     from paper_2105_07388_amd import inputs
-    if name in ("c2", "qr", "hrtt", "srct", "ady", "paper"):
+    if name in ("c2", "qr", "hrtt", "srct", "ady", "paper", "srht_long", "srct_long", "hrtt_long"):
         return inputs.c2_matrix(w["m"], w["n"], w["R"], device=device)
     if name == "c1":
         return inputs.c1_matrix(device=device)

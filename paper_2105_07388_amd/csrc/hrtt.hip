@@ -824,30 +824,44 @@ __global__ void __launch_bounds__(256) k_dct_long_values(const float2* __restric
   for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) T[i * N + j] = dct_value(W + i * M, d);
 }
 
-// HRTT, second part: B[i][b] = sk sum over the chunks c, in order, of the
-// bucket's list entries of chunk c (increasing coordinate), each T[i][c NC + j]
-// with its sign: the coordinates of bucket b in increasing order.
-__global__ void __launch_bounds__(256) k_dct_long_buckets(const float* __restrict__ T, int64_t rows, int64_t N,
-                                                         int chunks, const int32_t* __restrict__ ptr,
-                                                         const uint16_t* __restrict__ code16, size_t chunk_bytes,
-                                                         int64_t k, float sk, float* __restrict__ B, int64_t ldb) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= k) return;
+// HRTT, second part, one workgroup per row: each chunk of the row's values
+// (NC = 16384 coordinates, 64 KiB) is staged in LDS, every bucket sums its
+// list entries of that chunk (increasing coordinate, with their signs) and
+// adds the chunk's sum to its total in LDS, chunks in order; then
+// B[i][b] = sk * total.
+constexpr int kBucketThreads = 512;
+
+__global__ void __launch_bounds__(kBucketThreads) k_dct_long_buckets(const float* __restrict__ T, int64_t rows,
+                                                                    int64_t N, int chunks,
+                                                                    const int32_t* __restrict__ ptr,
+                                                                    const uint16_t* __restrict__ code16,
+                                                                    size_t chunk_bytes, int k, float sk,
+                                                                    float* __restrict__ B, int64_t ldb) {
   constexpr int NC = (int)kHrttMaxN;
-  for (int64_t i = blockIdx.y; i < rows; i += gridDim.y) {
-    const float* __restrict__ t = T + i * N;
-    float acc = 0.0f;
+  __shared__ __align__(16) float tl[NC];
+  __shared__ float acc[NC];  // k <= NC bucket totals
+  const int tid = threadIdx.x;
+  for (int64_t i = blockIdx.x; i < rows; i += gridDim.x) {
+    for (int b = tid; b < k; b += kBucketThreads) acc[b] = 0.0f;
     for (int c = 0; c < chunks; ++c) {
+      const float4* src = reinterpret_cast<const float4*>(T + i * N + (int64_t)c * NC);
+      for (int q = tid; q < NC / 4; q += kBucketThreads) reinterpret_cast<float4*>(tl)[q] = src[q];
+      __syncthreads();
       const int32_t* pc = (const int32_t*)((const char*)ptr + (size_t)c * chunk_bytes);
       const uint16_t* cc = (const uint16_t*)((const char*)code16 + (size_t)c * chunk_bytes);
-      const float* tc = t + (int64_t)c * NC;
-      for (int p = pc[b]; p < pc[b + 1]; ++p) {
-        const uint32_t e = cc[p];
-        const float x = tc[e & 0x3fffu];
-        acc += (e & 0x8000u) ? -x : x;
+      for (int b = tid; b < k; b += kBucketThreads) {
+        float part = 0.0f;
+        for (int p = pc[b]; p < pc[b + 1]; ++p) {
+          const uint32_t e = cc[p];
+          const float x = tl[e & 0x3fffu];
+          part += (e & 0x8000u) ? -x : x;
+        }
+        acc[b] += part;
       }
+      __syncthreads();
     }
-    B[i * ldb + b] = sk * acc;
+    for (int b = tid; b < k; b += kBucketThreads) B[i * ldb + b] = sk * acc[b];
+    __syncthreads();
   }
 }
 
@@ -1032,10 +1046,10 @@ static re_status launch_long(hipStream_t s, bool hash, const float* A, int64_t m
     } else {
       hipLaunchKernelGGL(k_dct_long_values, dim3((unsigned)(N / 256), gy), dim3(256), 0, s, (const float2*)W, rows,
                          lgN, T);
-      hipLaunchKernelGGL(k_dct_long_buckets, dim3((unsigned)cdiv(k, 256), (unsigned)rows), dim3(256), 0, s,
-                         (const float*)T, rows,
-                         N, chunks, (const int32_t*)h->ptr, (const uint16_t*)h->code16, h->bytes, k, sk,
-                         B + r0 * ldb, ldb);
+      const unsigned gb = (unsigned)(rows < 2 * (int64_t)cus ? rows : 2 * (int64_t)cus);
+      hipLaunchKernelGGL(k_dct_long_buckets, dim3(gb), dim3(kBucketThreads), 0, s, (const float*)T, rows, N, chunks,
+                         (const int32_t*)h->ptr, (const uint16_t*)h->code16, h->bytes, (int)k, sk, B + r0 * ldb,
+                         ldb);
     }
     RE_TRY_HIP(hipGetLastError());
   }
