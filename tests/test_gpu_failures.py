@@ -199,3 +199,45 @@ def test_plain_svd_give_up_is_redone():
     r1, s1, fl = json.loads(res.stdout.strip().splitlines()[-1])
     assert fl & re_.FLAG_SVD_RELAUNCHED
     assert r1 == r0 and np.array_equal(np.array(s1), s0)
+
+
+def test_mixed_sketch_kinds_in_flight_match_one_at_a_time():
+    """Four handles in flight, each running a different sketch pair (SRHT,
+    BF16 Gaussian X with an SRHT Y, hashed DCT X with a subsampled DCT Y,
+    subsampled DCT X), every multi-workgroup small SVD on a plain launch:
+    each estimate equals the same estimate run alone, bit for bit."""
+    import threading
+    A = _matrix(8192, 4096, 23)
+    kinds = [dict(x="srht", y="srht"), dict(x="gaussian", y="srht", precision="bf16"),
+             dict(x="hrtt", y="srct"), dict(x="srct", y="srht")]
+    eps = 1e-2
+    ref = {}
+    h0 = re_.Handle()
+    for t, kw in enumerate(kinds):
+        for sd in range(3):
+            ref[(t, sd)] = re_.rank_estimate(A, eps, k=384, l=576, seed=50 + sd, handle=h0, **kw)
+    torch.cuda.synchronize()
+    hs = [re_.Handle() for _ in kinds]
+    sts = [torch.cuda.Stream() for _ in kinds]
+    got = {}
+    errs = []
+
+    def work(t):
+        try:
+            with torch.cuda.stream(sts[t]):
+                for sd in range(3):
+                    got[(t, sd)] = re_.rank_estimate(A, eps, k=384, l=576, seed=50 + sd, handle=hs[t], **kinds[t])
+        except Exception as e:  # reported below, on the main thread
+            errs.append(e)
+
+    th = [threading.Thread(target=work, args=(t,)) for t in range(len(kinds))]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    torch.cuda.synchronize()
+    assert not errs, errs
+    for key, (r, s, info) in got.items():
+        r0, s0, info0 = ref[key]
+        assert r == r0 and np.array_equal(s, s0), key
+        assert info["flags"] & ~re_.FLAG_SVD_RELAUNCHED == info0["flags"] & ~re_.FLAG_SVD_RELAUNCHED, key
