@@ -959,27 +959,8 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_1wg(SmallBatch sb) {
 // diagonal, off-diagonal b[0..nb), bb[j] = b[j]^2) at a shift x > 0.  The
 // number of eigenvalues of T below x, minus its k negative ones, is the
 // number of singular values below x; by Sylvester's law of inertia it is the
-// number of negative pivots of T - x I.  Each pivot comes from the previous
-// one by a division, done as a hardware reciprocal refined by one Newton step;
-// a pivot smaller in magnitude than pivmin is replaced by -pivmin.
-__device__ __forceinline__ double sturm_step(double piv, double bbj, double x, double pivmin) {
-  double r = __builtin_amdgcn_rcp(piv);
-  r = fma(r, fma(-piv, r, 1.0), r);
-  const double nxt = fma(-bbj, r, -x);
-  return fabs(nxt) < pivmin ? -pivmin : nxt;
-}
-
-// The LDL^T pivots top-down: q_0 = -x, q_j = -x - bb[j-1] / q_{j-1}.
-__device__ int count_below(const double* bb, int nb, double x, double pivmin) {
-  double q = -x;
-  int neg = 1;  // q_0 = -x < 0
-#pragma unroll 4
-  for (int j = 0; j < nb; ++j) {
-    q = sturm_step(q, bb[j], x, pivmin);
-    neg += (q < 0.0);
-  }
-  return neg - (nb + 1) / 2;
-}
+// number of negative pivots of T - x I, whose LDL^T pivots run top-down as
+// q_0 = -x, q_j = -x - bb[j-1] / q_{j-1}.
 
 // The factorisation twisted at row r = k has the same inertia: top-down
 // pivots q_0 .. q_r as above, bottom-up p_{n-1} = -x, p_j = -x - bb[j] /
@@ -1418,27 +1399,40 @@ __global__ void __launch_bounds__(256) k_sv_bisect(const SvDesc* __restrict__ de
   double* b = reinterpret_cast<double*>(smem_raw);
   const int nb = 2 * k - 1;
   double* bb = b + nb;
-  for (int j = threadIdx.x; j < nb; j += blockDim.x) {
-    b[j] = (j & 1) ? dsc.e[j >> 1] : dsc.d[j >> 1];
-    bb[j] = b[j] * b[j];
-  }
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) b[j] = (j & 1) ? dsc.e[j >> 1] : dsc.d[j >> 1];
   __syncthreads();
-  double bound = 0.0, maxb2 = 0.0;
+  double bound = 0.0;
   for (int j = 0; j < nb; ++j) {  // every thread, same order
     const double left = j > 0 ? fabs(b[j - 1]) : 0.0;
     bound = fmax(bound, fabs(b[j]) + left);
-    maxb2 = fmax(maxb2, bb[j]);
   }
   bound = fmax(bound, nb > 0 ? fabs(b[nb - 1]) : 0.0);
   const bool all_zero = !(bound > 0.0);
   bound = bound * (1.0 + 1e-14) + 1e-300;
-  const double pivmin = 0x1.0p-1022 * fmax(1.0, maxb2);
+  // the counts run on the entries scaled by 2^-eb (bound < 2^eb), exactly, in
+  // the minors form of the factorisation twisted at r = (nb + 1) / 2 (one FMA
+  // on each half's dependent chain, the halves independent): the same count as
+  // the pivots' signs, as in the one-matrix multisection
+  const int eb = __builtin_amdgcn_frexp_exp(bound);
+  const double xs = __builtin_ldexp(1.0, -eb);
+  __syncthreads();
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+    const double bs = __builtin_ldexp(b[j], -eb);
+    bb[j] = bs * bs;
+  }
+  __syncthreads();
+  const int r = (nb + 1) >> 1;
   for (int jj = threadIdx.x; jj < k; jj += blockDim.x) {
     const int want = k - 1 - jj;  // #{sigma < lo} <= want < #{sigma < hi}
     double lo = 0.0, hi = bound;
     for (int it = 0; it < kBisectSteps; ++it) {
       const double x = 0.5 * (lo + hi);
-      if (count_below(bb, nb, x, pivmin) <= want) lo = x;
+      int nt = 0, nbt = 0;
+      const double pt = minors_top(bb, r, x * xs, nt);
+      const double pb = minors_bottom(bb, nb, r, x * xs, nbt);
+      double g = pt + pb + x * xs;  // the twisted pivot, scaled entries
+      if (fabs(g) < 0x1.0p-1020) g = -0x1.0p-1020;
+      if (nt + nbt + (g < 0.0) - r <= want) lo = x;
       else hi = x;
     }
     dsc.sigma[jj] = all_zero ? 0.0 : 0.5 * (lo + hi) * dsc.scale;
