@@ -204,33 +204,38 @@ __global__ void k_gauss_master(const BatchHeader* __restrict__ hdr, int64_t nmax
 // C_b (l x k, FP64) = Y[:, :m_b] (FP32, leading dimension ldy) B_b (m_b x k,
 // FP32) on the FP64 matrix cores (v_mfma_f64_16x16x4f64: lane q holds
 // operand row / column q % 16 at K index q / 16; accumulator r of lane q is
-// row q / 16 + 4 r, column q % 16, as measured on gfx950).  One workgroup per (block, slab of
-// 16 * waves rows of C); wavefront w owns rows 16 w .. 16 w + 15 of the slab
-// and up to six 16-column tiles; K runs over m in chunks of 16 staged in LDS
-// as FP64 (the FP32 products are exact in FP64).  The sum over m is a sum of
-// groups of kYGroup chunks: each group is accumulated on the matrix cores from
-// zero, in chunk order, and the group sums are added in group order.  A batch
-// runs the groups of a block one after another; a single call with many
-// groups gives each its own workgroup (gridDim.z = groups, partials to
-// `parts`) and adds the partials in the same order, so both agree.
+// row q / 16 + 4 r, column q % 16, as measured on gfx950).  One workgroup per
+// (block, slab of 48 WR rows of C) runs WR x WC wavefronts; wavefront (i, j)
+// owns the 3 x 3 tiles of 16 x 16 at rows 48 i .. 48 i + 47 and columns
+// 48 j .. 48 j + 47 of each pass of 48 WC columns.  Six wavefronts (WR = 3,
+// WC = 2) at up to 168 VGPRs let two workgroups share a CU, three wavefronts
+// on each SIMD.  K runs over m in chunks of 16 staged in LDS as FP64 (the
+// FP32 products are exact in FP64).  The sum over m is a sum of groups of
+// kYGroup chunks: each group is accumulated on the matrix cores from zero, in
+// chunk order, and the group sums are added in group order.  A batch runs the
+// groups of a block one after another; a single call with many groups gives
+// each its own workgroup (gridDim.z = groups, partials to `parts`) and adds
+// the partials in the same order, so both agree.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int kYKC = 16;                 // K per chunk
-constexpr int kYNT = 6, kYN = 16 * kYNT;  // column tiles per pass
-constexpr int kYApad = kYKC + 1, kYBpad = kYN + 4;
-constexpr int kYMinWaves = 4, kYMaxWaves = 9;
+constexpr int kYKC = 16;    // K per chunk
+constexpr int kYT = 3;      // 16 x 16 tiles per wavefront along rows and along columns
+constexpr int kYApad = kYKC + 1;
 constexpr int kYGroup = 32;  // chunks per group (512 rows of m)
 
-__global__ void __launch_bounds__(64 * kYMaxWaves) k_ygemm_mfma(const YDesc* __restrict__ desc,
-                                                                const float* __restrict__ Y, int64_t ldy, int64_t l,
-                                                                int64_t k, double* __restrict__ parts) {
+template <int WR, int WC>
+__global__ void __launch_bounds__(64 * WR * WC) __attribute__((amdgpu_waves_per_eu(WR * WC >= 4 ? 3 : 2))) k_ygemm_mfma(const YDesc* __restrict__ desc,
+                                                             const float* __restrict__ Y, int64_t ldy, int64_t l,
+                                                             int64_t k, double* __restrict__ parts) {
+  constexpr int nth = 64 * WR * WC, rows = 16 * kYT * WR, cols = 16 * kYT * WC, bpad = cols + 4;
+  constexpr int perY = rows * kYKC / nth, perB = kYKC * cols / nth;  // staged floats per thread
+  static_assert(perY * nth == rows * kYKC && perB * nth == kYKC * cols, "exact staging");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int waves = blockDim.x >> 6, nth = blockDim.x;
-  const int rows = 16 * waves;
   double* sY = reinterpret_cast<double*>(smem_raw);  // [2][rows][kYApad]
-  double* sB = sY + 2 * rows * kYApad;                // [2][kYKC][kYBpad]
+  double* sB = sY + 2 * rows * kYApad;                // [2][kYKC][bpad]
   const YDesc d = desc[blockIdx.y];
   const int64_t s0 = (int64_t)blockIdx.x * rows;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WC, wc = wave % WC;
   const int q16 = lane & 15, kq = lane >> 4;
   const int64_t m = d.m;
   const int64_t nchunks = (m + kYKC - 1) / kYKC;
@@ -239,46 +244,65 @@ __global__ void __launch_bounds__(64 * kYMaxWaves) k_ygemm_mfma(const YDesc* __r
   const int64_t ch_end = split ? (ch_begin + kYGroup < nchunks ? ch_begin + kYGroup : nchunks) : nchunks;
   double* __restrict__ out = split ? parts + (int64_t)blockIdx.z * l * k : d.C;
   // register staging: the next chunk's loads are in flight while the
-  // matrix cores work on the current one
-  constexpr int kPerY = 4;                          // rows * 16 / (64 * waves)
-  constexpr int kMaxPerB = kYKC * kYN / (64 * kYMinWaves);  // 6
-  const int perB = (kYKC * kYN + nth - 1) / nth;
-  const int yr = (tid * kPerY) / kYKC, yc = (tid * kPerY) % kYKC;
-  for (int64_t c0 = 0; c0 < k; c0 += kYN) {
-    float ry[kPerY], rb[kMaxPerB];
-    const bool yrow_ok = s0 + yr < l;
-    const float* __restrict__ yrow = Y + (yrow_ok ? s0 + yr : 0) * ldy;
+  // matrix cores work on the current one.  Element e = tid + q nth of the Y
+  // tile is row e / 16, K index e % 16 = tid % 16.
+  const int yc = tid % kYKC, yr0 = tid / kYKC;
+  for (int64_t c0 = 0; c0 < k; c0 += cols) {
+    float ry[perY], rb[perB];
     const unsigned ldb = (unsigned)d.ldb;  // 16 rows of B per chunk: 32-bit offsets
     auto load = [&](int64_t i0) {
+      const bool col_ok = i0 + yc < m;
 #pragma unroll
-      for (int q = 0; q < kPerY; ++q) {
-        const int64_t gi = i0 + yc + q;
-        ry[q] = (yrow_ok && gi < m) ? yrow[gi] : 0.0f;
+      for (int q = 0; q < perY; ++q) {
+        const int64_t gr = s0 + yr0 + q * (nth / kYKC);
+        ry[q] = (col_ok && gr < l) ? Y[gr * ldy + i0 + yc] : 0.0f;
       }
       const gcfloat bch = (gcfloat)(d.B + i0 * d.ldb + c0);
 #pragma unroll
-      for (int q = 0; q < kMaxPerB; ++q) {
-        const int e = tid + q * nth;
-        if (q < perB) {
-          const int r = e / kYN, c = e % kYN;
-          rb[q] = (e < kYKC * kYN && i0 + r < m && c0 + c < k) ? bch[r * ldb + c] : 0.0f;
-        }
+      for (int q = 0; q < perB; ++q) {
+        const int e = tid + q * nth, r = e / cols, c = e % cols;
+        rb[q] = (i0 + r < m && c0 + c < k) ? bch[r * ldb + c] : 0.0f;
       }
     };
     auto store = [&](int buf) {
       double* y = sY + buf * rows * kYApad;
 #pragma unroll
-      for (int q = 0; q < kPerY; ++q) y[yr * kYApad + yc + q] = (double)ry[q];
-      double* bb = sB + buf * kYKC * kYBpad;
+      for (int q = 0; q < perY; ++q) y[(yr0 + q * (nth / kYKC)) * kYApad + yc] = (double)ry[q];
+      double* bb = sB + buf * kYKC * bpad;
 #pragma unroll
-      for (int q = 0; q < kMaxPerB; ++q) {
+      for (int q = 0; q < perB; ++q) {
         const int e = tid + q * nth;
-        if (q < perB && e < kYKC * kYN) bb[(e / kYN) * kYBpad + e % kYN] = (double)rb[q];
+        bb[(e / cols) * bpad + e % cols] = (double)rb[q];
       }
     };
-    f64x4 acc[kYNT];
+    f64x4 acc[kYT][kYT];
 #pragma unroll
-    for (int t = 0; t < kYNT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < kYT; ++i)
+#pragma unroll
+      for (int j = 0; j < kYT; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // writes the accumulators to the thread's outputs (or adds them) and
+    // clears them.  The row and column of output (i, j, r) are formed from
+    // two values made opaque to the optimiser, so that the output addresses
+    // are not held across the chunk loop.
+    auto put = [&](bool overwrite) {
+      int rs = 16 * kYT * wr + kq, cs = 16 * kYT * wc + q16;
+      asm volatile("" : "+v"(rs), "+v"(cs));
+      const int64_t gs0 = s0 + rs, gc0 = c0 + cs;
+      const gdouble obase = (gdouble)out + (gs0 * k + gc0);
+#pragma unroll
+      for (int i = 0; i < kYT; ++i)
+#pragma unroll
+        for (int j = 0; j < kYT; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (gs0 + 16 * i + 4 * r < l && gc0 + 16 * j < k) {
+              const gdouble o = obase + ((16 * i + 4 * r) * k + 16 * j);
+              *o = overwrite ? acc[i][j][r] : *o + acc[i][j][r];
+            }
+          }
+          acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+        }
+    };
     bool first = true;
     load(ch_begin * kYKC);
     store(0);
@@ -286,43 +310,31 @@ __global__ void __launch_bounds__(64 * kYMaxWaves) k_ygemm_mfma(const YDesc* __r
     for (int64_t ch = ch_begin; ch < ch_end; ++ch) {
       const int buf = (ch - ch_begin) & 1;
       if (ch + 1 < ch_end) load((ch + 1) * kYKC);
-      const double* y = sY + buf * rows * kYApad + (16 * wave + q16) * kYApad;
-      const double* bb = sB + buf * kYKC * kYBpad;
-#pragma unroll
+      const double* y = sY + buf * rows * kYApad + (16 * kYT * wr + q16) * kYApad;
+      const double* bb = sB + buf * kYKC * bpad + 16 * kYT * wc + q16;
+#pragma unroll 1
       for (int kk = 0; kk < kYKC; kk += 4) {
-        const double av = y[kk + kq];
+        double av[kYT], bv[kYT];
 #pragma unroll
-        for (int t = 0; t < kYNT; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bb[(kk + kq) * kYBpad + 16 * t + q16], acc[t], 0, 0, 0);
+        for (int i = 0; i < kYT; ++i) av[i] = y[16 * i * kYApad + kk + kq];
+#pragma unroll
+        for (int j = 0; j < kYT; ++j) bv[j] = bb[(kk + kq) * bpad + 16 * j];
+#pragma unroll
+        for (int i = 0; i < kYT; ++i)
+#pragma unroll
+          for (int j = 0; j < kYT; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
       }
       if ((ch + 1) % kYGroup == 0 || ch + 1 == ch_end) {
         // a group ends: its sum goes to the thread's own outputs (first
         // group) or is added to them
-#pragma unroll
-        for (int t = 0; t < kYNT; ++t) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int64_t gs = s0 + 16 * wave + kq + 4 * r, gc = c0 + 16 * t + q16;
-            if (gs < l && gc < k) {
-              const gdouble o = (gdouble)out + (gs * k + gc);
-              *o = first ? acc[t][r] : *o + acc[t][r];
-            }
-          }
-          acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-        }
+        put(first);
         first = false;
       }
       if (ch + 1 < ch_end) store(buf ^ 1);
       __syncthreads();
     }
-    if (first)  // m = 0
-#pragma unroll
-      for (int t = 0; t < kYNT; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t gs = s0 + 16 * wave + kq + 4 * r, gc = c0 + 16 * t + q16;
-          if (gs < l && gc < k) ((gdouble)out)[gs * k + gc] = 0.0;
-        }
+    if (first) put(true);  // m = 0: the zero accumulators
     __syncthreads();
   }
 }
@@ -456,19 +468,35 @@ re_status launch_ygemm_batched(hipStream_t s, const YDesc* desc, int nblk, const
   return launch_ygemm_grid(s, desc, nblk, Y, ldy, l, k, 1, nullptr);
 }
 
+template <int WR, int WC>
+re_status launch_ygemm_shape(hipStream_t s, const YDesc* desc, int nblk, const float* Y, int64_t ldy, int64_t l,
+                             int64_t k, unsigned groups, double* parts) {
+  constexpr int rows = 16 * kYT * WR, cols = 16 * kYT * WC;
+  const size_t lds = (size_t)(2 * rows * kYApad + 2 * kYKC * (cols + 4)) * sizeof(double);
+  if (lds > 64 * 1024)
+    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_ygemm_mfma<WR, WC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+  hipLaunchKernelGGL((k_ygemm_mfma<WR, WC>), dim3((unsigned)cdiv(l, rows), (unsigned)nblk, groups),
+                     dim3(64 * WR * WC), lds, s, desc, Y, ldy, l, k, parts);
+  RE_TRY_HIP(hipGetLastError());
+  return RE_OK;
+}
+
+// Slabs of 48, 96 or 144 rows (the fewest that cover l, at most three
+// wavefront rows) and passes of 48 or 96 columns.
 re_status launch_ygemm_grid(hipStream_t s, const YDesc* desc, int nblk, const float* Y, int64_t ldy, int64_t l,
                             int64_t k, unsigned groups, double* parts) {
   if (nblk <= 0 || l <= 0 || k <= 0) return RE_OK;
-  int waves = (int)(cdiv(l, 16) < kYMaxWaves ? cdiv(l, 16) : kYMaxWaves);
-  if (waves < kYMinWaves) waves = kYMinWaves;
-  const int rows = 16 * waves;
-  const size_t lds = (size_t)(2 * rows * kYApad + 2 * kYKC * kYBpad) * sizeof(double);
-  if (lds > 64 * 1024)
-    RE_TRY_HIP(hipFuncSetAttribute((const void*)k_ygemm_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_ygemm_mfma, dim3((unsigned)cdiv(l, rows), (unsigned)nblk, groups), dim3(64 * waves), lds, s, desc,
-                     Y, ldy, l, k, parts);
-  RE_TRY_HIP(hipGetLastError());
-  return RE_OK;
+  const int wr = (int)(cdiv(l, 16 * kYT) < 3 ? cdiv(l, 16 * kYT) : 3);
+  const bool wide = k > 16 * kYT;
+  switch (wr * 2 + (wide ? 1 : 0)) {
+    case 2: return launch_ygemm_shape<1, 1>(s, desc, nblk, Y, ldy, l, k, groups, parts);
+    case 3: return launch_ygemm_shape<1, 2>(s, desc, nblk, Y, ldy, l, k, groups, parts);
+    case 4: return launch_ygemm_shape<2, 1>(s, desc, nblk, Y, ldy, l, k, groups, parts);
+    case 5: return launch_ygemm_shape<2, 2>(s, desc, nblk, Y, ldy, l, k, groups, parts);
+    case 6: return launch_ygemm_shape<3, 1>(s, desc, nblk, Y, ldy, l, k, groups, parts);
+    default: return launch_ygemm_shape<3, 2>(s, desc, nblk, Y, ldy, l, k, groups, parts);
+  }
 }
 
 }  // namespace re
