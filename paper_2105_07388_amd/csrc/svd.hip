@@ -953,6 +953,137 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_1wg(SmallBatch sb) {
   }
 }
 
+// ---- bidiagonalisation with the sketch held in registers ----------------
+// The same reflectors as above for sketches of up to 64 KPL columns and
+// 8 RPW rows: row i lives in the registers of wavefront i % 8 (slot i / 8),
+// column j in lane j % 64 (slot j / 64), so a workgroup needs LDS only for
+// the column partials and the pivot row (about 18 KPL KiB) and two workgroups
+// share a CU.  Per column one workgroup barrier: the wavefronts' partials of
+// the Gram row x . W[:, c + j] go to LDS (double-buffered by the parity of c,
+// so a wavefront can write the next column's while another still reads this
+// column's), every wavefront sums them in the same order and so forms the
+// same reflectors, and each updates its own rows with wavefront sums.
+constexpr int kBRWaves = 8, kBRThreads = 64 * kBRWaves;
+
+// Lane `src` (uniform) of a double in every lane.
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const uint64_t u = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, src);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+  return __longlong_as_double(((uint64_t)hi << 32) | lo);
+}
+
+template <int KPL, int RPW>
+__global__ void __launch_bounds__(kBRThreads) __attribute__((amdgpu_waves_per_eu(KPL * RPW <= 36 ? 4 : 1)))
+k_bidiag_rows(SmallBatch sb) {
+  static_assert(KPL == 1 || KPL == 2, "one or two columns per lane");
+  constexpr int S = 64 * KPL;  // LDS row stride of the partials
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  const bool one = sb.C == nullptr;
+  const int l = one ? sb.l1 : sb.l[b], k = one ? sb.k1 : sb.k[b];
+  const double* __restrict__ C = one ? sb.C1 : sb.C[b];
+  double* dd = one ? sb.d1 : sb.d[b];
+  double* ee = one ? sb.e1 : sb.e[b];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* part = reinterpret_cast<double*>(smem_raw);  // [2][kBRWaves][S]
+  double* rowc = part + 2 * kBRWaves * S;              // [2][S]
+  double R[RPW][KPL];
+  int bad = 0;
+#pragma unroll
+  for (int s = 0; s < RPW; ++s) {
+    const int i = wave + kBRWaves * s;
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) {
+      const int j = lane + 64 * t;
+      const double x = (i < l && j < k) ? C[(int64_t)i * k + j] : 0.0;
+      bad |= !isfinite(x);
+      R[s][t] = x;
+    }
+  }
+  bad = __syncthreads_or(bad);
+  if (tid == 0) sb.info[b] = bad ? (int32_t)RE_ERR_NONFINITE : 0;
+  for (int c = 0; c < k; ++c) {
+    const int buf = c & 1, lc = c & 63, tc = c >> 6;
+    double* pb = part + buf * kBRWaves * S;
+    double* rb = rowc + buf * S;
+    // this wavefront's partials of x . W[:, j] over its rows i >= c, and the
+    // pivot row from its owner
+    double p[KPL];
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) p[t] = 0.0;
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      const int i = wave + kBRWaves * s;
+      if (i >= c && i < l) {
+        const double xc = lane_value(KPL == 1 || tc == 0 ? R[s][0] : R[s][KPL - 1], lc);
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) p[t] = fma(xc, R[s][t], p[t]);
+      }
+      if (i == c)
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) rb[lane + 64 * t] = R[s][t];
+    }
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) pb[wave * S + lane + 64 * t] = p[t];
+    __syncthreads();
+    double s0 = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBRWaves; ++w) s0 += pb[w * S + c];
+    const double x0 = rb[c];
+    const double nx = sqrt(s0);
+    const double alpha = nx > 0.0 ? -copysign(nx, x0) : 0.0;
+    const double tau = nx > 0.0 ? 1.0 / (s0 - alpha * x0) : 0.0;
+    const double u0 = x0 - alpha;
+    if (tid == 0) dd[c] = alpha;
+    // the pivot row after the left reflector (y, columns j > c) and the
+    // left reflector's row factors w
+    double wj[KPL], y[KPL];
+    double pp = 0.0;
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) {
+      const int j = lane + 64 * t;
+      double g = 0.0;
+#pragma unroll
+      for (int w = 0; w < kBRWaves; ++w) g += pb[w * S + j];
+      const double row = rb[j];
+      const bool live = j > c && j < k;
+      wj[t] = live ? tau * (g - alpha * row) : 0.0;
+      y[t] = live ? row - u0 * wj[t] : 0.0;
+      pp += y[t] * y[t];
+    }
+    const double ny2 = wave_sum_dpp(pp);
+    const int c1 = c + 1 < k ? c + 1 : c;
+    const double y0 = c + 1 < k ? lane_value(KPL == 1 || (c1 >> 6) == 0 ? y[0] : y[KPL - 1], c1 & 63) : 0.0;
+    const double ny = sqrt(ny2);
+    const double beta = ny > 0.0 ? -copysign(ny, y0) : 0.0;
+    const double tau2 = ny > 0.0 ? 1.0 / (ny2 - beta * y0) : 0.0;
+    const double v1 = y0 - beta;
+    if (tid == 0 && c + 1 < k) ee[c] = beta;
+    double v[KPL];
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) v[t] = lane + 64 * t == c + 1 ? v1 : y[t];
+    // rows below the pivot: left reflector, then right reflector
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      const int i = wave + kBRWaves * s;
+      if (i > c && i < l) {
+        const double ur = lane_value(KPL == 1 || tc == 0 ? R[s][0] : R[s][KPL - 1], lc);
+        double tv[KPL];
+        double zp = 0.0;
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+          tv[t] = R[s][t] - ur * wj[t];
+          zp += tv[t] * v[t];
+        }
+        const double z = wave_sum_dpp(zp) * tau2;
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) R[s][t] = tv[t] - z * v[t];
+      }
+    }
+  }
+}
+
 // ---- singular values of the bidiagonal by multisection on Sturm counts ----
 
 // Sturm counts of the Golub-Kahan tridiagonal T of order n = nb + 1 = 2k (zero
@@ -1252,6 +1383,32 @@ int64_t lds_stride(int64_t k) { return k + ((16 - k % 32) + 32) % 32; }
 // LDS bytes of the single-workgroup bidiagonalisation of an l x k sketch.
 size_t small_lds_bytes(int64_t l, int64_t k) {
   return (size_t)l * lds_stride(k) * 8 + (size_t)(2 * (k + 1) + kB2Waves + kB2Threads) * 8;
+}
+
+// The register-held bidiagonalisation for an l x k sketch: kernel and LDS
+// bytes, or no kernel when the sketch exceeds 128 columns or 8 x 48 rows
+// (8 x 24 rows above 64 columns).
+struct RowsKernel {
+  const void* fn;
+  size_t lds;
+};
+RowsKernel rows_kernel(int64_t l, int64_t k) {
+  const int64_t rpw = (l + kBRWaves - 1) / kBRWaves;
+  const void* fn = nullptr;
+  if (k <= 64)
+    fn = rpw <= 8    ? (const void*)k_bidiag_rows<1, 8>
+         : rpw <= 16 ? (const void*)k_bidiag_rows<1, 16>
+         : rpw <= 24 ? (const void*)k_bidiag_rows<1, 24>
+         : rpw <= 32 ? (const void*)k_bidiag_rows<1, 32>
+         : rpw <= 48 ? (const void*)k_bidiag_rows<1, 48>
+                     : nullptr;
+  else if (k <= 128)
+    fn = rpw <= 8    ? (const void*)k_bidiag_rows<2, 8>
+         : rpw <= 12 ? (const void*)k_bidiag_rows<2, 12>
+         : rpw <= 18 ? (const void*)k_bidiag_rows<2, 18>
+         : rpw <= 24 ? (const void*)k_bidiag_rows<2, 24>
+                     : nullptr;
+  return {fn, (size_t)(2 * kBRWaves + 2) * 64 * (k <= 64 ? 1 : 2) * sizeof(double)};
 }
 
 // Rows per workgroup at most `svd_rows_target()` (fewer rows shorten the
@@ -1559,7 +1716,17 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
   hipLaunchKernelGGL(k_svd_init, dim3(1), dim3(64), 0, s, a.bar, info);
   const LdsPlan lp = lds_plan(l, k);
   const size_t one_bytes = small_lds_bytes(l, k);
-  if (one_bytes <= kLdsBudget) {
+  if (const RowsKernel rk = rows_kernel(l, k); rk.fn) {
+    SmallBatch sb{};
+    sb.C1 = C;
+    sb.d1 = a.d;
+    sb.e1 = a.e;
+    sb.l1 = (int32_t)l;
+    sb.k1 = (int32_t)k;
+    sb.info = info;
+    void* args[] = {&sb};
+    RE_TRY_HIP(hipLaunchKernel(rk.fn, dim3(1), dim3(kBRThreads), args, rk.lds, s));
+  } else if (one_bytes <= kLdsBudget) {
     SmallBatch sb{};
     sb.kp = (int)lds_stride(k);
     sb.C1 = C;
@@ -1694,6 +1861,11 @@ re_status launch_bidiag_batched(hipStream_t s, const double* const* C, double* c
   sb.k = k;
   sb.info = info;
   sb.kp = (int)lds_stride(kmax);
+  if (const RowsKernel rk = rows_kernel(lmax, kmax); rk.fn) {
+    void* args[] = {&sb};
+    RE_TRY_HIP(hipLaunchKernel(rk.fn, dim3((unsigned)nblk), dim3(kBRThreads), args, rk.lds, s));
+    return RE_OK;
+  }
   if (bytes > 64 * 1024)
     RE_TRY_HIP(hipFuncSetAttribute((const void*)k_bidiag_1wg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   hipLaunchKernelGGL(k_bidiag_1wg, dim3((unsigned)nblk), dim3(kB2Threads), bytes, s, sb);
