@@ -954,15 +954,18 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_1wg(SmallBatch sb) {
 }
 
 // ---- bidiagonalisation with the sketch held in registers ----------------
-// The same reflectors as above for sketches of up to 64 KPL columns and
-// 8 RPW rows: row i lives in the registers of wavefront i % 8 (slot i / 8),
-// column j in lane j % 64 (slot j / 64), so a workgroup needs LDS only for
-// the column partials and the pivot row (about 18 KPL KiB) and two workgroups
-// share a CU.  Per column one workgroup barrier: the wavefronts' partials of
-// the Gram row x . W[:, c + j] go to LDS (double-buffered by the parity of c,
-// so a wavefront can write the next column's while another still reads this
-// column's), every wavefront sums them in the same order and so forms the
-// same reflectors, and each updates its own rows with wavefront sums.
+// The same reflectors as above for sketches of up to 16 KT columns and
+// 32 RS rows.  Eight wavefronts; each row sits in one row of 16 lanes:
+// row i in wavefront (i / 4) mod 8, lanes 16 (i mod 4) .. + 15, slot i / 32,
+// and column j in lane j mod 16 of that row, slot j / 16.  So the reflector
+// of a row ends in a 16-lane sum, four rows at a time, rather than in a sum
+// over the wavefront.  A workgroup needs LDS only for the column partials and
+// the pivot row (about 2.3 KT KiB), and two share a CU.  Per column one
+// workgroup barrier: the wavefronts' partials of the Gram row x . W[:, j] go
+// to LDS (double-buffered by the parity of c, so a wavefront can write the
+// next column's while another still reads this column's); every wavefront
+// sums them in the same order and so forms the same reflectors, and each
+// updates its own rows.
 constexpr int kBRWaves = 8, kBRThreads = 64 * kBRWaves;
 
 // Lane `src` (uniform) of a double in every lane.
@@ -973,11 +976,10 @@ __device__ __forceinline__ double lane_value(double v, int src) {
   return __longlong_as_double(((uint64_t)hi << 32) | lo);
 }
 
-template <int KPL, int RPW>
-__global__ void __launch_bounds__(kBRThreads) __attribute__((amdgpu_waves_per_eu(KPL * RPW <= 36 ? 4 : 1)))
+template <int KT, int RS>
+__global__ void __launch_bounds__(kBRThreads) __attribute__((amdgpu_waves_per_eu(KT * RS <= 32 && KT < 8 ? 4 : 1)))
 k_bidiag_rows(SmallBatch sb) {
-  static_assert(KPL == 1 || KPL == 2, "one or two columns per lane");
-  constexpr int S = 64 * KPL;  // LDS row stride of the partials
+  constexpr int S = 16 * KT;  // LDS row stride of the partials
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b = blockIdx.x;
   const bool one = sb.C == nullptr;
@@ -986,16 +988,18 @@ k_bidiag_rows(SmallBatch sb) {
   double* dd = one ? sb.d1 : sb.d[b];
   double* ee = one ? sb.e1 : sb.e[b];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q = lane >> 4, l16 = lane & 15;
+  const int i0 = 4 * wave + q;  // row of slot 0; slot s holds row i0 + 32 s
   double* part = reinterpret_cast<double*>(smem_raw);  // [2][kBRWaves][S]
   double* rowc = part + 2 * kBRWaves * S;              // [2][S]
-  double R[RPW][KPL];
+  double R[RS][KT];
   int bad = 0;
 #pragma unroll
-  for (int s = 0; s < RPW; ++s) {
-    const int i = wave + kBRWaves * s;
+  for (int s = 0; s < RS; ++s) {
+    const int i = i0 + 32 * s;
 #pragma unroll
-    for (int t = 0; t < KPL; ++t) {
-      const int j = lane + 64 * t;
+    for (int t = 0; t < KT; ++t) {
+      const int j = l16 + 16 * t;
       const double x = (i < l && j < k) ? C[(int64_t)i * k + j] : 0.0;
       bad |= !isfinite(x);
       R[s][t] = x;
@@ -1003,82 +1007,96 @@ k_bidiag_rows(SmallBatch sb) {
   }
   bad = __syncthreads_or(bad);
   if (tid == 0) sb.info[b] = bad ? (int32_t)RE_ERR_NONFINITE : 0;
-  for (int c = 0; c < k; ++c) {
-    const int buf = c & 1, lc = c & 63, tc = c >> 6;
-    double* pb = part + buf * kBRWaves * S;
-    double* rb = rowc + buf * S;
-    // this wavefront's partials of x . W[:, j] over its rows i >= c, and the
-    // pivot row from its owner
-    double p[KPL];
 #pragma unroll
-    for (int t = 0; t < KPL; ++t) p[t] = 0.0;
+  for (int tc = 0; tc < KT; ++tc) {
+    for (int lc = 0; lc < 16; ++lc) {
+      const int c = 16 * tc + lc;
+      if (c >= k) break;
+      const int buf = c & 1;
+      double* pb = part + buf * kBRWaves * S;
+      double* rb = rowc + buf * S;
+      const int src = (lane & 48) | lc;  // lane of column c in this row of lanes
+      // this wavefront's partials of x . W[:, j] over its rows i >= c, summed
+      // over its four rows of lanes, and the pivot row from its owner
+      double p[KT];
 #pragma unroll
-    for (int s = 0; s < RPW; ++s) {
-      const int i = wave + kBRWaves * s;
-      if (i >= c && i < l) {
-        const double xc = lane_value(KPL == 1 || tc == 0 ? R[s][0] : R[s][KPL - 1], lc);
+      for (int t = 0; t < KT; ++t) p[t] = 0.0;
 #pragma unroll
-        for (int t = 0; t < KPL; ++t) p[t] = fma(xc, R[s][t], p[t]);
-      }
-      if (i == c)
+      for (int s = 0; s < RS; ++s) {
+        const int i = i0 + 32 * s;
+        if (4 * wave + 32 * s + 3 >= c && 4 * wave + 32 * s < l) {  // some row of this slot counts
+          double xc = __shfl(R[s][tc], src, 64);
+          xc = (i >= c && i < l) ? xc : 0.0;
 #pragma unroll
-        for (int t = 0; t < KPL; ++t) rb[lane + 64 * t] = R[s][t];
-    }
-#pragma unroll
-    for (int t = 0; t < KPL; ++t) pb[wave * S + lane + 64 * t] = p[t];
-    __syncthreads();
-    double s0 = 0.0;
-#pragma unroll
-    for (int w = 0; w < kBRWaves; ++w) s0 += pb[w * S + c];
-    const double x0 = rb[c];
-    const double nx = sqrt(s0);
-    const double alpha = nx > 0.0 ? -copysign(nx, x0) : 0.0;
-    const double tau = nx > 0.0 ? 1.0 / (s0 - alpha * x0) : 0.0;
-    const double u0 = x0 - alpha;
-    if (tid == 0) dd[c] = alpha;
-    // the pivot row after the left reflector (y, columns j > c) and the
-    // left reflector's row factors w
-    double wj[KPL], y[KPL];
-    double pp = 0.0;
-#pragma unroll
-    for (int t = 0; t < KPL; ++t) {
-      const int j = lane + 64 * t;
-      double g = 0.0;
-#pragma unroll
-      for (int w = 0; w < kBRWaves; ++w) g += pb[w * S + j];
-      const double row = rb[j];
-      const bool live = j > c && j < k;
-      wj[t] = live ? tau * (g - alpha * row) : 0.0;
-      y[t] = live ? row - u0 * wj[t] : 0.0;
-      pp += y[t] * y[t];
-    }
-    const double ny2 = wave_sum_dpp(pp);
-    const int c1 = c + 1 < k ? c + 1 : c;
-    const double y0 = c + 1 < k ? lane_value(KPL == 1 || (c1 >> 6) == 0 ? y[0] : y[KPL - 1], c1 & 63) : 0.0;
-    const double ny = sqrt(ny2);
-    const double beta = ny > 0.0 ? -copysign(ny, y0) : 0.0;
-    const double tau2 = ny > 0.0 ? 1.0 / (ny2 - beta * y0) : 0.0;
-    const double v1 = y0 - beta;
-    if (tid == 0 && c + 1 < k) ee[c] = beta;
-    double v[KPL];
-#pragma unroll
-    for (int t = 0; t < KPL; ++t) v[t] = lane + 64 * t == c + 1 ? v1 : y[t];
-    // rows below the pivot: left reflector, then right reflector
-#pragma unroll
-    for (int s = 0; s < RPW; ++s) {
-      const int i = wave + kBRWaves * s;
-      if (i > c && i < l) {
-        const double ur = lane_value(KPL == 1 || tc == 0 ? R[s][0] : R[s][KPL - 1], lc);
-        double tv[KPL];
-        double zp = 0.0;
-#pragma unroll
-        for (int t = 0; t < KPL; ++t) {
-          tv[t] = R[s][t] - ur * wj[t];
-          zp += tv[t] * v[t];
+          for (int t = 0; t < KT; ++t) p[t] = fma(xc, R[s][t], p[t]);
         }
-        const double z = wave_sum_dpp(zp) * tau2;
+        if (i == c)
 #pragma unroll
-        for (int t = 0; t < KPL; ++t) R[s][t] = tv[t] - z * v[t];
+          for (int t = 0; t < KT; ++t) rb[l16 + 16 * t] = R[s][t];
+      }
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        p[t] += __shfl_xor(p[t], 16, 64);
+        p[t] += __shfl_xor(p[t], 32, 64);
+        if (q == 0) pb[wave * S + l16 + 16 * t] = p[t];
+      }
+      __syncthreads();
+      double s0 = 0.0;
+#pragma unroll
+      for (int w = 0; w < kBRWaves; ++w) s0 += pb[w * S + c];
+      const double x0 = rb[c];
+      const double nx = sqrt(s0);
+      const double alpha = nx > 0.0 ? -copysign(nx, x0) : 0.0;
+      const double tau = nx > 0.0 ? 1.0 / (s0 - alpha * x0) : 0.0;
+      const double u0 = x0 - alpha;
+      if (tid == 0) dd[c] = alpha;
+      // the pivot row after the left reflector (y, columns j > c) and the
+      // left reflector's row factors w
+      double wj[KT], v[KT];  // v holds y until the right reflector is formed
+      double pp = 0.0;
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        const int j = l16 + 16 * t;
+        double g = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBRWaves; ++w) g += pb[w * S + j];
+        const double row = rb[j];
+        const bool live = j > c && j < k;
+        wj[t] = live ? tau * (g - alpha * row) : 0.0;
+        v[t] = live ? row - u0 * wj[t] : 0.0;
+        pp += v[t] * v[t];
+        if (t % 2 == 1) asm volatile("" ::: "memory");  // at most two columns' partials in flight
+      }
+      const double ny2 = row16_sum(pp);
+      const double ysrc = (lc == 15 && tc + 1 < KT) ? v[tc + 1 < KT ? tc + 1 : tc] : v[tc];
+      const double y0 = c + 1 < k ? lane_value(ysrc, (c + 1) & 15) : 0.0;
+      const double ny = sqrt(ny2);
+      const double beta = ny > 0.0 ? -copysign(ny, y0) : 0.0;
+      const double tau2 = ny > 0.0 ? 1.0 / (ny2 - beta * y0) : 0.0;
+      const double v1 = y0 - beta;
+      if (tid == 0 && c + 1 < k) ee[c] = beta;
+#pragma unroll
+      for (int t = 0; t < KT; ++t) v[t] = l16 + 16 * t == c + 1 ? v1 : v[t];
+      // rows below the pivot: left reflector, then right reflector (rows at
+      // or above it take ur = z = 0 and keep their values)
+#pragma unroll
+      for (int s = 0; s < RS; ++s) {
+        const int i = i0 + 32 * s;
+        if (4 * wave + 32 * s + 3 > c && 4 * wave + 32 * s < l) {
+          const bool live = i > c && i < l;
+          double ur = __shfl(R[s][tc], src, 64);
+          ur = live ? ur : 0.0;
+          double zp = 0.0;
+#pragma unroll
+          for (int t = 0; t < KT; ++t) {
+            R[s][t] = R[s][t] - ur * wj[t];
+            zp += R[s][t] * v[t];
+          }
+          double z = row16_sum(zp) * tau2;
+          z = live ? z : 0.0;
+#pragma unroll
+          for (int t = 0; t < KT; ++t) R[s][t] = R[s][t] - z * v[t];
+        }
       }
     }
   }
@@ -1386,29 +1404,31 @@ size_t small_lds_bytes(int64_t l, int64_t k) {
 }
 
 // The register-held bidiagonalisation for an l x k sketch: kernel and LDS
-// bytes, or no kernel when the sketch exceeds 128 columns or 8 x 48 rows
-// (8 x 24 rows above 64 columns).
+// bytes, or no kernel when the sketch exceeds 128 columns or 32 x 12 rows
+// (32 x 6 rows above 64 columns).
 struct RowsKernel {
   const void* fn;
   size_t lds;
 };
 RowsKernel rows_kernel(int64_t l, int64_t k) {
-  const int64_t rpw = (l + kBRWaves - 1) / kBRWaves;
+  const int64_t rs = (l + 31) / 32;
   const void* fn = nullptr;
-  if (k <= 64)
-    fn = rpw <= 8    ? (const void*)k_bidiag_rows<1, 8>
-         : rpw <= 16 ? (const void*)k_bidiag_rows<1, 16>
-         : rpw <= 24 ? (const void*)k_bidiag_rows<1, 24>
-         : rpw <= 32 ? (const void*)k_bidiag_rows<1, 32>
-         : rpw <= 48 ? (const void*)k_bidiag_rows<1, 48>
-                     : nullptr;
-  else if (k <= 128)
-    fn = rpw <= 8    ? (const void*)k_bidiag_rows<2, 8>
-         : rpw <= 12 ? (const void*)k_bidiag_rows<2, 12>
-         : rpw <= 18 ? (const void*)k_bidiag_rows<2, 18>
-         : rpw <= 24 ? (const void*)k_bidiag_rows<2, 24>
-                     : nullptr;
-  return {fn, (size_t)(2 * kBRWaves + 2) * 64 * (k <= 64 ? 1 : 2) * sizeof(double)};
+  int kt = 0;
+  if (k <= 64) {
+    kt = 4;
+    fn = rs <= 2   ? (const void*)k_bidiag_rows<4, 2>
+         : rs <= 4 ? (const void*)k_bidiag_rows<4, 4>
+         : rs <= 8 ? (const void*)k_bidiag_rows<4, 8>
+         : rs <= 12 ? (const void*)k_bidiag_rows<4, 12>
+                    : nullptr;
+  } else if (k <= 96) {
+    kt = 6;
+    fn = rs <= 3 ? (const void*)k_bidiag_rows<6, 3> : rs <= 5 ? (const void*)k_bidiag_rows<6, 5> : nullptr;
+  } else if (k <= 128) {
+    kt = 8;
+    fn = rs <= 4 ? (const void*)k_bidiag_rows<8, 4> : rs <= 6 ? (const void*)k_bidiag_rows<8, 6> : nullptr;
+  }
+  return {fn, (size_t)(2 * kBRWaves + 2) * 16 * kt * sizeof(double)};
 }
 
 // Rows per workgroup at most `svd_rows_target()` (fewer rows shorten the
