@@ -1565,18 +1565,27 @@ SvdLayout svd_layout(int64_t l, int64_t k) {
 // Singular values of small bidiagonals, one lane per value: 56 bisection
 // steps on the Sturm count (the interval shrinks below 2^-56 of the bound,
 // as the 65-way multisection does in 9 rounds), one workgroup per problem
-// (problem = blockIdx.x of desc, or `one` when desc is NULL).  Used for every
-// sketch whose bidiagonalisation fits one workgroup, single or batched, so a
-// block of a batch and the same matrix alone give the same bits.
+// (`one` when desc is NULL).  A workgroup takes ppw problems: problem
+// blockIdx.x ppw + p on lanes p kslot .. p kslot + kslot - 1, so that 96
+// values of two problems fill three wavefronts (ppw = 1: the whole workgroup,
+// values strided by blockDim.x).  Used for every sketch whose
+// bidiagonalisation fits one workgroup, single or batched; a lane's
+// arithmetic depends only on its problem and value, so a block of a batch
+// and the same matrix alone give the same bits.
 constexpr int kBisectSteps = 56;
-__global__ void __launch_bounds__(256) k_sv_bisect(const SvDesc* __restrict__ desc, SvDesc one) {
+__global__ void __launch_bounds__(256) k_sv_bisect(const SvDesc* __restrict__ desc, SvDesc one, int nprob, int ppw,
+                                                   int kslot, int kmax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const SvDesc dsc = desc ? desc[blockIdx.x] : one;
-  const int k = dsc.k;
-  double* b = reinterpret_cast<double*>(smem_raw);
+  const int p = ppw > 1 ? (int)threadIdx.x / kslot : 0;
+  const int prob = (int)blockIdx.x * ppw + p;
+  const bool live = p < ppw && prob < nprob;
+  const int k = live ? (desc ? desc[prob].k : one.k) : 0;
+  const SvDesc dsc = live ? (desc ? desc[prob] : one) : one;
+  const int base = ppw > 1 ? p * kslot : 0, stride = ppw > 1 ? kslot : (int)blockDim.x;
+  double* b = reinterpret_cast<double*>(smem_raw) + (size_t)(live ? p : 0) * 4 * kmax;
   const int nb = 2 * k - 1;
-  double* bb = b + nb;
-  for (int j = threadIdx.x; j < nb; j += blockDim.x) b[j] = (j & 1) ? dsc.e[j >> 1] : dsc.d[j >> 1];
+  double* bb = b + 2 * kmax;
+  for (int j = (int)threadIdx.x - base; j < nb; j += stride) b[j] = (j & 1) ? dsc.e[j >> 1] : dsc.d[j >> 1];
   __syncthreads();
   double bound = 0.0;
   for (int j = 0; j < nb; ++j) {  // every thread, same order
@@ -1593,13 +1602,13 @@ __global__ void __launch_bounds__(256) k_sv_bisect(const SvDesc* __restrict__ de
   const int eb = __builtin_amdgcn_frexp_exp(bound);
   const double xs = __builtin_ldexp(1.0, -eb);
   __syncthreads();
-  for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+  for (int j = (int)threadIdx.x - base; j < nb; j += stride) {
     const double bs = __builtin_ldexp(b[j], -eb);
     bb[j] = bs * bs;
   }
   __syncthreads();
   const int r = (nb + 1) >> 1;
-  for (int jj = threadIdx.x; jj < k; jj += blockDim.x) {
+  for (int jj = (int)threadIdx.x - base; jj < k; jj += stride) {
     const int want = k - 1 - jj;  // #{sigma < lo} <= want < #{sigma < hi}
     double lo = 0.0, hi = bound;
     for (int it = 0; it < kBisectSteps; ++it) {
@@ -1853,7 +1862,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
     one.k = (int32_t)k;
     one.scale = scale;
     const int thr = k >= 256 ? 256 : (int)cdiv(k, 64) * 64;
-    hipLaunchKernelGGL(k_sv_bisect, dim3(1), dim3(thr), lds2, s, (const SvDesc*)nullptr, one);
+    hipLaunchKernelGGL(k_sv_bisect, dim3(1), dim3(thr), lds2, s, (const SvDesc*)nullptr, one, 1, 1, thr, (int)k);
     RE_TRY_HIP(hipGetLastError());
     return RE_OK;
   }
@@ -1895,12 +1904,15 @@ re_status launch_bidiag_batched(hipStream_t s, const double* const* C, double* c
 
 re_status launch_sv_count_batched(hipStream_t s, const SvDesc* desc, int nblk, int64_t kmax) {
   if (nblk <= 0) return RE_OK;
-  const size_t lds2 = (size_t)(4 * kmax) * 8;
+  // problems per workgroup: as many as 256 lanes hold, one value per lane
+  const int ppw = kmax <= 128 ? (int)(256 / kmax) : 1;
+  const size_t lds2 = (size_t)ppw * (4 * kmax) * 8;
   if (lds2 > 160 * 1024) return RE_ERR_UNSUPPORTED;
   if (lds2 > 64 * 1024)
     RE_TRY_HIP(hipFuncSetAttribute((const void*)k_sv_bisect, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
-  const int thr = kmax >= 256 ? 256 : (int)cdiv(kmax, 64) * 64;
-  hipLaunchKernelGGL(k_sv_bisect, dim3((unsigned)nblk), dim3(thr), lds2, s, desc, SvDesc{});
+  const int thr = ppw > 1 ? (int)cdiv(ppw * kmax, 64) * 64 : kmax >= 256 ? 256 : (int)cdiv(kmax, 64) * 64;
+  hipLaunchKernelGGL(k_sv_bisect, dim3((unsigned)cdiv(nblk, ppw)), dim3(thr), lds2, s, desc, SvDesc{}, nblk, ppw,
+                     ppw > 1 ? (int)kmax : thr, (int)kmax);
   hipLaunchKernelGGL(k_count_batched, dim3((unsigned)nblk), dim3(256), 0, s, desc);
   RE_TRY_HIP(hipGetLastError());
   return RE_OK;
