@@ -959,13 +959,13 @@ __global__ void __launch_bounds__(kB2Threads) k_bidiag_1wg(SmallBatch sb) {
 // row i in wavefront (i / 4) mod 8, lanes 16 (i mod 4) .. + 15, slot i / 32,
 // and column j in lane j mod 16 of that row, slot j / 16.  So the reflector
 // of a row ends in a 16-lane sum, four rows at a time, rather than in a sum
-// over the wavefront.  A workgroup needs LDS only for the column partials and
-// the pivot row (about 2.3 KT KiB), and two share a CU.  Per column one
-// workgroup barrier: the wavefronts' partials of the Gram row x . W[:, j] go
-// to LDS (double-buffered by the parity of c, so a wavefront can write the
-// next column's while another still reads this column's); every wavefront
-// sums them in the same order and so forms the same reflectors, and each
-// updates its own rows.
+// over the wavefront.  A workgroup needs LDS only for the column partials,
+// the Gram row and the pivot row (about 2.5 KT KiB), and two share a CU.  Per
+// column two workgroup barriers: the wavefronts' partials of the Gram row
+// x . W[:, j] go to LDS, then the first 16 KT threads sum them in wavefront
+// order into the Gram row (buffers double-buffered by the parity of c).
+// Every wavefront reads the same Gram row and pivot row and so forms the
+// same reflectors, and each updates its own rows.
 constexpr int kBRWaves = 8, kBRThreads = 64 * kBRWaves;
 
 // Lane `src` (uniform) of a double in every lane.
@@ -992,6 +992,7 @@ k_bidiag_rows(SmallBatch sb) {
   const int i0 = 4 * wave + q;  // row of slot 0; slot s holds row i0 + 32 s
   double* part = reinterpret_cast<double*>(smem_raw);  // [2][kBRWaves][S]
   double* rowc = part + 2 * kBRWaves * S;              // [2][S]
+  double* gsum = rowc + 2 * S;                         // [2][S]
   double R[RS][KT];
   int bad = 0;
 #pragma unroll
@@ -1015,6 +1016,7 @@ k_bidiag_rows(SmallBatch sb) {
       const int buf = c & 1;
       double* pb = part + buf * kBRWaves * S;
       double* rb = rowc + buf * S;
+      double* gb = gsum + buf * S;
       const int src = (lane & 48) | lc;  // lane of column c in this row of lanes
       // this wavefront's partials of x . W[:, j] over its rows i >= c, summed
       // over its four rows of lanes, and the pivot row from its owner
@@ -1041,9 +1043,15 @@ k_bidiag_rows(SmallBatch sb) {
         if (q == 0) pb[wave * S + l16 + 16 * t] = p[t];
       }
       __syncthreads();
-      double s0 = 0.0;
+      // the Gram row, summed over the wavefronts in order once per column
+      if (tid < S) {
+        double g = 0.0;
 #pragma unroll
-      for (int w = 0; w < kBRWaves; ++w) s0 += pb[w * S + c];
+        for (int w = 0; w < kBRWaves; ++w) g += pb[w * S + tid];
+        gb[tid] = g;
+      }
+      __syncthreads();
+      const double s0 = gb[c];
       const double x0 = rb[c];
       const double nx = sqrt(s0);
       const double alpha = nx > 0.0 ? -copysign(nx, x0) : 0.0;
@@ -1057,15 +1065,12 @@ k_bidiag_rows(SmallBatch sb) {
 #pragma unroll
       for (int t = 0; t < KT; ++t) {
         const int j = l16 + 16 * t;
-        double g = 0.0;
-#pragma unroll
-        for (int w = 0; w < kBRWaves; ++w) g += pb[w * S + j];
+        const double g = gb[j];
         const double row = rb[j];
         const bool live = j > c && j < k;
         wj[t] = live ? tau * (g - alpha * row) : 0.0;
         v[t] = live ? row - u0 * wj[t] : 0.0;
         pp += v[t] * v[t];
-        if (t % 2 == 1) asm volatile("" ::: "memory");  // at most two columns' partials in flight
       }
       const double ny2 = row16_sum(pp);
       const double ysrc = (lc == 15 && tc + 1 < KT) ? v[tc + 1 < KT ? tc + 1 : tc] : v[tc];
@@ -1428,7 +1433,7 @@ RowsKernel rows_kernel(int64_t l, int64_t k) {
     kt = 8;
     fn = rs <= 4 ? (const void*)k_bidiag_rows<8, 4> : rs <= 6 ? (const void*)k_bidiag_rows<8, 6> : nullptr;
   }
-  return {fn, (size_t)(2 * kBRWaves + 2) * 16 * kt * sizeof(double)};
+  return {fn, (size_t)(2 * kBRWaves + 4) * 16 * kt * sizeof(double)};
 }
 
 // Rows per workgroup at most `svd_rows_target()` (fewer rows shorten the
