@@ -450,8 +450,11 @@ re_status run_once(re_handle h, const Plan& p, const void* A, int32_t dt, int64_
   const double scale = 1.0 / sqrt((double)rs.k * (double)rs.l);
   mark(h, RE_STAGE_SVD);
   bool plain = false;
+  // FP64 inputs never reach the batched form (FP32 only), so their small
+  // sketches take the multisection
+  const bool ms = dt == RE_F64;
   RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info, h->spin_limit, h->xcd,
-                    fl.n <= kPlainInFlight ? 1 : 0, &plain));
+                    fl.n <= kPlainInFlight ? 1 : 0, &plain, ms));
   mark(h, RE_STAGE_RANK);
   RE_TRY(launch_rank_count(h->stream, sigma, rs.k, r1, eps, info, out3));
   char* host = (char*)h->host;
@@ -463,7 +466,8 @@ re_status run_once(re_handle h, const Plan& p, const void* A, int32_t dt, int64_
     // a participant of the plain launch waited past its short poll limit: the
     // same step again, plain under the default limit (C is intact; the SVD
     // starts from it afresh)
-    RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info, h->spin_limit, h->xcd, 2));
+    RE_TRY(launch_svd(h->stream, C, rs.l, rs.k, scale, at(h, p.svd), sigma, info, h->spin_limit, h->xcd, 2, nullptr,
+                      ms));
     RE_TRY(launch_rank_count(h->stream, sigma, rs.k, r1, eps, info, out3));
     RE_TRY_HIP(hipMemcpyAsync(host, out3, 16, hipMemcpyDeviceToHost, h->stream));
     RE_TRY_HIP(hipMemcpyAsync(host + 64, sigma, (size_t)rs.k * 8, hipMemcpyDeviceToHost, h->stream));

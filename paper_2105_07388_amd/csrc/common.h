@@ -169,9 +169,13 @@ RE_HIDDEN size_t svd_scratch_bytes(int64_t l, int64_t k);
 // cooperative form runs one kernel at a time device-wide), 1 with a short
 // barrier poll limit, 2 with the default one; *used_plain (if given) tells
 // whether it did, so that a caller can redo a give-up (C is left untouched).
+// A sketch small enough for one workgroup takes the batched form's per-lane
+// bisection (the same bits as a block of a batch), or with multisect_small
+// the 64-way multisection (shorter on one small sketch; for inputs the
+// batched form never takes).
 RE_HIDDEN re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, double scale, void* scratch,
                                double* sigma, int32_t* info, long spin_limit = 0, int xcd = 0,
-                               int allow_plain = 0, bool* used_plain = nullptr);
+                               int allow_plain = 0, bool* used_plain = nullptr, bool multisect_small = false);
 RE_HIDDEN re_status launch_rank_count(hipStream_t s, const double* sigma, int64_t k, int32_t r1, double eps,
                                       const int32_t* info, int32_t* out3);
 // Gap statistics of descending estimates (search without a tolerance).

@@ -1726,7 +1726,8 @@ re_status launch_grid(const void* fn, dim3 grid, dim3 block, void** params, unsi
 }  // namespace
 
 re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, double scale, void* scratch,
-                     double* sigma, int32_t* info, long spin_limit, int xcd, int allow_plain, bool* used_plain) {
+                     double* sigma, int32_t* info, long spin_limit, int xcd, int allow_plain, bool* used_plain,
+                     bool multisect_small) {
   if (used_plain) *used_plain = false;
   if (k <= 0) return RE_OK;
   const long spins = spin_limit == 0 ? (1l << 26) : spin_limit;
@@ -1859,7 +1860,7 @@ re_status launch_svd(hipStream_t s, const double* C, int64_t l, int64_t k, doubl
   }
   const size_t lds2 = (size_t)(4 * k) * 8;
   if (lds2 > 160 * 1024) return RE_ERR_UNSUPPORTED;
-  if (one_bytes <= kLdsBudget) {  // the batched form's per-lane bisection
+  if (one_bytes <= kLdsBudget && !multisect_small) {  // the batched form's per-lane bisection
     SvDesc one{};
     one.d = a.d;
     one.e = a.e;
