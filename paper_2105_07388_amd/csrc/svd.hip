@@ -1569,12 +1569,13 @@ SvdLayout svd_layout(int64_t l, int64_t k) {
 // Batched counts (problem = blockIdx.x); same arithmetic as k_count.
 // Singular values of small bidiagonals, one lane per value: 56 bisection
 // steps on the Sturm count (the interval shrinks below 2^-56 of the bound,
-// as the 65-way multisection does in 9 rounds), one workgroup per problem
-// (`one` when desc is NULL).  A workgroup takes ppw problems: problem
+// as the 65-way multisection does in 9 rounds) (`one` when desc is NULL).
+// A workgroup takes ppw problems: problem
 // blockIdx.x ppw + p on lanes p kslot .. p kslot + kslot - 1, so that 96
 // values of two problems fill three wavefronts (ppw = 1: the whole workgroup,
-// values strided by blockDim.x).  Used for every sketch whose
-// bidiagonalisation fits one workgroup, single or batched; a lane's
+// values strided by blockDim.x).  Used for every batched block and for the
+// single calls' sketches whose bidiagonalisation fits one workgroup (except
+// the plain method on FP64 inputs, which takes the multisection); a lane's
 // arithmetic depends only on its problem and value, so a block of a batch
 // and the same matrix alone give the same bits.
 constexpr int kBisectSteps = 56;
