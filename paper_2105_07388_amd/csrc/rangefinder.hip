@@ -776,13 +776,16 @@ re_status launch_yb_tiled(hipStream_t s, const float* B, int64_t m, int64_t k, i
 // FP64 C (M x N, ldc) = A (M x K) B (K x N) on the FP64 matrix cores (the
 // 64 x 64 tiles of k_nn64).  K is split into S slices only when M is short
 // (fewer than 64 row tiles) and K long, so that a short, wide product still
-// fills the chip; the slices' partial products are then summed in slice
-// order.  S depends on M and K alone, so every column of C gets the same
-// arithmetic whatever N is (a product over the appended columns of B gives
-// the bits of the same columns in a wider product).
+// fills the chip: slices of 4096 rows (at most 32) past K = 4096, of 256 rows
+// from K = 513 to 4096 (a 60 x 40 product over 2000 rows is otherwise one
+// workgroup's sequential sweep); the slices' partial products are then summed
+// in slice order.  S depends on M and K alone, so every column of C gets the
+// same arithmetic whatever N is (a product over the appended columns of B
+// gives the bits of the same columns in a wider product).
 void gemm64_split(int64_t M, int64_t K, int64_t* splits, int64_t* rows_per_split) {
   int64_t sp = 1;
   if (cdiv(M, 64) < 64 && K > 4096) sp = cdiv(K, 4096) < 32 ? cdiv(K, 4096) : 32;
+  else if (cdiv(M, 64) < 64 && K > 512) sp = cdiv(K, 256);
   const int64_t rps = cdiv(cdiv(K, sp), kABK) * kABK;
   *rows_per_split = rps;
   *splits = cdiv(K, rps);
